@@ -1,0 +1,259 @@
+/*
+ * c3tod -- time-ordered-data (TOD) step of a Commander3-style Gibbs sampler
+ * (Galloway et al., "BeyondPlanck III. Commander3", arXiv:2201.03509) on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Data model (Eq. 1, reduced to one pixelised sky and no beam):
+ *     d_t = g P_t m + n_corr,t + n_w,t,
+ *     P_t m = T[p_t] + Q[p_t] cos 2psi_t + U[p_t] sin 2psi_t,
+ * where p_t is a HEALPix pixel and psi_t the centre 2 pi (b_t + 1/2)/n_psi of
+ * a quantised polarisation-angle bin b_t (section 4.1, n_psi = 4096).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Segment: one (scan, detector) pair -- the paper's comm_detscan (Listing of
+ *   the TOD classes, section 3.3) -- with n_s samples.  All per-sample arrays
+ *   are flat: segment s occupies [seg_off[s], seg_off[s+1]).
+ * Band: one frequency channel with its own nside, sampling rate and map.
+ *   The maps of all bands are concatenated along the pixel axis: band b's
+ *   pixel p is global pixel pix_off[b] + p; npix_total = sum of npix.
+ * Maps: [3][npix_total] (T block, Q block, U block), FP32 for TOD_MIXED,
+ *   FP64 for TOD_PLAIN_FP64.
+ * Binned accumulators: [npix_total][10] FP64 per pixel:
+ *   { b_T, b_Q, b_U, A_TT, A_TQ, A_TU, A_QQ, A_QU, A_UU, hits }.
+ * Pointers: "device" = HIP device memory on the context's device; "host" =
+ *   ordinary host memory.  The caller owns every buffer it passes; the
+ *   context owns its scratch (FFT workspace, plans, task lists, graphs).
+ * Streams: every call is asynchronous on the context's stream; one context
+ *   serves one stream and one host thread at a time.
+ * Errors: host-detectable problems return a status before any device work
+ *   is queued.  Device-detected problems (corrupt Huffman stream, decoded
+ *   value out of range) raise a sticky device error word that tod_sync()
+ *   returns as TOD_ECORRUPT; it stays set until tod_clear_error().
+ *   tod_last_error() describes the last failure.
+ * Precision: TOD_MIXED runs projection, residuals, FFTs and draws in FP32
+ *   and keeps per-pixel accumulation and the 3x3 solve in FP64;
+ *   TOD_PLAIN_FP64 runs everything in FP64 (the TOD d may still be FP32).
+ */
+#ifndef C3TOD_H
+#define C3TOD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tod_ctx_s *tod_ctx;
+
+typedef enum {
+    TOD_OK = 0,
+    TOD_EINVAL = 1,     /* bad argument, detected on the host before any launch */
+    TOD_ENOMEM = 2,     /* device allocation of context scratch failed */
+    TOD_EHIP = 3,       /* a HIP runtime call failed */
+    TOD_ECORRUPT = 4,   /* sticky device error: corrupt stream / value out of range */
+    TOD_ENOTSUP = 5     /* unsupported size (e.g. FFT length beyond the plan limits) */
+} tod_status;
+
+typedef enum { TOD_PLAIN_FP64 = 0, TOD_MIXED = 1 } tod_prec;
+typedef enum { TOD_F32 = 0, TOD_F64 = 1 } tod_dtype;
+
+/* One frequency band (host struct).  npsi must be 4096 (section 4.1). */
+typedef struct {
+    int32_t nside;
+    int32_t npsi;
+    int64_t npix;       /* 12 nside^2 */
+    int64_t pix_off;    /* first global pixel of this band */
+    double fsamp;       /* sampling rate, Hz */
+} tod_band;
+
+/* Segment table (the paper's comm_tod -> comm_scan -> comm_detscan tree,
+ * flattened).  Device arrays are read by kernels; host mirrors are read when
+ * planning work, so they must hold the same values. */
+typedef struct {
+    int32_t nseg;                /* number of (scan, detector) segments */
+    int32_t nband;               /* number of bands */
+    int32_t ndet;                /* number of detectors (per-detector gradients) */
+    int32_t reserved;
+    int64_t nsamp;               /* seg_off[nseg] */
+    int64_t npix_total;          /* sum of band npix */
+    const int64_t *seg_off;      /* device [nseg+1], non-decreasing, seg_off[0] = 0 */
+    const int32_t *seg_band;     /* device [nseg], in [0, nband) */
+    const int32_t *seg_det;      /* device [nseg], in [0, ndet) */
+    const uint8_t *seg_accept;   /* device [nseg], the paper's `accept`: 0 = leave out
+                                    of binning and chi^2; may be NULL (all accepted) */
+    const int64_t *h_seg_off;    /* host mirror [nseg+1] */
+    const int32_t *h_seg_band;   /* host mirror [nseg] */
+    const tod_band *bands;       /* host [nband] */
+} tod_layout;
+
+/* One Huffman-coded, sample-differenced pointing stream kind (section 4.1):
+ * the pixel stream or the psi-bin stream.  All arrays are device arrays.
+ * Table blob t (uint32 words, at tables[table_off[t]]):
+ *   [nsym, maxlen, count[1..32], sym[0..nsym)]
+ * with sym the int32 difference values in canonical code order (codes of one
+ * length consecutive, first code of length L = (first(L-1) + count(L-1)) << 1).
+ * Segment s's bitstream is MSB-first in words[seg_word_off[s] .. seg_word_off[s+1]),
+ * zero padded.  Its first symbol is the absolute first value (d(-1) = 0).
+ * Side index: chunk c of segment s (symbols [c*chunk_len, (c+1)*chunk_len))
+ * starts at bit chunk_bit[seg_chunk_off[s] + c] of the segment stream and the
+ * undifferenced value before it is chunk_prev[...] (0 for c = 0). */
+typedef struct {
+    const uint32_t *words;
+    const int64_t *seg_word_off;     /* [nseg+1] */
+    const int32_t *seg_table;        /* [nseg] table id of each segment */
+    const uint32_t *tables;
+    const int64_t *table_off;        /* [ntable+1] */
+    const uint32_t *chunk_bit;       /* [nchunk] */
+    const int32_t *chunk_prev;       /* [nchunk] */
+    const int64_t *seg_chunk_off;    /* [nseg+1], seg_chunk_off[s+1]-seg_chunk_off[s] = ceil(n_s/chunk_len) */
+    int32_t chunk_len;               /* 32 .. 4096, multiple of 32 */
+    int32_t ntable;
+    int64_t nwords;
+    int64_t nchunk;
+} tod_huff;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The stream must outlive the ctx. */
+tod_status tod_ctx_create(tod_ctx *ctx, int device, void *hip_stream);
+/* Free the context and its scratch (synchronises its stream first). */
+tod_status tod_ctx_destroy(tod_ctx ctx);
+/* Wait for the stream; return TOD_ECORRUPT if the sticky device error is set. */
+tod_status tod_sync(tod_ctx ctx);
+/* Clear the sticky device error word. */
+tod_status tod_clear_error(tod_ctx ctx);
+/* Text of the last failure on this context ("" if none).  Owned by the ctx. */
+const char *tod_last_error(tod_ctx ctx);
+/* Device error word bits (after tod_sync): 1 = invalid code, 2 = chunk
+ * boundary mismatch, 4 = pixel out of range, 8 = psi bin out of range. */
+uint32_t tod_device_error_bits(tod_ctx ctx);
+
+/* ------------------------------------------------------------- hot path */
+
+/* Huffman decode + undifferencing of the pixel and psi streams (section 4.1;
+ * decompression row of the resource table).  Output: pix_out[nsamp] int32
+ * band-local HEALPix RING pixel, psi_out[nsamp] uint16 bin in [0, npsi).
+ * Bit-exact.  Corruption is reported through the sticky error word. */
+tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay,
+                           const tod_huff *pix, const tod_huff *psi,
+                           int32_t *pix_out, uint16_t *psi_out);
+
+/* Projection s = g P m (Eq. 1; pointing matrix as pixel + psi streams,
+ * section 2.1).  pix/psi: device [nsamp] as produced by decode_pointing.
+ * maps: device [3][npix_total] FP32 (mixed) or FP64 (plain).  gain: device
+ * [nseg] FP64.  s_out: device [nsamp] FP32 (mixed) or FP64 (plain). */
+tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                       const int32_t *pix, const uint16_t *psi,
+                       const void *maps, const double *gain, void *s_out);
+
+/* Correlated-noise draw n_corr <- P(n_corr | d, g, xi_n, sky) (Eq. 4) as a
+ * Fourier-domain constrained realisation on the mirrored segment (section 4.2):
+ *   r = d - s;  e = [r, reverse(r), r_0 ...] of length N = smallest even
+ *   5-smooth >= 2n;  R = FFT(e)/sqrt(N);  with P_k = sigma0^2 (f_k/f_knee)^alpha,
+ *   f_k = k fsamp/N, 1/P_0 = 0:
+ *   nhat_k = (R_k/sigma0^2 + W1_k/sigma0 + W2_k P_k^-1/2) / (1/sigma0^2 + 1/P_k);
+ *   n_corr = first n samples of the unitary inverse FFT of nhat.
+ * W1, W2: unit complex normals (real at k = 0 and N/2) from Philox4x32-10 with
+ *   key = (seed & 0xffffffff, segment), counter = (k, iter lo, iter hi, seed hi),
+ *   u = (x + 1/2) 2^-32 and Box-Muller on (u0,u1), (u2,u3).  mean_only != 0
+ *   sets W = 0 (the Wiener-filter mean).
+ * d: device [nsamp] of d_dtype; s: device [nsamp] (FP32 mixed / FP64 plain);
+ * sigma0, fknee, alpha: device [nseg] FP64 (sigma0 > 0, fknee > 0, alpha < 0
+ * is the caller's responsibility: they are not read on the host).
+ * ncorr_out: device [nsamp] (FP32 mixed / FP64 plain). */
+tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                        const void *d, tod_dtype d_dtype, const void *s,
+                        const double *sigma0, const double *fknee, const double *alpha,
+                        uint64_t seed, uint64_t iter, int mean_only, void *ncorr_out);
+
+/* Binning into per-pixel P^T N^-1 d and P^T N^-1 P (section 2.4: co-added on
+ * the fly during the TOD loop; binning row of the resource table): with
+ * w = g/sigma0^2, v = d - n_corr, (c, s) = (cos 2psi, sin 2psi):
+ *   b_p += w v (1, c, s),  A_p += g w (1, c, s)^T (1, c, s),  hits_p += 1.
+ * acc: device [npix_total][10] FP64.  accumulate = 0 zeroes acc first.
+ * ncorr may be NULL (v = d).  Segments with accept = 0 are skipped. */
+tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                   const int32_t *pix, const uint16_t *psi,
+                   const void *d, tod_dtype d_dtype, const void *ncorr,
+                   const double *gain, const double *sigma0,
+                   double *acc, int accumulate);
+
+/* Per-pixel map solve m_p = A_p^-1 b_p in FP64 with the condition number
+ * rcond_p = lambda_min / lambda_max of A_p; pixels with hits < 3 or
+ * rcond < rcond_min get NaN.  acc: device [npix][10]; map_out: device
+ * [3][npix] of map_dtype; rcond_out: device [npix] FP64 (may be NULL). */
+tod_status solve_maps(tod_ctx ctx, int64_t npix, const double *acc, double rcond_min,
+                      void *map_out, tod_dtype map_dtype, double *rcond_out);
+
+/* chi^2 per segment (the likelihood evaluation of the TOD step):
+ *   J_s = sum_t r_t^2/sigma0^2 + sum_{k=1}^{N/2} (I_k/P_k + ln P_k),
+ *   r = d - g P m - n_corr,  I_k = |FFT(e(n_corr))_k|^2 / N on the same
+ *   mirrored extension and N as sample_ncorr.
+ * chisq_seg: device [nseg] FP64 (0 for rejected segments). */
+tod_status tod_chisq(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                     const int32_t *pix, const uint16_t *psi,
+                     const void *d, tod_dtype d_dtype, const void *ncorr,
+                     const void *maps, const double *gain,
+                     const double *sigma0, const double *fknee, const double *alpha,
+                     double *chisq_seg);
+
+/* Adjoint of tod_chisq, scaled by grad_scale (dL/dJ):
+ *   dJ/dm = -2 P^T (g r / sigma0^2)                       -> grad_maps [3][npix_total] FP64
+ *   dJ/dg_s = -2 sum_t (P m)_t r_t / sigma0^2             -> grad_gain [nseg]
+ *   dJ/dsigma0 = -2 sum r^2/sigma0^3 + sum_k (2/sigma0)(1 - I_k/P_k)
+ *   dJ/df_knee = sum_k (1 - I_k/P_k)(-alpha/f_knee)
+ *   dJ/dalpha  = sum_k (1 - I_k/P_k) ln(f_k/f_knee)
+ * the last three summed over each detector's segments -> [ndet] arrays.
+ * All outputs are device FP64 and are overwritten.  Any of them may be NULL. */
+tod_status tod_chisq_backward(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                              const int32_t *pix, const uint16_t *psi,
+                              const void *d, tod_dtype d_dtype, const void *ncorr,
+                              const void *maps, const double *gain,
+                              const double *sigma0, const double *fknee, const double *alpha,
+                              double grad_scale,
+                              double *grad_maps, double *grad_gain,
+                              double *grad_sigma0, double *grad_fknee, double *grad_alpha);
+
+/* One fused TOD sweep: decode -> project -> n_corr draw -> binning (the
+ * decompress / project / correlated-noise / bin rows of the TOD loop).
+ * Writes ncorr_out [nsamp] (FP32 mixed / FP64 plain), zeroes and fills acc
+ * [npix_total][10].  pix_work/psi_work: device [nsamp] scratch that receives
+ * the decoded pointing.  use_graph != 0 captures the sweep's kernels into a
+ * hipGraph on the first call with a given set of arguments and replays it
+ * afterwards (seed and iter are read from device memory, so they may change
+ * between replays). */
+tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                     const tod_huff *pix, const tod_huff *psi,
+                     const void *d, tod_dtype d_dtype, const void *maps,
+                     const double *gain, const double *sigma0,
+                     const double *fknee, const double *alpha,
+                     uint64_t seed, uint64_t iter,
+                     void *ncorr_out, double *acc,
+                     int32_t *pix_work, uint16_t *psi_work, int use_graph);
+
+/* --------------------------------------------------------- planning/tuning */
+
+/* Measure candidate FFT splits/radix orders for every FFT length the layout
+ * needs and candidate binning strides, keep the fastest in the context, and
+ * (if cache_path != NULL) merge them into a JSON cache file.  Needs the
+ * decoded pointing (pix) for the binning probe; may be NULL to skip it. */
+tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                        const int32_t *pix, const char *cache_path);
+/* Load plans from a JSON cache written by tod_autotune (missing file: OK). */
+tod_status tod_load_tuning(tod_ctx ctx, const char *cache_path);
+/* Binning stride (samples between revisits of a pixel) per band; 0 = let the
+ * library choose.  Correct for any value; only speed depends on it. */
+tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride);
+
+/* Kernel time of the last call per phase (ms, from HIP events on the ctx
+ * stream) when timing is enabled; phases: 0 decode, 1 project, 2 ncorr FFT
+ * passes, 3 bin, 4 solve, 5 chisq. */
+tod_status tod_enable_timing(tod_ctx ctx, int enable);
+tod_status tod_phase_ms(tod_ctx ctx, double *ms6);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* C3TOD_H */

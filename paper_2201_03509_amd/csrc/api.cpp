@@ -1,0 +1,1028 @@
+// C-ABI of c3tod: context, host-side validation, planning and launch order.
+//
+// Planning turns the segment table into device-resident work lists once per
+// distinct layout (keyed by a hash of the host mirrors) and caches them:
+//   * one FFT plan per distinct complex length M (split M = M1 x M2, radix
+//     orders, twiddle tables computed in extended precision on the host);
+//   * column and row task lists for the three FFT passes, ordered longest
+//     segment first (LPT) so the tail of every launch is short;
+//   * decode tasks (blocks of up to 256 chunks of one segment);
+//   * strided bin tiles per segment (revisit period per band).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "tune.h"
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n && p) return hipSuccess;
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+            n = 0;
+        }
+        if (bytes == 0) bytes = 8;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipSuccess) n = bytes;
+        return e;
+    }
+    template <typename T>
+    hipError_t upload(const std::vector<T> &v, hipStream_t st) {
+        hipError_t e = ensure(v.size() * sizeof(T));
+        if (e != hipSuccess || v.empty()) return e;
+        e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    }
+};
+
+uint64_t fnv(uint64_t h, const void *data, size_t n) {
+    const uint8_t *b = (const uint8_t *)data;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+int64_t next_5smooth(int64_t n) {
+    if (n <= 1) return 1;
+    for (int64_t m = n;; ++m) {
+        int64_t x = m;
+        while (x % 2 == 0) x /= 2;
+        while (x % 3 == 0) x /= 3;
+        while (x % 5 == 0) x /= 5;
+        if (x == 1) return m;
+    }
+}
+
+struct Plan {
+    uint64_t key = 0;
+    int mixed = 0;
+    std::vector<SegInfo> h_segs;
+    std::vector<int32_t> seg_order;       // LPT order
+    std::vector<FftPlan> h_plans;
+    std::map<int64_t, int> plan_of_M;
+    DevBuf segs, plans, twpool, col_tasks, row_tasks, fsamp;
+    int ncol = 0, nrow = 0;
+    int64_t work_elems = 0;
+    DevBuf sample_tiles;
+    int nsample_tiles = 0;
+    // decode tasks per chunk length
+    std::map<int, std::unique_ptr<DevBuf>> dec_tasks;
+    std::map<int, int> ndec;
+    // bin tiles, rebuilt when strides change
+    DevBuf bin_tiles;
+    int nbin = 0;
+    std::vector<int> bin_stride;          // per band, as used for bin_tiles
+};
+
+}  // namespace
+
+struct tod_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint32_t *d_err = nullptr;
+    uint64_t *d_seed_iter = nullptr;
+    DevBuf trig32, trig64, work, seg_sums, seg_whittle, probe_counts, resid;
+    std::map<uint64_t, std::unique_ptr<Plan>> plans;
+    std::map<int, int> band_stride;       // band index -> stride (tuned or set)
+    std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
+    c3tune::Table tuned;                  // FFT choices
+    std::string last_error;
+    uint32_t last_err_bits = 0;
+    bool timing = false;
+    hipEvent_t ev[8] = {};
+    double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+    struct GraphEntry {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+    };
+    std::map<uint64_t, GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;     // capture-only stream (default priority)
+};
+
+namespace {
+
+std::string band_key(const tod_band &b);
+
+tod_status fail(tod_ctx c, tod_status s, const std::string &msg) {
+    if (c) c->last_error = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                      \
+    do {                                                                                  \
+        hipError_t _e = (call);                                                           \
+        if (_e != hipSuccess)                                                             \
+            return fail(ctx, TOD_EHIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+tod_status check_layout(tod_ctx ctx, const tod_layout *L) {
+    if (!L) return fail(ctx, TOD_EINVAL, "layout is NULL");
+    if (L->nseg < 0 || L->nband < 1 || L->nband > C3_MAXBAND || L->ndet < 1)
+        return fail(ctx, TOD_EINVAL, "nseg/nband/ndet out of range");
+    if (!L->seg_off || !L->seg_band || !L->seg_det || !L->h_seg_off || !L->h_seg_band || !L->bands)
+        return fail(ctx, TOD_EINVAL, "layout has a NULL array");
+    if (L->h_seg_off[0] != 0) return fail(ctx, TOD_EINVAL, "seg_off[0] != 0");
+    for (int s = 0; s < L->nseg; ++s) {
+        const int64_t n = L->h_seg_off[s + 1] - L->h_seg_off[s];
+        if (n < 0) return fail(ctx, TOD_EINVAL, "seg_off is not non-decreasing");
+        if (n > (1 << 30)) return fail(ctx, TOD_ENOTSUP, "segment longer than 2^30 samples");
+        if (L->h_seg_band[s] < 0 || L->h_seg_band[s] >= L->nband)
+            return fail(ctx, TOD_EINVAL, "seg_band out of range");
+    }
+    if (L->h_seg_off[L->nseg] != L->nsamp) return fail(ctx, TOD_EINVAL, "nsamp != seg_off[nseg]");
+    int64_t off = 0;
+    for (int b = 0; b < L->nband; ++b) {
+        const tod_band &B = L->bands[b];
+        if (B.npsi != 4096) return fail(ctx, TOD_EINVAL, "npsi must be 4096");
+        if (B.nside < 1 || B.npix != 12ll * B.nside * B.nside)
+            return fail(ctx, TOD_EINVAL, "npix != 12 nside^2");
+        if (B.pix_off != off) return fail(ctx, TOD_EINVAL, "band pix_off not contiguous");
+        if (!(B.fsamp > 0)) return fail(ctx, TOD_EINVAL, "fsamp must be > 0");
+        off += B.npix;
+    }
+    if (off != L->npix_total) return fail(ctx, TOD_EINVAL, "npix_total != sum of band npix");
+    return TOD_OK;
+}
+
+tod_status check_huff(tod_ctx ctx, const tod_huff *h, const char *what) {
+    if (!h || !h->words || !h->seg_word_off || !h->seg_table || !h->tables || !h->table_off ||
+        !h->chunk_bit || !h->chunk_prev || !h->seg_chunk_off)
+        return fail(ctx, TOD_EINVAL, std::string(what) + " stream has a NULL array");
+    if (h->chunk_len < 32 || h->chunk_len > 4096 || (h->chunk_len % 32))
+        return fail(ctx, TOD_EINVAL, std::string(what) + " chunk_len must be a multiple of 32 in [32, 4096]");
+    if (h->ntable < 1) return fail(ctx, TOD_EINVAL, std::string(what) + " has no tables");
+    return TOD_OK;
+}
+
+LayoutDev make_layout_dev(const tod_layout *L) {
+    LayoutDev d;
+    memset(&d, 0, sizeof(d));
+    d.seg_off = L->seg_off;
+    d.seg_band = L->seg_band;
+    d.seg_det = L->seg_det;
+    d.seg_accept = L->seg_accept;
+    d.nseg = L->nseg;
+    d.nband = L->nband;
+    d.ndet = L->ndet;
+    d.nsamp = L->nsamp;
+    d.npix_total = L->npix_total;
+    for (int b = 0; b < L->nband; ++b) {
+        d.band[b].npix = L->bands[b].npix;
+        d.band[b].pix_off = L->bands[b].pix_off;
+        d.band[b].fsamp = L->bands[b].fsamp;
+        d.band[b].npsi = L->bands[b].npsi;
+        d.band[b].nside = L->bands[b].nside;
+    }
+    return d;
+}
+
+HuffDev make_huff_dev(const tod_huff *h) {
+    HuffDev d;
+    d.words = h->words;
+    d.seg_word_off = h->seg_word_off;
+    d.seg_table = h->seg_table;
+    d.tables = h->tables;
+    d.table_off = h->table_off;
+    d.chunk_bit = h->chunk_bit;
+    d.chunk_prev = h->chunk_prev;
+    d.seg_chunk_off = h->seg_chunk_off;
+    d.chunk_len = h->chunk_len;
+    d.ntable = h->ntable;
+    return d;
+}
+
+// ------------------------------------------------------------- twiddles
+struct Pool {
+    std::vector<long double> re, im;
+    std::map<int64_t, int64_t> sub_tab;  // L -> offset of w_L^m
+    int64_t add_sub(int64_t L) {
+        auto it = sub_tab.find(L);
+        if (it != sub_tab.end()) return it->second;
+        const int64_t off = (int64_t)re.size();
+        for (int64_t m = 0; m < L; ++m) push(m, L);
+        sub_tab[L] = off;
+        return off;
+    }
+    void push(int64_t m, int64_t L) {  // e^{-2 pi i m / L}
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)L;
+        re.push_back(cosl(a));
+        im.push_back(sinl(a));
+    }
+};
+
+tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key, Plan **out) {
+    auto P = std::make_unique<Plan>();
+    P->key = key;
+    P->mixed = mixed;
+    const int S = mixed ? 8192 : 4096;  // LDS complex capacity per block
+    const int nseg = L->nseg;
+    P->h_segs.resize(nseg);
+    Pool pool;
+    int64_t scr = 0;
+    for (int s = 0; s < nseg; ++s) {
+        SegInfo &g = P->h_segs[s];
+        g.samp_off = L->h_seg_off[s];
+        g.n = (int32_t)(L->h_seg_off[s + 1] - L->h_seg_off[s]);
+        g.band = L->h_seg_band[s];
+        g.det = 0;
+        g.accept = 1;
+        g.pad = 0;
+        g.scr_off = scr;
+        g.plan = -1;
+        if (g.n <= 0) continue;
+        const int64_t M = next_5smooth(g.n);
+        auto it = P->plan_of_M.find(M);
+        if (it == P->plan_of_M.end()) {
+            c3tune::FftChoice ch;
+            if (!ctx->tuned.get(mixed, M, ch)) {
+                if (!c3tune::default_choice(M, S, ch))
+                    return fail(ctx, TOD_ENOTSUP, "no FFT plan for M = " + std::to_string(M));
+            }
+            FftPlan fp;
+            memset(&fp, 0, sizeof(fp));
+            fp.M = (int32_t)M;
+            fp.M1 = ch.M1;
+            fp.M2 = ch.M2;
+            fp.B = ch.B;
+            fp.nr1 = (int)ch.r1.size();
+            fp.nr2 = (int)ch.r2.size();
+            for (size_t i = 0; i < ch.r1.size(); ++i) fp.r1[i] = (int8_t)ch.r1[i];
+            for (size_t i = 0; i < ch.r2.size(); ++i) fp.r2[i] = (int8_t)ch.r2[i];
+            fp.tw1 = pool.add_sub(ch.M1);
+            fp.tw2 = pool.add_sub(ch.M2);
+            const int64_t N = 2 * M;
+            fp.twlo = (int64_t)pool.re.size();
+            for (int64_t m = 0; m < 1024; ++m) pool.push(m, N);
+            fp.twhi = (int64_t)pool.re.size();
+            for (int64_t h = 0; h <= N / 1024 + 1; ++h) pool.push(h * 1024, N);
+            P->plan_of_M[M] = (int)P->h_plans.size();
+            P->h_plans.push_back(fp);
+            it = P->plan_of_M.find(M);
+        }
+        g.plan = it->second;
+        scr += M;
+    }
+    P->work_elems = scr;
+    // LPT order: longest FFT first
+    P->seg_order.resize(nseg);
+    for (int s = 0; s < nseg; ++s) P->seg_order[s] = s;
+    std::stable_sort(P->seg_order.begin(), P->seg_order.end(), [&](int a, int b) {
+        return P->h_segs[a].n > P->h_segs[b].n;
+    });
+    std::vector<int2> col, row;
+    for (int s : P->seg_order) {
+        const SegInfo &g = P->h_segs[s];
+        if (g.plan < 0) continue;
+        const FftPlan &fp = P->h_plans[g.plan];
+        for (int c0 = 0; c0 < fp.M2; c0 += fp.B) col.push_back(make_int2(s, c0));
+        for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) row.push_back(make_int2(s, k1));
+    }
+    P->ncol = (int)col.size();
+    P->nrow = (int)row.size();
+    std::vector<double> fs(L->nband);
+    for (int b = 0; b < L->nband; ++b) fs[b] = L->bands[b].fsamp;
+    // sample tiles (projection): 4096 samples per block
+    std::vector<int4> tiles;
+    for (int s = 0; s < nseg; ++s) {
+        const int n = P->h_segs[s].n;
+        for (int t0 = 0; t0 < n; t0 += 4096) tiles.push_back(make_int4(s, t0, std::min(4096, n - t0), 0));
+    }
+    P->nsample_tiles = (int)tiles.size();
+    hipStream_t st = ctx->stream;
+    HIPCHK(P->segs.upload(P->h_segs, st));
+    HIPCHK(P->plans.upload(P->h_plans, st));
+    HIPCHK(P->col_tasks.upload(col, st));
+    HIPCHK(P->row_tasks.upload(row, st));
+    HIPCHK(P->fsamp.upload(fs, st));
+    HIPCHK(P->sample_tiles.upload(tiles, st));
+    if (mixed) {
+        std::vector<cx<float>> tw(pool.re.size());
+        for (size_t i = 0; i < tw.size(); ++i) tw[i] = {(float)pool.re[i], (float)pool.im[i]};
+        HIPCHK(P->twpool.upload(tw, st));
+    } else {
+        std::vector<cx<double>> tw(pool.re.size());
+        for (size_t i = 0; i < tw.size(); ++i) tw[i] = {(double)pool.re[i], (double)pool.im[i]};
+        HIPCHK(P->twpool.upload(tw, st));
+    }
+    *out = P.get();
+    ctx->plans[key] = std::move(P);
+    return TOD_OK;
+}
+
+uint64_t layout_key(const tod_layout *L, int mixed, uint64_t salt) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &mixed, sizeof(mixed));
+    h = fnv(h, &salt, sizeof(salt));
+    h = fnv(h, &L->nseg, sizeof(L->nseg));
+    h = fnv(h, L->h_seg_off, sizeof(int64_t) * (L->nseg + 1));
+    h = fnv(h, L->h_seg_band, sizeof(int32_t) * L->nseg);
+    h = fnv(h, L->bands, sizeof(tod_band) * L->nband);
+    return h;
+}
+
+tod_status get_plan(tod_ctx ctx, const tod_layout *L, int mixed, Plan **out) {
+    const uint64_t key = layout_key(L, mixed, ctx->tuned.version);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) {
+        *out = it->second.get();
+        return TOD_OK;
+    }
+    if (ctx->plans.size() > 16) ctx->plans.clear();
+    return build_plan(ctx, L, mixed, key, out);
+}
+
+tod_status get_decode_tasks(tod_ctx ctx, Plan *P, int C, const DecodeTask **tasks, int *ntask) {
+    auto it = P->dec_tasks.find(C);
+    if (it == P->dec_tasks.end()) {
+        std::vector<DecodeTask> v;
+        for (int s : P->seg_order) {
+            const int n = P->h_segs[s].n;
+            const int nch = (n + C - 1) / C;
+            for (int c0 = 0; c0 < nch; c0 += C3_NT) {
+                DecodeTask t;
+                t.seg = s;
+                t.chunk0 = c0;
+                t.nchunk = std::min(C3_NT, nch - c0);
+                t.pad = 0;
+                v.push_back(t);
+            }
+        }
+        auto b = std::make_unique<DevBuf>();
+        HIPCHK(b->upload(v, ctx->stream));
+        P->ndec[C] = (int)v.size();
+        it = P->dec_tasks.emplace(C, std::move(b)).first;
+    }
+    *tasks = (const DecodeTask *)it->second->p;
+    *ntask = P->ndec[C];
+    return TOD_OK;
+}
+
+// Revisit period of the pixel stream of a band: the lag with the most equal
+// pixels, probed on up to three of the band's segments.
+tod_status probe_stride(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_t *pix, int band,
+                        int *stride) {
+    const int maxlag = 16384;
+    HIPCHK(ctx->probe_counts.ensure(sizeof(unsigned long long) * (maxlag + 1)));
+    HIPCHK(c3::launch_zero(ctx->stream, ctx->probe_counts.p, sizeof(unsigned long long) * (maxlag + 1)));
+    int used = 0;
+    for (int s = 0; s < L->nseg && used < 3; ++s) {
+        if (L->h_seg_band[s] != band) continue;
+        const SegInfo &g = P->h_segs[s];
+        if (g.n < 2 * 64) continue;
+        HIPCHK(c3::launch_repeat_probe(ctx->stream, pix, g.samp_off, g.n, std::min(maxlag, g.n - 1),
+                                       (unsigned long long *)ctx->probe_counts.p));
+        ++used;
+    }
+    std::vector<unsigned long long> cnt(maxlag + 1);
+    HIPCHK(hipMemcpyAsync(cnt.data(), ctx->probe_counts.p, cnt.size() * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int best = 0;
+    unsigned long long bc = 0;
+    for (int l = 64; l <= maxlag; ++l)
+        if (cnt[l] > bc) {
+            bc = cnt[l];
+            best = l;
+        }
+    *stride = best > 0 ? best : 256;
+    return TOD_OK;
+}
+
+tod_status get_bin_tiles(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_t *pix,
+                         const int4 **tiles, int *ntile) {
+    std::vector<int> st(L->nband, 0);
+    for (int b = 0; b < L->nband; ++b) {
+        auto it = ctx->band_stride.find(b);
+        auto kt = ctx->stride_by_key.find(band_key(L->bands[b]));
+        if (it != ctx->band_stride.end() && it->second > 0) {
+            st[b] = it->second;
+        } else if (kt != ctx->stride_by_key.end() && kt->second > 0) {
+            st[b] = kt->second;
+        } else if (pix) {
+            tod_status r = probe_stride(ctx, L, P, pix, b, &st[b]);
+            if (r != TOD_OK) return r;
+            ctx->band_stride[b] = st[b];
+        } else {
+            st[b] = 256;
+        }
+    }
+    if (st != P->bin_stride || P->nbin == 0) {
+        std::vector<int4> v;
+        for (int s : P->seg_order) {
+            const int n = P->h_segs[s].n;
+            const int S = st[P->h_segs[s].band];
+            const int nph = std::min(S, n);
+            for (int p0 = 0; p0 < nph; p0 += C3_NT) v.push_back(make_int4(s, p0, S, std::min(C3_NT, nph - p0)));
+        }
+        HIPCHK(P->bin_tiles.upload(v, ctx->stream));
+        P->nbin = (int)v.size();
+        P->bin_stride = st;
+    }
+    *tiles = (const int4 *)P->bin_tiles.p;
+    *ntile = P->nbin;
+    return TOD_OK;
+}
+
+c3::FftArgs fft_args(tod_ctx ctx, Plan *P, const tod_layout *L) {
+    c3::FftArgs a;
+    memset(&a, 0, sizeof(a));
+    a.segs = (const SegInfo *)P->segs.p;
+    a.plans = (const FftPlan *)P->plans.p;
+    a.twpool = P->twpool.p;
+    a.work = ctx->work.p;
+    a.col_tasks = (const int2 *)P->col_tasks.p;
+    a.ncol_tasks = P->ncol;
+    a.row_tasks = (const int2 *)P->row_tasks.p;
+    a.nrow_tasks = P->nrow;
+    a.fsamp_band = (const double *)P->fsamp.p;
+    a.seed_iter = ctx->d_seed_iter;
+    (void)L;
+    return a;
+}
+
+tod_status ensure_work(tod_ctx ctx, Plan *P) {
+    const size_t elt = P->mixed ? sizeof(cx<float>) : sizeof(cx<double>);
+    HIPCHK(ctx->work.ensure((size_t)P->work_elems * elt + 64));
+    return TOD_OK;
+}
+
+struct PhaseTimer {
+    tod_ctx c;
+    int phase;
+    PhaseTimer(tod_ctx ctx, int ph) : c(ctx), phase(ph) {
+        if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
+    }
+    ~PhaseTimer() {
+        if (c->timing) {
+            (void)hipEventRecord(c->ev[1], c->stream);
+            (void)hipEventSynchronize(c->ev[1]);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+            c->phase_ms[phase] = ms;
+        }
+    }
+};
+
+}  // namespace
+
+// ============================================================== C-ABI
+extern "C" {
+
+tod_status tod_ctx_create(tod_ctx *out, int device, void *hip_stream) {
+    if (!out) return TOD_EINVAL;
+    *out = nullptr;
+    tod_ctx ctx = new tod_ctx_s();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return TOD_EHIP;
+    }
+    if (hipMalloc(&ctx->d_err, 64) != hipSuccess || hipMalloc(&ctx->d_seed_iter, 64) != hipSuccess) {
+        delete ctx;
+        return TOD_ENOMEM;
+    }
+    (void)hipMemset(ctx->d_err, 0, 64);
+    (void)hipMemset(ctx->d_seed_iter, 0, 64);
+    // cos 2psi / sin 2psi at the centres of the 4096 psi bins, 2 psi = pi (2b+1)/2048
+    std::vector<cx<float>> t32(4096);
+    std::vector<cx<double>> t64(4096);
+    for (int b = 0; b < 4096; ++b) {
+        const long double a = 3.14159265358979323846264338327950288L * (2.0L * b + 1.0L) / 2048.0L;
+        t64[b] = {(double)cosl(a), (double)sinl(a)};
+        t32[b] = {(float)t64[b].x, (float)t64[b].y};
+    }
+    if (ctx->trig32.ensure(sizeof(cx<float>) * 4096) != hipSuccess ||
+        ctx->trig64.ensure(sizeof(cx<double>) * 4096) != hipSuccess ||
+        hipMemcpy(ctx->trig32.p, t32.data(), sizeof(cx<float>) * 4096, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->trig64.p, t64.data(), sizeof(cx<double>) * 4096, hipMemcpyHostToDevice) != hipSuccess) {
+        delete ctx;
+        return TOD_EHIP;
+    }
+    for (auto &e : ctx->ev) (void)hipEventCreate(&e);
+    (void)hipDeviceSynchronize();
+    *out = ctx;
+    return TOD_OK;
+}
+
+tod_status tod_ctx_destroy(tod_ctx ctx) {
+    if (!ctx) return TOD_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
+        if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+    }
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->d_err) (void)hipFree(ctx->d_err);
+    if (ctx->d_seed_iter) (void)hipFree(ctx->d_seed_iter);
+    delete ctx;
+    return TOD_OK;
+}
+
+tod_status tod_sync(tod_ctx ctx) {
+    if (!ctx) return TOD_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    uint32_t e = 0;
+    HIPCHK(hipMemcpy(&e, ctx->d_err, sizeof(e), hipMemcpyDeviceToHost));
+    ctx->last_err_bits = e;
+    if (e) {
+        char buf[160];
+        snprintf(buf, sizeof(buf), "device error bits 0x%x (1 invalid code, 2 chunk mismatch, 4 pixel range, 8 psi range)", e);
+        return fail(ctx, TOD_ECORRUPT, buf);
+    }
+    return TOD_OK;
+}
+
+tod_status tod_clear_error(tod_ctx ctx) {
+    if (!ctx) return TOD_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(c3::launch_zero(ctx->stream, ctx->d_err, 8));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->last_err_bits = 0;
+    ctx->last_error.clear();
+    return TOD_OK;
+}
+
+const char *tod_last_error(tod_ctx ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+uint32_t tod_device_error_bits(tod_ctx ctx) { return ctx ? ctx->last_err_bits : 0u; }
+
+tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay, const tod_huff *pix,
+                           const tod_huff *psi, int32_t *pix_out, uint16_t *psi_out) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if ((r = check_huff(ctx, pix, "pix")) != TOD_OK) return r;
+    if ((r = check_huff(ctx, psi, "psi")) != TOD_OK) return r;
+    if (pix->chunk_len != psi->chunk_len) return fail(ctx, TOD_EINVAL, "pix and psi chunk_len differ");
+    if (!pix_out || !psi_out) return fail(ctx, TOD_EINVAL, "NULL output");
+    Plan *P;
+    if ((r = get_plan(ctx, lay, 1, &P)) != TOD_OK) return r;
+    const DecodeTask *tasks;
+    int nt;
+    if ((r = get_decode_tasks(ctx, P, pix->chunk_len, &tasks, &nt)) != TOD_OK) return r;
+    PhaseTimer pt(ctx, 0);
+    HIPCHK(c3::launch_decode(ctx->stream, make_layout_dev(lay), make_huff_dev(pix), make_huff_dev(psi),
+                             tasks, nt, pix_out, psi_out, c3::DEC_POINTING, 1, nullptr, 0, nullptr,
+                             nullptr, nullptr, nullptr, ctx->d_err));
+    return TOD_OK;
+}
+
+tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int32_t *pix,
+                       const uint16_t *psi, const void *maps, const double *gain, void *s_out) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (!pix || !psi || !maps || !gain || !s_out) return fail(ctx, TOD_EINVAL, "NULL argument");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    PhaseTimer pt(ctx, 1);
+    HIPCHK(c3::launch_project_tiles(ctx->stream, make_layout_dev(lay), mixed,
+                                    (const int4 *)P->sample_tiles.p, P->nsample_tiles, pix, psi, maps,
+                                    gain, mixed ? ctx->trig32.p : ctx->trig64.p, s_out));
+    return TOD_OK;
+}
+
+static tod_status ncorr_impl(tod_ctx ctx, const tod_layout *lay, int mixed, Plan *P, const void *d,
+                             tod_dtype d_dtype, const void *s, int s_f64, const double *sigma0,
+                             const double *fknee, const double *alpha, int mean_only, void *out) {
+    tod_status r;
+    if ((r = ensure_work(ctx, P)) != TOD_OK) return r;
+    c3::FftArgs a = fft_args(ctx, P, lay);
+    a.in_a = d;
+    a.in_a_f64 = d_dtype == TOD_F64;
+    a.in_b = s;
+    a.in_b_f64 = s_f64;
+    a.out = out;
+    a.sigma0 = sigma0;
+    a.fknee = fknee;
+    a.alpha = alpha;
+    a.mean_only = mean_only;
+    a.mode = 0;
+    HIPCHK(c3::launch_fft_ncorr(ctx->stream, mixed, a));
+    return TOD_OK;
+}
+
+tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const void *d,
+                        tod_dtype d_dtype, const void *s, const double *sigma0, const double *fknee,
+                        const double *alpha, uint64_t seed, uint64_t iter, int mean_only,
+                        void *ncorr_out) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (!d || !sigma0 || !fknee || !alpha || !ncorr_out) return fail(ctx, TOD_EINVAL, "NULL argument");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    HIPCHK(c3::launch_set_u64(ctx->stream, ctx->d_seed_iter, seed, iter));
+    PhaseTimer pt(ctx, 2);
+    return ncorr_impl(ctx, lay, mixed, P, d, d_dtype, s, !mixed, sigma0, fknee, alpha, mean_only,
+                      ncorr_out);
+}
+
+tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int32_t *pix,
+                   const uint16_t *psi, const void *d, tod_dtype d_dtype, const void *ncorr,
+                   const double *gain, const double *sigma0, double *acc, int accumulate) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (!pix || !psi || !d || !gain || !sigma0 || !acc) return fail(ctx, TOD_EINVAL, "NULL argument");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    const int4 *tiles;
+    int nt;
+    if ((r = get_bin_tiles(ctx, lay, P, pix, &tiles, &nt)) != TOD_OK) return r;
+    PhaseTimer pt(ctx, 3);
+    if (!accumulate) HIPCHK(c3::launch_zero(ctx->stream, acc, lay->npix_total * 10 * sizeof(double)));
+    HIPCHK(c3::launch_bin_tiles(ctx->stream, make_layout_dev(lay), mixed, tiles, nt, pix, psi, d,
+                                d_dtype == TOD_F64, ncorr, gain, sigma0, ctx->trig64.p, acc));
+    return TOD_OK;
+}
+
+tod_status solve_maps(tod_ctx ctx, int64_t npix, const double *acc, double rcond_min,
+                      void *map_out, tod_dtype map_dtype, double *rcond_out) {
+    if (!ctx) return TOD_EINVAL;
+    if (npix < 0 || !acc || !map_out) return fail(ctx, TOD_EINVAL, "bad argument");
+    if (map_dtype != TOD_F32 && map_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad map dtype");
+    PhaseTimer pt(ctx, 4);
+    HIPCHK(c3::launch_solve(ctx->stream, npix, acc, rcond_min, map_out, map_dtype == TOD_F64, rcond_out));
+    return TOD_OK;
+}
+
+static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int32_t *pix,
+                               const uint16_t *psi, const void *d, tod_dtype d_dtype,
+                               const void *ncorr, const void *maps, const double *gain,
+                               const double *sigma0, const double *fknee, const double *alpha,
+                               double gscale, double *grad_maps, double *chisq_seg,
+                               double *grad_gain, double *gsig, double *gfk, double *galpha) {
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (!pix || !psi || !d || !ncorr || !maps || !gain || !sigma0 || !fknee || !alpha)
+        return fail(ctx, TOD_EINVAL, "NULL argument");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    if ((r = ensure_work(ctx, P)) != TOD_OK) return r;
+    const int4 *tiles;
+    int nt;
+    if ((r = get_bin_tiles(ctx, lay, P, pix, &tiles, &nt)) != TOD_OK) return r;
+    const size_t ssz = sizeof(double) * 4 * (size_t)std::max(1, lay->nseg);
+    HIPCHK(ctx->seg_sums.ensure(ssz));
+    HIPCHK(ctx->seg_whittle.ensure(ssz));
+    PhaseTimer pt(ctx, 5);
+    hipStream_t st = ctx->stream;
+    HIPCHK(c3::launch_zero(st, ctx->seg_sums.p, ssz));
+    HIPCHK(c3::launch_zero(st, ctx->seg_whittle.p, ssz));
+    if (grad_maps) HIPCHK(c3::launch_zero(st, grad_maps, sizeof(double) * 3 * lay->npix_total));
+    if (gsig) HIPCHK(c3::launch_zero(st, gsig, sizeof(double) * lay->ndet));
+    if (gfk) HIPCHK(c3::launch_zero(st, gfk, sizeof(double) * lay->ndet));
+    if (galpha) HIPCHK(c3::launch_zero(st, galpha, sizeof(double) * lay->ndet));
+    const LayoutDev Ld = make_layout_dev(lay);
+    HIPCHK(c3::launch_chisq_time_tiles(st, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64, ncorr,
+                                       maps, gain, sigma0, ctx->trig64.p, (double *)ctx->seg_sums.p,
+                                       grad_maps, gscale));
+    c3::FftArgs a = fft_args(ctx, P, lay);
+    a.in_a = ncorr;
+    a.in_a_f64 = !mixed;
+    a.in_b = nullptr;
+    a.sigma0 = sigma0;
+    a.fknee = fknee;
+    a.alpha = alpha;
+    a.mode = 1;
+    a.whittle = (double *)ctx->seg_whittle.p;
+    HIPCHK(c3::launch_fft_whittle(st, mixed, a));
+    HIPCHK(c3::launch_chisq_finish(st, Ld, (const double *)ctx->seg_sums.p,
+                                   (const double *)ctx->seg_whittle.p, gain, sigma0, fknee, alpha,
+                                   gscale, chisq_seg, grad_gain, gsig, gfk, galpha));
+    return TOD_OK;
+}
+
+tod_status tod_chisq(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int32_t *pix,
+                     const uint16_t *psi, const void *d, tod_dtype d_dtype, const void *ncorr,
+                     const void *maps, const double *gain, const double *sigma0,
+                     const double *fknee, const double *alpha, double *chisq_seg) {
+    if (!ctx) return TOD_EINVAL;
+    if (!chisq_seg) return fail(ctx, TOD_EINVAL, "NULL chisq_seg");
+    return chisq_common(ctx, lay, prec, pix, psi, d, d_dtype, ncorr, maps, gain, sigma0, fknee, alpha,
+                        1.0, nullptr, chisq_seg, nullptr, nullptr, nullptr, nullptr);
+}
+
+tod_status tod_chisq_backward(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                              const int32_t *pix, const uint16_t *psi, const void *d,
+                              tod_dtype d_dtype, const void *ncorr, const void *maps,
+                              const double *gain, const double *sigma0, const double *fknee,
+                              const double *alpha, double grad_scale, double *grad_maps,
+                              double *grad_gain, double *grad_sigma0, double *grad_fknee,
+                              double *grad_alpha) {
+    if (!ctx) return TOD_EINVAL;
+    return chisq_common(ctx, lay, prec, pix, psi, d, d_dtype, ncorr, maps, gain, sigma0, fknee, alpha,
+                        grad_scale, grad_maps, nullptr, grad_gain, grad_sigma0, grad_fknee,
+                        grad_alpha);
+}
+
+tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const tod_huff *pix,
+                     const tod_huff *psi, const void *d, tod_dtype d_dtype, const void *maps,
+                     const double *gain, const double *sigma0, const double *fknee,
+                     const double *alpha, uint64_t seed, uint64_t iter, void *ncorr_out,
+                     double *acc, int32_t *pix_work, uint16_t *psi_work, int use_graph) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if ((r = check_huff(ctx, pix, "pix")) != TOD_OK) return r;
+    if ((r = check_huff(ctx, psi, "psi")) != TOD_OK) return r;
+    if (pix->chunk_len != psi->chunk_len) return fail(ctx, TOD_EINVAL, "pix and psi chunk_len differ");
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (!d || !maps || !gain || !sigma0 || !fknee || !alpha || !ncorr_out || !acc || !pix_work || !psi_work)
+        return fail(ctx, TOD_EINVAL, "NULL argument");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    if ((r = ensure_work(ctx, P)) != TOD_OK) return r;
+    const size_t rsz = (size_t)lay->nsamp * (mixed ? 4 : 8);
+    HIPCHK(ctx->resid.ensure(rsz + 64));
+    const DecodeTask *dt;
+    int ndt;
+    if ((r = get_decode_tasks(ctx, P, pix->chunk_len, &dt, &ndt)) != TOD_OK) return r;
+    hipStream_t st = ctx->stream;
+    const LayoutDev Ld = make_layout_dev(lay);
+
+    // graph key: every pointer and size the captured kernels bake in
+    uint64_t gk = 1469598103934665603ull;
+    const void *ptrs[] = {pix->words, psi->words, pix->tables, psi->tables, d, maps, gain, sigma0,
+                          fknee, alpha, ncorr_out, acc, pix_work, psi_work, ctx->work.p,
+                          ctx->resid.p, P->segs.p};
+    gk = fnv(gk, ptrs, sizeof(ptrs));
+    gk = fnv(gk, &P->key, sizeof(P->key));
+    gk = fnv(gk, &d_dtype, sizeof(d_dtype));
+
+    HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
+    const bool have_tiles = P->nbin > 0;
+    if (use_graph && have_tiles) {
+        auto it = ctx->graphs.find(gk);
+        if (it != ctx->graphs.end()) {
+            HIPCHK(hipGraphLaunch(it->second.ex, st));
+            return TOD_OK;
+        }
+    }
+    // eager (or capture) sequence
+    auto run = [&](bool capture) -> tod_status {
+        const int4 *tiles = (const int4 *)P->bin_tiles.p;
+        int nt = P->nbin;
+        {
+            PhaseTimer pt(ctx, 0);
+            HIPCHK(c3::launch_decode(st, Ld, make_huff_dev(pix), make_huff_dev(psi), dt, ndt, pix_work,
+                                     psi_work, c3::DEC_RESIDUAL, mixed, d, d_dtype == TOD_F64, maps, gain,
+                                     mixed ? ctx->trig32.p : ctx->trig64.p, ctx->resid.p, ctx->d_err));
+        }
+        {
+            PhaseTimer pt(ctx, 2);
+            c3::FftArgs a = fft_args(ctx, P, lay);
+            a.in_a = ctx->resid.p;
+            a.in_a_f64 = !mixed;
+            a.in_b = nullptr;
+            a.out = ncorr_out;
+            a.sigma0 = sigma0;
+            a.fknee = fknee;
+            a.alpha = alpha;
+            a.mean_only = 0;
+            HIPCHK(c3::launch_fft_ncorr(st, mixed, a));
+        }
+        if (!capture && !have_tiles) {
+            tod_status rr = get_bin_tiles(ctx, lay, P, pix_work, &tiles, &nt);
+            if (rr != TOD_OK) return rr;
+        }
+        {
+            PhaseTimer pt(ctx, 3);
+            HIPCHK(c3::launch_zero(st, acc, lay->npix_total * 10 * sizeof(double)));
+            HIPCHK(c3::launch_bin_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
+                                        d_dtype == TOD_F64, ncorr_out, gain, sigma0, ctx->trig64.p, acc));
+        }
+        return TOD_OK;
+    };
+    if (!(use_graph && have_tiles) || ctx->timing) return run(false);
+    // capture on a context-owned stream (the caller's may be the null stream),
+    // then launch the graph on the caller's stream
+    if (!ctx->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    tod_ctx_s::GraphEntry ge;
+    st = ctx->cap_stream;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    tod_status rr = run(true);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(st, &g);
+    st = ctx->stream;
+    if (rr != TOD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rr;
+    }
+    HIPCHK(e2);
+    ge.g = g;
+    HIPCHK(hipGraphInstantiate(&ge.ex, g, nullptr, nullptr, 0));
+    ctx->graphs[gk] = ge;
+    HIPCHK(hipGraphLaunch(ge.ex, st));
+    return TOD_OK;
+}
+
+tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride) {
+    if (!ctx) return TOD_EINVAL;
+    if (band < 0 || band >= C3_MAXBAND || stride < 0) return fail(ctx, TOD_EINVAL, "bad band/stride");
+    if (stride == 0)
+        ctx->band_stride.erase(band);
+    else
+        ctx->band_stride[band] = stride;
+    return TOD_OK;
+}
+
+tod_status tod_enable_timing(tod_ctx ctx, int enable) {
+    if (!ctx) return TOD_EINVAL;
+    ctx->timing = enable != 0;
+    return TOD_OK;
+}
+
+tod_status tod_phase_ms(tod_ctx ctx, double *ms6) {
+    if (!ctx || !ms6) return TOD_EINVAL;
+    for (int i = 0; i < 6; ++i) ms6[i] = ctx->phase_ms[i];
+    return TOD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuning
+namespace {
+
+std::string band_key(const tod_band &b) {
+    char buf[64];
+    snprintf(buf, sizeof(buf), "%d:%.6g", b.nside, b.fsamp);
+    return buf;
+}
+
+// Mean time (ms) of the three n_corr FFT passes for K segments of length M
+// with the FFT split `ch`.
+tod_status time_fft_choice(tod_ctx ctx, int mixed, int64_t M, const c3tune::FftChoice &ch, int K,
+                           float *ms_out) {
+    c3tune::Table saved = ctx->tuned;
+    ctx->tuned.put(mixed, M, ch);
+    std::vector<int64_t> off(K + 1);
+    std::vector<int32_t> band(K, 0);
+    for (int i = 0; i <= K; ++i) off[i] = (int64_t)i * M;
+    tod_band b;
+    b.nside = 1;
+    b.npsi = 4096;
+    b.npix = 12;
+    b.pix_off = 0;
+    b.fsamp = 1.0;
+    tod_layout L;
+    memset(&L, 0, sizeof(L));
+    L.nseg = K;
+    L.nband = 1;
+    L.ndet = 1;
+    L.nsamp = off[K];
+    L.npix_total = 12;
+    L.h_seg_off = off.data();
+    L.h_seg_band = band.data();
+    L.bands = &b;
+    const uint64_t key = layout_key(&L, mixed, 0x7475ull ^ ctx->tuned.version);
+    Plan *P = nullptr;
+    tod_status r = build_plan(ctx, &L, mixed, key, &P);
+    ctx->tuned = saved;
+    if (r != TOD_OK) return r;
+    r = ensure_work(ctx, P);
+    if (r != TOD_OK) return r;
+    const size_t esz = mixed ? 4 : 8;
+    DevBuf din, dout, prm;
+    HIPCHK(din.ensure(off[K] * esz));
+    HIPCHK(dout.ensure(off[K] * esz));
+    HIPCHK(prm.ensure(3 * K * sizeof(double)));
+    std::vector<double> hp(3 * K);
+    for (int i = 0; i < K; ++i) {
+        hp[i] = 1.0;
+        hp[K + i] = 0.1;
+        hp[2 * K + i] = -1.5;
+    }
+    HIPCHK(hipMemcpy(prm.p, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c3::launch_zero(ctx->stream, din.p, off[K] * esz));
+    c3::FftArgs a = fft_args(ctx, P, &L);
+    a.in_a = din.p;
+    a.in_a_f64 = !mixed;
+    a.out = dout.p;
+    a.sigma0 = (const double *)prm.p;
+    a.fknee = (const double *)prm.p + K;
+    a.alpha = (const double *)prm.p + 2 * K;
+    HIPCHK(c3::launch_fft_ncorr(ctx->stream, mixed, a));
+    HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
+    const int reps = 3;
+    for (int i = 0; i < reps; ++i) HIPCHK(c3::launch_fft_ncorr(ctx->stream, mixed, a));
+    HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
+    HIPCHK(hipEventSynchronize(ctx->ev[3]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+    *ms_out = ms / reps;
+    ctx->plans.erase(key);
+    return TOD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tod_status tod_load_tuning(tod_ctx ctx, const char *cache_path) {
+    if (!ctx) return TOD_EINVAL;
+    if (!cache_path) return fail(ctx, TOD_EINVAL, "NULL path");
+    FILE *f = fopen(cache_path, "rb");
+    if (!f) return TOD_OK;
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, k);
+    fclose(f);
+    std::map<std::string, int> strides;
+    if (!c3tune::from_json(s, ctx->tuned, strides)) return fail(ctx, TOD_EINVAL, "unreadable tuning cache");
+    for (auto &kv : strides) ctx->stride_by_key[kv.first] = kv.second;
+    return TOD_OK;
+}
+
+tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int32_t *pix,
+                        const char *cache_path) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    const int mixed = prec == TOD_MIXED;
+    const int S = mixed ? 8192 : 4096;
+    if (cache_path) {
+        if ((r = tod_load_tuning(ctx, cache_path)) != TOD_OK) return r;
+    }
+    std::map<int64_t, int> count;
+    for (int s = 0; s < lay->nseg; ++s) {
+        const int64_t n = lay->h_seg_off[s + 1] - lay->h_seg_off[s];
+        if (n > 0) count[next_5smooth(n)]++;
+    }
+    for (auto &kv : count) {
+        const int64_t M = kv.first;
+        c3tune::FftChoice have;
+        if (ctx->tuned.get(mixed, M, have)) continue;
+        const int K = (int)std::max<int64_t>(2, std::min<int64_t>(32, (int64_t)(64ll << 20) / (8 * M)));
+        float best = 1e30f;
+        c3tune::FftChoice bc;
+        for (const c3tune::FftChoice &c : c3tune::candidates(M, S)) {
+            float ms;
+            if ((r = time_fft_choice(ctx, mixed, M, c, K, &ms)) != TOD_OK) return r;
+            if (ms < best) {
+                best = ms;
+                bc = c;
+            }
+        }
+        if (best < 1e30f) ctx->tuned.put(mixed, M, bc);
+    }
+    if (pix) {
+        Plan *P;
+        if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+        for (int b = 0; b < lay->nband; ++b) {
+            int st = 0;
+            if ((r = probe_stride(ctx, lay, P, pix, b, &st)) != TOD_OK) return r;
+            ctx->band_stride[b] = st;
+            ctx->stride_by_key[band_key(lay->bands[b])] = st;
+        }
+    }
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "wb");
+        if (!f) return fail(ctx, TOD_EINVAL, std::string("cannot write ") + cache_path);
+        const std::string js = c3tune::to_json(ctx->tuned, ctx->stride_by_key);
+        fwrite(js.data(), 1, js.size(), f);
+        fclose(f);
+    }
+    return TOD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Internal declarations shared by the c3tod kernels and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/c3tod.h"
+
+#define C3_NT 256            // threads per block of every kernel
+
+// sticky device error bits
+#define C3_ERR_CODE 1u       // bit pattern matches no code
+#define C3_ERR_CHUNK 2u      // chunk end does not meet the next chunk's start
+#define C3_ERR_PIX 4u        // decoded pixel outside [0, npix)
+#define C3_ERR_PSI 8u        // decoded psi bin outside [0, npsi)
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // a * conj(b)
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// Per-segment record built on the host for every kernel that walks segments.
+struct SegInfo {
+    int64_t samp_off;    // first sample
+    int64_t scr_off;     // first complex element of the FFT workspace (ncorr/chisq)
+    int32_t n;           // samples
+    int32_t plan;        // FFT plan index (-1: none)
+    int32_t band;
+    int32_t det;
+    int32_t accept;
+    int32_t pad;
+};
+
+// FFT plan of one complex length M = M1 * M2 (the real length is N = 2M).
+#define C3_MAXRAD 16
+struct FftPlan {
+    int32_t M, M1, M2, B;        // B: columns per column-pass tile
+    int32_t nr1, nr2;            // radix counts of the M1 and M2 sub-transforms
+    int8_t r1[C3_MAXRAD];
+    int8_t r2[C3_MAXRAD];
+    int64_t tw1;                 // offset of w_M1^m (m < M1) in the twiddle pool
+    int64_t tw2;                 // offset of w_M2^m (m < M2)
+    int64_t twlo;                // w_N^m, m < 1024           (N = 2M)
+    int64_t twhi;                // w_N^(1024 h), h < N/1024 + 1
+};
+
+// Context-side view of the layout kept on the device.
+struct BandDev {
+    int64_t npix;
+    int64_t pix_off;
+    double fsamp;
+    int32_t npsi;
+    int32_t nside;
+};
+
+#define C3_MAXBAND 16
+
+struct LayoutDev {
+    const int64_t *seg_off;
+    const int32_t *seg_band;
+    const int32_t *seg_det;
+    const uint8_t *seg_accept;
+    int32_t nseg, nband, ndet, pad;
+    int64_t nsamp, npix_total;
+    BandDev band[C3_MAXBAND];
+};
+
+// Device-side Huffman stream (copy of tod_huff, by value into kernels).
+struct HuffDev {
+    const uint32_t *words;
+    const int64_t *seg_word_off;
+    const int32_t *seg_table;
+    const uint32_t *tables;
+    const int64_t *table_off;
+    const uint32_t *chunk_bit;
+    const int32_t *chunk_prev;
+    const int64_t *seg_chunk_off;
+    int32_t chunk_len;
+    int32_t ntable;
+};
+
+// Decode work item: one block decodes up to C3_NT consecutive chunks of one segment.
+struct DecodeTask {
+    int32_t seg;
+    int32_t chunk0;   // first chunk (segment-local)
+    int32_t nchunk;   // chunks in this task (<= C3_NT)
+    int32_t pad;
+};
+
+// ------------------------------------------------------------ launchers
+// Implemented in the .hip files; all return hipError_t of the launch.
+namespace c3 {
+
+enum DecodeMode { DEC_POINTING = 0, DEC_RESIDUAL = 1 };
+
+hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
+                         const DecodeTask *tasks, int ntask, int32_t *pix_out, uint16_t *psi_out,
+                         int mode, int prec_mixed, const void *d, int d_f64, const void *maps,
+                         const double *gain, const void *trig, void *r_out, uint32_t *err);
+
+// FFT-based passes.  mode: 0 = n_corr draw, 1 = Whittle sums (chi^2), 2 = chi^2 adjoint sums
+struct FftArgs {
+    const SegInfo *segs;
+    const FftPlan *plans;
+    const void *twpool;         // cx<T> pool
+    void *work;                 // cx<T> workspace
+    const int2 *col_tasks;      // (seg, first column)
+    int ncol_tasks;
+    const int2 *row_tasks;      // (seg, k1)
+    int nrow_tasks;
+    const void *in_a;           // pass-1 input: r = in_a - in_b (in_b may be NULL)
+    int in_a_f64;
+    const void *in_b;
+    int in_b_f64;
+    void *out;                  // pass-3 output
+    const double *sigma0, *fknee, *alpha;
+    const double *fsamp_band;   // [nband]
+    const uint64_t *seed_iter;  // device {seed, iter}
+    int mean_only;
+    int mode;
+    double *whittle;            // mode 1/2: per-segment sums [nseg][4]
+};
+hipError_t launch_fft_ncorr(hipStream_t st, int prec_mixed, const FftArgs &a);
+hipError_t launch_fft_whittle(hipStream_t st, int prec_mixed, const FftArgs &a);
+
+hipError_t launch_project_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                                int ntile, const int32_t *pix, const uint16_t *psi,
+                                const void *maps, const double *gain, const void *trig,
+                                void *s_out);
+hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                            int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
+                            int d_f64, const void *ncorr, const double *gain,
+                            const double *sigma0, const void *trig64, double *acc);
+hipError_t launch_zero(hipStream_t st, void *p, int64_t bytes);
+hipError_t launch_solve(hipStream_t st, int64_t npix, const double *acc, double rcond_min,
+                        void *map_out, int map_f64, double *rcond_out);
+hipError_t launch_repeat_probe(hipStream_t st, const int32_t *pix, int64_t off, int n, int maxlag,
+                               unsigned long long *counts);
+
+// chi^2 time-domain part on strided tiles: per segment sum r^2/sigma0^2 (-> seg_sums[4s]),
+// sum (Pm) r (-> [4s+1]), sum r^2 (-> [4s+2]); with grad_maps != NULL also the map adjoint.
+hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                                   int ntile, const int32_t *pix, const uint16_t *psi,
+                                   const void *d, int d_f64, const void *ncorr, const void *maps,
+                                   const double *gain, const double *sigma0, const void *trig64,
+                                   double *seg_sums, double *grad_maps, double grad_scale);
+hipError_t launch_chisq_finish(hipStream_t st, const LayoutDev &L, const double *seg_time,
+                               const double *seg_whittle, const double *gain, const double *sigma0,
+                               const double *fknee, const double *alpha, double grad_scale,
+                               double *chisq_seg, double *grad_gain, double *grad_sigma0,
+                               double *grad_fknee, double *grad_alpha);
+hipError_t launch_set_u64(hipStream_t st, uint64_t *p, uint64_t a, uint64_t b);
+
+}  // namespace c3

@@ -1,0 +1,501 @@
+// Batched mixed-radix real FFTs for the correlated-noise draw (section 4.2) and
+// the Fourier-domain chi^2 terms, as a three-pass four-step transform.
+//
+// A segment of n samples is mirrored and padded to N = 2M real points (M
+// 5-smooth), packed as M complex points z_j = e_2j + i e_2j+1, and transformed
+// with M = M1 x M2:
+//   pass 1 (columns): for each column j2, FFT_M1 over z[M2 j1 + j2], times
+//           w_M^(j2 k1); written row-major Y[k1][j2].
+//   pass 2 (rows):    block k1 takes rows k1 and M1-k1 (the rows holding the
+//           mirror modes M-k of its modes k), FFT_M2 each, splits the complex
+//           spectrum into the real-FFT spectrum E_k (k = 0..M), applies the
+//           constrained-realisation filter and draw per mode, re-packs, runs
+//           the inverse FFT_M2, multiplies by w_M^(-j2 k1) and writes back.
+//   pass 3 (columns): inverse FFT_M1 per column; the first n real samples are
+//           the output.
+// Every sub-transform is an in-LDS Stockham FFT with radix 2/3/4/5 stages.
+#include "common.h"
+
+namespace {
+using c3::FftArgs;
+
+template <typename T>
+struct Lim;
+template <>
+struct Lim<float> {
+    static constexpr int S = 8192;  // complex elements a block may hold in LDS
+};
+template <>
+struct Lim<double> {
+    static constexpr int S = 4096;
+};
+
+template <typename T, int R>
+constexpr int maxb() {
+    return (Lim<T>::S / R + C3_NT - 1) / C3_NT;
+}
+
+// ---------------------------------------------------------------- DFT kernels
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) {  // a * (DIR * i)
+    return DIR < 0 ? cx<T>{a.y, -a.x} : cx<T>{-a.y, a.x};
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T> *v) {
+    if constexpr (R == 2) {
+        cx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        const T h = (T)0.86602540378443864676;  // sin(60 deg)
+        cx<T> a = v[0], b = v[1], c = v[2];
+        cx<T> t1 = cadd(b, c);
+        cx<T> t2 = {a.x - (T)0.5 * t1.x, a.y - (T)0.5 * t1.y};
+        cx<T> t3 = mul_i<DIR>(cscale(csub(b, c), h));
+        v[0] = cadd(a, t1);
+        v[1] = cadd(t2, t3);
+        v[2] = csub(t2, t3);
+    } else if constexpr (R == 4) {
+        cx<T> a = v[0], b = v[1], c = v[2], d = v[3];
+        cx<T> s0 = cadd(a, c), d0 = csub(a, c);
+        cx<T> s1 = cadd(b, d), d1 = mul_i<DIR>(csub(b, d));
+        v[0] = cadd(s0, s1);
+        v[2] = csub(s0, s1);
+        v[1] = cadd(d0, d1);
+        v[3] = csub(d0, d1);
+    } else {  // R == 5
+        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+        cx<T> x0 = v[0];
+        cx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+        cx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+        cx<T> a1 = {x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y};
+        cx<T> a2 = {x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y};
+        cx<T> b1 = mul_i<DIR>(cx<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
+        cx<T> b2 = mul_i<DIR>(cx<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
+        v[0] = cadd(x0, cadd(t1, t2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
+    }
+}
+
+// One Stockham stage of radix R on B transforms of length L in LDS; element i
+// of transform b lives at buf[i*si + b*sb].  B = 1 << lb.
+template <int R, int DIR, typename T>
+__device__ __attribute__((noinline)) void fft_stage(cx<T> *buf, int L, int lb, int si, int sb, int Ns,
+                          const cx<T> *__restrict__ tw) {
+    constexpr int MB = maxb<T, R>();
+    const int LR = L / R;
+    const int nb = LR << lb;
+    const int bm = (1 << lb) - 1;
+    const int step = L / (Ns * R);
+    const uint32_t magic = 0xFFFFFFFFu / (uint32_t)Ns + 1u;  // j / Ns == umulhi(j, magic)
+    cx<T> v[MB][R];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int q = threadIdx.x + m * C3_NT;
+        if (q < nb) {
+            const int b = q & bm, j = q >> lb;
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[m][t] = buf[(j + t * LR) * si + b * sb];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int q = threadIdx.x + m * C3_NT;
+        if (q < nb) {
+            const int b = q & bm, j = q >> lb;
+            const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
+            const int k = j - jd * Ns;
+            if (Ns > 1) {
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    cx<T> w = tw[k * t * step];
+                    v[m][t] = DIR < 0 ? cmul(v[m][t], w) : cmulc(v[m][t], w);
+                }
+            }
+            dft<R, DIR>(v[m]);
+            const int o = jd * Ns * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[(o + t * Ns) * si + b * sb] = v[m][t];
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, typename T>
+__device__ void lds_fft(cx<T> *buf, int L, int lb, int si, int sb, const int8_t *rad, int nrad,
+                        const cx<T> *tw) {
+    int Ns = 1;
+    for (int s = 0; s < nrad; ++s) {
+        const int R = rad[s];
+        if (R == 4)
+            fft_stage<4, DIR>(buf, L, lb, si, sb, Ns, tw);
+        else if (R == 2)
+            fft_stage<2, DIR>(buf, L, lb, si, sb, Ns, tw);
+        else if (R == 3)
+            fft_stage<3, DIR>(buf, L, lb, si, sb, Ns, tw);
+        else
+            fft_stage<5, DIR>(buf, L, lb, si, sb, Ns, tw);
+        Ns *= R;
+    }
+}
+
+// w_N^m for 0 <= m <= N from the two-level table
+template <typename T>
+__device__ __forceinline__ cx<T> twN(const cx<T> *pool, const FftPlan &p, int64_t m) {
+    const cx<T> lo = pool[p.twlo + (m & 1023)];
+    const cx<T> hi = pool[p.twhi + (m >> 10)];
+    return cmul(hi, lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T load_as(const void *p, int f64, int64_t i) {
+    return f64 ? (T)((const double *)p)[i] : (T)((const float *)p)[i];
+}
+
+// mirrored, padded extension of r = a - b at real index t
+template <typename T>
+__device__ __forceinline__ T ext_at(const FftArgs &a, int64_t s0, int n, int64_t t) {
+    int64_t u = t < n ? t : (t < 2 * (int64_t)n ? 2 * (int64_t)n - 1 - t : 0);
+    T v = load_as<T>(a.in_a, a.in_a_f64, s0 + u);
+    if (a.in_b) v -= load_as<T>(a.in_b, a.in_b_f64, s0 + u);
+    return v;
+}
+
+// ------------------------------------------------------------- pass 1
+template <typename T>
+__global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
+    __shared__ cx<T> buf[Lim<T>::S];
+    const int2 task = a.col_tasks[blockIdx.x];
+    const SegInfo sg = a.segs[task.x];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M1 = p.M1, M2 = p.M2, B = p.B;
+    const int lb = __ffs(B) - 1;
+    const int col0 = task.y;
+    const cx<T> *pool = (const cx<T> *)a.twpool;
+    cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
+    const int tot = M1 * B;
+    for (int i = threadIdx.x; i < tot; i += C3_NT) {
+        const int j1 = i >> lb, c = i & (B - 1);
+        const int j2 = col0 + c;
+        cx<T> v = {0, 0};
+        if (j2 < M2) {
+            const int64_t j = (int64_t)M2 * j1 + j2;
+            v.x = ext_at<T>(a, sg.samp_off, sg.n, 2 * j);
+            v.y = ext_at<T>(a, sg.samp_off, sg.n, 2 * j + 1);
+        }
+        buf[i] = v;
+    }
+    __syncthreads();
+    lds_fft<-1>(buf, M1, lb, B, 1, p.r1, p.nr1, pool + p.tw1);
+    for (int i = threadIdx.x; i < tot; i += C3_NT) {
+        const int k1 = i >> lb, c = i & (B - 1);
+        const int j2 = col0 + c;
+        if (j2 < M2) {
+            const cx<T> w = twN(pool, p, 2 * (int64_t)j2 * k1);  // w_M^(j2 k1)
+            Y[(int64_t)k1 * M2 + j2] = cmul(buf[i], w);
+        }
+    }
+}
+
+// ------------------------------------------------------------- pass 3
+template <typename T>
+__global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
+    __shared__ cx<T> buf[Lim<T>::S];
+    const int2 task = a.col_tasks[blockIdx.x];
+    const SegInfo sg = a.segs[task.x];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M1 = p.M1, M2 = p.M2, B = p.B;
+    const int lb = __ffs(B) - 1;
+    const int col0 = task.y;
+    const cx<T> *pool = (const cx<T> *)a.twpool;
+    const cx<T> *Y = (const cx<T> *)a.work + sg.scr_off;
+    const int tot = M1 * B;
+    for (int i = threadIdx.x; i < tot; i += C3_NT) {
+        const int k1 = i >> lb, c = i & (B - 1);
+        const int j2 = col0 + c;
+        buf[i] = j2 < M2 ? Y[(int64_t)k1 * M2 + j2] : cx<T>{0, 0};
+    }
+    __syncthreads();
+    lds_fft<1>(buf, M1, lb, B, 1, p.r1, p.nr1, pool + p.tw1);
+    T *out = (T *)a.out + sg.samp_off;
+    const int n = sg.n;
+    for (int i = threadIdx.x; i < tot; i += C3_NT) {
+        const int j1 = i >> lb, c = i & (B - 1);
+        const int j2 = col0 + c;
+        if (j2 < M2) {
+            const int64_t t = 2 * ((int64_t)M2 * j1 + j2);
+            const cx<T> v = buf[i];
+            if (t < n) out[t] = v.x;
+            if (t + 1 < n) out[t + 1] = v.y;
+        }
+    }
+}
+
+// ------------------------------------------------------------- randomness
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// -2 ln u for u = (x + 1/2) 2^-32, accurate on both sides of 1/2
+__device__ __forceinline__ float m2log_u(uint32_t x) {
+    if (x < 0x80000000u) return -2.0f * logf(((float)x + 0.5f) * 2.3283064365386963e-10f);
+    return -2.0f * log1pf(-(((float)(~x) + 0.5f) * 2.3283064365386963e-10f));
+}
+__device__ __forceinline__ double m2log_u_d(uint32_t x) {
+    return -2.0 * log(((double)x + 0.5) * 2.3283064365386963e-10);
+}
+
+template <typename T>
+__device__ __forceinline__ void normals4(uint4 w, T *z) {
+    if constexpr (sizeof(T) == 4) {
+        float r0 = sqrtf(m2log_u(w.x)), r1 = sqrtf(m2log_u(w.z));
+        float s0, c0, s1, c1;
+        sincospif(((float)w.y + 0.5f) * 4.6566128730773926e-10f, &s0, &c0);  // 2 pi u
+        sincospif(((float)w.w + 0.5f) * 4.6566128730773926e-10f, &s1, &c1);
+        z[0] = r0 * c0;
+        z[1] = r0 * s0;
+        z[2] = r1 * c1;
+        z[3] = r1 * s1;
+    } else {
+        double r0 = sqrt(m2log_u_d(w.x)), r1 = sqrt(m2log_u_d(w.z));
+        double s0, c0, s1, c1;
+        sincospi(((double)w.y + 0.5) * 4.656612873077392578125e-10, &s0, &c0);
+        sincospi(((double)w.w + 0.5) * 4.656612873077392578125e-10, &s1, &c1);
+        z[0] = r0 * c0;
+        z[1] = r0 * s0;
+        z[2] = r1 * c1;
+        z[3] = r1 * s1;
+    }
+}
+
+struct ModeCtx {
+    double sigma0, lbase, malpha, fknee_ratio;  // lbase = ln(fsamp / (N fknee)), malpha = -alpha
+    double invsqrtN, outscale;                 // 1/sqrt(N), sqrt(N)/M
+    uint2 key;
+    uint32_t it_lo, it_hi, seed_hi;
+    int M;
+    int mean_only;
+};
+
+// constrained-realisation value nhat_k from the unnormalised spectrum E_k
+template <typename T>
+__device__ __forceinline__ cx<T> cr_mode(const ModeCtx &mc, int64_t k, cx<T> E) {
+    const T s0 = (T)mc.sigma0;
+    T q = 0;
+    if (k > 0) {
+        if constexpr (sizeof(T) == 4)
+            q = __expf((float)mc.malpha * (logf((float)k) + (float)mc.lbase));
+        else
+            q = exp(mc.malpha * (log((double)k) + mc.lbase));
+    }
+    const T inv = (T)1 / ((T)1 + q);
+    cx<T> R = cscale(E, (T)mc.invsqrtN);
+    cx<T> out = R;
+    if (!mc.mean_only) {
+        T z[4];
+        normals4<T>(philox4x32_10(make_uint4((uint32_t)k, mc.it_lo, mc.it_hi, mc.seed_hi), mc.key), z);
+        cx<T> W1, W2;
+        if (k == 0 || k == mc.M) {
+            W1 = {z[0], 0};
+            W2 = {z[2], 0};
+        } else {
+            const T h = (T)0.70710678118654752440;
+            W1 = {z[0] * h, z[1] * h};
+            W2 = {z[2] * h, z[3] * h};
+        }
+        T sq;
+        if constexpr (sizeof(T) == 4)
+            sq = sqrtf(q);
+        else
+            sq = sqrt(q);
+        out.x += s0 * (W1.x + sq * W2.x);
+        out.y += s0 * (W1.y + sq * W2.y);
+    }
+    return cscale(out, inv);
+}
+
+// Whittle sums for one mode k >= 1
+struct Wsum {
+    double a, b, c;  // sum(I/P + ln P), sum(1 - I/P), sum((1 - I/P) ln(f/fknee))
+};
+template <typename T>
+__device__ __forceinline__ void whittle_mode(const ModeCtx &mc, int64_t k, cx<T> E, Wsum &s) {
+    const double I = ((double)E.x * E.x + (double)E.y * E.y) * mc.invsqrtN * mc.invsqrtN;
+    const double lr = log((double)k) + mc.lbase;           // ln(f_k / f_knee)
+    const double lnP = 2.0 * log(mc.sigma0) - mc.malpha * lr;
+    const double IP = I * exp(-lnP);
+    s.a += IP + lnP;
+    s.b += 1.0 - IP;
+    s.c += (1.0 - IP) * lr;
+}
+
+// ------------------------------------------------------------- pass 2
+template <typename T, int MODE>
+__global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
+    __shared__ cx<T> buf[Lim<T>::S];
+    __shared__ double red[3][C3_NT / 64];
+    const int2 task = a.row_tasks[blockIdx.x];
+    const int seg = task.x;
+    const SegInfo sg = a.segs[seg];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M1 = p.M1, M2 = p.M2, M = p.M;
+    const int ka = task.y, kb = (M1 - ka) % M1;
+    const int two = (kb != ka) ? 1 : 0;      // second row present
+    const int lb = two;                      // rows interleaved: element (k2, row) at 2*k2 + row
+    const int si = two ? 2 : 1;
+    const cx<T> *pool = (const cx<T> *)a.twpool;
+    cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
+
+    for (int i = threadIdx.x; i < M2; i += C3_NT) {
+        buf[i * si] = Y[(int64_t)ka * M2 + i];
+        if (two) buf[i * si + 1] = Y[(int64_t)kb * M2 + i];
+    }
+    __syncthreads();
+    lds_fft<-1>(buf, M2, lb, si, 1, p.r2, p.nr2, pool + p.tw2);
+
+    ModeCtx mc;
+    {
+        const double fs = a.fsamp_band[sg.band];
+        const double N = 2.0 * M;
+        mc.sigma0 = a.sigma0[seg];
+        mc.malpha = -a.alpha[seg];
+        mc.lbase = log(fs / (N * a.fknee[seg]));
+        mc.invsqrtN = 1.0 / sqrt(N);
+        mc.outscale = sqrt(N) / M;
+        const uint64_t seed = a.seed_iter ? a.seed_iter[0] : 0, it = a.seed_iter ? a.seed_iter[1] : 0;
+        mc.key = make_uint2((uint32_t)seed, (uint32_t)seg);
+        mc.it_lo = (uint32_t)it;
+        mc.it_hi = (uint32_t)(it >> 32);
+        mc.seed_hi = (uint32_t)(seed >> 32);
+        mc.M = M;
+        mc.mean_only = a.mean_only;
+    }
+    Wsum ws = {0, 0, 0};
+    const T half = (T)0.5;
+    const T osc = (T)mc.outscale;
+
+    // pair (element e of row a, its mirror-mode partner)
+    for (int k2 = threadIdx.x; k2 < M2; k2 += C3_NT) {
+        int pk2, prow;  // partner position
+        if (ka == 0) {
+            pk2 = (M2 - k2) % M2;
+            prow = 0;
+        } else {
+            pk2 = M2 - 1 - k2;
+            prow = two;  // row b (or row a when single)
+        }
+        if (!two && pk2 < k2) continue;  // single row: each pair once
+        const int ea = k2 * si, eb = pk2 * si + prow;
+        const int64_t k = ka + (int64_t)M1 * k2;
+        const cx<T> Za = buf[ea], Zb = buf[eb];
+        if (k == 0) {
+            // E_0 = Re Z0 + Im Z0, E_M = Re Z0 - Im Z0 (both real)
+            const cx<T> E0 = {Za.x + Za.y, 0}, EM = {Za.x - Za.y, 0};
+            if (MODE == 0) {
+                const cx<T> n0 = cr_mode(mc, 0, E0), nM = cr_mode(mc, M, EM);
+                buf[ea] = cx<T>{half * osc * (n0.x + nM.x), half * osc * (n0.x - nM.x)};
+            } else {
+                whittle_mode(mc, M, EM, ws);
+            }
+            continue;
+        }
+        const int64_t kp = (int64_t)M - k;
+        // A = (Zk + conj Zp)/2, B = -i (Zk - conj Zp)/2, E_k = A + w_N^k B
+        const cx<T> w = twN(pool, p, k);                 // w_N^k
+        const cx<T> Ak = {half * (Za.x + Zb.x), half * (Za.y - Zb.y)};
+        const cx<T> Dk = {half * (Za.x - Zb.x), half * (Za.y + Zb.y)};
+        const cx<T> Bk = {Dk.y, -Dk.x};
+        const cx<T> Ek = cadd(Ak, cmul(w, Bk));
+        // partner: A_p = conj A_k, B_p = conj B_k, w_N^p = -conj(w_N^k)
+        const cx<T> wp = {-w.x, w.y};
+        const cx<T> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
+        if (MODE == 0) {
+            const cx<T> nk = cr_mode(mc, k, Ek);
+            const cx<T> np = (kp == k) ? nk : cr_mode(mc, kp, Ep);
+            // Z'_k = (nk + conj np)/2 + i (nk - conj np) conj(w_N^k)/2, scaled
+            const cx<T> Ap = {half * (nk.x + np.x), half * (nk.y - np.y)};
+            const cx<T> Dp = {half * (nk.x - np.x), half * (nk.y + np.y)};
+            const cx<T> Bp = cmulc(Dp, w);
+            const cx<T> Zk = {osc * (Ap.x - Bp.y), osc * (Ap.y + Bp.x)};
+            // partner: A'_p = conj A'_k, B'_p = -conj(D') conj(w_N^p) = conj(D') w_N^k
+            const cx<T> Bq = cmul(cconj(Dp), w);
+            const cx<T> Zq = {osc * (Ap.x - Bq.y), osc * (-Ap.y + Bq.x)};
+            buf[ea] = Zk;
+            if (eb != ea) buf[eb] = Zq;
+        } else {
+            whittle_mode(mc, k, Ek, ws);
+            if (kp != k) whittle_mode(mc, kp, Ep, ws);
+        }
+    }
+    if (MODE == 0) {
+        __syncthreads();
+        lds_fft<1>(buf, M2, lb, si, 1, p.r2, p.nr2, pool + p.tw2);
+        for (int i = threadIdx.x; i < M2; i += C3_NT) {
+            // times w_M^(-j2 k1) = conj(w_N^(2 j2 k1))
+            Y[(int64_t)ka * M2 + i] = cmulc(buf[i * si], twN(pool, p, 2 * (int64_t)i * ka));
+            if (two) Y[(int64_t)kb * M2 + i] = cmulc(buf[i * si + 1], twN(pool, p, 2 * (int64_t)i * kb));
+        }
+    } else {
+        // block reduction of the Whittle sums
+        double v[3] = {ws.a, ws.b, ws.c};
+        for (int j = 0; j < 3; ++j) {
+            double x = v[j];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+            if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double x = 0;
+            for (int w = 0; w < C3_NT / 64; ++w) x += red[threadIdx.x][w];
+            atomicAdd(&a.whittle[(int64_t)seg * 4 + threadIdx.x], x);
+        }
+    }
+}
+
+}  // namespace
+
+namespace c3 {
+
+hipError_t launch_fft_ncorr(hipStream_t st, int mixed, const FftArgs &a) {
+    if (a.ncol_tasks <= 0) return hipSuccess;
+    dim3 b(C3_NT);
+    if (mixed) {
+        hipLaunchKernelGGL(k_col_fwd<float>, dim3(a.ncol_tasks), b, 0, st, a);
+        hipLaunchKernelGGL((k_row<float, 0>), dim3(a.nrow_tasks), b, 0, st, a);
+        hipLaunchKernelGGL(k_col_inv<float>, dim3(a.ncol_tasks), b, 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_col_fwd<double>, dim3(a.ncol_tasks), b, 0, st, a);
+        hipLaunchKernelGGL((k_row<double, 0>), dim3(a.nrow_tasks), b, 0, st, a);
+        hipLaunchKernelGGL(k_col_inv<double>, dim3(a.ncol_tasks), b, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_whittle(hipStream_t st, int mixed, const FftArgs &a) {
+    if (a.ncol_tasks <= 0) return hipSuccess;
+    dim3 b(C3_NT);
+    if (mixed) {
+        hipLaunchKernelGGL(k_col_fwd<float>, dim3(a.ncol_tasks), b, 0, st, a);
+        hipLaunchKernelGGL((k_row<float, 1>), dim3(a.nrow_tasks), b, 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_col_fwd<double>, dim3(a.ncol_tasks), b, 0, st, a);
+        hipLaunchKernelGGL((k_row<double, 1>), dim3(a.nrow_tasks), b, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace c3

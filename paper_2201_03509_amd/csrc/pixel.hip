@@ -1,0 +1,425 @@
+// Pixel-domain kernels: projection P m, binning P^T N^-1 (d - n_corr) and
+// P^T N^-1 P, the per-pixel 3x3 solve, the time-domain chi^2 terms with their
+// map adjoint, and small helpers.
+//
+// Binning and the map adjoint walk a segment in *strided tiles*: thread phi of
+// a tile visits samples phi, phi + S, phi + 2S, ... where S is the segment's
+// revisit period (the spin period in samples for a spinning scan, found by
+// the autotuner's repeat probe).  Consecutive visits of one thread then hit
+// the same pixel, so each thread accumulates its pixel's 3-vector and 3x3 in
+// registers and touches global memory (FP64 atomics) only when the pixel
+// changes.  Any S is correct; only the atomic traffic depends on it.
+#include "common.h"
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T ld(const void *p, int f64, int64_t i) {
+    return f64 ? (T)((const double *)p)[i] : (T)((const float *)p)[i];
+}
+
+// ---------------------------------------------------------------- projection
+template <typename T>
+__global__ __launch_bounds__(C3_NT) void k_project(LayoutDev Ld, const int4 *__restrict__ tiles,
+                                                   const int32_t *__restrict__ pix,
+                                                   const uint16_t *__restrict__ psi,
+                                                   const T *__restrict__ maps,
+                                                   const double *__restrict__ gain,
+                                                   const cx<T> *__restrict__ trig,
+                                                   T *__restrict__ s_out) {
+    __shared__ cx<T> tr[4096];
+    for (int b = threadIdx.x; b < 4096; b += C3_NT) tr[b] = trig[b];
+    __syncthreads();
+    const int4 tl = tiles[blockIdx.x];
+    const int seg = tl.x;
+    const int band = Ld.seg_band[seg];
+    const int64_t poff = Ld.band[band].pix_off;
+    const int64_t npix = Ld.band[band].npix;
+    const int64_t npt = Ld.npix_total;
+    const T g = (T)gain[seg];
+    const int64_t base = Ld.seg_off[seg] + tl.y;
+    for (int t = threadIdx.x; t < tl.z; t += C3_NT) {
+        const int64_t i = base + t;
+        const int p = pix[i];
+        if ((uint32_t)p >= (uint32_t)npix) {
+            s_out[i] = (T)NAN;
+            continue;
+        }
+        const int64_t gp = poff + p;
+        const cx<T> cs = tr[psi[i] & 4095];
+        s_out[i] = g * (maps[gp] + maps[npt + gp] * cs.x + maps[2 * npt + gp] * cs.y);
+    }
+}
+
+// ---------------------------------------------------------------- binning
+__device__ __forceinline__ void flush_acc(double *acc, int64_t gp, const double *a) {
+    double *dst = acc + gp * 10;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) atomicAdd(dst + j, a[j]);
+}
+
+template <typename TN>
+__global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restrict__ tiles,
+                                               const int32_t *__restrict__ pix,
+                                               const uint16_t *__restrict__ psi, const void *d,
+                                               int d_f64, const TN *__restrict__ ncorr,
+                                               const double *__restrict__ gain,
+                                               const double *__restrict__ sigma0,
+                                               const cx<double> *__restrict__ trig,
+                                               double *__restrict__ acc) {
+    __shared__ cx<double> tr[4096];
+    const int4 tl = tiles[blockIdx.x];
+    const int seg = tl.x;
+    if (Ld.seg_accept && !Ld.seg_accept[seg]) return;  // uniform over the block
+    for (int b = threadIdx.x; b < 4096; b += C3_NT) tr[b] = trig[b];
+    __syncthreads();
+    const int S = tl.z;
+    const int phi = tl.y + threadIdx.x;
+    if ((int)threadIdx.x >= tl.w) return;
+    const int64_t s0 = Ld.seg_off[seg];
+    const int n = (int)(Ld.seg_off[seg + 1] - s0);
+    const int64_t poff = Ld.band[Ld.seg_band[seg]].pix_off;
+    const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg]].npix;
+    const double g = gain[seg];
+    const double s2 = sigma0[seg];
+    const double w = g / (s2 * s2);
+    const double gw = g * w;
+    double a[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) a[j] = 0.0;
+    int cur = -1;
+    for (int t = phi; t < n; t += S) {
+        const int64_t i = s0 + t;
+        const int p = pix[i];
+        if ((uint32_t)p >= npix) continue;  // out-of-range pixels are not binned
+        const cx<double> cs = tr[psi[i] & 4095];
+        double v = d_f64 ? ((const double *)d)[i] : (double)((const float *)d)[i];
+        if (ncorr) v -= (double)ncorr[i];
+        if (p != cur) {
+            if (cur >= 0) flush_acc(acc, poff + cur, a);
+#pragma unroll
+            for (int j = 0; j < 10; ++j) a[j] = 0.0;
+            cur = p;
+        }
+        const double wv = w * v;
+        a[0] += wv;
+        a[1] += wv * cs.x;
+        a[2] += wv * cs.y;
+        a[3] += gw;
+        a[4] += gw * cs.x;
+        a[5] += gw * cs.y;
+        a[6] += gw * cs.x * cs.x;
+        a[7] += gw * cs.x * cs.y;
+        a[8] += gw * cs.y * cs.y;
+        a[9] += 1.0;
+    }
+    if (cur >= 0) flush_acc(acc, poff + cur, a);
+}
+
+// ---------------------------------------------------------------- solve
+// Extreme eigenvalues of a symmetric 3x3 by cyclic Jacobi rotations: each
+// rotation zeroes one off-diagonal pair; eigenvalues come out with absolute
+// accuracy ~eps ||A|| even when two of them coincide (1- and 2-hit pixels).
+__device__ void eig3_minmax(const double A[3][3], double &lmin, double &lmax) {
+    double a[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) a[i][j] = A[i][j];
+    const double scale = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]);
+    for (int sweep = 0; sweep < 8; ++sweep) {
+        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        if (off <= 1e-40 * scale * scale) break;
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2, r = 3 - p - q;
+            const double apq = a[p][q];
+            if (apq == 0.0) continue;
+            const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+            double t;
+            if (fabs(th) > 1e150)
+                t = 0.5 / th;
+            else
+                t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+            a[p][p] -= t * apq;
+            a[q][q] += t * apq;
+            a[p][q] = a[q][p] = 0.0;
+            const double arp = a[r][p], arq = a[r][q];
+            a[r][p] = a[p][r] = c * arp - s * arq;
+            a[r][q] = a[q][r] = s * arp + c * arq;
+        }
+    }
+    lmin = fmin(a[0][0], fmin(a[1][1], a[2][2]));
+    lmax = fmax(a[0][0], fmax(a[1][1], a[2][2]));
+}
+
+template <typename TM>
+__global__ __launch_bounds__(C3_NT) void k_solve(int64_t npix, const double *__restrict__ acc,
+                                                 double rcmin, TM *__restrict__ map,
+                                                 double *__restrict__ rc_out) {
+    const int64_t p = (int64_t)blockIdx.x * C3_NT + threadIdx.x;
+    if (p >= npix) return;
+    const double *a = acc + p * 10;
+    const double b0 = a[0], b1 = a[1], b2 = a[2];
+    double A[3][3] = {{a[3], a[4], a[5]}, {a[4], a[6], a[7]}, {a[5], a[7], a[8]}};
+    const double hits = a[9];
+    double lmin, lmax;
+    eig3_minmax(A, lmin, lmax);
+    const double rc = lmax > 0.0 ? lmin / lmax : 0.0;
+    if (rc_out) rc_out[p] = rc;
+    double m0 = NAN, m1 = NAN, m2 = NAN;
+    if (hits >= 3.0 && rc >= rcmin) {
+        // Cholesky A = L L^T
+        const double l00 = sqrt(A[0][0]);
+        const double l10 = A[1][0] / l00, l20 = A[2][0] / l00;
+        const double l11 = sqrt(A[1][1] - l10 * l10);
+        const double l21 = (A[2][1] - l20 * l10) / l11;
+        const double l22 = sqrt(A[2][2] - l20 * l20 - l21 * l21);
+        const double y0 = b0 / l00;
+        const double y1 = (b1 - l10 * y0) / l11;
+        const double y2 = (b2 - l20 * y0 - l21 * y1) / l22;
+        m2 = y2 / l22;
+        m1 = (y1 - l21 * m2) / l11;
+        m0 = (y0 - l10 * m1 - l20 * m2) / l00;
+    }
+    map[p] = (TM)m0;
+    map[npix + p] = (TM)m1;
+    map[2 * npix + p] = (TM)m2;
+}
+
+// ---------------------------------------------------------------- zero / set
+__global__ void k_zero(uint64_t *p, int64_t nwords) {
+    for (int64_t i = (int64_t)blockIdx.x * C3_NT + threadIdx.x; i < nwords;
+         i += (int64_t)gridDim.x * C3_NT)
+        p[i] = 0;
+}
+__global__ void k_zero_bytes(uint8_t *p, int64_t nbytes) {
+    const int64_t i = threadIdx.x;
+    if (i < nbytes) p[i] = 0;
+}
+__global__ void k_set2(uint64_t *p, uint64_t a, uint64_t b) {
+    if (threadIdx.x == 0) {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
+// ---------------------------------------------------------------- repeat probe
+// counts[L] += #{t : pix[t] == pix[t + L]} for L in [1, maxlag], t < tmax
+__global__ __launch_bounds__(C3_NT) void k_probe(const int32_t *__restrict__ pix, int64_t off,
+                                                 int n, int maxlag,
+                                                 unsigned long long *counts) {
+    const int L = blockIdx.x * C3_NT + threadIdx.x + 1;
+    if (L > maxlag) return;
+    const int tmax = min(n - L, 8192);
+    unsigned long long c = 0;
+    for (int t = 0; t < tmax; ++t) c += (pix[off + t] == pix[off + t + L]);
+    atomicAdd(counts + L, c);
+}
+
+// ---------------------------------------------------------------- chi^2 time part
+__global__ __launch_bounds__(C3_NT) void k_chisq_time(
+    LayoutDev Ld, const int4 *__restrict__ tiles, int mixed, const int32_t *__restrict__ pix,
+    const uint16_t *__restrict__ psi, const void *d, int d_f64, const void *ncorr,
+    const void *maps, const double *__restrict__ gain, const double *__restrict__ sigma0,
+    const cx<double> *__restrict__ trig, double *__restrict__ seg_sums,
+    double *__restrict__ gmap, double gscale) {
+    __shared__ cx<double> tr[4096];
+    __shared__ double red[3][C3_NT / 64];
+    const int4 tl = tiles[blockIdx.x];
+    const int seg = tl.x;
+    if (Ld.seg_accept && !Ld.seg_accept[seg]) return;
+    for (int b = threadIdx.x; b < 4096; b += C3_NT) tr[b] = trig[b];
+    __syncthreads();
+    const int S = tl.z;
+    const int phi = tl.y + threadIdx.x;
+    const bool act = (int)threadIdx.x < tl.w;
+    const int64_t s0 = Ld.seg_off[seg];
+    const int n = (int)(Ld.seg_off[seg + 1] - s0);
+    const int64_t poff = Ld.band[Ld.seg_band[seg]].pix_off;
+    const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg]].npix;
+    const int64_t npt = Ld.npix_total;
+    const double g = gain[seg];
+    const double sg = sigma0[seg];
+    const double is2 = 1.0 / (sg * sg);
+    const double cfac = -2.0 * g * is2 * gscale;
+    double sr2 = 0, spr = 0;
+    double a0 = 0, a1 = 0, a2 = 0;
+    int cur = -1;
+    for (int t = act ? phi : n; t < n; t += S) {
+        const int64_t i = s0 + t;
+        const int p = pix[i];
+        if ((uint32_t)p >= npix) continue;
+        const int64_t gp = poff + p;
+        const cx<double> cs = tr[psi[i] & 4095];
+        double T, Q, U, nc;
+        if (mixed) {
+            const float *m = (const float *)maps;
+            T = m[gp];
+            Q = m[npt + gp];
+            U = m[2 * npt + gp];
+            nc = ncorr ? (double)((const float *)ncorr)[i] : 0.0;
+        } else {
+            const double *m = (const double *)maps;
+            T = m[gp];
+            Q = m[npt + gp];
+            U = m[2 * npt + gp];
+            nc = ncorr ? ((const double *)ncorr)[i] : 0.0;
+        }
+        const double Pm = T + Q * cs.x + U * cs.y;
+        const double dv = d_f64 ? ((const double *)d)[i] : (double)((const float *)d)[i];
+        const double r = dv - g * Pm - nc;
+        sr2 += r * r;
+        spr += Pm * r;
+        if (gmap) {
+            if (p != cur) {
+                if (cur >= 0) {
+                    atomicAdd(gmap + poff + cur, a0);
+                    atomicAdd(gmap + npt + poff + cur, a1);
+                    atomicAdd(gmap + 2 * npt + poff + cur, a2);
+                }
+                a0 = a1 = a2 = 0;
+                cur = p;
+            }
+            const double cr = cfac * r;
+            a0 += cr;
+            a1 += cr * cs.x;
+            a2 += cr * cs.y;
+        }
+    }
+    if (gmap && cur >= 0) {
+        atomicAdd(gmap + poff + cur, a0);
+        atomicAdd(gmap + npt + poff + cur, a1);
+        atomicAdd(gmap + 2 * npt + poff + cur, a2);
+    }
+    double v[3] = {sr2 * is2, spr, sr2};
+    for (int j = 0; j < 3; ++j) {
+        double x = v[j];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double x = 0;
+        for (int w = 0; w < C3_NT / 64; ++w) x += red[threadIdx.x][w];
+        atomicAdd(seg_sums + (int64_t)seg * 4 + threadIdx.x, x);
+    }
+}
+
+__global__ __launch_bounds__(C3_NT) void k_chisq_finish(
+    LayoutDev Ld, const double *__restrict__ st, const double *__restrict__ sw,
+    const double *__restrict__ gain, const double *__restrict__ sigma0,
+    const double *__restrict__ fknee, const double *__restrict__ alpha, double gscale,
+    double *chisq, double *ggain, double *gsig, double *gfk, double *galpha) {
+    const int s = blockIdx.x * C3_NT + threadIdx.x;
+    if (s >= Ld.nseg) return;
+    const bool ok = !Ld.seg_accept || Ld.seg_accept[s];
+    const double sg = sigma0[s];
+    const double *t = st + (int64_t)s * 4;
+    const double *w = sw + (int64_t)s * 4;
+    if (chisq) chisq[s] = ok ? t[0] + w[0] : 0.0;
+    if (ggain) ggain[s] = ok ? -2.0 * t[1] / (sg * sg) * gscale : 0.0;
+    if (!ok) return;
+    const int det = Ld.seg_det[s];
+    if (gsig) atomicAdd(gsig + det, gscale * (-2.0 * t[2] / (sg * sg * sg) + 2.0 / sg * w[1]));
+    if (gfk) atomicAdd(gfk + det, gscale * (-alpha[s] / fknee[s]) * w[1]);
+    if (galpha) atomicAdd(galpha + det, gscale * w[2]);
+}
+
+}  // namespace
+
+namespace c3 {
+
+hipError_t launch_project_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                                int ntile, const int32_t *pix, const uint16_t *psi,
+                                const void *maps, const double *gain, const void *trig,
+                                void *s_out) {
+    if (ntile <= 0) return hipSuccess;
+    if (mixed)
+        hipLaunchKernelGGL(k_project<float>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi,
+                           (const float *)maps, gain, (const cx<float> *)trig, (float *)s_out);
+    else
+        hipLaunchKernelGGL(k_project<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi,
+                           (const double *)maps, gain, (const cx<double> *)trig, (double *)s_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                            int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
+                            int d_f64, const void *ncorr, const double *gain,
+                            const double *sigma0, const void *trig64, double *acc) {
+    if (ntile <= 0) return hipSuccess;
+    if (mixed)
+        hipLaunchKernelGGL(k_bin<float>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
+                           d_f64, (const float *)ncorr, gain, sigma0,
+                           (const cx<double> *)trig64, acc);
+    else
+        hipLaunchKernelGGL(k_bin<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
+                           d_f64, (const double *)ncorr, gain, sigma0,
+                           (const cx<double> *)trig64, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(hipStream_t st, void *p, int64_t bytes) {
+    if (bytes <= 0) return hipSuccess;
+    const int64_t nw = bytes / 8;
+    if (nw > 0) {
+        int64_t nb = (nw + C3_NT - 1) / C3_NT;
+        if (nb > 65536) nb = 65536;
+        hipLaunchKernelGGL(k_zero, dim3((unsigned)nb), dim3(C3_NT), 0, st, (uint64_t *)p, nw);
+    }
+    const int64_t rem = bytes - nw * 8;
+    if (rem > 0)
+        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(C3_NT), 0, st, (uint8_t *)p + nw * 8, rem);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u64(hipStream_t st, uint64_t *p, uint64_t a, uint64_t b) {
+    hipLaunchKernelGGL(k_set2, dim3(1), dim3(64), 0, st, p, a, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(hipStream_t st, int64_t npix, const double *acc, double rcond_min,
+                        void *map_out, int map_f64, double *rcond_out) {
+    if (npix <= 0) return hipSuccess;
+    const int64_t nb = (npix + C3_NT - 1) / C3_NT;
+    if (map_f64)
+        hipLaunchKernelGGL(k_solve<double>, dim3((unsigned)nb), dim3(C3_NT), 0, st, npix, acc,
+                           rcond_min, (double *)map_out, rcond_out);
+    else
+        hipLaunchKernelGGL(k_solve<float>, dim3((unsigned)nb), dim3(C3_NT), 0, st, npix, acc,
+                           rcond_min, (float *)map_out, rcond_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_repeat_probe(hipStream_t st, const int32_t *pix, int64_t off, int n, int maxlag,
+                               unsigned long long *counts) {
+    const int nb = (maxlag + C3_NT - 1) / C3_NT;
+    hipLaunchKernelGGL(k_probe, dim3(nb), dim3(C3_NT), 0, st, pix, off, n, maxlag, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                                   int ntile, const int32_t *pix, const uint16_t *psi,
+                                   const void *d, int d_f64, const void *ncorr, const void *maps,
+                                   const double *gain, const double *sigma0, const void *trig64,
+                                   double *seg_sums, double *grad_maps, double grad_scale) {
+    if (ntile <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chisq_time, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, mixed, pix, psi, d,
+                       d_f64, ncorr, maps, gain, sigma0, (const cx<double> *)trig64, seg_sums,
+                       grad_maps, grad_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_chisq_finish(hipStream_t st, const LayoutDev &L, const double *seg_time,
+                               const double *seg_whittle, const double *gain, const double *sigma0,
+                               const double *fknee, const double *alpha, double grad_scale,
+                               double *chisq_seg, double *grad_gain, double *grad_sigma0,
+                               double *grad_fknee, double *grad_alpha) {
+    if (L.nseg <= 0) return hipSuccess;
+    const int nb = (L.nseg + C3_NT - 1) / C3_NT;
+    hipLaunchKernelGGL(k_chisq_finish, dim3(nb), dim3(C3_NT), 0, st, L, seg_time, seg_whittle,
+                       gain, sigma0, fknee, alpha, grad_scale, chisq_seg, grad_gain, grad_sigma0,
+                       grad_fknee, grad_alpha);
+    return hipGetLastError();
+}
+
+}  // namespace c3

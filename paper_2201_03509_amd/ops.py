@@ -1,0 +1,259 @@
+"""Python binding of the c3tod C-ABI: the same entry points, taking torch tensors.
+
+Every step of the TOD path runs in the HIP kernels of libc3tod.so; this module
+only turns tensors into device pointers and status codes into exceptions.
+PyTorch provides device memory and the stream.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class C3todError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (L.STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class InvalidArgument(C3todError):
+    pass
+
+
+class CorruptStream(C3todError):
+    pass
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(prec):
+    if prec in ("mixed", L.TOD_MIXED):
+        return L.TOD_MIXED
+    if prec in ("fp64", "plain", L.TOD_PLAIN_FP64):
+        return L.TOD_PLAIN_FP64
+    raise ValueError("precision must be 'mixed' or 'fp64'")
+
+
+def _dt(t):
+    if t.dtype == torch.float32:
+        return L.TOD_F32
+    if t.dtype == torch.float64:
+        return L.TOD_F64
+    raise ValueError("TOD must be float32 or float64")
+
+
+class DeviceTod:
+    """A TOD set resident on the GPU plus the C structs that describe it.
+
+    ``src`` is any object with the numpy arrays of a TOD set (segment table,
+    bands, Huffman streams, d, per-segment gain and noise parameters)."""
+
+    def __init__(self, src, device="cuda"):
+        dev = torch.device(device)
+        self.device = dev
+        to = lambda a, dt=None: torch.from_numpy(np.ascontiguousarray(a if dt is None else a.astype(dt))).to(dev)
+        self.nseg = int(src.nseg)
+        self.nband = int(src.nband)
+        self.ndet = int(src.ndet)
+        self.nsamp = int(src.nsamp)
+        self.npix_total = int(src.npix_total)
+        self.h_seg_off = np.ascontiguousarray(src.seg_off, dtype=np.int64)
+        self.h_seg_band = np.ascontiguousarray(src.seg_band, dtype=np.int32)
+        self.seg_off = to(self.h_seg_off)
+        self.seg_band = to(self.h_seg_band)
+        self.seg_det = to(src.seg_det, np.int32)
+        self.seg_accept = to(src.seg_accept, np.uint8)
+        self.seg_det_h = np.asarray(src.seg_det, dtype=np.int32)
+        bands = (L.tod_band * self.nband)()
+        for b in range(self.nband):
+            bands[b].nside = int(src.band_nside[b])
+            bands[b].npsi = 4096
+            bands[b].npix = int(src.band_npix[b])
+            bands[b].pix_off = int(src.band_pix_off[b])
+            bands[b].fsamp = float(src.band_fsamp[b])
+        self._bands = bands
+        lay = L.tod_layout()
+        lay.nseg, lay.nband, lay.ndet = self.nseg, self.nband, self.ndet
+        lay.nsamp, lay.npix_total = self.nsamp, self.npix_total
+        lay.seg_off = self.seg_off.data_ptr()
+        lay.seg_band = self.seg_band.data_ptr()
+        lay.seg_det = self.seg_det.data_ptr()
+        lay.seg_accept = self.seg_accept.data_ptr()
+        lay.h_seg_off = self.h_seg_off.ctypes.data
+        lay.h_seg_band = self.h_seg_band.ctypes.data
+        lay.bands = bands
+        self.layout = lay
+        self.d = to(src.d)
+        self.gain = to(src.gain, np.float64)
+        self.sigma0 = to(src.sigma0, np.float64)
+        self.fknee = to(src.fknee, np.float64)
+        self.alpha = to(src.alpha, np.float64)
+        self.pix_huff, self._pt = self._huff(src.pix_huff, to)
+        self.psi_huff, self._qt = self._huff(src.psi_huff, to)
+
+    def refresh_accept(self):
+        self.layout.seg_accept = self.seg_accept.data_ptr()
+
+    @staticmethod
+    def _huff(hs, to):
+        t = {
+            "words": to(hs.words, np.uint32),
+            "seg_word_off": to(hs.seg_word_off, np.int64),
+            "seg_table": to(hs.seg_table, np.int32),
+            "tables": to(hs.tables, np.uint32),
+            "table_off": to(hs.table_off, np.int64),
+            "chunk_bit": to(hs.chunk_bit, np.uint32),
+            "chunk_prev": to(hs.chunk_prev, np.int32),
+            "seg_chunk_off": to(hs.seg_chunk_off, np.int64),
+        }
+        h = L.tod_huff()
+        for k, v in t.items():
+            setattr(h, k, v.data_ptr())
+        h.chunk_len = int(hs.chunk_len)
+        h.ntable = int(len(hs.table_off) - 1)
+        h.nwords = int(len(hs.words))
+        h.nchunk = int(len(hs.chunk_bit))
+        return h, t
+
+
+class Context:
+    """One c3tod context on one device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise C3todError(L.TOD_EHIP, "no HIP device available")
+        torch.cuda.set_device(device)
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = st
+        h = ctypes.c_void_p()
+        self._chk(self.lib.tod_ctx_create(ctypes.byref(h), int(device),
+                                          ctypes.c_void_p(st.cuda_stream)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tod_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st == L.TOD_OK:
+            return
+        msg = ""
+        if getattr(self, "h", None):
+            m = self.lib.tod_last_error(self.h)
+            msg = m.decode() if m else ""
+        if st == L.TOD_EINVAL:
+            raise InvalidArgument(st, msg)
+        if st == L.TOD_ECORRUPT:
+            raise CorruptStream(st, msg)
+        raise C3todError(st, msg)
+
+    # --------------------------------------------------------------- entry points
+    def sync(self):
+        self._chk(self.lib.tod_sync(self.h))
+
+    def clear_error(self):
+        self._chk(self.lib.tod_clear_error(self.h))
+
+    def device_error_bits(self):
+        return int(self.lib.tod_device_error_bits(self.h))
+
+    def decode_pointing(self, tod, pix_out, psi_out, pix_huff=None, psi_huff=None):
+        self._chk(self.lib.decode_pointing(self.h, ctypes.byref(tod.layout),
+                                           ctypes.byref(pix_huff or tod.pix_huff),
+                                           ctypes.byref(psi_huff or tod.psi_huff),
+                                           _ptr(pix_out), _ptr(psi_out)))
+
+    def project_sky(self, tod, prec, pix, psi, maps, s_out, gain=None):
+        self._chk(self.lib.project_sky(self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix),
+                                       _ptr(psi), _ptr(maps), _ptr(tod.gain if gain is None else gain),
+                                       _ptr(s_out)))
+
+    def sample_ncorr(self, tod, prec, d, s, seed, it, out, mean_only=False, sigma0=None,
+                     fknee=None, alpha=None):
+        self._chk(self.lib.sample_ncorr(
+            self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(d), _dt(d), _ptr(s),
+            _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(tod.fknee if fknee is None else fknee),
+            _ptr(tod.alpha if alpha is None else alpha), ctypes.c_uint64(int(seed)),
+            ctypes.c_uint64(int(it)), int(bool(mean_only)), _ptr(out)))
+
+    def bin_tod(self, tod, prec, pix, psi, d, ncorr, acc, accumulate=False, gain=None, sigma0=None):
+        self._chk(self.lib.bin_tod(
+            self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
+            _ptr(ncorr), _ptr(tod.gain if gain is None else gain),
+            _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(acc), int(bool(accumulate))))
+
+    def solve_maps(self, acc, rcond_min, map_out, rcond_out=None):
+        npix = acc.shape[0]
+        self._chk(self.lib.solve_maps(self.h, int(npix), _ptr(acc), float(rcond_min), _ptr(map_out),
+                                      _dt(map_out), _ptr(rcond_out)))
+
+    def tod_chisq(self, tod, prec, pix, psi, d, ncorr, maps, chisq_seg, gain=None, sigma0=None,
+                  fknee=None, alpha=None):
+        self._chk(self.lib.tod_chisq(
+            self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
+            _ptr(ncorr), _ptr(maps), _ptr(tod.gain if gain is None else gain),
+            _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(tod.fknee if fknee is None else fknee),
+            _ptr(tod.alpha if alpha is None else alpha), _ptr(chisq_seg)))
+
+    def tod_chisq_backward(self, tod, prec, pix, psi, d, ncorr, maps, grad_scale, grad_maps=None,
+                           grad_gain=None, grad_sigma0=None, grad_fknee=None, grad_alpha=None,
+                           gain=None, sigma0=None, fknee=None, alpha=None):
+        self._chk(self.lib.tod_chisq_backward(
+            self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
+            _ptr(ncorr), _ptr(maps), _ptr(tod.gain if gain is None else gain),
+            _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(tod.fknee if fknee is None else fknee),
+            _ptr(tod.alpha if alpha is None else alpha), float(grad_scale), _ptr(grad_maps),
+            _ptr(grad_gain), _ptr(grad_sigma0), _ptr(grad_fknee), _ptr(grad_alpha)))
+
+    def tod_sweep(self, tod, prec, maps, seed, it, ncorr_out, acc, pix_work, psi_work,
+                  use_graph=False):
+        self._chk(self.lib.tod_sweep(
+            self.h, ctypes.byref(tod.layout), _prec(prec), ctypes.byref(tod.pix_huff),
+            ctypes.byref(tod.psi_huff), _ptr(tod.d), _dt(tod.d), _ptr(maps), _ptr(tod.gain),
+            _ptr(tod.sigma0), _ptr(tod.fknee), _ptr(tod.alpha), ctypes.c_uint64(int(seed)),
+            ctypes.c_uint64(int(it)), _ptr(ncorr_out), _ptr(acc), _ptr(pix_work), _ptr(psi_work),
+            int(bool(use_graph))))
+
+    def autotune(self, tod, prec, pix=None, cache_path=None):
+        self._chk(self.lib.tod_autotune(self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix),
+                                        cache_path.encode() if cache_path else None))
+
+    def load_tuning(self, path):
+        self._chk(self.lib.tod_load_tuning(self.h, path.encode()))
+
+    def set_bin_stride(self, band, stride):
+        self._chk(self.lib.tod_set_bin_stride(self.h, int(band), int(stride)))
+
+    def enable_timing(self, on=True):
+        self._chk(self.lib.tod_enable_timing(self.h, int(bool(on))))
+
+    def phase_ms(self):
+        a = (ctypes.c_double * 6)()
+        self._chk(self.lib.tod_phase_ms(self.h, a))
+        return list(a)
+
+
+def new_outputs(tod, prec):
+    """Allocate the per-sample and per-pixel outputs of one sweep."""
+    dev = tod.device
+    ft = torch.float32 if _prec(prec) == L.TOD_MIXED else torch.float64
+    return {
+        "pix": torch.empty(tod.nsamp, dtype=torch.int32, device=dev),
+        "psi": torch.empty(tod.nsamp, dtype=torch.uint16, device=dev),
+        "ncorr": torch.empty(tod.nsamp, dtype=ft, device=dev),
+        "acc": torch.empty((tod.npix_total, 10), dtype=torch.float64, device=dev),
+    }
