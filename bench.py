@@ -1,0 +1,340 @@
+#!/usr/bin/env python3
+"""Throughput of the TOD sweep (decode -> project -> n_corr draw -> bin) on one GPU.
+
+One *step* is one fused sweep over the whole synthetic TOD set of the chosen
+workload (default: the 70 GHz-like set, nside 1024, 12 detectors x 300 scans of
+230k-290k samples at 78.8 Hz, i.e. ~9.4e8 samples) with all inputs resident in
+HBM.  Prints ONE JSON line on stdout; progress goes to stderr.
+
+The timed region runs the mixed-precision sweep eagerly with HIP events
+around every kernel (on the context stream), so the dominant kernel's
+duration is measured live; the graph-replayed sweep and the plain-FP64 sweep
+are timed separately and reported beside it.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(ts, tod, prec, sum_m):
+    """Compulsory bytes per launch of each kernel of the sweep: every input
+    array the kernel needs read once, every output written once."""
+    f = 4 if prec == "mixed" else 8
+    ns = ts.nsamp
+    dsz = ts.d.dtype.itemsize
+    comp = 0
+    for hs in (ts.pix_huff, ts.psi_huff):
+        comp += hs.words.nbytes + hs.chunk_bit.nbytes + hs.chunk_prev.nbytes + hs.tables.nbytes
+    npt = ts.npix_total
+    return {
+        "decode": comp + ns * dsz + 3 * f * npt + ns * (f + 4 + 2),
+        "fft_col_fwd": ns * f + 2 * f * sum_m,
+        "fft_row": 2 * (2 * f * sum_m),
+        "fft_col_inv": 2 * f * sum_m + ns * f,
+        "bin": ns * (4 + 2 + dsz + f) + 2 * 80 * npt,
+        "project": ns * (4 + 2 + f) + 3 * f * npt,
+        "solve": 80 * npt + 3 * f * npt + 8 * npt,
+        "chisq_time": ns * (4 + 2 + dsz + f) + 3 * f * npt,
+    }
+
+
+def next5(n):
+    m = max(1, n)
+    while True:
+        x = m
+        for q in (2, 3, 5):
+            while x % q == 0:
+                x //= q
+        if x == 1:
+            return m
+        m += 1
+
+
+def source_sha():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2201_03509_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".cpp", ".h")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+    except ValueError:
+        return None
+    e = t.get(workload, {}).get(kernel)
+    if not e or e.get("source_sha") != source_sha():
+        return None
+    return e.get("bytes_per_launch")
+
+
+# ------------------------------------------------------------- CPU baseline
+_BASE = {}
+
+
+def _oracle_segment(q):
+    ts, seed, it, maps32 = _BASE["ts"], _BASE["seed"], _BASE["it"], _BASE["maps"]
+    import numpy as np
+    from oracle import huffman as oh
+    from oracle import tod as ot
+    n = int(ts.seg_off[q + 1] - ts.seg_off[q])
+    pix = oh.StreamDecoder(ts.pix_huff).segment(q, n)
+    psi = oh.StreamDecoder(ts.psi_huff).segment(q, n)
+    a = ts.seg_off[q]
+    gp = pix + ts.band_pix_off[ts.seg_band[q]]
+    s = ot.project(maps32, gp, psi, ts.gain[q])
+    r = ts.d[a:a + n].astype(np.float64) - s
+    fs = ts.band_fsamp[ts.seg_band[q]]
+    nc = ot.sample_ncorr_segment(r, fs, ts.sigma0[q], ts.fknee[q], ts.alpha[q], seed, q, it)
+    _, c, sn = ot.pointing_rows(gp, psi)
+    g = ts.gain[q]
+    w = g / ts.sigma0[q] ** 2
+    v = ts.d[a:a + n] - nc
+    npt = ts.npix_total
+    b = np.zeros((3, npt))
+    A = np.zeros((6, npt))
+    rows = (np.ones(n), c, sn)
+    for i in range(3):
+        np.add.at(b[i], gp, w * v * rows[i])
+    for k, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
+        np.add.at(A[k], gp, g * w * rows[i] * rows[j])
+    return q, pix, nc
+
+
+def cpu_baseline(ts, seed, it, maps32, budget_s=15.0):
+    """The oracle, as it stands, over a bounded sample of the same workload,
+    one segment per worker process.  Runs before the GPU is touched (the
+    worker processes are forked)."""
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    _BASE.update(ts=ts, seed=seed, it=it, maps=maps32)
+    t0 = time.perf_counter()
+    _oracle_segment(0)
+    t1 = time.perf_counter() - t0
+    nseg = int(max(workers, min(ts.nseg, budget_s * workers / max(t1, 1e-3))))
+    nseg = min(nseg, ts.nseg)
+    log("cpu baseline: %.2fs per segment, sampling %d segments on %d processes" % (t1, nseg, workers))
+    ctx = mp.get_context("fork")
+    res = []
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        for r in pool.imap_unordered(_oracle_segment, range(nseg)):
+            res.append(r)
+            if len(res) % workers == 0:
+                log("  oracle segments done: %d/%d" % (len(res), nseg))
+    wall = time.perf_counter() - t0
+    nsamp = int(sum(ts.seg_off[q + 1] - ts.seg_off[q] for q in range(nseg)))
+    return {
+        "value": nsamp / wall, "unit": "TOD samples/s", "cores": workers, "kind": "oracle",
+        "sample": "%d of %d segments (%d samples): decode+project+n_corr+bin, FP64 numpy/C, "
+                  "one segment per process" % (nseg, ts.nseg, nsamp),
+    }, res
+
+
+def compare_to_oracle(ts, res, gpu_ncorr, gpu_pix):
+    import numpy as np
+    errs, exact = [], True
+    for q, pix, nc in res:
+        a, b = ts.seg_off[q], ts.seg_off[q + 1]
+        g = gpu_ncorr[a:b].astype(np.float64)
+        errs.append(float(np.linalg.norm(g - nc) / np.linalg.norm(nc)))
+        exact &= bool(np.array_equal(gpu_pix[a:b], pix))
+    return {"ncorr_rel_l2_max": max(errs), "ncorr_rel_l2_median": float(np.median(errs)),
+            "decode_bit_exact": exact, "segments": len(res)}
+
+
+# ------------------------------------------------------------------ main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--nscan", type=int, default=None, help="fewer scans (quick runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cache-dir", default=None, help="reuse generated inputs saved here")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2201_03509_amd import ops
+
+    t0 = time.perf_counter()
+    ts = synth.make_cached(args.config, cache_dir=args.cache_dir, nscan=args.nscan)
+    log("generated config %d: %d segments, %d samples in %.1fs" %
+        (args.config, ts.nseg, ts.nsamp, time.perf_counter() - t0))
+    seed = synth.seed32(args.config)
+    last_it = args.warmup + args.steps - 1
+    maps32_h = ts.maps.astype(np.float32)
+    cpu, oracle_res = None, None
+    if not args.no_cpu_baseline:
+        c0 = time.perf_counter()
+        cpu, oracle_res = cpu_baseline(ts, seed, last_it, maps32_h.astype(np.float64))
+        log("cpu baseline %.3e samples/s on %d cores (%.1fs)" %
+            (cpu["value"], cpu["cores"], time.perf_counter() - c0))
+    dev = torch.device("cuda:0")
+    ctx = ops.Context(0)
+    tod = ops.DeviceTod(ts, dev)
+    maps32 = torch.from_numpy(maps32_h).to(dev)
+    maps64 = torch.from_numpy(ts.maps).to(dev)
+    out = ops.new_outputs(tod, "mixed")
+    # plans: autotune FFT splits and the binning stride on the decoded pointing
+    ctx.decode_pointing(tod, out["pix"], out["psi"])
+    ctx.sync()
+    t1 = time.perf_counter()
+    tune_path = os.path.join(args.cache_dir or "/tmp", "c3tod_tune_%d.json" % os.getpid())
+    ctx.autotune(tod, "mixed", out["pix"], cache_path=tune_path)
+    log("autotuned mixed plans in %.1fs" % (time.perf_counter() - t1))
+    tuned = json.load(open(tune_path))
+    os.remove(tune_path)
+    plans = {}
+    for e in tuned.get("fft", []):
+        if e["mixed"] == 1:
+            k = "%dx%d/B%d" % (e["M1"], e["M2"], e["B"])
+            plans[k] = plans.get(k, 0) + 1
+
+    def sweeps(prec, maps, o, k, it0, graph=False):
+        for i in range(k):
+            ctx.tod_sweep(tod, prec, maps, seed, it0 + i, o["ncorr"], o["acc"], o["pix"], o["psi"],
+                          use_graph=graph)
+
+    # warm-up
+    sweeps("mixed", maps32, out, args.warmup, 0)
+    ctx.sync()
+    # timed region: eager sweeps, HIP events around every kernel
+    ctx.enable_timing(True)
+    ctx.kernel_times()
+    st = ctx.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    sweeps("mixed", maps32, out, args.steps, args.warmup)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms_total = e0.elapsed_time(e1)
+    kt = ctx.kernel_times()
+    ctx.enable_timing(False)
+    ms_step = ms_total / args.steps
+    value = ts.nsamp * args.steps / (ms_total / 1e3)
+    log("mixed eager: %.3f ms/step, %.3e samples/s" % (ms_step, value))
+
+    # graph-replayed sweeps
+    sweeps("mixed", maps32, out, 2, 1000, graph=True)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    sweeps("mixed", maps32, out, args.steps, 1000, graph=True)
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - g0) * 1e3 / args.steps
+    # restore the eager last iteration's n_corr for the accuracy check
+    sweeps("mixed", maps32, out, 1, last_it)
+    ctx.sync()
+    gpu_nc = out["ncorr"].cpu().numpy()
+    gpu_pix = out["pix"].cpu().numpy()
+
+    sum_m = sum(next5(int(ts.seg_off[q + 1] - ts.seg_off[q])) for q in range(ts.nseg))
+    kb = kernel_bytes(ts, tod, "mixed", sum_m)
+    per = {k: {"ms_per_launch": (v[0] / v[1]) if v[1] else None, "launches": v[1],
+               "compulsory_gb_per_launch": kb[k] / 1e9 if k in kb else None}
+           for k, v in kt.items() if v[1]}
+    dom = max(per, key=lambda k: kt[k][0])
+    avg_ms = per[dom]["ms_per_launch"]
+    ach = kb[dom] / (avg_ms / 1e3) / 1e9
+    workload = "lfi70" if args.config == 2 and args.nscan is None else "config%d_nscan%s" % (args.config, args.nscan)
+    traffic = measured_traffic(dom, workload)
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "bytes_per_launch": kb[dom], "avg_ms": round(avg_ms, 4)}
+    sweep_alg = (2 * (sum(h.words.nbytes for h in (ts.pix_huff, ts.psi_huff))) + ts.nsamp * (4 + 4)
+                 + 84 * ts.npix_total)
+    log("dominant kernel %s: %.3f ms, %.0f GB/s compulsory" % (dom, avg_ms, ach))
+
+    plain = None
+    if not args.no_plain:
+        outp = ops.new_outputs(tod, "fp64")
+        ctx.autotune(tod, "fp64", out["pix"])
+        sweeps("fp64", maps64, outp, 1, 0)
+        ctx.sync()
+        p0 = time.perf_counter()
+        ksteps = max(1, args.steps // 2)
+        sweeps("fp64", maps64, outp, ksteps, 1)
+        ctx.sync()
+        ms_plain = (time.perf_counter() - p0) * 1e3 / ksteps
+        plain = {"value": ts.nsamp / (ms_plain / 1e3), "ms_per_step": round(ms_plain, 3)}
+        log("plain fp64: %.3f ms/step" % ms_plain)
+        del outp
+        torch.cuda.empty_cache()
+
+    copy = None
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        copy = {"bytes": 2 * a.numel() * 4}
+
+    acc_report = compare_to_oracle(ts, oracle_res, gpu_nc, gpu_pix) if oracle_res else None
+
+    line = {
+        "metric": "TOD samples/s (decode+project+n_corr+bin), mixed-FP32 vs FP64 plain, 1 GPU",
+        "value": value,
+        "unit": "TOD samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "nside": [int(x) for x in ts.band_nside],
+                   "segments": ts.nseg, "samples": ts.nsamp,
+                   "precision": "FP32 projection/FFT/draws, FP64 pixel accumulation",
+                   "fft_padding": "even 5-smooth >= 2n"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "graph_ms_per_step": round(ms_graph, 3),
+        "plain_fp64": plain,
+        "sweep_algorithmic_gb": round(sweep_alg / 1e9, 3),
+        "sweep_algorithmic_frac": round(sweep_alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "kernels": per,
+        "fft_splits": plans,
+        "bin_stride": tuned.get("bin_stride"),
+        "accuracy_vs_oracle": acc_report,
+        "copy_probe": copy,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

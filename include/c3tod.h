@@ -247,11 +247,15 @@ tod_status tod_load_tuning(tod_ctx ctx, const char *cache_path);
  * library choose.  Correct for any value; only speed depends on it. */
 tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride);
 
-/* Kernel time of the last call per phase (ms, from HIP events on the ctx
- * stream) when timing is enabled; phases: 0 decode, 1 project, 2 ncorr FFT
- * passes, 3 bin, 4 solve, 5 chisq. */
+/* Per-kernel timing.  While enabled, every launch the context makes outside
+ * graph capture is bracketed by HIP events on the context stream (the sweep
+ * then runs eagerly).  tod_kernel_times synchronises the stream, returns the
+ * summed milliseconds and launch counts since the previous read and resets
+ * them.  Kernel ids (arrays of 8): 0 decode, 1 projection, 2 FFT forward
+ * column pass, 3 FFT row pass (filter + draw, or Whittle sums), 4 FFT inverse
+ * column pass, 5 binning, 6 per-pixel solve, 7 chi^2 time-domain terms. */
 tod_status tod_enable_timing(tod_ctx ctx, int enable);
-tod_status tod_phase_ms(tod_ctx ctx, double *ms6);
+tod_status tod_kernel_times(tod_ctx ctx, double *total_ms, int32_t *launches);
 
 #ifdef __cplusplus
 }

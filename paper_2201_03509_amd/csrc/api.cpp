@@ -109,8 +109,13 @@ struct tod_ctx_s {
     std::string last_error;
     uint32_t last_err_bits = 0;
     bool timing = false;
-    hipEvent_t ev[8] = {};
-    double phase_ms[6] = {0, 0, 0, 0, 0, 0};
+    hipEvent_t ev[8] = {};                 // scratch events (autotuning)
+    std::vector<hipEvent_t> ev_pool;       // recycled timing events
+    struct Rec {
+        int kid;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;                 // launches timed since the last read
     struct GraphEntry {
         hipGraph_t g = nullptr;
         hipGraphExec_t ex = nullptr;
@@ -466,19 +471,37 @@ tod_status ensure_work(tod_ctx ctx, Plan *P) {
     return TOD_OK;
 }
 
-struct PhaseTimer {
-    tod_ctx c;
-    int phase;
-    PhaseTimer(tod_ctx ctx, int ph) : c(ctx), phase(ph) {
-        if (c->timing) (void)hipEventRecord(c->ev[0], c->stream);
+// kernel ids of tod_kernel_times
+enum { K_DECODE = 0, K_PROJECT, K_COLF, K_ROW, K_COLI, K_BIN, K_SOLVE, K_CHISQ, K_NKERNEL };
+
+hipEvent_t pool_event(tod_ctx c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
     }
-    ~PhaseTimer() {
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// brackets one launch with events on `st` when timing is on (never in capture)
+struct KTimer {
+    tod_ctx c;
+    int kid;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    KTimer(tod_ctx ctx, int k, hipStream_t s) : c(ctx), kid(k), st(s) {
         if (c->timing) {
-            (void)hipEventRecord(c->ev[1], c->stream);
-            (void)hipEventSynchronize(c->ev[1]);
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
-            c->phase_ms[phase] = ms;
+            a = pool_event(c);
+            (void)hipEventRecord(a, st);
+        }
+    }
+    ~KTimer() {
+        if (a) {
+            hipEvent_t b = pool_event(c);
+            (void)hipEventRecord(b, st);
+            c->recs.push_back({kid, a, b});
         }
     }
 };
@@ -534,6 +557,11 @@ tod_status tod_ctx_destroy(tod_ctx ctx) {
     }
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto &e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->d_err) (void)hipFree(ctx->d_err);
     if (ctx->d_seed_iter) (void)hipFree(ctx->d_seed_iter);
@@ -583,10 +611,9 @@ tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay, const tod_huff *p
     const DecodeTask *tasks;
     int nt;
     if ((r = get_decode_tasks(ctx, P, pix->chunk_len, &tasks, &nt)) != TOD_OK) return r;
-    PhaseTimer pt(ctx, 0);
+    KTimer kt(ctx, K_DECODE, ctx->stream);
     HIPCHK(c3::launch_decode(ctx->stream, make_layout_dev(lay), make_huff_dev(pix), make_huff_dev(psi),
-                             tasks, nt, pix_out, psi_out, c3::DEC_POINTING, 1, nullptr, 0, nullptr,
-                             nullptr, nullptr, nullptr, ctx->d_err));
+                             tasks, nt, pix_out, psi_out, ctx->d_err));
     return TOD_OK;
 }
 
@@ -600,7 +627,7 @@ tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const 
     const int mixed = prec == TOD_MIXED;
     Plan *P;
     if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
-    PhaseTimer pt(ctx, 1);
+    KTimer kt(ctx, K_PROJECT, ctx->stream);
     HIPCHK(c3::launch_project_tiles(ctx->stream, make_layout_dev(lay), mixed,
                                     (const int4 *)P->sample_tiles.p, P->nsample_tiles, pix, psi, maps,
                                     gain, mixed ? ctx->trig32.p : ctx->trig64.p, s_out));
@@ -623,7 +650,10 @@ static tod_status ncorr_impl(tod_ctx ctx, const tod_layout *lay, int mixed, Plan
     a.alpha = alpha;
     a.mean_only = mean_only;
     a.mode = 0;
-    HIPCHK(c3::launch_fft_ncorr(ctx->stream, mixed, a));
+    for (int pass = 0; pass < 3; ++pass) {
+        KTimer kt(ctx, K_COLF + pass, ctx->stream);
+        HIPCHK(c3::launch_fft_pass(ctx->stream, mixed, a, pass));
+    }
     return TOD_OK;
 }
 
@@ -641,7 +671,6 @@ tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
     Plan *P;
     if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
     HIPCHK(c3::launch_set_u64(ctx->stream, ctx->d_seed_iter, seed, iter));
-    PhaseTimer pt(ctx, 2);
     return ncorr_impl(ctx, lay, mixed, P, d, d_dtype, s, !mixed, sigma0, fknee, alpha, mean_only,
                       ncorr_out);
 }
@@ -661,8 +690,8 @@ tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int3
     const int4 *tiles;
     int nt;
     if ((r = get_bin_tiles(ctx, lay, P, pix, &tiles, &nt)) != TOD_OK) return r;
-    PhaseTimer pt(ctx, 3);
     if (!accumulate) HIPCHK(c3::launch_zero(ctx->stream, acc, lay->npix_total * 10 * sizeof(double)));
+    KTimer kt(ctx, K_BIN, ctx->stream);
     HIPCHK(c3::launch_bin_tiles(ctx->stream, make_layout_dev(lay), mixed, tiles, nt, pix, psi, d,
                                 d_dtype == TOD_F64, ncorr, gain, sigma0, ctx->trig64.p, acc));
     return TOD_OK;
@@ -673,7 +702,7 @@ tod_status solve_maps(tod_ctx ctx, int64_t npix, const double *acc, double rcond
     if (!ctx) return TOD_EINVAL;
     if (npix < 0 || !acc || !map_out) return fail(ctx, TOD_EINVAL, "bad argument");
     if (map_dtype != TOD_F32 && map_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad map dtype");
-    PhaseTimer pt(ctx, 4);
+    KTimer kt(ctx, K_SOLVE, ctx->stream);
     HIPCHK(c3::launch_solve(ctx->stream, npix, acc, rcond_min, map_out, map_dtype == TOD_F64, rcond_out));
     return TOD_OK;
 }
@@ -700,7 +729,6 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     const size_t ssz = sizeof(double) * 4 * (size_t)std::max(1, lay->nseg);
     HIPCHK(ctx->seg_sums.ensure(ssz));
     HIPCHK(ctx->seg_whittle.ensure(ssz));
-    PhaseTimer pt(ctx, 5);
     hipStream_t st = ctx->stream;
     HIPCHK(c3::launch_zero(st, ctx->seg_sums.p, ssz));
     HIPCHK(c3::launch_zero(st, ctx->seg_whittle.p, ssz));
@@ -709,9 +737,12 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     if (gfk) HIPCHK(c3::launch_zero(st, gfk, sizeof(double) * lay->ndet));
     if (galpha) HIPCHK(c3::launch_zero(st, galpha, sizeof(double) * lay->ndet));
     const LayoutDev Ld = make_layout_dev(lay);
-    HIPCHK(c3::launch_chisq_time_tiles(st, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64, ncorr,
-                                       maps, gain, sigma0, ctx->trig64.p, (double *)ctx->seg_sums.p,
-                                       grad_maps, gscale));
+    {
+        KTimer kt(ctx, K_CHISQ, st);
+        HIPCHK(c3::launch_chisq_time_tiles(st, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64,
+                                           ncorr, maps, gain, sigma0, ctx->trig64.p,
+                                           (double *)ctx->seg_sums.p, grad_maps, gscale));
+    }
     c3::FftArgs a = fft_args(ctx, P, lay);
     a.in_a = ncorr;
     a.in_a_f64 = !mixed;
@@ -721,7 +752,10 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     a.alpha = alpha;
     a.mode = 1;
     a.whittle = (double *)ctx->seg_whittle.p;
-    HIPCHK(c3::launch_fft_whittle(st, mixed, a));
+    for (int pass = 0; pass < 2; ++pass) {
+        KTimer kt(ctx, K_COLF + pass, st);
+        HIPCHK(c3::launch_fft_pass(st, mixed, a, pass));
+    }
     HIPCHK(c3::launch_chisq_finish(st, Ld, (const double *)ctx->seg_sums.p,
                                    (const double *)ctx->seg_whittle.p, gain, sigma0, fknee, alpha,
                                    gscale, chisq_seg, grad_gain, gsig, gfk, galpha));
@@ -798,16 +832,24 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     }
     // eager (or capture) sequence
     auto run = [&](bool capture) -> tod_status {
+        {
+            KTimer kt(ctx, K_DECODE, st);
+            HIPCHK(c3::launch_decode(st, Ld, make_huff_dev(pix), make_huff_dev(psi), dt, ndt, pix_work,
+                                     psi_work, ctx->d_err));
+        }
         const int4 *tiles = (const int4 *)P->bin_tiles.p;
         int nt = P->nbin;
-        {
-            PhaseTimer pt(ctx, 0);
-            HIPCHK(c3::launch_decode(st, Ld, make_huff_dev(pix), make_huff_dev(psi), dt, ndt, pix_work,
-                                     psi_work, c3::DEC_RESIDUAL, mixed, d, d_dtype == TOD_F64, maps, gain,
-                                     mixed ? ctx->trig32.p : ctx->trig64.p, ctx->resid.p, ctx->d_err));
+        if (!capture && !have_tiles) {
+            tod_status rr = get_bin_tiles(ctx, lay, P, pix_work, &tiles, &nt);
+            if (rr != TOD_OK) return rr;
         }
         {
-            PhaseTimer pt(ctx, 2);
+            KTimer kt(ctx, K_PROJECT, st);
+            HIPCHK(c3::launch_resid_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
+                                          d_dtype == TOD_F64, maps, gain,
+                                          mixed ? ctx->trig32.p : ctx->trig64.p, ctx->resid.p));
+        }
+        {
             c3::FftArgs a = fft_args(ctx, P, lay);
             a.in_a = ctx->resid.p;
             a.in_a_f64 = !mixed;
@@ -817,15 +859,14 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
             a.fknee = fknee;
             a.alpha = alpha;
             a.mean_only = 0;
-            HIPCHK(c3::launch_fft_ncorr(st, mixed, a));
-        }
-        if (!capture && !have_tiles) {
-            tod_status rr = get_bin_tiles(ctx, lay, P, pix_work, &tiles, &nt);
-            if (rr != TOD_OK) return rr;
+            for (int pass = 0; pass < 3; ++pass) {
+                KTimer kt(ctx, K_COLF + pass, st);
+                HIPCHK(c3::launch_fft_pass(st, mixed, a, pass));
+            }
         }
         {
-            PhaseTimer pt(ctx, 3);
             HIPCHK(c3::launch_zero(st, acc, lay->npix_total * 10 * sizeof(double)));
+            KTimer kt(ctx, K_BIN, st);
             HIPCHK(c3::launch_bin_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
                                         d_dtype == TOD_F64, ncorr_out, gain, sigma0, ctx->trig64.p, acc));
         }
@@ -870,9 +911,22 @@ tod_status tod_enable_timing(tod_ctx ctx, int enable) {
     return TOD_OK;
 }
 
-tod_status tod_phase_ms(tod_ctx ctx, double *ms6) {
-    if (!ctx || !ms6) return TOD_EINVAL;
-    for (int i = 0; i < 6; ++i) ms6[i] = ctx->phase_ms[i];
+tod_status tod_kernel_times(tod_ctx ctx, double *total_ms, int32_t *launches) {
+    if (!ctx || !total_ms || !launches) return TOD_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < K_NKERNEL; ++i) {
+        total_ms[i] = 0;
+        launches[i] = 0;
+    }
+    for (auto &r : ctx->recs) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        total_ms[r.kid] += ms;
+        launches[r.kid] += 1;
+        ctx->ev_pool.push_back(r.a);
+        ctx->ev_pool.push_back(r.b);
+    }
+    ctx->recs.clear();
     return TOD_OK;
 }
 
@@ -939,10 +993,11 @@ tod_status time_fft_choice(tod_ctx ctx, int mixed, int64_t M, const c3tune::FftC
     a.sigma0 = (const double *)prm.p;
     a.fknee = (const double *)prm.p + K;
     a.alpha = (const double *)prm.p + 2 * K;
-    HIPCHK(c3::launch_fft_ncorr(ctx->stream, mixed, a));
+    for (int pass = 0; pass < 3; ++pass) HIPCHK(c3::launch_fft_pass(ctx->stream, mixed, a, pass));
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     const int reps = 3;
-    for (int i = 0; i < reps; ++i) HIPCHK(c3::launch_fft_ncorr(ctx->stream, mixed, a));
+    for (int i = 0; i < reps; ++i)
+        for (int pass = 0; pass < 3; ++pass) HIPCHK(c3::launch_fft_pass(ctx->stream, mixed, a, pass));
     HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[3]));
     float ms = 0;

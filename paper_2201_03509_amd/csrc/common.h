@@ -14,7 +14,7 @@
 #define C3_ERR_PSI 8u        // decoded psi bin outside [0, npsi)
 
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
     T x, y;
 };
 
@@ -107,12 +107,15 @@ struct DecodeTask {
 // Implemented in the .hip files; all return hipError_t of the launch.
 namespace c3 {
 
-enum DecodeMode { DEC_POINTING = 0, DEC_RESIDUAL = 1 };
-
 hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
                          const DecodeTask *tasks, int ntask, int32_t *pix_out, uint16_t *psi_out,
-                         int mode, int prec_mixed, const void *d, int d_f64, const void *maps,
-                         const double *gain, const void *trig, void *r_out, uint32_t *err);
+                         uint32_t *err);
+
+// r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs)
+hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                              int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
+                              int d_f64, const void *maps, const double *gain, const void *trig,
+                              void *r_out);
 
 // FFT-based passes.  mode: 0 = n_corr draw, 1 = Whittle sums (chi^2), 2 = chi^2 adjoint sums
 struct FftArgs {
@@ -136,8 +139,9 @@ struct FftArgs {
     int mode;
     double *whittle;            // mode 1/2: per-segment sums [nseg][4]
 };
-hipError_t launch_fft_ncorr(hipStream_t st, int prec_mixed, const FftArgs &a);
-hipError_t launch_fft_whittle(hipStream_t st, int prec_mixed, const FftArgs &a);
+// pass 0: forward column FFTs; 1: row pass (mode 0 n_corr draw, 1 Whittle sums);
+// 2: inverse column FFTs
+hipError_t launch_fft_pass(hipStream_t st, int prec_mixed, const FftArgs &a, int pass);
 
 hipError_t launch_project_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                                 int ntile, const int32_t *pix, const uint16_t *psi,

@@ -19,6 +19,16 @@
 namespace {
 using c3::FftArgs;
 
+// explicit LDS / global address spaces for the out-of-line stage functions
+// (only meaningful in the device compilation pass)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LDSP __attribute__((address_space(3)))
+#define GLBP __attribute__((address_space(1)))
+#else
+#define LDSP
+#define GLBP
+#endif
+
 template <typename T>
 struct Lim;
 template <>
@@ -82,16 +92,18 @@ __device__ __forceinline__ void dft(cx<T> *v) {
     }
 }
 
-// One Stockham stage of radix R on B transforms of length L in LDS; element i
-// of transform b lives at buf[i*si + b*sb].  B = 1 << lb.
+// One Stockham stage of radix R on B = 1 << lb transforms of length L in LDS;
+// element i of transform b lives at buf[(i << lsi) + b].
 template <int R, int DIR, typename T>
-__device__ __attribute__((noinline)) void fft_stage(cx<T> *buf, int L, int lb, int si, int sb, int Ns,
-                          const cx<T> *__restrict__ tw) {
+__device__ __attribute__((noinline)) void fft_stage(LDSP cx<T> *buf, int L, int lb, int lsi, int Ns,
+                                                    const GLBP cx<T> *__restrict__ tw) {
     constexpr int MB = maxb<T, R>();
     const int LR = L / R;
     const int nb = LR << lb;
     const int bm = (1 << lb) - 1;
     const int step = L / (Ns * R);
+    const int in_stride = LR << lsi;  // between the R inputs of a butterfly
+    const int out_stride = Ns << lsi; // between its R outputs
     const uint32_t magic = 0xFFFFFFFFu / (uint32_t)Ns + 1u;  // j / Ns == umulhi(j, magic)
     cx<T> v[MB][R];
 #pragma unroll
@@ -99,8 +111,9 @@ __device__ __attribute__((noinline)) void fft_stage(cx<T> *buf, int L, int lb, i
         const int q = threadIdx.x + m * C3_NT;
         if (q < nb) {
             const int b = q & bm, j = q >> lb;
+            const int base = (j << lsi) + b;
 #pragma unroll
-            for (int t = 0; t < R; ++t) v[m][t] = buf[(j + t * LR) * si + b * sb];
+            for (int t = 0; t < R; ++t) v[m][t] = buf[base + t * in_stride];
         }
     }
     __syncthreads();
@@ -112,35 +125,38 @@ __device__ __attribute__((noinline)) void fft_stage(cx<T> *buf, int L, int lb, i
             const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
             const int k = j - jd * Ns;
             if (Ns > 1) {
+                const int ks = k * step;
 #pragma unroll
                 for (int t = 1; t < R; ++t) {
-                    cx<T> w = tw[k * t * step];
+                    const cx<T> w = tw[t * ks];
                     v[m][t] = DIR < 0 ? cmul(v[m][t], w) : cmulc(v[m][t], w);
                 }
             }
             dft<R, DIR>(v[m]);
-            const int o = jd * Ns * R + k;
+            const int base = (((j - k) * R + k) << lsi) + b;
 #pragma unroll
-            for (int t = 0; t < R; ++t) buf[(o + t * Ns) * si + b * sb] = v[m][t];
+            for (int t = 0; t < R; ++t) buf[base + t * out_stride] = v[m][t];
         }
     }
     __syncthreads();
 }
 
 template <int DIR, typename T>
-__device__ void lds_fft(cx<T> *buf, int L, int lb, int si, int sb, const int8_t *rad, int nrad,
-                        const cx<T> *tw) {
+__device__ void lds_fft(cx<T> *buf_, int L, int lb, int lsi, const int8_t *rad, int nrad,
+                        const cx<T> *tw_) {
+    LDSP cx<T> *buf = (LDSP cx<T> *)buf_;
+    const GLBP cx<T> *tw = (const GLBP cx<T> *)tw_;
     int Ns = 1;
     for (int s = 0; s < nrad; ++s) {
         const int R = rad[s];
         if (R == 4)
-            fft_stage<4, DIR>(buf, L, lb, si, sb, Ns, tw);
+            fft_stage<4, DIR>(buf, L, lb, lsi, Ns, tw);
         else if (R == 2)
-            fft_stage<2, DIR>(buf, L, lb, si, sb, Ns, tw);
+            fft_stage<2, DIR>(buf, L, lb, lsi, Ns, tw);
         else if (R == 3)
-            fft_stage<3, DIR>(buf, L, lb, si, sb, Ns, tw);
+            fft_stage<3, DIR>(buf, L, lb, lsi, Ns, tw);
         else
-            fft_stage<5, DIR>(buf, L, lb, si, sb, Ns, tw);
+            fft_stage<5, DIR>(buf, L, lb, lsi, Ns, tw);
         Ns *= R;
     }
 }
@@ -192,7 +208,7 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
         buf[i] = v;
     }
     __syncthreads();
-    lds_fft<-1>(buf, M1, lb, B, 1, p.r1, p.nr1, pool + p.tw1);
+    lds_fft<-1>(buf, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
         const int k1 = i >> lb, c = i & (B - 1);
         const int j2 = col0 + c;
@@ -222,7 +238,7 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
         buf[i] = j2 < M2 ? Y[(int64_t)k1 * M2 + j2] : cx<T>{0, 0};
     }
     __syncthreads();
-    lds_fft<1>(buf, M1, lb, B, 1, p.r1, p.nr1, pool + p.tw1);
+    lds_fft<1>(buf, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
     T *out = (T *)a.out + sg.samp_off;
     const int n = sg.n;
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
@@ -365,7 +381,7 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
         if (two) buf[i * si + 1] = Y[(int64_t)kb * M2 + i];
     }
     __syncthreads();
-    lds_fft<-1>(buf, M2, lb, si, 1, p.r2, p.nr2, pool + p.tw2);
+    lds_fft<-1>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
 
     ModeCtx mc;
     {
@@ -443,7 +459,7 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
     }
     if (MODE == 0) {
         __syncthreads();
-        lds_fft<1>(buf, M2, lb, si, 1, p.r2, p.nr2, pool + p.tw2);
+        lds_fft<1>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
         for (int i = threadIdx.x; i < M2; i += C3_NT) {
             // times w_M^(-j2 k1) = conj(w_N^(2 j2 k1))
             Y[(int64_t)ka * M2 + i] = cmulc(buf[i * si], twN(pool, p, 2 * (int64_t)i * ka));
@@ -470,30 +486,21 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
 
 namespace c3 {
 
-hipError_t launch_fft_ncorr(hipStream_t st, int mixed, const FftArgs &a) {
-    if (a.ncol_tasks <= 0) return hipSuccess;
+hipError_t launch_fft_pass(hipStream_t st, int mixed, const FftArgs &a, int pass) {
     dim3 b(C3_NT);
+    if (pass == 1 && a.nrow_tasks <= 0) return hipSuccess;
+    if (pass != 1 && a.ncol_tasks <= 0) return hipSuccess;
+    const dim3 gc(a.ncol_tasks), gr(a.nrow_tasks);
     if (mixed) {
-        hipLaunchKernelGGL(k_col_fwd<float>, dim3(a.ncol_tasks), b, 0, st, a);
-        hipLaunchKernelGGL((k_row<float, 0>), dim3(a.nrow_tasks), b, 0, st, a);
-        hipLaunchKernelGGL(k_col_inv<float>, dim3(a.ncol_tasks), b, 0, st, a);
+        if (pass == 0) hipLaunchKernelGGL(k_col_fwd<float>, gc, b, 0, st, a);
+        else if (pass == 2) hipLaunchKernelGGL(k_col_inv<float>, gc, b, 0, st, a);
+        else if (a.mode == 0) hipLaunchKernelGGL((k_row<float, 0>), gr, b, 0, st, a);
+        else hipLaunchKernelGGL((k_row<float, 1>), gr, b, 0, st, a);
     } else {
-        hipLaunchKernelGGL(k_col_fwd<double>, dim3(a.ncol_tasks), b, 0, st, a);
-        hipLaunchKernelGGL((k_row<double, 0>), dim3(a.nrow_tasks), b, 0, st, a);
-        hipLaunchKernelGGL(k_col_inv<double>, dim3(a.ncol_tasks), b, 0, st, a);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_fft_whittle(hipStream_t st, int mixed, const FftArgs &a) {
-    if (a.ncol_tasks <= 0) return hipSuccess;
-    dim3 b(C3_NT);
-    if (mixed) {
-        hipLaunchKernelGGL(k_col_fwd<float>, dim3(a.ncol_tasks), b, 0, st, a);
-        hipLaunchKernelGGL((k_row<float, 1>), dim3(a.nrow_tasks), b, 0, st, a);
-    } else {
-        hipLaunchKernelGGL(k_col_fwd<double>, dim3(a.ncol_tasks), b, 0, st, a);
-        hipLaunchKernelGGL((k_row<double, 1>), dim3(a.nrow_tasks), b, 0, st, a);
+        if (pass == 0) hipLaunchKernelGGL(k_col_fwd<double>, gc, b, 0, st, a);
+        else if (pass == 2) hipLaunchKernelGGL(k_col_inv<double>, gc, b, 0, st, a);
+        else if (a.mode == 0) hipLaunchKernelGGL((k_row<double, 0>), gr, b, 0, st, a);
+        else hipLaunchKernelGGL((k_row<double, 1>), gr, b, 0, st, a);
     }
     return hipGetLastError();
 }

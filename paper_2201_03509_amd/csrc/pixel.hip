@@ -27,8 +27,8 @@ __global__ __launch_bounds__(C3_NT) void k_project(LayoutDev Ld, const int4 *__r
                                                    const double *__restrict__ gain,
                                                    const cx<T> *__restrict__ trig,
                                                    T *__restrict__ s_out) {
-    __shared__ cx<T> tr[4096];
-    for (int b = threadIdx.x; b < 4096; b += C3_NT) tr[b] = trig[b];
+    __shared__ cx<T> tr[2048];
+    for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
     const int4 tl = tiles[blockIdx.x];
     const int seg = tl.x;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(C3_NT) void k_project(LayoutDev Ld, const int4 *__r
             continue;
         }
         const int64_t gp = poff + p;
-        const cx<T> cs = tr[psi[i] & 4095];
+        const cx<T> cs = tr[psi[i] & 2047];
         s_out[i] = g * (maps[gp] + maps[npt + gp] * cs.x + maps[2 * npt + gp] * cs.y);
     }
 }
@@ -67,11 +67,12 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
                                                const double *__restrict__ sigma0,
                                                const cx<double> *__restrict__ trig,
                                                double *__restrict__ acc) {
-    __shared__ cx<double> tr[4096];
+    // cos/sin 2psi repeat every 2048 psi bins
+    __shared__ cx<double> tr[2048];
     const int4 tl = tiles[blockIdx.x];
     const int seg = tl.x;
     if (Ld.seg_accept && !Ld.seg_accept[seg]) return;  // uniform over the block
-    for (int b = threadIdx.x; b < 4096; b += C3_NT) tr[b] = trig[b];
+    for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
     const int S = tl.z;
     const int phi = tl.y + threadIdx.x;
@@ -84,23 +85,21 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     const double s2 = sigma0[seg];
     const double w = g / (s2 * s2);
     const double gw = g * w;
+    const float *df = (const float *)d;
+    const double *dd = (const double *)d;
     double a[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) a[j] = 0.0;
     int cur = -1;
-    for (int t = phi; t < n; t += S) {
-        const int64_t i = s0 + t;
-        const int p = pix[i];
-        if ((uint32_t)p >= npix) continue;  // out-of-range pixels are not binned
-        const cx<double> cs = tr[psi[i] & 4095];
-        double v = d_f64 ? ((const double *)d)[i] : (double)((const float *)d)[i];
-        if (ncorr) v -= (double)ncorr[i];
+    auto step = [&](int p, int b, double v) {
+        if ((uint32_t)p >= npix) return;  // out-of-range pixels are not binned
         if (p != cur) {
             if (cur >= 0) flush_acc(acc, poff + cur, a);
 #pragma unroll
             for (int j = 0; j < 10; ++j) a[j] = 0.0;
             cur = p;
         }
+        const cx<double> cs = tr[b & 2047];
         const double wv = w * v;
         a[0] += wv;
         a[1] += wv * cs.x;
@@ -112,8 +111,94 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         a[7] += gw * cs.x * cs.y;
         a[8] += gw * cs.y * cs.y;
         a[9] += 1.0;
+    };
+    int t = phi;
+    for (; t + 3 * S < n; t += 4 * S) {
+        int p[4], b[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = s0 + t + u * S;
+            p[u] = pix[i];
+            b[u] = psi[i];
+            v[u] = d_f64 ? dd[i] : (double)df[i];
+            if (ncorr) v[u] -= (double)ncorr[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) step(p[u], b[u], v[u]);
+    }
+    for (; t < n; t += S) {
+        const int64_t i = s0 + t;
+        double v = d_f64 ? dd[i] : (double)df[i];
+        if (ncorr) v -= (double)ncorr[i];
+        step(pix[i], psi[i], v);
     }
     if (cur >= 0) flush_acc(acc, poff + cur, a);
+}
+
+// ---------------------------------------------------------------- residual
+// r = d - g (T + Q cos 2psi + U sin 2psi) on strided tiles; the thread keeps
+// the map values of its current pixel in registers across revisits.
+template <typename T>
+__global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__restrict__ tiles,
+                                                 const int32_t *__restrict__ pix,
+                                                 const uint16_t *__restrict__ psi, const void *d,
+                                                 int d_f64, const T *__restrict__ maps,
+                                                 const double *__restrict__ gain,
+                                                 const cx<T> *__restrict__ trig,
+                                                 T *__restrict__ r_out) {
+    __shared__ cx<T> tr[2048];
+    const int4 tl = tiles[blockIdx.x];
+    const int seg = tl.x;
+    for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
+    __syncthreads();
+    const int S = tl.z;
+    const int phi = tl.y + threadIdx.x;
+    if ((int)threadIdx.x >= tl.w) return;
+    const int64_t s0 = Ld.seg_off[seg];
+    const int n = (int)(Ld.seg_off[seg + 1] - s0);
+    const int band = Ld.seg_band[seg];
+    const int64_t poff = Ld.band[band].pix_off;
+    const uint32_t npix = (uint32_t)Ld.band[band].npix;
+    const int64_t npt = Ld.npix_total;
+    const T g = (T)gain[seg];
+    const float *df = (const float *)d;
+    const double *dd = (const double *)d;
+    int cur = -1;
+    T mT = 0, mQ = 0, mU = 0;
+    auto step = [&](int64_t i, int p, int b, T dv) {
+        if (p != cur) {
+            cur = p;
+            if ((uint32_t)p < npix) {
+                const int64_t gp = poff + p;
+                mT = maps[gp];
+                mQ = maps[npt + gp];
+                mU = maps[2 * npt + gp];
+            } else {
+                mT = mQ = mU = (T)NAN;
+            }
+        }
+        const cx<T> cs = tr[b & 2047];
+        r_out[i] = dv - g * (mT + mQ * cs.x + mU * cs.y);
+    };
+    int t = phi;
+    for (; t + 3 * S < n; t += 4 * S) {
+        int p[4], b[4];
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = s0 + t + u * S;
+            p[u] = pix[i];
+            b[u] = psi[i];
+            v[u] = d_f64 ? (T)dd[i] : (T)df[i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], v[u]);
+    }
+    for (; t < n; t += S) {
+        const int64_t i = s0 + t;
+        step(i, pix[i], psi[i], d_f64 ? (T)dd[i] : (T)df[i]);
+    }
 }
 
 // ---------------------------------------------------------------- solve
@@ -222,12 +307,12 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     const void *maps, const double *__restrict__ gain, const double *__restrict__ sigma0,
     const cx<double> *__restrict__ trig, double *__restrict__ seg_sums,
     double *__restrict__ gmap, double gscale) {
-    __shared__ cx<double> tr[4096];
+    __shared__ cx<double> tr[2048];
     __shared__ double red[3][C3_NT / 64];
     const int4 tl = tiles[blockIdx.x];
     const int seg = tl.x;
     if (Ld.seg_accept && !Ld.seg_accept[seg]) return;
-    for (int b = threadIdx.x; b < 4096; b += C3_NT) tr[b] = trig[b];
+    for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
     const int S = tl.z;
     const int phi = tl.y + threadIdx.x;
@@ -249,7 +334,7 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
         const int p = pix[i];
         if ((uint32_t)p >= npix) continue;
         const int64_t gp = poff + p;
-        const cx<double> cs = tr[psi[i] & 4095];
+        const cx<double> cs = tr[psi[i] & 2047];
         double T, Q, U, nc;
         if (mixed) {
             const float *m = (const float *)maps;
@@ -355,6 +440,21 @@ hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const
         hipLaunchKernelGGL(k_bin<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
                            d_f64, (const double *)ncorr, gain, sigma0,
                            (const cx<double> *)trig64, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
+                              int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
+                              int d_f64, const void *maps, const double *gain, const void *trig,
+                              void *r_out) {
+    if (ntile <= 0) return hipSuccess;
+    if (mixed)
+        hipLaunchKernelGGL(k_resid<float>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
+                           d_f64, (const float *)maps, gain, (const cx<float> *)trig, (float *)r_out);
+    else
+        hipLaunchKernelGGL(k_resid<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
+                           d_f64, (const double *)maps, gain, (const cx<double> *)trig,
+                           (double *)r_out);
     return hipGetLastError();
 }
 

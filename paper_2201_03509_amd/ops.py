@@ -241,10 +241,15 @@ class Context:
     def enable_timing(self, on=True):
         self._chk(self.lib.tod_enable_timing(self.h, int(bool(on))))
 
-    def phase_ms(self):
-        a = (ctypes.c_double * 6)()
-        self._chk(self.lib.tod_phase_ms(self.h, a))
-        return list(a)
+    KERNELS = ["decode", "project", "fft_col_fwd", "fft_row", "fft_col_inv", "bin", "solve",
+               "chisq_time"]
+
+    def kernel_times(self):
+        """{kernel: (total_ms, launches)} since the previous read."""
+        t = (ctypes.c_double * 8)()
+        n = (ctypes.c_int32 * 8)()
+        self._chk(self.lib.tod_kernel_times(self.h, t, n))
+        return {k: (t[i], n[i]) for i, k in enumerate(self.KERNELS)}
 
 
 def new_outputs(tod, prec):

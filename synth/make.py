@@ -216,10 +216,19 @@ def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None)
               alpha=alpha_det, keep_truth=keep_truth)
     if workers is None:
         workers = min(16, os.cpu_count() or 1) if len(jobs) > 8 else 1
+    import sys
+    import time
+    t0 = time.time()
+    verbose = len(jobs) >= 100
     if workers > 1:
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
-            res = pool.map(_scan_worker, jobs, chunksize=1)
+            res = []
+            for r in pool.imap(_scan_worker, jobs, chunksize=1):
+                res.append(r)
+                if verbose and len(res) % 25 == 0:
+                    print("  generated %d/%d scans (%.0fs)" % (len(res), len(jobs), time.time() - t0),
+                          file=sys.stderr, flush=True)
     else:
         res = [_scan_worker(j) for j in jobs]
     _G.clear()
@@ -280,3 +289,60 @@ def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None)
 def seed32(k):
     """Sampler seed of a configuration."""
     return (0x22013509 ^ int(k)) & 0xFFFFFFFF
+
+
+_SCALARS = ("config", "nseg", "nband", "ndet", "nsamp", "npix_total")
+
+
+def save(ts, path):
+    """Write a TOD set as .npy files plus a small JSON of scalars."""
+    import json
+    os.makedirs(path, exist_ok=True)
+    meta = {k: int(getattr(ts, k)) for k in _SCALARS}
+    meta["cfg"] = [ts.cfg.index, ts.cfg.nscan, list(ts.cfg.length)]
+    meta["chunk_len"] = ts.pix_huff.chunk_len
+    for k, v in vars(ts).items():
+        if isinstance(v, np.ndarray):
+            np.save(os.path.join(path, k + ".npy"), v)
+    for name in ("pix_huff", "psi_huff"):
+        for k, v in vars(getattr(ts, name)).items():
+            if isinstance(v, np.ndarray):
+                np.save(os.path.join(path, name + "." + k + ".npy"), v)
+    with open(os.path.join(path, "meta.json"), "w") as f:
+        json.dump(meta, f)
+
+
+def load(path):
+    import json
+    meta = json.load(open(os.path.join(path, "meta.json")))
+    ts = TodSet()
+    for k in _SCALARS:
+        setattr(ts, k, meta[k])
+    idx, nscan, length = meta["cfg"]
+    ts.cfg = cfgmod.get(idx).scaled(nscan=nscan, length=length)
+    hs = {"pix_huff": HuffStream(meta["chunk_len"]), "psi_huff": HuffStream(meta["chunk_len"])}
+    for f in sorted(os.listdir(path)):
+        if not f.endswith(".npy"):
+            continue
+        arr = np.load(os.path.join(path, f))
+        key = f[:-4]
+        if "." in key:
+            a, b = key.split(".", 1)
+            setattr(hs[a], b, arr)
+        else:
+            setattr(ts, key, arr)
+    ts.pix_huff, ts.psi_huff = hs["pix_huff"], hs["psi_huff"]
+    return ts
+
+
+def make_cached(k, cache_dir=None, **kw):
+    """make(), reusing a copy saved under cache_dir when one exists."""
+    if not cache_dir:
+        return make(k, **kw)
+    tag = "c%d_n%s_l%s" % (k, kw.get("nscan"), "_".join(map(str, kw.get("length") or [])))
+    path = os.path.join(cache_dir, tag)
+    if os.path.exists(os.path.join(path, "meta.json")):
+        return load(path)
+    ts = make(k, **kw)
+    save(ts, path)
+    return ts
