@@ -82,6 +82,7 @@ struct Plan {
     std::map<int64_t, int> plan_of_M;
     DevBuf segs, plans, twpool, col_tasks, row_tasks, fsamp;
     int ncol = 0, nrow = 0;
+    int col_lds = 0, row_lds = 0;         // dynamic LDS bytes per FFT pass
     int64_t work_elems = 0;
     DevBuf sample_tiles;
     int nsample_tiles = 0;
@@ -239,7 +240,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     auto P = std::make_unique<Plan>();
     P->key = key;
     P->mixed = mixed;
-    const int S = mixed ? 8192 : 4096;  // LDS complex capacity per block
+    const int S = mixed ? 4096 : 2048;  // complex elements per LDS buffer (two buffers per block)
     const int nseg = L->nseg;
     P->h_segs.resize(nseg);
     Pool pool;
@@ -304,6 +305,11 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     }
     P->ncol = (int)col.size();
     P->nrow = (int)row.size();
+    const int esz = mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
+    for (const FftPlan &fp : P->h_plans) {
+        P->col_lds = std::max(P->col_lds, 2 * fp.M1 * fp.B * esz);  // two ping-pong buffers
+        P->row_lds = std::max(P->row_lds, 4 * fp.M2 * esz);
+    }
     std::vector<double> fs(L->nband);
     for (int b = 0; b < L->nband; ++b) fs[b] = L->bands[b].fsamp;
     // sample tiles (projection): 4096 samples per block
@@ -461,6 +467,8 @@ c3::FftArgs fft_args(tod_ctx ctx, Plan *P, const tod_layout *L) {
     a.nrow_tasks = P->nrow;
     a.fsamp_band = (const double *)P->fsamp.p;
     a.seed_iter = ctx->d_seed_iter;
+    a.col_lds = P->col_lds;
+    a.row_lds = P->row_lds;
     (void)L;
     return a;
 }
@@ -1034,7 +1042,7 @@ tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
     if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
     if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
     const int mixed = prec == TOD_MIXED;
-    const int S = mixed ? 8192 : 4096;
+    const int S = mixed ? 4096 : 2048;
     if (cache_path) {
         if ((r = tod_load_tuning(ctx, cache_path)) != TOD_OK) return r;
     }

@@ -138,6 +138,7 @@ struct FftArgs {
     int mean_only;
     int mode;
     double *whittle;            // mode 1/2: per-segment sums [nseg][4]
+    int col_lds, row_lds;       // dynamic LDS bytes of the column and row passes
 };
 // pass 0: forward column FFTs; 1: row pass (mode 0 n_corr draw, 1 Whittle sums);
 // 2: inverse column FFTs

@@ -29,22 +29,6 @@ using c3::FftArgs;
 #define GLBP
 #endif
 
-template <typename T>
-struct Lim;
-template <>
-struct Lim<float> {
-    static constexpr int S = 8192;  // complex elements a block may hold in LDS
-};
-template <>
-struct Lim<double> {
-    static constexpr int S = 4096;
-};
-
-template <typename T, int R>
-constexpr int maxb() {
-    return (Lim<T>::S / R + C3_NT - 1) / C3_NT;
-}
-
 // ---------------------------------------------------------------- DFT kernels
 template <int DIR, typename T>
 __device__ __forceinline__ cx<T> mul_i(cx<T> a) {  // a * (DIR * i)
@@ -92,73 +76,70 @@ __device__ __forceinline__ void dft(cx<T> *v) {
     }
 }
 
-// One Stockham stage of radix R on B = 1 << lb transforms of length L in LDS;
-// element i of transform b lives at buf[(i << lsi) + b].
+// One Stockham stage of radix R on B = 1 << lb transforms of length L, from
+// src to dst in LDS; element i of transform b lives at [(i << lsi) + b].
 template <int R, int DIR, typename T>
-__device__ __attribute__((noinline)) void fft_stage(LDSP cx<T> *buf, int L, int lb, int lsi, int Ns,
+__device__ __attribute__((noinline)) void fft_stage(const LDSP cx<T> *src, LDSP cx<T> *dst, int L,
+                                                    int lb, int lsi, int Ns,
                                                     const GLBP cx<T> *__restrict__ tw) {
-    constexpr int MB = maxb<T, R>();
     const int LR = L / R;
     const int nb = LR << lb;
     const int bm = (1 << lb) - 1;
     const int step = L / (Ns * R);
-    const int in_stride = LR << lsi;  // between the R inputs of a butterfly
-    const int out_stride = Ns << lsi; // between its R outputs
+    const int in_stride = LR << lsi;   // between the R inputs of a butterfly
+    const int out_stride = Ns << lsi;  // between its R outputs
     const uint32_t magic = 0xFFFFFFFFu / (uint32_t)Ns + 1u;  // j / Ns == umulhi(j, magic)
-    cx<T> v[MB][R];
+#pragma unroll 2
+    for (int q = threadIdx.x; q < nb; q += C3_NT) {
+        const int b = q & bm, j = q >> lb;
+        const int ib = (j << lsi) + b;
+        cx<T> v[R];
 #pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        const int q = threadIdx.x + m * C3_NT;
-        if (q < nb) {
-            const int b = q & bm, j = q >> lb;
-            const int base = (j << lsi) + b;
+        for (int t = 0; t < R; ++t) v[t] = src[ib + t * in_stride];
+        const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
+        const int k = j - jd * Ns;
+        if (Ns > 1) {
+            const int ks = k * step;
 #pragma unroll
-            for (int t = 0; t < R; ++t) v[m][t] = buf[base + t * in_stride];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        const int q = threadIdx.x + m * C3_NT;
-        if (q < nb) {
-            const int b = q & bm, j = q >> lb;
-            const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
-            const int k = j - jd * Ns;
-            if (Ns > 1) {
-                const int ks = k * step;
-#pragma unroll
-                for (int t = 1; t < R; ++t) {
-                    const cx<T> w = tw[t * ks];
-                    v[m][t] = DIR < 0 ? cmul(v[m][t], w) : cmulc(v[m][t], w);
-                }
+            for (int t = 1; t < R; ++t) {
+                const cx<T> w = tw[t * ks];
+                v[t] = DIR < 0 ? cmul(v[t], w) : cmulc(v[t], w);
             }
-            dft<R, DIR>(v[m]);
-            const int base = (((j - k) * R + k) << lsi) + b;
-#pragma unroll
-            for (int t = 0; t < R; ++t) buf[base + t * out_stride] = v[m][t];
         }
+        dft<R, DIR>(v);
+        const int ob = (((j - k) * R + k) << lsi) + b;
+#pragma unroll
+        for (int t = 0; t < R; ++t) dst[ob + t * out_stride] = v[t];
     }
     __syncthreads();
 }
 
+// In-LDS Stockham FFT between two buffers of the same size; returns the one
+// holding the result.
 template <int DIR, typename T>
-__device__ void lds_fft(cx<T> *buf_, int L, int lb, int lsi, const int8_t *rad, int nrad,
-                        const cx<T> *tw_) {
-    LDSP cx<T> *buf = (LDSP cx<T> *)buf_;
+__device__ cx<T> *lds_fft(cx<T> *b0, cx<T> *b1, int L, int lb, int lsi, const int8_t *rad, int nrad,
+                          const cx<T> *tw_) {
     const GLBP cx<T> *tw = (const GLBP cx<T> *)tw_;
     int Ns = 1;
+    cx<T> *src = b0, *dst = b1;
     for (int s = 0; s < nrad; ++s) {
         const int R = rad[s];
+        const LDSP cx<T> *ls = (const LDSP cx<T> *)src;
+        LDSP cx<T> *ld = (LDSP cx<T> *)dst;
         if (R == 4)
-            fft_stage<4, DIR>(buf, L, lb, lsi, Ns, tw);
+            fft_stage<4, DIR>(ls, ld, L, lb, lsi, Ns, tw);
         else if (R == 2)
-            fft_stage<2, DIR>(buf, L, lb, lsi, Ns, tw);
+            fft_stage<2, DIR>(ls, ld, L, lb, lsi, Ns, tw);
         else if (R == 3)
-            fft_stage<3, DIR>(buf, L, lb, lsi, Ns, tw);
+            fft_stage<3, DIR>(ls, ld, L, lb, lsi, Ns, tw);
         else
-            fft_stage<5, DIR>(buf, L, lb, lsi, Ns, tw);
+            fft_stage<5, DIR>(ls, ld, L, lb, lsi, Ns, tw);
         Ns *= R;
+        cx<T> *x = src;
+        src = dst;
+        dst = x;
     }
+    return src;
 }
 
 // w_N^m for 0 <= m <= N from the two-level table
@@ -184,9 +165,11 @@ __device__ __forceinline__ T ext_at(const FftArgs &a, int64_t s0, int n, int64_t
 }
 
 // ------------------------------------------------------------- pass 1
+extern __shared__ __attribute__((aligned(16))) unsigned char c3_dyn_lds[];
+
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
-    __shared__ cx<T> buf[Lim<T>::S];
+    cx<T> *buf = (cx<T> *)c3_dyn_lds;  // 2 x M1 * B elements (sized per launch)
     const int2 task = a.col_tasks[blockIdx.x];
     const SegInfo sg = a.segs[task.x];
     const FftPlan &p = a.plans[sg.plan];
@@ -208,13 +191,13 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
         buf[i] = v;
     }
     __syncthreads();
-    lds_fft<-1>(buf, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
+    const cx<T> *res = lds_fft<-1>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
         const int k1 = i >> lb, c = i & (B - 1);
         const int j2 = col0 + c;
         if (j2 < M2) {
             const cx<T> w = twN(pool, p, 2 * (int64_t)j2 * k1);  // w_M^(j2 k1)
-            Y[(int64_t)k1 * M2 + j2] = cmul(buf[i], w);
+            Y[(int64_t)k1 * M2 + j2] = cmul(res[i], w);
         }
     }
 }
@@ -222,7 +205,7 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
 // ------------------------------------------------------------- pass 3
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
-    __shared__ cx<T> buf[Lim<T>::S];
+    cx<T> *buf = (cx<T> *)c3_dyn_lds;
     const int2 task = a.col_tasks[blockIdx.x];
     const SegInfo sg = a.segs[task.x];
     const FftPlan &p = a.plans[sg.plan];
@@ -238,7 +221,7 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
         buf[i] = j2 < M2 ? Y[(int64_t)k1 * M2 + j2] : cx<T>{0, 0};
     }
     __syncthreads();
-    lds_fft<1>(buf, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
+    const cx<T> *res = lds_fft<1>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
     T *out = (T *)a.out + sg.samp_off;
     const int n = sg.n;
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
@@ -246,7 +229,7 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
         const int j2 = col0 + c;
         if (j2 < M2) {
             const int64_t t = 2 * ((int64_t)M2 * j1 + j2);
-            const cx<T> v = buf[i];
+            const cx<T> v = res[i];
             if (t < n) out[t] = v.x;
             if (t + 1 < n) out[t + 1] = v.y;
         }
@@ -266,10 +249,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
     return c;
 }
 
-// -2 ln u for u = (x + 1/2) 2^-32, accurate on both sides of 1/2
+// -2 ln u for u = (x + 1/2) 2^-32 with the hardware log2 (FP32 path)
 __device__ __forceinline__ float m2log_u(uint32_t x) {
-    if (x < 0x80000000u) return -2.0f * logf(((float)x + 0.5f) * 2.3283064365386963e-10f);
-    return -2.0f * log1pf(-(((float)(~x) + 0.5f) * 2.3283064365386963e-10f));
+    const float u = ((float)x + 0.5f) * 2.3283064365386963e-10f;
+    return -1.3862943611198906f * __builtin_amdgcn_logf(u);  // -2 ln 2 log2(u)
 }
 __device__ __forceinline__ double m2log_u_d(uint32_t x) {
     return -2.0 * log(((double)x + 0.5) * 2.3283064365386963e-10);
@@ -278,10 +261,12 @@ __device__ __forceinline__ double m2log_u_d(uint32_t x) {
 template <typename T>
 __device__ __forceinline__ void normals4(uint4 w, T *z) {
     if constexpr (sizeof(T) == 4) {
-        float r0 = sqrtf(m2log_u(w.x)), r1 = sqrtf(m2log_u(w.z));
-        float s0, c0, s1, c1;
-        sincospif(((float)w.y + 0.5f) * 4.6566128730773926e-10f, &s0, &c0);  // 2 pi u
-        sincospif(((float)w.w + 0.5f) * 4.6566128730773926e-10f, &s1, &c1);
+        const float r0 = __builtin_sqrtf(m2log_u(w.x)), r1 = __builtin_sqrtf(m2log_u(w.z));
+        // hardware sine/cosine take their argument in revolutions: sin(2 pi u)
+        const float u1 = ((float)w.y + 0.5f) * 2.3283064365386963e-10f;
+        const float u3 = ((float)w.w + 0.5f) * 2.3283064365386963e-10f;
+        const float s0 = __builtin_amdgcn_sinf(u1), c0 = __builtin_amdgcn_cosf(u1);
+        const float s1 = __builtin_amdgcn_sinf(u3), c1 = __builtin_amdgcn_cosf(u3);
         z[0] = r0 * c0;
         z[1] = r0 * s0;
         z[2] = r1 * c1;
@@ -299,7 +284,7 @@ __device__ __forceinline__ void normals4(uint4 w, T *z) {
 }
 
 struct ModeCtx {
-    double sigma0, lbase, malpha, fknee_ratio;  // lbase = ln(fsamp / (N fknee)), malpha = -alpha
+    double sigma0, lbase, lbase2, malpha;      // lbase = ln(fsamp / (N fknee)), lbase2 = log2 of it
     double invsqrtN, outscale;                 // 1/sqrt(N), sqrt(N)/M
     uint2 key;
     uint32_t it_lo, it_hi, seed_hi;
@@ -313,12 +298,17 @@ __device__ __forceinline__ cx<T> cr_mode(const ModeCtx &mc, int64_t k, cx<T> E) 
     const T s0 = (T)mc.sigma0;
     T q = 0;
     if (k > 0) {
-        if constexpr (sizeof(T) == 4)
-            q = __expf((float)mc.malpha * (logf((float)k) + (float)mc.lbase));
+        if constexpr (sizeof(T) == 4)  // q = 2^(-alpha log2(f_k / f_knee)), hardware exp2/log2
+            q = __builtin_amdgcn_exp2f((float)mc.malpha *
+                                       (__builtin_amdgcn_logf((float)k) + (float)mc.lbase2));
         else
             q = exp(mc.malpha * (log((double)k) + mc.lbase));
     }
-    const T inv = (T)1 / ((T)1 + q);
+    T inv;
+    if constexpr (sizeof(T) == 4)
+        inv = __builtin_amdgcn_rcpf(1.0f + q);
+    else
+        inv = 1.0 / (1.0 + q);
     cx<T> R = cscale(E, (T)mc.invsqrtN);
     cx<T> out = R;
     if (!mc.mean_only) {
@@ -335,7 +325,7 @@ __device__ __forceinline__ cx<T> cr_mode(const ModeCtx &mc, int64_t k, cx<T> E) 
         }
         T sq;
         if constexpr (sizeof(T) == 4)
-            sq = sqrtf(q);
+            sq = __builtin_sqrtf(q);
         else
             sq = sqrt(q);
         out.x += s0 * (W1.x + sq * W2.x);
@@ -362,7 +352,7 @@ __device__ __forceinline__ void whittle_mode(const ModeCtx &mc, int64_t k, cx<T>
 // ------------------------------------------------------------- pass 2
 template <typename T, int MODE>
 __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
-    __shared__ cx<T> buf[Lim<T>::S];
+    cx<T> *bufs = (cx<T> *)c3_dyn_lds;  // 2 x (2 * M2) elements (sized per launch)
     __shared__ double red[3][C3_NT / 64];
     const int2 task = a.row_tasks[blockIdx.x];
     const int seg = task.x;
@@ -376,12 +366,14 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
     const cx<T> *pool = (const cx<T> *)a.twpool;
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
 
+    const int nel = M2 << two;
     for (int i = threadIdx.x; i < M2; i += C3_NT) {
-        buf[i * si] = Y[(int64_t)ka * M2 + i];
-        if (two) buf[i * si + 1] = Y[(int64_t)kb * M2 + i];
+        bufs[i * si] = Y[(int64_t)ka * M2 + i];
+        if (two) bufs[i * si + 1] = Y[(int64_t)kb * M2 + i];
     }
     __syncthreads();
-    lds_fft<-1>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+    cx<T> *buf = lds_fft<-1>(bufs, bufs + nel, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+    cx<T> *spare = buf == bufs ? bufs + nel : bufs;
 
     ModeCtx mc;
     {
@@ -390,6 +382,7 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
         mc.sigma0 = a.sigma0[seg];
         mc.malpha = -a.alpha[seg];
         mc.lbase = log(fs / (N * a.fknee[seg]));
+        mc.lbase2 = mc.lbase * 1.4426950408889634;
         mc.invsqrtN = 1.0 / sqrt(N);
         mc.outscale = sqrt(N) / M;
         const uint64_t seed = a.seed_iter ? a.seed_iter[0] : 0, it = a.seed_iter ? a.seed_iter[1] : 0;
@@ -459,11 +452,11 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
     }
     if (MODE == 0) {
         __syncthreads();
-        lds_fft<1>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+        const cx<T> *res = lds_fft<1>(buf, spare, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
         for (int i = threadIdx.x; i < M2; i += C3_NT) {
             // times w_M^(-j2 k1) = conj(w_N^(2 j2 k1))
-            Y[(int64_t)ka * M2 + i] = cmulc(buf[i * si], twN(pool, p, 2 * (int64_t)i * ka));
-            if (two) Y[(int64_t)kb * M2 + i] = cmulc(buf[i * si + 1], twN(pool, p, 2 * (int64_t)i * kb));
+            Y[(int64_t)ka * M2 + i] = cmulc(res[i * si], twN(pool, p, 2 * (int64_t)i * ka));
+            if (two) Y[(int64_t)kb * M2 + i] = cmulc(res[i * si + 1], twN(pool, p, 2 * (int64_t)i * kb));
         }
     } else {
         // block reduction of the Whittle sums
@@ -491,16 +484,17 @@ hipError_t launch_fft_pass(hipStream_t st, int mixed, const FftArgs &a, int pass
     if (pass == 1 && a.nrow_tasks <= 0) return hipSuccess;
     if (pass != 1 && a.ncol_tasks <= 0) return hipSuccess;
     const dim3 gc(a.ncol_tasks), gr(a.nrow_tasks);
+    const unsigned lc = (unsigned)a.col_lds, lr = (unsigned)a.row_lds;
     if (mixed) {
-        if (pass == 0) hipLaunchKernelGGL(k_col_fwd<float>, gc, b, 0, st, a);
-        else if (pass == 2) hipLaunchKernelGGL(k_col_inv<float>, gc, b, 0, st, a);
-        else if (a.mode == 0) hipLaunchKernelGGL((k_row<float, 0>), gr, b, 0, st, a);
-        else hipLaunchKernelGGL((k_row<float, 1>), gr, b, 0, st, a);
+        if (pass == 0) hipLaunchKernelGGL(k_col_fwd<float>, gc, b, lc, st, a);
+        else if (pass == 2) hipLaunchKernelGGL(k_col_inv<float>, gc, b, lc, st, a);
+        else if (a.mode == 0) hipLaunchKernelGGL((k_row<float, 0>), gr, b, lr, st, a);
+        else hipLaunchKernelGGL((k_row<float, 1>), gr, b, lr, st, a);
     } else {
-        if (pass == 0) hipLaunchKernelGGL(k_col_fwd<double>, gc, b, 0, st, a);
-        else if (pass == 2) hipLaunchKernelGGL(k_col_inv<double>, gc, b, 0, st, a);
-        else if (a.mode == 0) hipLaunchKernelGGL((k_row<double, 0>), gr, b, 0, st, a);
-        else hipLaunchKernelGGL((k_row<double, 1>), gr, b, 0, st, a);
+        if (pass == 0) hipLaunchKernelGGL(k_col_fwd<double>, gc, b, lc, st, a);
+        else if (pass == 2) hipLaunchKernelGGL(k_col_inv<double>, gc, b, lc, st, a);
+        else if (a.mode == 0) hipLaunchKernelGGL((k_row<double, 0>), gr, b, lr, st, a);
+        else hipLaunchKernelGGL((k_row<double, 1>), gr, b, lr, st, a);
     }
     return hipGetLastError();
 }

@@ -87,17 +87,34 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     const double gw = g * w;
     const float *df = (const float *)d;
     const double *dd = (const double *)d;
-    double a[10];
+    // two register accumulators: the current pixel and the one before it, so a
+    // phase that crosses a pixel edge (and may cross back) rarely flushes early
+    double a[10], o[10];
 #pragma unroll
-    for (int j = 0; j < 10; ++j) a[j] = 0.0;
-    int cur = -1;
+    for (int j = 0; j < 10; ++j) a[j] = o[j] = 0.0;
+    int cur = -1, old = -1;
     auto step = [&](int p, int b, double v) {
         if ((uint32_t)p >= npix) return;  // out-of-range pixels are not binned
         if (p != cur) {
-            if (cur >= 0) flush_acc(acc, poff + cur, a);
+            if (p == old) {
 #pragma unroll
-            for (int j = 0; j < 10; ++j) a[j] = 0.0;
-            cur = p;
+                for (int j = 0; j < 10; ++j) {
+                    const double x = a[j];
+                    a[j] = o[j];
+                    o[j] = x;
+                }
+                old = cur;
+                cur = p;
+            } else {
+                if (old >= 0) flush_acc(acc, poff + old, o);
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    o[j] = a[j];
+                    a[j] = 0.0;
+                }
+                old = cur;
+                cur = p;
+            }
         }
         const cx<double> cs = tr[b & 2047];
         const double wv = w * v;
@@ -134,6 +151,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         step(pix[i], psi[i], v);
     }
     if (cur >= 0) flush_acc(acc, poff + cur, a);
+    if (old >= 0) flush_acc(acc, poff + old, o);
 }
 
 // ---------------------------------------------------------------- residual
