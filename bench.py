@@ -173,6 +173,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cache-dir", default=None, help="reuse generated inputs saved here")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--fft-batch", type=int, default=None,
+                    help="complex elements per FFT batch (0 = all segments at once)")
+    ap.add_argument("--bin-stride", type=int, default=None, help="override the binning stride")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -202,6 +205,8 @@ def main():
             (cpu["value"], cpu["cores"], time.perf_counter() - c0))
     dev = torch.device("cuda:0")
     ctx = ops.Context(0)
+    if args.fft_batch is not None:
+        ctx.set_fft_batch(args.fft_batch)
     tod = ops.DeviceTod(ts, dev)
     maps32 = torch.from_numpy(maps32_h).to(dev)
     maps64 = torch.from_numpy(ts.maps).to(dev)
@@ -215,6 +220,9 @@ def main():
     log("autotuned mixed plans in %.1fs" % (time.perf_counter() - t1))
     tuned = json.load(open(tune_path))
     os.remove(tune_path)
+    if args.bin_stride:
+        for b in range(ts.nband):
+            ctx.set_bin_stride(b, args.bin_stride)
     plans = {}
     for e in tuned.get("fft", []):
         if e["mixed"] == 1:

@@ -247,6 +247,12 @@ tod_status tod_load_tuning(tod_ctx ctx, const char *cache_path);
  * library choose.  Correct for any value; only speed depends on it. */
 tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride);
 
+/* FFT work batching: the column/row passes run batch by batch over groups of
+ * segments whose complex workspace totals at most complex_elems (0 = all
+ * segments in one batch).  Smaller batches keep the intermediate spectrum in
+ * the device's last-level cache between passes; results do not depend on it. */
+tod_status tod_set_fft_batch(tod_ctx ctx, int64_t complex_elems);
+
 /* Per-kernel timing.  While enabled, every launch the context makes outside
  * graph capture is bracketed by HIP events on the context stream (the sweep
  * then runs eagerly).  tod_kernel_times synchronises the stream, returns the

@@ -17,7 +17,8 @@ EXPORTS = [
     "tod_ctx_create", "tod_ctx_destroy", "tod_sync", "tod_clear_error", "tod_last_error",
     "tod_device_error_bits", "decode_pointing", "project_sky", "sample_ncorr", "bin_tod",
     "solve_maps", "tod_chisq", "tod_chisq_backward", "tod_sweep", "tod_autotune",
-    "tod_load_tuning", "tod_set_bin_stride", "tod_enable_timing", "tod_kernel_times",
+    "tod_load_tuning", "tod_set_bin_stride", "tod_set_fft_batch", "tod_enable_timing",
+    "tod_kernel_times",
 ]
 
 
@@ -85,6 +86,7 @@ def load():
         "tod_autotune": [P, LP, ctypes.c_int, P, ctypes.c_char_p],
         "tod_load_tuning": [P, ctypes.c_char_p],
         "tod_set_bin_stride": [P, I32, I32],
+        "tod_set_fft_batch": [P, I64],
         "tod_enable_timing": [P, ctypes.c_int],
         "tod_kernel_times": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],
     }

@@ -82,6 +82,12 @@ struct Plan {
     std::map<int64_t, int> plan_of_M;
     DevBuf segs, plans, twpool, col_tasks, row_tasks, fsamp;
     int ncol = 0, nrow = 0;
+    // FFT batches: contiguous ranges of the column/row task lists whose
+    // segments share one workspace region (sized to stay cache resident)
+    struct Batch {
+        int col0, ncol, row0, nrow;
+    };
+    std::vector<Batch> batches;
     int col_lds = 0, row_lds = 0;         // dynamic LDS bytes per FFT pass
     int64_t work_elems = 0;
     DevBuf sample_tiles;
@@ -106,6 +112,7 @@ struct tod_ctx_s {
     std::map<uint64_t, std::unique_ptr<Plan>> plans;
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
+    int64_t fft_batch = 0;                // complex elements per FFT batch (0: all segments)
     c3tune::Table tuned;                  // FFT choices
     std::string last_error;
     uint32_t last_err_bits = 0;
@@ -286,23 +293,36 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
             it = P->plan_of_M.find(M);
         }
         g.plan = it->second;
-        scr += M;
     }
-    P->work_elems = scr;
     // LPT order: longest FFT first
     P->seg_order.resize(nseg);
     for (int s = 0; s < nseg; ++s) P->seg_order[s] = s;
     std::stable_sort(P->seg_order.begin(), P->seg_order.end(), [&](int a, int b) {
         return P->h_segs[a].n > P->h_segs[b].n;
     });
+    // batches in LPT order; each batch reuses the workspace from offset 0
     std::vector<int2> col, row;
+    Plan::Batch cur{0, 0, 0, 0};
     for (int s : P->seg_order) {
-        const SegInfo &g = P->h_segs[s];
+        SegInfo &g = P->h_segs[s];
         if (g.plan < 0) continue;
         const FftPlan &fp = P->h_plans[g.plan];
+        if (ctx->fft_batch > 0 && scr > 0 && scr + fp.M > ctx->fft_batch) {
+            cur.ncol = (int)col.size() - cur.col0;
+            cur.nrow = (int)row.size() - cur.row0;
+            P->batches.push_back(cur);
+            cur = Plan::Batch{(int)col.size(), 0, (int)row.size(), 0};
+            scr = 0;
+        }
+        g.scr_off = scr;
+        scr += fp.M;
+        P->work_elems = std::max(P->work_elems, scr);
         for (int c0 = 0; c0 < fp.M2; c0 += fp.B) col.push_back(make_int2(s, c0));
         for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) row.push_back(make_int2(s, k1));
     }
+    cur.ncol = (int)col.size() - cur.col0;
+    cur.nrow = (int)row.size() - cur.row0;
+    if (cur.ncol > 0) P->batches.push_back(cur);
     P->ncol = (int)col.size();
     P->nrow = (int)row.size();
     const int esz = mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
@@ -342,6 +362,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
 
 uint64_t layout_key(const tod_layout *L, int mixed, uint64_t salt) {
     uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &salt, sizeof(salt));
     h = fnv(h, &mixed, sizeof(mixed));
     h = fnv(h, &salt, sizeof(salt));
     h = fnv(h, &L->nseg, sizeof(L->nseg));
@@ -352,7 +373,7 @@ uint64_t layout_key(const tod_layout *L, int mixed, uint64_t salt) {
 }
 
 tod_status get_plan(tod_ctx ctx, const tod_layout *L, int mixed, Plan **out) {
-    const uint64_t key = layout_key(L, mixed, ctx->tuned.version);
+    const uint64_t key = layout_key(L, mixed, ctx->tuned.version * 1000003ull + (uint64_t)ctx->fft_batch);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
         *out = it->second.get();
@@ -514,6 +535,23 @@ struct KTimer {
     }
 };
 
+// the FFT passes over every batch: per batch forward columns, rows, inverse columns
+tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::FftArgs &a0, int npass) {
+    for (const Plan::Batch &b : P->batches) {
+        c3::FftArgs a = a0;
+        a.col_tasks = (const int2 *)P->col_tasks.p + b.col0;
+        a.ncol_tasks = b.ncol;
+        a.row_tasks = (const int2 *)P->row_tasks.p + b.row0;
+        a.nrow_tasks = b.nrow;
+        for (int pass = 0; pass < npass; ++pass) {
+            KTimer kt(ctx, K_COLF + pass, st);
+            HIPCHK(c3::launch_fft_pass(st, mixed, a, pass));
+        }
+    }
+    return TOD_OK;
+}
+
+
 }  // namespace
 
 // ============================================================== C-ABI
@@ -658,11 +696,7 @@ static tod_status ncorr_impl(tod_ctx ctx, const tod_layout *lay, int mixed, Plan
     a.alpha = alpha;
     a.mean_only = mean_only;
     a.mode = 0;
-    for (int pass = 0; pass < 3; ++pass) {
-        KTimer kt(ctx, K_COLF + pass, ctx->stream);
-        HIPCHK(c3::launch_fft_pass(ctx->stream, mixed, a, pass));
-    }
-    return TOD_OK;
+    return run_fft(ctx, ctx->stream, P, mixed, a, 3);
 }
 
 tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const void *d,
@@ -760,9 +794,9 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     a.alpha = alpha;
     a.mode = 1;
     a.whittle = (double *)ctx->seg_whittle.p;
-    for (int pass = 0; pass < 2; ++pass) {
-        KTimer kt(ctx, K_COLF + pass, st);
-        HIPCHK(c3::launch_fft_pass(st, mixed, a, pass));
+    {
+        tod_status rr = run_fft(ctx, st, P, mixed, a, 2);
+        if (rr != TOD_OK) return rr;
     }
     HIPCHK(c3::launch_chisq_finish(st, Ld, (const double *)ctx->seg_sums.p,
                                    (const double *)ctx->seg_whittle.p, gain, sigma0, fknee, alpha,
@@ -867,10 +901,8 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
             a.fknee = fknee;
             a.alpha = alpha;
             a.mean_only = 0;
-            for (int pass = 0; pass < 3; ++pass) {
-                KTimer kt(ctx, K_COLF + pass, st);
-                HIPCHK(c3::launch_fft_pass(st, mixed, a, pass));
-            }
+            tod_status rr = run_fft(ctx, st, P, mixed, a, 3);
+            if (rr != TOD_OK) return rr;
         }
         {
             HIPCHK(c3::launch_zero(st, acc, lay->npix_total * 10 * sizeof(double)));
@@ -910,6 +942,13 @@ tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride) {
         ctx->band_stride.erase(band);
     else
         ctx->band_stride[band] = stride;
+    return TOD_OK;
+}
+
+tod_status tod_set_fft_batch(tod_ctx ctx, int64_t complex_elems) {
+    if (!ctx) return TOD_EINVAL;
+    if (complex_elems < 0) return fail(ctx, TOD_EINVAL, "negative batch size");
+    ctx->fft_batch = complex_elems;
     return TOD_OK;
 }
 
@@ -1001,11 +1040,16 @@ tod_status time_fft_choice(tod_ctx ctx, int mixed, int64_t M, const c3tune::FftC
     a.sigma0 = (const double *)prm.p;
     a.fknee = (const double *)prm.p + K;
     a.alpha = (const double *)prm.p + 2 * K;
-    for (int pass = 0; pass < 3; ++pass) HIPCHK(c3::launch_fft_pass(ctx->stream, mixed, a, pass));
+    {
+        tod_status rr = run_fft(ctx, ctx->stream, P, mixed, a, 3);
+        if (rr != TOD_OK) return rr;
+    }
     HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
     const int reps = 3;
-    for (int i = 0; i < reps; ++i)
-        for (int pass = 0; pass < 3; ++pass) HIPCHK(c3::launch_fft_pass(ctx->stream, mixed, a, pass));
+    for (int i = 0; i < reps; ++i) {
+        tod_status rr = run_fft(ctx, ctx->stream, P, mixed, a, 3);
+        if (rr != TOD_OK) return rr;
+    }
     HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(hipEventSynchronize(ctx->ev[3]));
     float ms = 0;

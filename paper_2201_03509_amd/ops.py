@@ -238,6 +238,9 @@ class Context:
     def set_bin_stride(self, band, stride):
         self._chk(self.lib.tod_set_bin_stride(self.h, int(band), int(stride)))
 
+    def set_fft_batch(self, complex_elems):
+        self._chk(self.lib.tod_set_fft_batch(self.h, int(complex_elems)))
+
     def enable_timing(self, on=True):
         self._chk(self.lib.tod_enable_timing(self.h, int(bool(on))))
 
