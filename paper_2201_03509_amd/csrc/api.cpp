@@ -459,12 +459,27 @@ tod_status get_bin_tiles(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_
         }
     }
     if (st != P->bin_stride || P->nbin == 0) {
+        // tiles over groups of up to two consecutive segments of equal length
+        // and band (one horn's radiometers share pointing); phases in the low
+        // 16 bits of .w, the group size above them
         std::vector<int4> v;
+        std::vector<char> done(L->nseg, 0);
         for (int s : P->seg_order) {
-            const int n = P->h_segs[s].n;
-            const int S = st[P->h_segs[s].band];
+            if (done[s]) continue;
+            int grp = 1;
+            const int base = (s % 2 == 0) ? s : s - 1;
+            int first = s;
+            if (base + 1 < L->nseg && !done[base] && !done[base + 1] &&
+                P->h_segs[base].n == P->h_segs[base + 1].n && P->h_segs[base].band == P->h_segs[base + 1].band) {
+                first = base;
+                grp = 2;
+            }
+            for (int g = 0; g < grp; ++g) done[first + g] = 1;
+            const int n = P->h_segs[first].n;
+            const int S = st[P->h_segs[first].band];
             const int nph = std::min(S, n);
-            for (int p0 = 0; p0 < nph; p0 += C3_NT) v.push_back(make_int4(s, p0, S, std::min(C3_NT, nph - p0)));
+            for (int p0 = 0; p0 < nph; p0 += C3_NT)
+                v.push_back(make_int4(first, p0, S, std::min(C3_NT, nph - p0) | (grp << 16)));
         }
         HIPCHK(P->bin_tiles.upload(v, ctx->stream));
         P->nbin = (int)v.size();

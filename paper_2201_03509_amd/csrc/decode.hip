@@ -195,23 +195,26 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
             }
         }
         __syncthreads();
-        // rows of 16 samples: resolve symbols, undo the differencing with a
-        // 16-lane inclusive scan plus the row's running value, write out
+        // rows of 16 samples: resolve symbols (every gather issued before the
+        // first scan), undo the differencing with a 16-lane inclusive scan plus
+        // the row's running value, write out
+        int32_t valp[G], valq[G];
+#pragma unroll
         for (int m = 0; m < G; ++m) {
             const int q = m * C3_NT + tid;
             const int ll = q >> 4, kk = q & 15;
-            int32_t vp = 0, vq = 0;
-            bool valid = false;
-            int t = 0;
-            if (ll < task.nchunk && task.chunk0 + ll < nch_idx) {
-                const int cc = task.chunk0 + ll;
-                t = cc * C + k0 + kk;
-                valid = (k0 + kk < C) && t < n;
-                if (valid) {
-                    vp = cp.sym[tp[ll * GP + kk]];
-                    vq = cq.sym[tq[ll * GP + kk]];
-                }
-            }
+            const int t = (task.chunk0 + ll) * C + k0 + kk;
+            const bool valid = ll < task.nchunk && task.chunk0 + ll < nch_idx && t < n;
+            valp[m] = valid ? cp.sym[tp[ll * GP + kk]] : 0;
+            valq[m] = valid ? cq.sym[tq[ll * GP + kk]] : 0;
+        }
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+            const int q = m * C3_NT + tid;
+            const int ll = q >> 4, kk = q & 15;
+            const int t = (task.chunk0 + ll) * C + k0 + kk;
+            const bool valid = ll < task.nchunk && task.chunk0 + ll < nch_idx && t < n;
+            int32_t vp = valp[m], vq = valq[m];
 #pragma unroll
             for (int o = 1; o < 16; o <<= 1) {
                 const int yp = __shfl_up(vp, o, 16), yq = __shfl_up(vq, o, 16);

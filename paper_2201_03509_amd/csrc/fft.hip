@@ -58,6 +58,27 @@ __device__ __forceinline__ void dft(cx<T> *v) {
         v[2] = csub(s0, s1);
         v[1] = cadd(d0, d1);
         v[3] = csub(d0, d1);
+    } else if constexpr (R == 8) {
+        // split into two radix-4 transforms: a_k = x_k + x_k+4, b_k = (x_k - x_k+4) w8^k
+        const T h = (T)0.70710678118654752440;
+        cx<T> a[4], b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = cadd(v[k], v[k + 4]);
+            b[k] = csub(v[k], v[k + 4]);
+        }
+        // w8 = (1 + DIR i)/sqrt2, w8^2 = DIR i, w8^3 = (-1 + DIR i)/sqrt2
+        const cx<T> b1 = b[1], b3 = b[3];
+        b[1] = cscale(cadd(b1, mul_i<DIR>(b1)), h);
+        b[2] = mul_i<DIR>(b[2]);
+        b[3] = cscale(csub(mul_i<DIR>(b3), b3), h);
+        dft<4, DIR>(a);
+        dft<4, DIR>(b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = a[k];
+            v[2 * k + 1] = b[k];
+        }
     } else {  // R == 5
         const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
         const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
@@ -78,6 +99,7 @@ __device__ __forceinline__ void dft(cx<T> *v) {
 
 // One Stockham stage of radix R on B = 1 << lb transforms of length L, from
 // src to dst in LDS; element i of transform b lives at [(i << lsi) + b].
+// Twiddles: w^k and w^2k from the table, higher powers by multiplication.
 template <int R, int DIR, typename T>
 __device__ __attribute__((noinline)) void fft_stage(const LDSP cx<T> *src, LDSP cx<T> *dst, int L,
                                                     int lb, int lsi, int Ns,
@@ -88,28 +110,46 @@ __device__ __attribute__((noinline)) void fft_stage(const LDSP cx<T> *src, LDSP 
     const int step = L / (Ns * R);
     const int in_stride = LR << lsi;   // between the R inputs of a butterfly
     const int out_stride = Ns << lsi;  // between its R outputs
+    const int NsR = Ns * R;
     const uint32_t magic = 0xFFFFFFFFu / (uint32_t)Ns + 1u;  // j / Ns == umulhi(j, magic)
 #pragma unroll 2
     for (int q = threadIdx.x; q < nb; q += C3_NT) {
         const int b = q & bm, j = q >> lb;
-        const int ib = (j << lsi) + b;
         cx<T> v[R];
+        int ia = (j << lsi) + b;
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[t] = src[ib + t * in_stride];
+        for (int t = 0; t < R; ++t) {
+            v[t] = src[ia];
+            ia += in_stride;
+        }
         const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
         const int k = j - jd * Ns;
         if (Ns > 1) {
             const int ks = k * step;
+            const cx<T> w1 = tw[ks];
+            v[1] = DIR < 0 ? cmul(v[1], w1) : cmulc(v[1], w1);
+            if constexpr (R > 2) {
+                const cx<T> w2 = tw[2 * ks];
+                v[2] = DIR < 0 ? cmul(v[2], w2) : cmulc(v[2], w2);
+                cx<T> wa = w1, wb = w2;
 #pragma unroll
-            for (int t = 1; t < R; ++t) {
-                const cx<T> w = tw[t * ks];
-                v[t] = DIR < 0 ? cmul(v[t], w) : cmulc(v[t], w);
+                for (int t = 3; t < R; ++t) {
+                    const cx<T> w = cmul((t & 1) ? wa : wb, w2);
+                    if (t & 1)
+                        wa = w;
+                    else
+                        wb = w;
+                    v[t] = DIR < 0 ? cmul(v[t], w) : cmulc(v[t], w);
+                }
             }
         }
         dft<R, DIR>(v);
-        const int ob = (((j - k) * R + k) << lsi) + b;
+        int ob = ((jd * NsR + k) << lsi) + b;
 #pragma unroll
-        for (int t = 0; t < R; ++t) dst[ob + t * out_stride] = v[t];
+        for (int t = 0; t < R; ++t) {
+            dst[ob] = v[t];
+            ob += out_stride;
+        }
     }
     __syncthreads();
 }
@@ -128,6 +168,8 @@ __device__ cx<T> *lds_fft(cx<T> *b0, cx<T> *b1, int L, int lb, int lsi, const in
         LDSP cx<T> *ld = (LDSP cx<T> *)dst;
         if (R == 4)
             fft_stage<4, DIR>(ls, ld, L, lb, lsi, Ns, tw);
+        else if (R == 8)
+            fft_stage<8, DIR>(ls, ld, L, lb, lsi, Ns, tw);
         else if (R == 2)
             fft_stage<2, DIR>(ls, ld, L, lb, lsi, Ns, tw);
         else if (R == 3)

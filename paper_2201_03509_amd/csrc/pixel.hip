@@ -58,6 +58,10 @@ __device__ __forceinline__ void flush_acc(double *acc, int64_t gp, const double 
     for (int j = 0; j < 10; ++j) atomicAdd(dst + j, a[j]);
 }
 
+// Bin tile (x = first segment, y = first phase, z = stride S, w = phases | nseg << 16):
+// the tile's segments are consecutive and of equal length; a lane visits its
+// phase in each of them in turn, so segments that see the same pixels (the two
+// radiometers of a horn) share one register accumulation and one flush.
 template <typename TN>
 __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restrict__ tiles,
                                                const int32_t *__restrict__ pix,
@@ -70,29 +74,25 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     // cos/sin 2psi repeat every 2048 psi bins
     __shared__ cx<double> tr[2048];
     const int4 tl = tiles[blockIdx.x];
-    const int seg = tl.x;
-    if (Ld.seg_accept && !Ld.seg_accept[seg]) return;  // uniform over the block
     for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
     const int S = tl.z;
+    const int nph = tl.w & 0xFFFF, ngrp = tl.w >> 16;
     const int phi = tl.y + threadIdx.x;
-    if ((int)threadIdx.x >= tl.w) return;
-    const int64_t s0 = Ld.seg_off[seg];
-    const int n = (int)(Ld.seg_off[seg + 1] - s0);
-    const int64_t poff = Ld.band[Ld.seg_band[seg]].pix_off;
-    const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg]].npix;
-    const double g = gain[seg];
-    const double s2 = sigma0[seg];
-    const double w = g / (s2 * s2);
-    const double gw = g * w;
+    if ((int)threadIdx.x >= nph) return;
+    const int seg0 = tl.x;
+    const int64_t poff = Ld.band[Ld.seg_band[seg0]].pix_off;
+    const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg0]].npix;
     const float *df = (const float *)d;
     const double *dd = (const double *)d;
     // two register accumulators: the current pixel and the one before it, so a
-    // phase that crosses a pixel edge (and may cross back) rarely flushes early
+    // phase that crosses a pixel edge (or alternates between two segments'
+    // pixels) rarely flushes early
     double a[10], o[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) a[j] = o[j] = 0.0;
     int cur = -1, old = -1;
+    double w = 0, gw = 0;
     auto step = [&](int p, int b, double v) {
         if ((uint32_t)p >= npix) return;  // out-of-range pixels are not binned
         if (p != cur) {
@@ -129,26 +129,36 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         a[8] += gw * cs.y * cs.y;
         a[9] += 1.0;
     };
-    int t = phi;
-    for (; t + 3 * S < n; t += 4 * S) {
-        int p[4], b[4];
-        double v[4];
+    for (int gi = 0; gi < ngrp; ++gi) {
+        const int seg = seg0 + gi;
+        if (Ld.seg_accept && !Ld.seg_accept[seg]) continue;
+        const int64_t s0 = Ld.seg_off[seg];
+        const int n = (int)(Ld.seg_off[seg + 1] - s0);
+        const double g = gain[seg];
+        const double s2 = sigma0[seg];
+        w = g / (s2 * s2);
+        gw = g * w;
+        int t = phi;
+        for (; t + 3 * S < n; t += 4 * S) {
+            int p[4], b[4];
+            double v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t i = s0 + t + u * S;
-            p[u] = pix[i];
-            b[u] = psi[i];
-            v[u] = d_f64 ? dd[i] : (double)df[i];
-            if (ncorr) v[u] -= (double)ncorr[i];
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = s0 + t + u * S;
+                p[u] = pix[i];
+                b[u] = psi[i];
+                v[u] = d_f64 ? dd[i] : (double)df[i];
+                if (ncorr) v[u] -= (double)ncorr[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) step(p[u], b[u], v[u]);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) step(p[u], b[u], v[u]);
-    }
-    for (; t < n; t += S) {
-        const int64_t i = s0 + t;
-        double v = d_f64 ? dd[i] : (double)df[i];
-        if (ncorr) v -= (double)ncorr[i];
-        step(pix[i], psi[i], v);
+        for (; t < n; t += S) {
+            const int64_t i = s0 + t;
+            double v = d_f64 ? dd[i] : (double)df[i];
+            if (ncorr) v -= (double)ncorr[i];
+            step(pix[i], psi[i], v);
+        }
     }
     if (cur >= 0) flush_acc(acc, poff + cur, a);
     if (old >= 0) flush_acc(acc, poff + old, o);
@@ -156,7 +166,8 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
 
 // ---------------------------------------------------------------- residual
 // r = d - g (T + Q cos 2psi + U sin 2psi) on strided tiles; the thread keeps
-// the map values of its current pixel in registers across revisits.
+// the map values of its current pixel in registers across revisits (and
+// across the tile's segments).
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__restrict__ tiles,
                                                  const int32_t *__restrict__ pix,
@@ -167,23 +178,21 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
                                                  T *__restrict__ r_out) {
     __shared__ cx<T> tr[2048];
     const int4 tl = tiles[blockIdx.x];
-    const int seg = tl.x;
     for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
     const int S = tl.z;
+    const int nph = tl.w & 0xFFFF, ngrp = tl.w >> 16;
     const int phi = tl.y + threadIdx.x;
-    if ((int)threadIdx.x >= tl.w) return;
-    const int64_t s0 = Ld.seg_off[seg];
-    const int n = (int)(Ld.seg_off[seg + 1] - s0);
-    const int band = Ld.seg_band[seg];
+    if ((int)threadIdx.x >= nph) return;
+    const int band = Ld.seg_band[tl.x];
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
     const int64_t npt = Ld.npix_total;
-    const T g = (T)gain[seg];
     const float *df = (const float *)d;
     const double *dd = (const double *)d;
     int cur = -1;
     T mT = 0, mQ = 0, mU = 0;
+    T g = 0;
     auto step = [&](int64_t i, int p, int b, T dv) {
         if (p != cur) {
             cur = p;
@@ -199,23 +208,29 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
         const cx<T> cs = tr[b & 2047];
         r_out[i] = dv - g * (mT + mQ * cs.x + mU * cs.y);
     };
-    int t = phi;
-    for (; t + 3 * S < n; t += 4 * S) {
-        int p[4], b[4];
-        T v[4];
+    for (int gi = 0; gi < ngrp; ++gi) {
+        const int seg = tl.x + gi;
+        const int64_t s0 = Ld.seg_off[seg];
+        const int n = (int)(Ld.seg_off[seg + 1] - s0);
+        g = (T)gain[seg];
+        int t = phi;
+        for (; t + 3 * S < n; t += 4 * S) {
+            int p[4], b[4];
+            T v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t i = s0 + t + u * S;
-            p[u] = pix[i];
-            b[u] = psi[i];
-            v[u] = d_f64 ? (T)dd[i] : (T)df[i];
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = s0 + t + u * S;
+                p[u] = pix[i];
+                b[u] = psi[i];
+                v[u] = d_f64 ? (T)dd[i] : (T)df[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], v[u]);
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], v[u]);
-    }
-    for (; t < n; t += S) {
-        const int64_t i = s0 + t;
-        step(i, pix[i], psi[i], d_f64 ? (T)dd[i] : (T)df[i]);
+        for (; t < n; t += S) {
+            const int64_t i = s0 + t;
+            step(i, pix[i], psi[i], d_f64 ? (T)dd[i] : (T)df[i]);
+        }
     }
 }
 
@@ -328,82 +343,88 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     __shared__ cx<double> tr[2048];
     __shared__ double red[3][C3_NT / 64];
     const int4 tl = tiles[blockIdx.x];
-    const int seg = tl.x;
-    if (Ld.seg_accept && !Ld.seg_accept[seg]) return;
     for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
     const int S = tl.z;
+    const int nph = tl.w & 0xFFFF, ngrp = tl.w >> 16;
     const int phi = tl.y + threadIdx.x;
-    const bool act = (int)threadIdx.x < tl.w;
-    const int64_t s0 = Ld.seg_off[seg];
-    const int n = (int)(Ld.seg_off[seg + 1] - s0);
-    const int64_t poff = Ld.band[Ld.seg_band[seg]].pix_off;
-    const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg]].npix;
+    const bool act = (int)threadIdx.x < nph;
+    const int band = Ld.seg_band[tl.x];
+    const int64_t poff = Ld.band[band].pix_off;
+    const uint32_t npix = (uint32_t)Ld.band[band].npix;
     const int64_t npt = Ld.npix_total;
-    const double g = gain[seg];
-    const double sg = sigma0[seg];
-    const double is2 = 1.0 / (sg * sg);
-    const double cfac = -2.0 * g * is2 * gscale;
-    double sr2 = 0, spr = 0;
     double a0 = 0, a1 = 0, a2 = 0;
     int cur = -1;
-    for (int t = act ? phi : n; t < n; t += S) {
-        const int64_t i = s0 + t;
-        const int p = pix[i];
-        if ((uint32_t)p >= npix) continue;
-        const int64_t gp = poff + p;
-        const cx<double> cs = tr[psi[i] & 2047];
-        double T, Q, U, nc;
-        if (mixed) {
-            const float *m = (const float *)maps;
-            T = m[gp];
-            Q = m[npt + gp];
-            U = m[2 * npt + gp];
-            nc = ncorr ? (double)((const float *)ncorr)[i] : 0.0;
-        } else {
-            const double *m = (const double *)maps;
-            T = m[gp];
-            Q = m[npt + gp];
-            U = m[2 * npt + gp];
-            nc = ncorr ? ((const double *)ncorr)[i] : 0.0;
-        }
-        const double Pm = T + Q * cs.x + U * cs.y;
-        const double dv = d_f64 ? ((const double *)d)[i] : (double)((const float *)d)[i];
-        const double r = dv - g * Pm - nc;
-        sr2 += r * r;
-        spr += Pm * r;
-        if (gmap) {
-            if (p != cur) {
-                if (cur >= 0) {
-                    atomicAdd(gmap + poff + cur, a0);
-                    atomicAdd(gmap + npt + poff + cur, a1);
-                    atomicAdd(gmap + 2 * npt + poff + cur, a2);
-                }
-                a0 = a1 = a2 = 0;
-                cur = p;
+    for (int gi = 0; gi < ngrp; ++gi) {
+        const int seg = tl.x + gi;
+        if (Ld.seg_accept && !Ld.seg_accept[seg]) continue;  // uniform over the block
+        const int64_t s0 = Ld.seg_off[seg];
+        const int n = (int)(Ld.seg_off[seg + 1] - s0);
+        const double g = gain[seg];
+        const double sg = sigma0[seg];
+        const double is2 = 1.0 / (sg * sg);
+        const double cfac = -2.0 * g * is2 * gscale;
+        double sr2 = 0, spr = 0;
+        for (int t = act ? phi : n; t < n; t += S) {
+            const int64_t i = s0 + t;
+            const int p = pix[i];
+            if ((uint32_t)p >= npix) continue;
+            const int64_t gp = poff + p;
+            const cx<double> cs = tr[psi[i] & 2047];
+            double T, Q, U, nc;
+            if (mixed) {
+                const float *m = (const float *)maps;
+                T = m[gp];
+                Q = m[npt + gp];
+                U = m[2 * npt + gp];
+                nc = ncorr ? (double)((const float *)ncorr)[i] : 0.0;
+            } else {
+                const double *m = (const double *)maps;
+                T = m[gp];
+                Q = m[npt + gp];
+                U = m[2 * npt + gp];
+                nc = ncorr ? ((const double *)ncorr)[i] : 0.0;
             }
-            const double cr = cfac * r;
-            a0 += cr;
-            a1 += cr * cs.x;
-            a2 += cr * cs.y;
+            const double Pm = T + Q * cs.x + U * cs.y;
+            const double dv = d_f64 ? ((const double *)d)[i] : (double)((const float *)d)[i];
+            const double r = dv - g * Pm - nc;
+            sr2 += r * r;
+            spr += Pm * r;
+            if (gmap) {
+                if (p != cur) {
+                    if (cur >= 0) {
+                        atomicAdd(gmap + poff + cur, a0);
+                        atomicAdd(gmap + npt + poff + cur, a1);
+                        atomicAdd(gmap + 2 * npt + poff + cur, a2);
+                    }
+                    a0 = a1 = a2 = 0;
+                    cur = p;
+                }
+                const double cr = cfac * r;
+                a0 += cr;
+                a1 += cr * cs.x;
+                a2 += cr * cs.y;
+            }
         }
+        // per-segment sums: block reduction, one atomic per sum
+        double v[3] = {sr2 * is2, spr, sr2};
+        for (int j = 0; j < 3; ++j) {
+            double x = v[j];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+            if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double x = 0;
+            for (int w = 0; w < C3_NT / 64; ++w) x += red[threadIdx.x][w];
+            atomicAdd(seg_sums + (int64_t)seg * 4 + threadIdx.x, x);
+        }
+        __syncthreads();
     }
     if (gmap && cur >= 0) {
         atomicAdd(gmap + poff + cur, a0);
         atomicAdd(gmap + npt + poff + cur, a1);
         atomicAdd(gmap + 2 * npt + poff + cur, a2);
-    }
-    double v[3] = {sr2 * is2, spr, sr2};
-    for (int j = 0; j < 3; ++j) {
-        double x = v[j];
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-        if ((threadIdx.x & 63) == 0) red[j][threadIdx.x >> 6] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        double x = 0;
-        for (int w = 0; w < C3_NT / 64; ++w) x += red[threadIdx.x][w];
-        atomicAdd(seg_sums + (int64_t)seg * 4 + threadIdx.x, x);
     }
 }
 

@@ -34,11 +34,15 @@ inline std::vector<int> factor235(int64_t L) {
     return f;
 }
 
-// radix order: order 0 = 4s, 2, 3s, 5s; order 1 = 5s, 3s, 2, 4s
+// radix order: order 0 = 8s, 4, 2, 3s, 5s; order 1 = 5s, 3s, 2, 4, 8s
 inline std::vector<int> radices(int64_t L, int order) {
     std::vector<int> f = factor235(L), r;
     if (f.empty()) return r;
-    std::vector<int> r4(f[0] / 2, 4), r2(f[0] % 2, 2), r3(f[1], 3), r5(f[2], 5);
+    const int n8 = f[0] / 3, rem = f[0] % 3;
+    std::vector<int> r4(n8, 8), r2;
+    if (rem == 2) r4.push_back(4);
+    if (rem == 1) r2.push_back(2);
+    std::vector<int> r3(f[1], 3), r5(f[2], 5);
     if (order == 0) {
         r.insert(r.end(), r4.begin(), r4.end());
         r.insert(r.end(), r2.begin(), r2.end());
