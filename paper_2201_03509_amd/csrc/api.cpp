@@ -84,8 +84,13 @@ struct Plan {
     int ncol = 0, nrow = 0;
     // FFT batches: contiguous ranges of the column/row task lists whose
     // segments share one workspace region (sized to stay cache resident)
+    struct ColGroup {
+        int m1reg;                        // register column length, 0: LDS tiles
+        int t0, nt;                       // range of the column task list
+    };
     struct Batch {
         int col0, ncol, row0, nrow;
+        std::vector<ColGroup> groups;     // column tasks of the batch, by kernel
     };
     std::vector<Batch> batches;
     int col_lds = 0, row_lds = 0;         // dynamic LDS bytes per FFT pass
@@ -247,7 +252,6 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     auto P = std::make_unique<Plan>();
     P->key = key;
     P->mixed = mixed;
-    const int S = mixed ? 4096 : 2048;  // complex elements per LDS buffer (two buffers per block)
     const int nseg = L->nseg;
     P->h_segs.resize(nseg);
     Pool pool;
@@ -266,17 +270,20 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         const int64_t M = next_5smooth(g.n);
         auto it = P->plan_of_M.find(M);
         if (it == P->plan_of_M.end()) {
-            c3tune::FftChoice ch;
-            if (!ctx->tuned.get(mixed, M, ch)) {
-                if (!c3tune::default_choice(M, S, ch))
-                    return fail(ctx, TOD_ENOTSUP, "no FFT plan for M = " + std::to_string(M));
-            }
+            c3tune::FftChoice ch, chk;
+            // a tuned choice is used only if it is still a valid split here
+            const bool tuned = ctx->tuned.get(mixed, M, ch) &&
+                               c3tune::make_choice(M, ch.M2, mixed, 1 << 30, 0, ch.colreg, chk) &&
+                               (ch.colreg || (ch.B >= 1 && (int64_t)ch.M1 * ch.B <= c3tune::col_tile(mixed)));
+            if (!tuned && !c3tune::default_choice(M, mixed, ch))
+                return fail(ctx, TOD_ENOTSUP, "no FFT plan for M = " + std::to_string(M));
             FftPlan fp;
             memset(&fp, 0, sizeof(fp));
             fp.M = (int32_t)M;
             fp.M1 = ch.M1;
             fp.M2 = ch.M2;
-            fp.B = ch.B;
+            fp.B = ch.colreg ? C3_COL_NT : ch.B;
+            fp.colreg = ch.colreg;
             fp.nr1 = (int)ch.r1.size();
             fp.nr2 = (int)ch.r2.size();
             for (size_t i = 0; i < ch.r1.size(); ++i) fp.r1[i] = (int8_t)ch.r1[i];
@@ -300,34 +307,44 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     std::stable_sort(P->seg_order.begin(), P->seg_order.end(), [&](int a, int b) {
         return P->h_segs[a].n > P->h_segs[b].n;
     });
-    // batches in LPT order; each batch reuses the workspace from offset 0
+    // batches in LPT order; each batch reuses the workspace from offset 0.
+    // Column tasks of a batch are grouped by column kernel (one launch each).
     std::vector<int2> col, row;
-    Plan::Batch cur{0, 0, 0, 0};
+    std::map<int, std::vector<int2>> bcol;  // m1reg -> column tasks of the open batch
+    Plan::Batch cur{0, 0, 0, 0, {}};
+    auto close_batch = [&]() {
+        cur.col0 = (int)col.size();
+        for (auto &kv : bcol) {
+            cur.groups.push_back({kv.first, (int)col.size(), (int)kv.second.size()});
+            col.insert(col.end(), kv.second.begin(), kv.second.end());
+        }
+        cur.ncol = (int)col.size() - cur.col0;
+        cur.nrow = (int)row.size() - cur.row0;
+        if (cur.ncol > 0 || cur.nrow > 0) P->batches.push_back(cur);
+        bcol.clear();
+        cur = Plan::Batch{(int)col.size(), 0, (int)row.size(), 0, {}};
+    };
     for (int s : P->seg_order) {
         SegInfo &g = P->h_segs[s];
         if (g.plan < 0) continue;
         const FftPlan &fp = P->h_plans[g.plan];
         if (ctx->fft_batch > 0 && scr > 0 && scr + fp.M > ctx->fft_batch) {
-            cur.ncol = (int)col.size() - cur.col0;
-            cur.nrow = (int)row.size() - cur.row0;
-            P->batches.push_back(cur);
-            cur = Plan::Batch{(int)col.size(), 0, (int)row.size(), 0};
+            close_batch();
             scr = 0;
         }
         g.scr_off = scr;
         scr += fp.M;
         P->work_elems = std::max(P->work_elems, scr);
-        for (int c0 = 0; c0 < fp.M2; c0 += fp.B) col.push_back(make_int2(s, c0));
+        std::vector<int2> &cv = bcol[fp.colreg ? fp.M1 : 0];
+        for (int c0 = 0; c0 < fp.M2; c0 += fp.B) cv.push_back(make_int2(s, c0));
         for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) row.push_back(make_int2(s, k1));
     }
-    cur.ncol = (int)col.size() - cur.col0;
-    cur.nrow = (int)row.size() - cur.row0;
-    if (cur.ncol > 0) P->batches.push_back(cur);
+    close_batch();
     P->ncol = (int)col.size();
     P->nrow = (int)row.size();
     const int esz = mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
     for (const FftPlan &fp : P->h_plans) {
-        P->col_lds = std::max(P->col_lds, 2 * fp.M1 * fp.B * esz);  // two ping-pong buffers
+        if (!fp.colreg) P->col_lds = std::max(P->col_lds, 2 * fp.M1 * fp.B * esz);  // ping-pong
         P->row_lds = std::max(P->row_lds, 4 * fp.M2 * esz);
     }
     std::vector<double> fs(L->nband);
@@ -559,8 +576,18 @@ tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::Ff
         a.row_tasks = (const int2 *)P->row_tasks.p + b.row0;
         a.nrow_tasks = b.nrow;
         for (int pass = 0; pass < npass; ++pass) {
-            KTimer kt(ctx, K_COLF + pass, st);
-            HIPCHK(c3::launch_fft_pass(st, mixed, a, pass));
+            if (pass == 1) {
+                KTimer kt(ctx, K_ROW, st);
+                HIPCHK(c3::launch_fft_pass(st, mixed, a, pass, 0));
+                continue;
+            }
+            for (const Plan::ColGroup &g : b.groups) {
+                c3::FftArgs ag = a;
+                ag.col_tasks = (const int2 *)P->col_tasks.p + g.t0;
+                ag.ncol_tasks = g.nt;
+                KTimer kt(ctx, K_COLF + pass, st);
+                HIPCHK(c3::launch_fft_pass(st, mixed, ag, pass, g.m1reg));
+            }
         }
     }
     return TOD_OK;
@@ -604,6 +631,10 @@ tod_status tod_ctx_create(tod_ctx *out, int device, void *hip_stream) {
         return TOD_EHIP;
     }
     for (auto &e : ctx->ev) (void)hipEventCreate(&e);
+    if (c3::fft_init_attributes() != hipSuccess) {
+        delete ctx;
+        return TOD_EHIP;
+    }
     (void)hipDeviceSynchronize();
     *out = ctx;
     return TOD_OK;
@@ -1101,7 +1132,6 @@ tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
     if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
     if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
     const int mixed = prec == TOD_MIXED;
-    const int S = mixed ? 4096 : 2048;
     if (cache_path) {
         if ((r = tod_load_tuning(ctx, cache_path)) != TOD_OK) return r;
     }
@@ -1117,7 +1147,7 @@ tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
         const int K = (int)std::max<int64_t>(2, std::min<int64_t>(32, (int64_t)(64ll << 20) / (8 * M)));
         float best = 1e30f;
         c3tune::FftChoice bc;
-        for (const c3tune::FftChoice &c : c3tune::candidates(M, S)) {
+        for (const c3tune::FftChoice &c : c3tune::candidates(M, mixed)) {
             float ms;
             if ((r = time_fft_choice(ctx, mixed, M, c, K, &ms)) != TOD_OK) return r;
             if (ms < best) {

@@ -5,7 +5,14 @@
 
 #include "../../include/c3tod.h"
 
-#define C3_NT 256            // threads per block of every kernel
+#define C3_NT 256            // threads per block of every kernel but the two below
+#define C3_ROW_NT 1024       // threads per block of the FFT row pass
+#define C3_COL_NT 64         // threads (= columns) per block of the register column passes
+#define C3_LDS_MAX 163840    // LDS bytes one workgroup may hold on gfx950
+
+// column lengths M1 with register column kernels (5-smooth, 16..81; FP32 only)
+#define C3_COLREG_LIST(X) \
+    X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(50) X(54) X(60) X(64) X(72) X(75) X(80) X(81)
 
 // sticky device error bits
 #define C3_ERR_CODE 1u       // bit pattern matches no code
@@ -52,6 +59,9 @@ struct SegInfo {
 struct FftPlan {
     int32_t M, M1, M2, B;        // B: columns per column-pass tile
     int32_t nr1, nr2;            // radix counts of the M1 and M2 sub-transforms
+    int32_t colreg;              // 1: column passes keep a whole column in registers (M1 fixed
+                                 //    at compile time); 0: LDS column tiles of B columns
+    int32_t pad;
     int8_t r1[C3_MAXRAD];
     int8_t r2[C3_MAXRAD];
     int64_t tw1;                 // offset of w_M1^m (m < M1) in the twiddle pool
@@ -141,8 +151,15 @@ struct FftArgs {
     int col_lds, row_lds;       // dynamic LDS bytes of the column and row passes
 };
 // pass 0: forward column FFTs; 1: row pass (mode 0 n_corr draw, 1 Whittle sums);
-// 2: inverse column FFTs
-hipError_t launch_fft_pass(hipStream_t st, int prec_mixed, const FftArgs &a, int pass);
+// 2: inverse column FFTs.  m1reg > 0 selects the register column kernels for
+// that column length (passes 0 and 2); 0 the LDS column tiles.
+hipError_t launch_fft_pass(hipStream_t st, int prec_mixed, const FftArgs &a, int pass, int m1reg);
+// register column kernels (fftcol.hip); returns hipErrorInvalidValue for a
+// column length without a compiled kernel
+hipError_t launch_fft_col_reg(hipStream_t st, int prec_mixed, const FftArgs &a, int pass, int m1);
+bool fft_col_reg_supported(int prec_mixed, int m1);
+// raise the dynamic LDS limit of the FFT kernels (once per process)
+hipError_t fft_init_attributes();
 
 hipError_t launch_project_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                                 int ntile, const int32_t *pix, const uint16_t *psi,

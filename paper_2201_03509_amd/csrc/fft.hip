@@ -10,14 +10,18 @@
 //           mirror modes M-k of its modes k), FFT_M2 each, splits the complex
 //           spectrum into the real-FFT spectrum E_k (k = 0..M), applies the
 //           constrained-realisation filter and draw per mode, re-packs, runs
-//           the inverse FFT_M2, multiplies by w_M^(-j2 k1) and writes back.
-//   pass 3 (columns): inverse FFT_M1 per column; the first n real samples are
-//           the output.
+//           the inverse FFT_M2 and writes back.
+//   pass 3 (columns): times w_M^(-j2 k1), inverse FFT_M1 per column; the
+//           first n real samples are the output.
+// This file holds the row pass and the LDS form of the column passes (tiles
+// of B columns, any M1); fftcol.hip holds the register form for fixed M1.
 // Every sub-transform is an in-LDS Stockham FFT with radix 2/3/4/5 stages.
 #include "common.h"
+#include "fftdev.h"
 
 namespace {
 using c3::FftArgs;
+using namespace c3fft;
 
 // explicit LDS / global address spaces for the out-of-line stage functions
 // (only meaningful in the device compilation pass)
@@ -29,78 +33,10 @@ using c3::FftArgs;
 #define GLBP
 #endif
 
-// ---------------------------------------------------------------- DFT kernels
-template <int DIR, typename T>
-__device__ __forceinline__ cx<T> mul_i(cx<T> a) {  // a * (DIR * i)
-    return DIR < 0 ? cx<T>{a.y, -a.x} : cx<T>{-a.y, a.x};
-}
-
-template <int R, int DIR, typename T>
-__device__ __forceinline__ void dft(cx<T> *v) {
-    if constexpr (R == 2) {
-        cx<T> a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
-    } else if constexpr (R == 3) {
-        const T h = (T)0.86602540378443864676;  // sin(60 deg)
-        cx<T> a = v[0], b = v[1], c = v[2];
-        cx<T> t1 = cadd(b, c);
-        cx<T> t2 = {a.x - (T)0.5 * t1.x, a.y - (T)0.5 * t1.y};
-        cx<T> t3 = mul_i<DIR>(cscale(csub(b, c), h));
-        v[0] = cadd(a, t1);
-        v[1] = cadd(t2, t3);
-        v[2] = csub(t2, t3);
-    } else if constexpr (R == 4) {
-        cx<T> a = v[0], b = v[1], c = v[2], d = v[3];
-        cx<T> s0 = cadd(a, c), d0 = csub(a, c);
-        cx<T> s1 = cadd(b, d), d1 = mul_i<DIR>(csub(b, d));
-        v[0] = cadd(s0, s1);
-        v[2] = csub(s0, s1);
-        v[1] = cadd(d0, d1);
-        v[3] = csub(d0, d1);
-    } else if constexpr (R == 8) {
-        // split into two radix-4 transforms: a_k = x_k + x_k+4, b_k = (x_k - x_k+4) w8^k
-        const T h = (T)0.70710678118654752440;
-        cx<T> a[4], b[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            a[k] = cadd(v[k], v[k + 4]);
-            b[k] = csub(v[k], v[k + 4]);
-        }
-        // w8 = (1 + DIR i)/sqrt2, w8^2 = DIR i, w8^3 = (-1 + DIR i)/sqrt2
-        const cx<T> b1 = b[1], b3 = b[3];
-        b[1] = cscale(cadd(b1, mul_i<DIR>(b1)), h);
-        b[2] = mul_i<DIR>(b[2]);
-        b[3] = cscale(csub(mul_i<DIR>(b3), b3), h);
-        dft<4, DIR>(a);
-        dft<4, DIR>(b);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            v[2 * k] = a[k];
-            v[2 * k + 1] = b[k];
-        }
-    } else {  // R == 5
-        const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
-        const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
-        cx<T> x0 = v[0];
-        cx<T> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-        cx<T> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-        cx<T> a1 = {x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y};
-        cx<T> a2 = {x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y};
-        cx<T> b1 = mul_i<DIR>(cx<T>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
-        cx<T> b2 = mul_i<DIR>(cx<T>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
-        v[0] = cadd(x0, cadd(t1, t2));
-        v[1] = cadd(a1, b1);
-        v[4] = csub(a1, b1);
-        v[2] = cadd(a2, b2);
-        v[3] = csub(a2, b2);
-    }
-}
-
 // One Stockham stage of radix R on B = 1 << lb transforms of length L, from
 // src to dst in LDS; element i of transform b lives at [(i << lsi) + b].
 // Twiddles: w^k and w^2k from the table, higher powers by multiplication.
-template <int R, int DIR, typename T>
+template <int R, int DIR, int NT, typename T>
 __device__ __attribute__((noinline)) void fft_stage(const LDSP cx<T> *src, LDSP cx<T> *dst, int L,
                                                     int lb, int lsi, int Ns,
                                                     const GLBP cx<T> *__restrict__ tw) {
@@ -113,7 +49,7 @@ __device__ __attribute__((noinline)) void fft_stage(const LDSP cx<T> *src, LDSP 
     const int NsR = Ns * R;
     const uint32_t magic = 0xFFFFFFFFu / (uint32_t)Ns + 1u;  // j / Ns == umulhi(j, magic)
 #pragma unroll 2
-    for (int q = threadIdx.x; q < nb; q += C3_NT) {
+    for (int q = threadIdx.x; q < nb; q += NT) {
         const int b = q & bm, j = q >> lb;
         cx<T> v[R];
         int ia = (j << lsi) + b;
@@ -156,7 +92,7 @@ __device__ __attribute__((noinline)) void fft_stage(const LDSP cx<T> *src, LDSP 
 
 // In-LDS Stockham FFT between two buffers of the same size; returns the one
 // holding the result.
-template <int DIR, typename T>
+template <int DIR, int NT, typename T>
 __device__ cx<T> *lds_fft(cx<T> *b0, cx<T> *b1, int L, int lb, int lsi, const int8_t *rad, int nrad,
                           const cx<T> *tw_) {
     const GLBP cx<T> *tw = (const GLBP cx<T> *)tw_;
@@ -167,43 +103,21 @@ __device__ cx<T> *lds_fft(cx<T> *b0, cx<T> *b1, int L, int lb, int lsi, const in
         const LDSP cx<T> *ls = (const LDSP cx<T> *)src;
         LDSP cx<T> *ld = (LDSP cx<T> *)dst;
         if (R == 4)
-            fft_stage<4, DIR>(ls, ld, L, lb, lsi, Ns, tw);
+            fft_stage<4, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
         else if (R == 8)
-            fft_stage<8, DIR>(ls, ld, L, lb, lsi, Ns, tw);
+            fft_stage<8, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
         else if (R == 2)
-            fft_stage<2, DIR>(ls, ld, L, lb, lsi, Ns, tw);
+            fft_stage<2, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
         else if (R == 3)
-            fft_stage<3, DIR>(ls, ld, L, lb, lsi, Ns, tw);
+            fft_stage<3, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
         else
-            fft_stage<5, DIR>(ls, ld, L, lb, lsi, Ns, tw);
+            fft_stage<5, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
         Ns *= R;
         cx<T> *x = src;
         src = dst;
         dst = x;
     }
     return src;
-}
-
-// w_N^m for 0 <= m <= N from the two-level table
-template <typename T>
-__device__ __forceinline__ cx<T> twN(const cx<T> *pool, const FftPlan &p, int64_t m) {
-    const cx<T> lo = pool[p.twlo + (m & 1023)];
-    const cx<T> hi = pool[p.twhi + (m >> 10)];
-    return cmul(hi, lo);
-}
-
-template <typename T>
-__device__ __forceinline__ T load_as(const void *p, int f64, int64_t i) {
-    return f64 ? (T)((const double *)p)[i] : (T)((const float *)p)[i];
-}
-
-// mirrored, padded extension of r = a - b at real index t
-template <typename T>
-__device__ __forceinline__ T ext_at(const FftArgs &a, int64_t s0, int n, int64_t t) {
-    int64_t u = t < n ? t : (t < 2 * (int64_t)n ? 2 * (int64_t)n - 1 - t : 0);
-    T v = load_as<T>(a.in_a, a.in_a_f64, s0 + u);
-    if (a.in_b) v -= load_as<T>(a.in_b, a.in_b_f64, s0 + u);
-    return v;
 }
 
 // ------------------------------------------------------------- pass 1
@@ -233,7 +147,7 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
         buf[i] = v;
     }
     __syncthreads();
-    const cx<T> *res = lds_fft<-1>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
+    const cx<T> *res = lds_fft<-1, C3_NT>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
         const int k1 = i >> lb, c = i & (B - 1);
         const int j2 = col0 + c;
@@ -260,10 +174,12 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
         const int k1 = i >> lb, c = i & (B - 1);
         const int j2 = col0 + c;
-        buf[i] = j2 < M2 ? Y[(int64_t)k1 * M2 + j2] : cx<T>{0, 0};
+        // times w_M^(-j2 k1) = conj(w_N^(2 j2 k1)), the inverse of pass 1's twiddle
+        buf[i] = j2 < M2 ? cmulc(Y[(int64_t)k1 * M2 + j2], twN(pool, p, 2 * (int64_t)j2 * k1))
+                         : cx<T>{0, 0};
     }
     __syncthreads();
-    const cx<T> *res = lds_fft<1>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
+    const cx<T> *res = lds_fft<1, C3_NT>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
     T *out = (T *)a.out + sg.samp_off;
     const int n = sg.n;
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
@@ -393,9 +309,10 @@ __device__ __forceinline__ void whittle_mode(const ModeCtx &mc, int64_t k, cx<T>
 
 // ------------------------------------------------------------- pass 2
 template <typename T, int MODE>
-__global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
+__global__ __launch_bounds__(C3_ROW_NT) void k_row(FftArgs a) {
+    constexpr int NT = C3_ROW_NT;
     cx<T> *bufs = (cx<T> *)c3_dyn_lds;  // 2 x (2 * M2) elements (sized per launch)
-    __shared__ double red[3][C3_NT / 64];
+    __shared__ double red[3][NT / 64];
     const int2 task = a.row_tasks[blockIdx.x];
     const int seg = task.x;
     const SegInfo sg = a.segs[seg];
@@ -409,12 +326,12 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
 
     const int nel = M2 << two;
-    for (int i = threadIdx.x; i < M2; i += C3_NT) {
+    for (int i = threadIdx.x; i < M2; i += NT) {
         bufs[i * si] = Y[(int64_t)ka * M2 + i];
         if (two) bufs[i * si + 1] = Y[(int64_t)kb * M2 + i];
     }
     __syncthreads();
-    cx<T> *buf = lds_fft<-1>(bufs, bufs + nel, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+    cx<T> *buf = lds_fft<-1, NT>(bufs, bufs + nel, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
     cx<T> *spare = buf == bufs ? bufs + nel : bufs;
 
     ModeCtx mc;
@@ -440,7 +357,7 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
     const T osc = (T)mc.outscale;
 
     // pair (element e of row a, its mirror-mode partner)
-    for (int k2 = threadIdx.x; k2 < M2; k2 += C3_NT) {
+    for (int k2 = threadIdx.x; k2 < M2; k2 += NT) {
         int pk2, prow;  // partner position
         if (ka == 0) {
             pk2 = (M2 - k2) % M2;
@@ -494,11 +411,10 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
     }
     if (MODE == 0) {
         __syncthreads();
-        const cx<T> *res = lds_fft<1>(buf, spare, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
-        for (int i = threadIdx.x; i < M2; i += C3_NT) {
-            // times w_M^(-j2 k1) = conj(w_N^(2 j2 k1))
-            Y[(int64_t)ka * M2 + i] = cmulc(res[i * si], twN(pool, p, 2 * (int64_t)i * ka));
-            if (two) Y[(int64_t)kb * M2 + i] = cmulc(res[i * si + 1], twN(pool, p, 2 * (int64_t)i * kb));
+        const cx<T> *res = lds_fft<1, NT>(buf, spare, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+        for (int i = threadIdx.x; i < M2; i += NT) {
+            Y[(int64_t)ka * M2 + i] = res[i * si];
+            if (two) Y[(int64_t)kb * M2 + i] = res[i * si + 1];
         }
     } else {
         // block reduction of the Whittle sums
@@ -511,7 +427,7 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
         __syncthreads();
         if (threadIdx.x < 3) {
             double x = 0;
-            for (int w = 0; w < C3_NT / 64; ++w) x += red[threadIdx.x][w];
+            for (int w = 0; w < NT / 64; ++w) x += red[threadIdx.x][w];
             atomicAdd(&a.whittle[(int64_t)seg * 4 + threadIdx.x], x);
         }
     }
@@ -521,22 +437,48 @@ __global__ __launch_bounds__(C3_NT) void k_row(FftArgs a) {
 
 namespace c3 {
 
-hipError_t launch_fft_pass(hipStream_t st, int mixed, const FftArgs &a, int pass) {
-    dim3 b(C3_NT);
+hipError_t fft_init_attributes() {
+    static hipError_t done = hipErrorNotReady;
+    if (done == hipSuccess) return done;
+    const int lim = C3_LDS_MAX - 1024;  // room for the static reduction array (384 B)
+    hipError_t e = hipSuccess;
+    auto set = [&](const void *f) {
+        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (r != hipSuccess) e = r;
+    };
+    set((const void *)k_col_fwd<float>);
+    set((const void *)k_col_inv<float>);
+    set((const void *)k_col_fwd<double>);
+    set((const void *)k_col_inv<double>);
+    set((const void *)k_row<float, 0>);
+    set((const void *)k_row<float, 1>);
+    set((const void *)k_row<double, 0>);
+    set((const void *)k_row<double, 1>);
+    done = e;
+    return e;
+}
+
+hipError_t launch_fft_pass(hipStream_t st, int mixed, const FftArgs &a, int pass, int m1reg) {
     if (pass == 1 && a.nrow_tasks <= 0) return hipSuccess;
     if (pass != 1 && a.ncol_tasks <= 0) return hipSuccess;
-    const dim3 gc(a.ncol_tasks), gr(a.nrow_tasks);
+    if (pass != 1 && m1reg > 0) return launch_fft_col_reg(st, mixed, a, pass, m1reg);
     const unsigned lc = (unsigned)a.col_lds, lr = (unsigned)a.row_lds;
+    if ((pass == 1 ? lr : lc) > 65536u) {
+        hipError_t e = fft_init_attributes();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 b(C3_NT), br(C3_ROW_NT);
+    const dim3 gc(a.ncol_tasks), gr(a.nrow_tasks);
     if (mixed) {
         if (pass == 0) hipLaunchKernelGGL(k_col_fwd<float>, gc, b, lc, st, a);
         else if (pass == 2) hipLaunchKernelGGL(k_col_inv<float>, gc, b, lc, st, a);
-        else if (a.mode == 0) hipLaunchKernelGGL((k_row<float, 0>), gr, b, lr, st, a);
-        else hipLaunchKernelGGL((k_row<float, 1>), gr, b, lr, st, a);
+        else if (a.mode == 0) hipLaunchKernelGGL((k_row<float, 0>), gr, br, lr, st, a);
+        else hipLaunchKernelGGL((k_row<float, 1>), gr, br, lr, st, a);
     } else {
         if (pass == 0) hipLaunchKernelGGL(k_col_fwd<double>, gc, b, lc, st, a);
         else if (pass == 2) hipLaunchKernelGGL(k_col_inv<double>, gc, b, lc, st, a);
-        else if (a.mode == 0) hipLaunchKernelGGL((k_row<double, 0>), gr, b, lr, st, a);
-        else hipLaunchKernelGGL((k_row<double, 1>), gr, b, lr, st, a);
+        else if (a.mode == 0) hipLaunchKernelGGL((k_row<double, 0>), gr, br, lr, st, a);
+        else hipLaunchKernelGGL((k_row<double, 1>), gr, br, lr, st, a);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,303 @@
+// Column passes of the four-step n_corr FFT (section 4.2) with the column
+// length M1 fixed at compile time.
+//
+// One lane owns one column j2 of a segment: it loads the M1 elements
+// z[M2 j1 + j2] (consecutive lanes read consecutive addresses), runs the whole
+// FFT_M1 in registers as unrolled Stockham stages whose twiddles are folded to
+// constants at compile time, applies the four-step twiddle w_M^(j2 k1) and
+// writes Y[k1][j2].  No LDS and no barriers: every lane keeps 2 M1 loads in
+// flight, which is what hides HBM latency in this pass.  The inverse kernel
+// takes Y[k1][j2] times w_M^(-j2 k1), inverts the column and writes the first
+// n real samples.  The LDS-tiled column kernels in fft.hip cover every other
+// M1 and the FP64 path.
+#include <utility>
+
+#include "common.h"
+#include "fftdev.h"
+
+namespace {
+using c3::FftArgs;
+using namespace c3fft;
+
+// ------------------------------------------ compile-time twiddle constants
+// cos and sin of 2 pi m / L: the angle is reduced to [0, pi/2) with integer
+// arithmetic (quarter turns are exact), then summed as Taylor series; 14
+// terms at |x| <= pi/2 leave a truncation error below 1e-20.
+constexpr double kQuarterTurn = 1.570796326794896619231321691639751442;
+
+constexpr double taylor_sin(double x) {
+    double t = x, s = x;
+    for (int i = 1; i < 14; ++i) {
+        t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double taylor_cos(double x) {
+    double t = 1.0, s = 1.0;
+    for (int i = 1; i < 14; ++i) {
+        t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+        s += t;
+    }
+    return s;
+}
+struct CS {
+    double c, s;
+};
+constexpr CS cis2pi(long m, long L) {
+    m %= L;
+    if (m < 0) m += L;
+    const long q = (4 * m) / L;      // whole quarter turns
+    const long r = 4 * m - q * L;    // remainder, in units of (pi/2) / L
+    const double th = kQuarterTurn * (double)r / (double)L;
+    double c = taylor_cos(th), s = taylor_sin(th);
+    for (long i = 0; i < q; ++i) {   // rotate by a quarter turn: (c, s) -> (-s, c)
+        const double t = c;
+        c = -s;
+        s = t;
+    }
+    return {c, s};
+}
+
+// ------------------------------------------ radix plan of a 5-smooth length
+struct RadPlan {
+    int n;       // number of stages (-1: not 5-smooth)
+    int r[16];   // radices in stage order
+};
+constexpr RadPlan rad_plan(int L) {
+    RadPlan p{0, {0}};
+    int a = 0, b = 0, c = 0;
+    while (L % 2 == 0) { L /= 2; ++a; }
+    while (L % 3 == 0) { L /= 3; ++b; }
+    while (L % 5 == 0) { L /= 5; ++c; }
+    while (a > 4 || a == 3) { p.r[p.n++] = 8; a -= 3; }
+    if (a == 4) { p.r[p.n++] = 4; p.r[p.n++] = 4; }
+    else if (a == 2) p.r[p.n++] = 4;
+    else if (a == 1) p.r[p.n++] = 2;
+    for (int i = 0; i < b; ++i) p.r[p.n++] = 3;
+    for (int i = 0; i < c; ++i) p.r[p.n++] = 5;
+    if (L != 1) p.n = -1;
+    return p;
+}
+constexpr int stage_ns(int L, int s) {  // product of the radices before stage s
+    const RadPlan p = rad_plan(L);
+    int ns = 1;
+    for (int i = 0; i < s; ++i) ns *= p.r[i];
+    return ns;
+}
+
+// v *= w_NSR^E with w = e^(DIR 2 pi i / NSR); quarter turns as swaps
+template <int DIR, int NSR, int E, typename T>
+__device__ __forceinline__ void twiddle(cx<T> &v) {
+    constexpr int m = ((DIR * E) % NSR + NSR) % NSR;
+    if constexpr (m == 0) {
+    } else if constexpr (4 * m == NSR) {
+        v = cx<T>{-v.y, v.x};
+    } else if constexpr (2 * m == NSR) {
+        v = cx<T>{-v.x, -v.y};
+    } else if constexpr (4 * m == 3 * NSR) {
+        v = cx<T>{v.y, -v.x};
+    } else {
+        constexpr CS w = cis2pi(m, NSR);
+        v = cmul(v, cx<T>{(T)w.c, (T)w.s});
+    }
+}
+
+// butterfly J of a Stockham stage (radix R, NS points already combined):
+// inputs x[J + t L/R], outputs y[(J / NS) NS R + J % NS + t NS]
+template <int L, int DIR, int R, int NS, int J, typename T, int... t>
+__device__ __forceinline__ void butterfly(const cx<T> *x, cx<T> *y, std::integer_sequence<int, t...>) {
+    constexpr int LR = L / R, k = J % NS, jd = J / NS;
+    cx<T> v[R] = {x[J + t * LR]...};
+    (twiddle<DIR, NS * R, t * k>(v[t]), ...);
+    dft<R, DIR>(v);
+    ((y[jd * NS * R + k + t * NS] = v[t]), ...);
+}
+
+template <int L, int DIR, int S, typename T, int... J>
+__device__ __forceinline__ void stage(const cx<T> *x, cx<T> *y, std::integer_sequence<int, J...>) {
+    constexpr RadPlan P = rad_plan(L);
+    constexpr int R = P.r[S];
+    constexpr int NS = stage_ns(L, S);
+    (butterfly<L, DIR, R, NS, J>(x, y, std::make_integer_sequence<int, R>{}), ...);
+}
+
+template <int L, int DIR, int S, typename T>
+__device__ __forceinline__ void stages(cx<T> *x, cx<T> *y) {
+    constexpr RadPlan P = rad_plan(L);
+    if constexpr (S < P.n) {
+        stage<L, DIR, S>(x, y, std::make_integer_sequence<int, L / P.r[S]>{});
+        stages<L, DIR, S + 1>(y, x);
+    }
+}
+
+// in-register FFT of length L (DIR -1 forward, +1 inverse, unnormalised)
+template <int L, int DIR, typename T>
+__device__ __forceinline__ void reg_fft(cx<T> (&x)[L]) {
+    constexpr RadPlan P = rad_plan(L);
+    static_assert(P.n > 0, "column length must be 5-smooth and > 1");
+    cx<T> y[L];
+    stages<L, DIR, 0>(x, y);
+    if constexpr (P.n % 2 == 1) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) x[i] = y[i];
+    }
+}
+
+// split k1 = a Q + b for the four-step twiddle: Q + M1/Q table reads per lane
+constexpr int tw_split(int M1) {
+    int q = 1;
+    while (q * q < M1) ++q;
+    return q;
+}
+
+// word 3 of a raw buffer resource on gfx9-family chips (untyped dword access)
+#define C3_BUF_WORD3 0x00020000
+
+// Loads and stores below address a uniform (scalar) base plus a 32-bit lane
+// offset, so the compiler needs no 64-bit address per element.
+template <typename V>
+__device__ __forceinline__ V ld_off(const void *base, uint32_t byte_off) {
+    return *(const V *)((const char *)base + byte_off);
+}
+template <typename V>
+__device__ __forceinline__ void st_off(void *base, uint32_t byte_off, V v) {
+    *(V *)((char *)base + byte_off) = v;
+}
+
+// f(k1, w_M^(j2 k1)) for k1 < M1, with w_M^(j2 (a Q + b)) = w_M^(j2 Q a) w_M^(j2 b)
+// from the two-level w_N table (N = 2M); each factor is used as soon as it is
+// formed, so no table of M1 twiddles is held in registers
+template <int M1, int Q, typename F>
+__device__ __forceinline__ void col_twiddles(const cx<float> *pool, const FftPlan &p, int j2, F &&f) {
+    cx<float> wb[Q];
+#pragma unroll
+    for (int b = 0; b < Q; ++b) wb[b] = twN(pool, p, 2 * (int64_t)j2 * b);
+#pragma unroll
+    for (int ai = 0; ai * Q < M1; ++ai) {
+        const cx<float> wa = twN(pool, p, 2 * (int64_t)j2 * Q * ai);
+#pragma unroll
+        for (int b = 0; b < Q; ++b)
+            if (ai * Q + b < M1) f(ai * Q + b, cmul(wa, wb[b]));
+    }
+}
+
+// ------------------------------------------------------------- pass 1
+template <int M1>
+__global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
+    const int2 task = a.col_tasks[blockIdx.x];
+    const SegInfo sg = a.segs[task.x];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M2 = p.M2;
+    const int j2 = task.y + (int)threadIdx.x;
+    if (j2 >= M2) return;
+    const uint32_t n = (uint32_t)sg.n, n2 = 2u * (uint32_t)sg.n;
+    cx<float> x[M1];
+    if (!a.in_b && !a.in_a_f64) {
+        // r = in_a (FP32): the sweep's residual
+        const float *r = (const float *)a.in_a + sg.samp_off;
+#pragma unroll
+        for (int j1 = 0; j1 < M1; ++j1) {
+            const uint32_t t = 2u * (uint32_t)(M2 * j1 + j2);
+            const uint32_t u0 = t < n ? t : (t < n2 ? n2 - 1u - t : 0u);
+            const uint32_t u1 = t + 1u < n ? t + 1u : (t + 1u < n2 ? n2 - 2u - t : 0u);
+            x[j1] = cx<float>{ld_off<float>(r, 4u * u0), ld_off<float>(r, 4u * u1)};
+            // keep the scheduler from computing every offset before the first
+            // load: 16 rows (32 loads per lane) in flight is plenty
+            if ((j1 & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        }
+    } else {
+        // r = in_a - in_b in any input precision, rounded to FP32
+        const int64_t s0 = sg.samp_off;
+#pragma unroll
+        for (int j1 = 0; j1 < M1; ++j1) {
+            const uint32_t t = 2u * (uint32_t)(M2 * j1 + j2);
+            float v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t th = t + (uint32_t)h;
+                const uint32_t u = th < n ? th : (th < n2 ? n2 - 1u - th : 0u);
+                v[h] = load_as<float>(a.in_a, a.in_a_f64, s0 + u);
+                if (a.in_b) v[h] -= load_as<float>(a.in_b, a.in_b_f64, s0 + u);
+            }
+            x[j1] = cx<float>{v[0], v[1]};
+        }
+    }
+    reg_fft<M1, -1>(x);
+    // the twiddle-table loads below must not be hoisted into the FFT, where
+    // every register already holds column data
+    __builtin_amdgcn_sched_barrier(0);
+    cx<float> *Y = (cx<float> *)a.work + sg.scr_off;
+    const uint32_t lo = 8u * (uint32_t)j2;
+    col_twiddles<M1, tw_split(M1)>((const cx<float> *)a.twpool, p, j2, [&](int k1, cx<float> w) {
+        st_off(Y + (int64_t)k1 * M2, lo, cmul(x[k1], w));
+    });
+}
+
+// ------------------------------------------------------------- pass 3
+template <int M1>
+__global__ __launch_bounds__(C3_COL_NT) void k_colr_inv(FftArgs a) {
+    const int2 task = a.col_tasks[blockIdx.x];
+    const SegInfo sg = a.segs[task.x];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M2 = p.M2;
+    const int j2 = task.y + (int)threadIdx.x;
+    if (j2 >= M2) return;
+    const cx<float> *Y = (const cx<float> *)a.work + sg.scr_off;
+    const uint32_t lo = 8u * (uint32_t)j2;
+    cx<float> x[M1];
+#pragma unroll
+    for (int k1 = 0; k1 < M1; ++k1) x[k1] = ld_off<cx<float>>(Y + (int64_t)k1 * M2, lo);
+    col_twiddles<M1, tw_split(M1)>((const cx<float> *)a.twpool, p, j2, [&](int k1, cx<float> w) {
+        x[k1] = cmulc(x[k1], w);  // times w_M^(-j2 k1)
+    });
+    reg_fft<M1, 1>(x);
+    // the first n real samples: a raw buffer of n floats, whose hardware range
+    // check drops the stores at t >= n (no per-element branch)
+    const __amdgpu_buffer_rsrc_t out =
+        __builtin_amdgcn_make_buffer_rsrc((float *)a.out + sg.samp_off, 0, 4 * sg.n, C3_BUF_WORD3);
+#pragma unroll
+    for (int j1 = 0; j1 < M1; ++j1) {
+        const uint32_t t = 2u * (uint32_t)(M2 * j1 + j2);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[j1].x), out, (int)(4u * t), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x[j1].y), out, (int)(4u * t + 4u), 0, 0);
+    }
+}
+
+}  // namespace
+
+namespace c3 {
+
+bool fft_col_reg_supported(int mixed, int m1) {
+    if (!mixed) return false;
+    switch (m1) {
+#define C3_SUP(M) case M:
+        C3_COLREG_LIST(C3_SUP)
+        return true;
+#undef C3_SUP
+    default:
+        return false;
+    }
+}
+
+hipError_t launch_fft_col_reg(hipStream_t st, int mixed, const FftArgs &a, int pass, int m1) {
+    if (!mixed || (pass != 0 && pass != 2)) return hipErrorInvalidValue;
+    if (a.ncol_tasks <= 0) return hipSuccess;
+    const dim3 g(a.ncol_tasks), b(C3_COL_NT);
+    switch (m1) {
+#define C3_CASE(M)                                                     \
+    case M:                                                            \
+        if (pass == 0)                                                 \
+            hipLaunchKernelGGL(k_colr_fwd<M>, g, b, 0, st, a);         \
+        else                                                           \
+            hipLaunchKernelGGL(k_colr_inv<M>, g, b, 0, st, a);         \
+        break;
+        C3_COLREG_LIST(C3_CASE)
+#undef C3_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace c3

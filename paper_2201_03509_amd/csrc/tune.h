@@ -4,9 +4,12 @@
 // The paper measured FFT cost against length and cut each chunk to a cheap
 // length (section 4.2); here every segment keeps all its samples, the length
 // is padded to a 5-smooth size, and what is measured per size is the way the
-// transform is split (M = M1 x M2), the column-tile width and the radix order.
+// transform is split (M = M1 x M2), the column kernel (register columns for a
+// compiled M1, or LDS tiles of B columns), the tile width and the radix order.
 #pragma once
 #include <stdint.h>
+
+#include "common.h"
 
 #include <cstdio>
 #include <map>
@@ -18,8 +21,27 @@ namespace c3tune {
 
 struct FftChoice {
     int M1 = 1, M2 = 1, B = 1;
+    int colreg = 0;  // 1: register column kernels (M1 compiled in)
     std::vector<int> r1, r2;
 };
+
+// longest row the row pass holds: two rows, two ping-pong buffers, within the
+// LDS of one workgroup (160 KB), less room for the static reduction array
+inline int row_cap(int mixed) { return mixed ? 5040 : 2520; }
+// complex elements of one LDS column tile buffer (two buffers per block)
+inline int col_tile(int mixed) { return mixed ? 4096 : 2048; }
+
+inline bool colreg_ok(int mixed, int64_t m1) {
+    if (!mixed) return false;
+    switch (m1) {
+#define C3_TUNE_OK(M) case M:
+        C3_COLREG_LIST(C3_TUNE_OK)
+        return true;
+#undef C3_TUNE_OK
+    default:
+        return false;
+    }
+}
 
 inline std::vector<int> factor235(int64_t L) {
     std::vector<int> f;
@@ -68,18 +90,23 @@ inline int pow2ceil(int x) {
     return p;
 }
 
-// S: complex elements one block holds in LDS (8192 FP32, 4096 FP64)
-inline bool make_choice(int64_t M, int64_t M2, int S, int bmax, int order, FftChoice &c) {
+inline bool make_choice(int64_t M, int64_t M2, int mixed, int bmax, int order, int colreg,
+                        FftChoice &c) {
     if (M2 < 1 || M % M2) return false;
     const int64_t M1 = M / M2;
-    if (2 * M2 > S || M1 > S) return false;
+    if (M2 > row_cap(mixed)) return false;
+    if (colreg ? !colreg_ok(mixed, M1) : M1 > col_tile(mixed)) return false;
     c.M1 = (int)M1;
     c.M2 = (int)M2;
-    int B = pow2floor((int)(S / M1));
-    if (B > bmax) B = bmax;
-    const int bc = pow2ceil((int)M2);
-    if (B > bc) B = bc;
-    if (B < 1) B = 1;
+    c.colreg = colreg;
+    int B = 1;
+    if (!colreg) {
+        B = pow2floor((int)(col_tile(mixed) / M1));
+        if (B > bmax) B = bmax;
+        const int bc = pow2ceil((int)M2);
+        if (B > bc) B = bc;
+        if (B < 1) B = 1;
+    }
     c.B = B;
     c.r1 = radices(M1, order);
     c.r2 = radices(M2, order);
@@ -87,29 +114,52 @@ inline bool make_choice(int64_t M, int64_t M2, int S, int bmax, int order, FftCh
     return true;
 }
 
-inline bool default_choice(int64_t M, int S, FftChoice &c) {
-    // largest row length that fits, so the row pass (which carries the filter
-    // and the draws) sees long contiguous rows
-    int64_t best = 0;
-    for (int64_t m2 = 1; m2 * 2 <= S && m2 <= M; ++m2)
-        if (M % m2 == 0 && M / m2 <= S) best = m2;
-    if (!best) return false;
-    return make_choice(M, best, S, 64, 0, c);
+// row lengths of the LDS-tiled splits, ascending
+inline std::vector<int64_t> lds_rows(int64_t M, int mixed) {
+    std::vector<int64_t> m2s;
+    for (int64_t m2 = 1; m2 <= row_cap(mixed) && m2 <= M; ++m2)
+        if (M % m2 == 0 && M / m2 <= col_tile(mixed)) m2s.push_back(m2);
+    return m2s;
+}
+// column lengths of the register splits, ascending
+inline std::vector<int64_t> reg_cols(int64_t M, int mixed) {
+    std::vector<int64_t> m1s;
+    for (int64_t m1 = 2; m1 <= 81 && m1 <= M; ++m1)
+        if (M % m1 == 0 && M / m1 <= row_cap(mixed) && colreg_ok(mixed, m1)) m1s.push_back(m1);
+    return m1s;
 }
 
-inline std::vector<FftChoice> candidates(int64_t M, int S) {
+inline bool default_choice(int64_t M, int mixed, FftChoice &c) {
+    // register columns where a compiled M1 fits: the largest M1 up to 64
+    // (fewest row-pass stages at two waves per SIMD in the column kernels),
+    // else the largest; otherwise LDS column tiles with the longest rows
+    const std::vector<int64_t> m1s = reg_cols(M, mixed);
+    if (!m1s.empty()) {
+        int64_t pick = m1s.back();
+        for (int64_t m1 : m1s)
+            if (m1 <= 64) pick = m1;
+        return make_choice(M, M / pick, mixed, 64, 0, 1, c);
+    }
+    const std::vector<int64_t> m2s = lds_rows(M, mixed);
+    if (m2s.empty()) return false;
+    return make_choice(M, m2s.back(), mixed, 64, 0, 0, c);
+}
+
+inline std::vector<FftChoice> candidates(int64_t M, int mixed) {
     std::vector<FftChoice> out;
-    std::vector<int64_t> m2s;
-    for (int64_t m2 = 1; m2 * 2 <= S && m2 <= M; ++m2)
-        if (M % m2 == 0 && M / m2 <= S) m2s.push_back(m2);
-    // the few largest row lengths, two tile widths, two radix orders
-    const size_t k0 = m2s.size() > 3 ? m2s.size() - 3 : 0;
+    for (int64_t m1 : reg_cols(M, mixed))
+        for (int order : {0, 1}) {
+            FftChoice c;
+            if (make_choice(M, M / m1, mixed, 64, order, 1, c)) out.push_back(c);
+        }
+    // the two longest LDS-tiled rows, two radix orders
+    const std::vector<int64_t> m2s = lds_rows(M, mixed);
+    const size_t k0 = m2s.size() > 2 ? m2s.size() - 2 : 0;
     for (size_t i = k0; i < m2s.size(); ++i)
-        for (int bmax : {16, 64})
-            for (int order : {0, 1}) {
-                FftChoice c;
-                if (make_choice(M, m2s[i], S, bmax, order, c)) out.push_back(c);
-            }
+        for (int order : {0, 1}) {
+            FftChoice c;
+            if (make_choice(M, m2s[i], mixed, 16, order, 0, c)) out.push_back(c);
+        }
     return out;
 }
 
@@ -134,8 +184,9 @@ inline std::string to_json(const Table &t, const std::map<std::string, int> &str
     for (auto &kv : t.m) {
         const FftChoice &c = kv.second;
         char buf[256];
-        snprintf(buf, sizeof(buf), "%s    {\"mixed\": %d, \"M\": %lld, \"M1\": %d, \"M2\": %d, \"B\": %d, \"r1\": [",
-                 first ? "" : ",\n", kv.first.first, (long long)kv.first.second, c.M1, c.M2, c.B);
+        snprintf(buf, sizeof(buf),
+                 "%s    {\"mixed\": %d, \"M\": %lld, \"M1\": %d, \"M2\": %d, \"B\": %d, \"colreg\": %d, \"r1\": [",
+                 first ? "" : ",\n", kv.first.first, (long long)kv.first.second, c.M1, c.M2, c.B, c.colreg);
         s += buf;
         for (size_t i = 0; i < c.r1.size(); ++i) s += (i ? ", " : "") + std::to_string(c.r1[i]);
         s += "], \"r2\": [";
@@ -185,8 +236,14 @@ inline bool from_json(const std::string &s, Table &t, std::map<std::string, int>
     while (true) {
         size_t o = s.find('{', q + 1);
         if (o == std::string::npos || (fend != std::string::npos && o > fend)) break;
-        long long mixed, M, M1, M2, B;
+        long long mixed, M, M1, M2, B, colreg = 0;
         if (num_after(o, "\"mixed\"", mixed) == std::string::npos) break;
+        {
+            // optional field: only read if it belongs to this record
+            const size_t q_end = s.find('}', o);
+            const size_t q_cr = s.find("\"colreg\"", o);
+            if (q_cr != std::string::npos && q_cr < q_end) num_after(o, "\"colreg\"", colreg);
+        }
         num_after(o, "\"M\"", M);
         num_after(o, "\"M1\"", M1);
         num_after(o, "\"M2\"", M2);
@@ -195,6 +252,7 @@ inline bool from_json(const std::string &s, Table &t, std::map<std::string, int>
         c.M1 = (int)M1;
         c.M2 = (int)M2;
         c.B = (int)B;
+        c.colreg = (int)colreg;
         list_after(o, "\"r1\"", c.r1);
         q = list_after(o, "\"r2\"", c.r2);
         if (q == std::string::npos) break;
