@@ -114,6 +114,7 @@ struct tod_ctx_s {
     uint32_t *d_err = nullptr;
     uint64_t *d_seed_iter = nullptr;
     DevBuf trig32, trig64, work, seg_sums, seg_whittle, probe_counts, resid;
+    DevBuf dec_tabs;                      // decoding tables, rebuilt by every decode
     std::map<uint64_t, std::unique_ptr<Plan>> plans;
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
@@ -703,9 +704,10 @@ tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay, const tod_huff *p
     const DecodeTask *tasks;
     int nt;
     if ((r = get_decode_tasks(ctx, P, pix->chunk_len, &tasks, &nt)) != TOD_OK) return r;
+    HIPCHK(ctx->dec_tabs.ensure(sizeof(DecTab) * (size_t)(pix->ntable + psi->ntable)));
     KTimer kt(ctx, K_DECODE, ctx->stream);
     HIPCHK(c3::launch_decode(ctx->stream, make_layout_dev(lay), make_huff_dev(pix), make_huff_dev(psi),
-                             tasks, nt, pix_out, psi_out, ctx->d_err));
+                             (DecTab *)ctx->dec_tabs.p, tasks, nt, pix_out, psi_out, ctx->d_err));
     return TOD_OK;
 }
 
@@ -897,6 +899,7 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     const DecodeTask *dt;
     int ndt;
     if ((r = get_decode_tasks(ctx, P, pix->chunk_len, &dt, &ndt)) != TOD_OK) return r;
+    HIPCHK(ctx->dec_tabs.ensure(sizeof(DecTab) * (size_t)(pix->ntable + psi->ntable)));
     hipStream_t st = ctx->stream;
     const LayoutDev Ld = make_layout_dev(lay);
 
@@ -904,7 +907,7 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     uint64_t gk = 1469598103934665603ull;
     const void *ptrs[] = {pix->words, psi->words, pix->tables, psi->tables, d, maps, gain, sigma0,
                           fknee, alpha, ncorr_out, acc, pix_work, psi_work, ctx->work.p,
-                          ctx->resid.p, P->segs.p};
+                          ctx->resid.p, P->segs.p, ctx->dec_tabs.p};
     gk = fnv(gk, ptrs, sizeof(ptrs));
     gk = fnv(gk, &P->key, sizeof(P->key));
     gk = fnv(gk, &d_dtype, sizeof(d_dtype));
@@ -922,8 +925,9 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     auto run = [&](bool capture) -> tod_status {
         {
             KTimer kt(ctx, K_DECODE, st);
-            HIPCHK(c3::launch_decode(st, Ld, make_huff_dev(pix), make_huff_dev(psi), dt, ndt, pix_work,
-                                     psi_work, ctx->d_err));
+            HIPCHK(c3::launch_decode(st, Ld, make_huff_dev(pix), make_huff_dev(psi),
+                                     (DecTab *)ctx->dec_tabs.p, dt, ndt, pix_work, psi_work,
+                                     ctx->d_err));
         }
         const int4 *tiles = (const int4 *)P->bin_tiles.p;
         int nt = P->nbin;

@@ -105,6 +105,20 @@ struct HuffDev {
     int32_t ntable;
 };
 
+// Canonical decoding table of one Huffman table blob, built on the device per
+// decode call (section 4.1 codes; canonical form of the encoder's lengths).
+#define C3_KLUT 12
+struct alignas(16) DecTab {
+    unsigned long long lim[34];  // left-justified limits (first_L + count_L) << (32 - L)
+    int32_t delta[34];           // off_L - first_L: symbol index = code + delta[L]
+    int32_t minlen, maxlen;
+    int32_t nsym;                // symbols with a code (sum of the counts)
+    int32_t ok;                  // 0: the table blob is not a valid prefix code
+    uint8_t lut[1 << C3_KLUT];   // code length shared by every code with this 12-bit
+                                 // prefix; 0 if the prefix holds several lengths or none
+    int32_t pad[2];
+};
+
 // Decode work item: one block decodes up to C3_NT consecutive chunks of one segment.
 struct DecodeTask {
     int32_t seg;
@@ -117,9 +131,10 @@ struct DecodeTask {
 // Implemented in the .hip files; all return hipError_t of the launch.
 namespace c3 {
 
+// tabs: workspace of hp.ntable + hs.ntable DecTab records (pixel tables first)
 hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
-                         const DecodeTask *tasks, int ntask, int32_t *pix_out, uint16_t *psi_out,
-                         uint32_t *err);
+                         DecTab *tabs, const DecodeTask *tasks, int ntask, int32_t *pix_out,
+                         uint16_t *psi_out, uint32_t *err);
 
 // r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs)
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,

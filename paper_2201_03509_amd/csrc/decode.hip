@@ -1,143 +1,171 @@
 // Huffman decode + undifferencing of the pointing streams (section 4.1).
 //
-// Work split: a block owns up to C3_NT consecutive chunks of one segment; each
-// thread parses one chunk of both streams (pixel and psi) from the side index,
-// G codes per round, and leaves symbol *indices* in an LDS tile.  The block
-// then walks the tile row by row (16 consecutive samples of one chunk per
-// 16-lane row): it fetches the symbol values, undoes the differencing with a
-// 16-lane inclusive scan plus the row's running value, range-checks and writes
-// contiguous runs.  The per-thread critical path is bit parsing only.
+// Two kernels per call.
 //
-// Canonical decoding: with the next 32 bits w of the stream left-justified,
-// the code length is the smallest L with w < lim[L], lim[L] = (first_L +
-// count_L) << (32 - L) (looked up on the first 12 bits when L <= 12); the
-// symbol is sym[off_L + (w >> (32-L)) - first_L].
+// k_tables turns every table blob into a DecTab: the canonical limits and a
+// 12-bit prefix table giving the code length of every prefix whose codes all
+// share one length.  The limit of a length L <= 12 is a multiple of 2^20 and
+// never splits a prefix, and each longer length splits at most one, so the
+// prefix table resolves the short codes and almost every long one too (the
+// psi differences are near-uniform on +-4095: almost all psi codes are longer
+// than 12 bits); only codes behind one of the <= 20 split prefixes search the
+// limits.
+//
+// k_decode: a block owns up to C3_NT consecutive chunks of one segment; each
+// thread parses one chunk of both streams from the side index, G codes per
+// round, adds the symbol values to its running value (x_i = x_{i-1} + d_i),
+// range-checks, and leaves the samples in an LDS tile; the block then writes
+// the tile in rows of 16 consecutive samples of a chunk.
 #include "common.h"
 
 namespace {
 
-constexpr int G = 16;          // symbols per thread per round (one 16-lane row each)
+constexpr int G = 16;          // symbols per thread per round
 constexpr int GP = G + 1;      // padded LDS row (no bank conflicts on the column writes)
-constexpr int KLUT = 12;       // code-length lookup on the first 12 bits
+constexpr int SPLIT = 32 - C3_KLUT;
 
-struct Canon {
-    unsigned long long lim[34];
-    int32_t delta[34];         // off_L - first_L
-    int32_t minlen, maxlen;
-    const int32_t *sym;
-    uint8_t lut[1 << KLUT];    // code length for codes <= KLUT bits, else 0
-};
-
-__device__ void build_canon_serial(Canon &c, const uint32_t *blob) {
-    unsigned long long first = 0;
-    int32_t off = 0;
-    c.minlen = 33;
-    c.maxlen = 0;
-    for (int L = 1; L <= 32; ++L) {
-        uint32_t cnt = blob[1 + L];
-        c.delta[L] = off - (int32_t)first;
-        c.lim[L] = (first + cnt) << (32 - L);
-        if (cnt) {
-            if (c.minlen > 32) c.minlen = L;
-            c.maxlen = L;
-        }
-        off += cnt;
-        first = (first + cnt) << 1;
-    }
-    c.lim[0] = 0;
-    c.delta[0] = 0;
-    c.lim[33] = c.lim[32];
-    c.delta[33] = 0;
-    if (c.minlen > 32) c.minlen = 32;
-    c.sym = (const int32_t *)(blob + 34);
+// smallest L in [minlen, maxlen] with w < lim[L]; 0 if there is none
+__device__ __forceinline__ int code_len(const DecTab &T, unsigned long long w) {
+    for (int L = T.minlen; L <= T.maxlen; ++L)
+        if (w < T.lim[L]) return L;
+    return 0;
 }
 
-__device__ void build_lut(Canon &c, int tid) {
-    const int top = min(c.maxlen, KLUT);
-    for (int e = tid; e < (1 << KLUT); e += C3_NT) {
-        const unsigned long long w = (unsigned long long)e << (32 - KLUT);
-        uint8_t L = 0;
-        for (int l = c.minlen; l <= top; ++l)
-            if (w < c.lim[l]) {
-                L = (uint8_t)l;
-                break;
+__global__ __launch_bounds__(C3_NT) void k_tables(HuffDev hp, HuffDev hs, DecTab *tabs) {
+    __shared__ DecTab T;
+    const int b = blockIdx.x;
+    const bool is_p = b < hp.ntable;
+    const uint32_t *tables = is_p ? hp.tables : hs.tables;
+    const int64_t *table_off = is_p ? hp.table_off : hs.table_off;
+    const int t = is_p ? b : b - hp.ntable;
+    const uint32_t *blob = tables + table_off[t];
+    if (threadIdx.x == 0) {
+        // blob: [nsym, maxlen, count_1 .. count_32, symbols...]
+        unsigned long long first = 0;
+        int64_t off = 0;
+        int ok = 1;
+        T.minlen = 33;
+        T.maxlen = 0;
+        for (int L = 1; L <= 32; ++L) {
+            const uint32_t cnt = blob[1 + L];
+            T.delta[L] = (int32_t)(off - (int64_t)first);
+            const unsigned long long end = first + cnt;
+            if (end > (1ull << L)) ok = 0;  // more codes of length <= L than L bits hold
+            T.lim[L] = end << (32 - L);
+            if (cnt) {
+                if (T.minlen > 32) T.minlen = L;
+                T.maxlen = L;
             }
-        c.lut[e] = L;
+            off += cnt;
+            first = end << 1;
+        }
+        T.lim[0] = 0;
+        T.delta[0] = 0;
+        T.lim[33] = T.lim[32];
+        T.delta[33] = 0;
+        if (T.maxlen == 0 || off != (int64_t)blob[0]) ok = 0;
+        if (T.minlen > 32) T.minlen = 32;
+        T.nsym = ok ? (int32_t)off : 0;
+        T.ok = ok;
+        T.pad[0] = T.pad[1] = 0;
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < (1 << C3_KLUT); e += C3_NT) {
+        uint8_t v = 0;
+        if (T.ok) {
+            const unsigned long long w0 = (unsigned long long)e << SPLIT;
+            const unsigned long long w1 = w0 | ((1ull << SPLIT) - 1);
+            const int L0 = code_len(T, w0);
+            v = (L0 != 0 && L0 == code_len(T, w1)) ? (uint8_t)L0 : 0;
+        }
+        T.lut[e] = v;
+    }
+    __syncthreads();
+    const uint4 *src = (const uint4 *)&T;
+    uint4 *dst = (uint4 *)(tabs + b);
+    for (int i = threadIdx.x; i < (int)(sizeof(DecTab) / 16); i += C3_NT) dst[i] = src[i];
 }
 
-// MSB-first bit reader with two doublewords of look-ahead in registers
-struct BitReader {
-    const uint32_t *w;
-    int64_t wp, wend;
-    unsigned long long buf, n0, n1;
-    int nbits, nh;
-    int64_t consumed;
+// word 3 of a raw buffer resource on gfx9-family chips (untyped dword access)
+#define C3_BUF_WORD3 0x00020000
 
-    __device__ __forceinline__ unsigned long long load2(int64_t p) const {
-        const unsigned long long a = p < wend ? w[p] : 0u;
-        const unsigned long long b = p + 1 < wend ? w[p + 1] : 0u;
-        return (a << 32) | b;
+// block-uniform values (one segment per block) moved to scalar registers, so
+// that the buffer resources built from them are scalar
+__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ const void *uni(const void *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const void *)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void *base, int32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)uni(base), 0, uni(bytes), C3_BUF_WORD3);
+}
+
+// dword i of a raw buffer: 0 past its end (the hardware range check)
+__device__ __forceinline__ uint32_t buf_word(__amdgpu_buffer_rsrc_t r, uint32_t i) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)(4u * i), 0, 0);
+}
+
+// MSB-first bit reader over one segment's stream (a raw buffer, so reads
+// past the end give zero bits), two doublewords of look-ahead in registers
+struct BitReader {
+    __amdgpu_buffer_rsrc_t rs;
+    unsigned long long buf, n0, n1;
+    uint32_t wp;
+    int nbits, nh;
+
+    __device__ __forceinline__ unsigned long long load2(uint32_t p) const {
+        return ((unsigned long long)buf_word(rs, p) << 32) | buf_word(rs, p + 1u);
     }
-    __device__ void init(const uint32_t *words, int64_t nw, uint32_t bit) {
-        w = words;
-        wend = nw;
-        const int64_t p = bit >> 5;
+    __device__ void init(__amdgpu_buffer_rsrc_t r, uint32_t bit) {
+        rs = r;
+        const uint32_t p = bit >> 5;
         const int s = bit & 31;
         buf = load2(p) << s;
         nbits = 64 - s;
-        n0 = load2(p + 2);
-        n1 = load2(p + 4);
+        n0 = load2(p + 2u);
+        n1 = load2(p + 4u);
         nh = 2;
-        wp = p + 6;
-        consumed = bit;
+        wp = p + 6u;
     }
     __device__ __forceinline__ void refill() {
-        if (nbits < 32) {
-            buf |= (n0 >> 32) << (32 - nbits);
-            nbits += 32;
-            n0 <<= 32;
-            if (--nh == 0) {
-                n0 = n1;
-                nh = 2;
-                n1 = load2(wp);
-                wp += 2;
-            }
+        const bool need = nbits < 32;
+        const int sh = need ? 32 - nbits : 0;
+        buf |= need ? (n0 >> 32) << sh : 0ull;
+        nbits += need ? 32 : 0;
+        n0 = need ? n0 << 32 : n0;
+        nh -= need ? 1 : 0;
+        if (nh == 0) {  // every second refill: next doubleword from memory
+            n0 = n1;
+            nh = 2;
+            n1 = load2(wp);
+            wp += 2u;
         }
     }
-    // index of the next code's symbol in the table; sets bad on an invalid code
-    __device__ __forceinline__ int32_t next(const Canon &c, uint32_t &bad) {
+    // symbol index of the next code; L = its length (0: invalid code)
+    __device__ __forceinline__ int32_t next(const DecTab &T, int &L) {
         refill();
         const uint32_t win = (uint32_t)(buf >> 32);
-        int L = c.lut[win >> (32 - KLUT)];
-        if (L == 0) {
-            L = KLUT + 1;
-            while (L < c.maxlen && (unsigned long long)win >= c.lim[L]) ++L;
-            if (L > 32 || (unsigned long long)win >= c.lim[L]) {
-                bad |= C3_ERR_CODE;
-                L = c.maxlen;
-                buf <<= L;
-                nbits -= L;
-                consumed += L;
-                return 0;
-            }
-        }
-        const int32_t idx = (int32_t)(win >> (32 - L)) + c.delta[L];
-        buf <<= L;
-        nbits -= L;
-        consumed += L;
-        return idx;
+        L = T.lut[win >> SPLIT];
+        if (L == 0) L = code_len(T, win);  // split or invalid prefix (rare)
+        const int Lc = L ? L : 1;
+        const int32_t idx = (int32_t)(win >> (32 - Lc)) + T.delta[Lc];
+        buf <<= Lc;
+        nbits -= Lc;
+        return L ? idx : -1;
     }
 };
 
 __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, HuffDev hs,
+                                                  const DecTab *__restrict__ tabs,
                                                   const DecodeTask *__restrict__ tasks,
                                                   int32_t *__restrict__ pix_out,
                                                   uint16_t *__restrict__ psi_out, uint32_t *err) {
-    __shared__ Canon cp, cq;
+    __shared__ DecTab cp, cq;
     __shared__ int32_t tp[C3_NT * GP];
-    __shared__ int32_t tq[C3_NT * GP];
-    __shared__ int32_t carp[C3_NT], carq[C3_NT];
+    __shared__ uint16_t tq[C3_NT * GP];
+    __shared__ int32_t tqi_[C3_NT * GP];  // psi symbol indices of the round
     __shared__ uint32_t blk_err;
 
     const DecodeTask task = tasks[blockIdx.x];
@@ -150,14 +178,26 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
     const uint32_t npsi = (uint32_t)Ld.band[band].npsi;
 
-    if (tid == 0) {
-        build_canon_serial(cp, hp.tables + hp.table_off[hp.seg_table[seg]]);
-        blk_err = 0;
+    // this segment's two tables (an out-of-range table id is an invalid code)
+    const int tpi = hp.seg_table[seg], tqi = hs.seg_table[seg];
+    const bool tabs_ok = tpi >= 0 && tpi < hp.ntable && tqi >= 0 && tqi < hs.ntable;
+    {
+        const uint4 *sp = (const uint4 *)(tabs + (tabs_ok ? tpi : 0));
+        const uint4 *sq = (const uint4 *)(tabs + hp.ntable + (tabs_ok ? tqi : 0));
+        uint4 *dp = (uint4 *)&cp, *dq = (uint4 *)&cq;
+        for (int i = tid; i < (int)(sizeof(DecTab) / 16); i += C3_NT) {
+            dp[i] = sp[i];
+            dq[i] = sq[i];
+        }
+        if (tid == 0) blk_err = 0;
     }
-    if (tid == 64) build_canon_serial(cq, hs.tables + hs.table_off[hs.seg_table[seg]]);
     __syncthreads();
-    build_lut(cp, tid);
-    build_lut(cq, tid);
+    const bool codes_ok = tabs_ok && cp.ok && cq.ok;
+    // symbol arrays as raw buffers of nsym entries: an invalid index reads 0
+    const __amdgpu_buffer_rsrc_t symp =
+        raw_buffer(hp.tables + hp.table_off[tabs_ok ? tpi : 0] + 34, 4 * cp.nsym);
+    const __amdgpu_buffer_rsrc_t symq =
+        raw_buffer(hs.tables + hs.table_off[tabs_ok ? tqi : 0] + 34, 4 * cq.nsym);
 
     const int l = tid;
     const int c = task.chunk0 + l;
@@ -165,97 +205,96 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
     const int nch_idx = (int)min(hp.seg_chunk_off[seg + 1] - hp.seg_chunk_off[seg],
                                  hs.seg_chunk_off[seg + 1] - hs.seg_chunk_off[seg]);
     const bool active = l < task.nchunk && c < nch_idx;
-    uint32_t bad = 0;
+    uint32_t bad = codes_ok ? 0u : C3_ERR_CODE;
     if (l < task.nchunk && c >= nch_idx) bad |= C3_ERR_CHUNK;
     BitReader rp, rq;
     int ns = 0;
+    int32_t xp = 0, xq = 0;      // running (undifferenced) values
+    int32_t bitp = 0, bitq = 0;  // bits consumed by this chunk's codes
+    uint32_t start_p = 0, start_q = 0;
+    // the two streams of this segment as raw buffers (at most 2^30 words each)
+    const int64_t wp0 = hp.seg_word_off[seg], wq0 = hs.seg_word_off[seg];
+    const int64_t nwp = hp.seg_word_off[seg + 1] - wp0, nwq = hs.seg_word_off[seg + 1] - wq0;
+    if (nwp >= (1ll << 30) || nwq >= (1ll << 30) || nwp < 0 || nwq < 0) bad |= C3_ERR_CHUNK;
+    const __amdgpu_buffer_rsrc_t rsp =
+        raw_buffer(hp.words + wp0, (int32_t)(4 * min(max(nwp, (int64_t)0), (int64_t)(1 << 29))));
+    const __amdgpu_buffer_rsrc_t rsq =
+        raw_buffer(hs.words + wq0, (int32_t)(4 * min(max(nwq, (int64_t)0), (int64_t)(1 << 29))));
     if (active) {
         const int64_t gp = hp.seg_chunk_off[seg] + c;
         const int64_t gq = hs.seg_chunk_off[seg] + c;
-        const int64_t wp0 = hp.seg_word_off[seg], wq0 = hs.seg_word_off[seg];
-        rp.init(hp.words + wp0, hp.seg_word_off[seg + 1] - wp0, hp.chunk_bit[gp]);
-        rq.init(hs.words + wq0, hs.seg_word_off[seg + 1] - wq0, hs.chunk_bit[gq]);
-        carp[l] = hp.chunk_prev[gp];
-        carq[l] = hs.chunk_prev[gq];
-        ns = min(C, n - c * C);
+        start_p = hp.chunk_bit[gp];
+        start_q = hs.chunk_bit[gq];
+        rp.init(rsp, start_p);
+        rq.init(rsq, start_q);
+        xp = hp.chunk_prev[gp];
+        xq = hs.chunk_prev[gq];
+        ns = codes_ok ? min(C, n - c * C) : 0;
     }
-    __syncthreads();
     const int nround = (C + G - 1) / G;
-    const int lane16 = tid & 15;
 
     for (int rd = 0; rd < nround; ++rd) {
         const int k0 = rd * G;
-        if (active) {
-#pragma unroll 4
+        if (active && k0 < ns) {
+            // parse: symbol indices into this thread's tile row; codes past the
+            // chunk end are parsed but never used
+#pragma unroll
             for (int k = 0; k < G; ++k) {
-                if (k0 + k < ns) {
-                    tp[l * GP + k] = rp.next(cp, bad);
-                    tq[l * GP + k] = rq.next(cq, bad);
-                }
+                int Lp, Lq;
+                const int32_t ip = rp.next(cp, Lp);
+                const int32_t iq = rq.next(cq, Lq);
+                const bool v = k0 + k < ns;
+                bad |= (v && (Lp == 0 || Lq == 0)) ? C3_ERR_CODE : 0u;
+                bitp += v ? Lp : 0;
+                bitq += v ? Lq : 0;
+                tp[l * GP + k] = ip;
+                tqi_[l * GP + k] = iq;
+            }
+            // symbol values (gathers issued together), running sums, range checks
+            int32_t gp_[G], gq_[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                gp_[k] = (int32_t)buf_word(symp, (uint32_t)tp[l * GP + k]);
+                gq_[k] = (int32_t)buf_word(symq, (uint32_t)tqi_[l * GP + k]);
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const bool v = k0 + k < ns;
+                xp += v ? gp_[k] : 0;
+                xq += v ? gq_[k] : 0;
+                const bool okp = (uint32_t)xp < npix, okq = (uint32_t)xq < npsi;
+                bad |= (v && !okp) ? C3_ERR_PIX : 0u;
+                bad |= (v && !okq) ? C3_ERR_PSI : 0u;
+                tp[l * GP + k] = okp ? xp : 0;
+                tq[l * GP + k] = (uint16_t)(okq ? xq : 0);
             }
         }
         __syncthreads();
-        // rows of 16 samples: resolve symbols (every gather issued before the
-        // first scan), undo the differencing with a 16-lane inclusive scan plus
-        // the row's running value, write out
-        int32_t valp[G], valq[G];
-#pragma unroll
+        // write the tile: 16-lane rows of consecutive samples of one chunk
+#pragma unroll 4
         for (int m = 0; m < G; ++m) {
             const int q = m * C3_NT + tid;
             const int ll = q >> 4, kk = q & 15;
-            const int t = (task.chunk0 + ll) * C + k0 + kk;
-            const bool valid = ll < task.nchunk && task.chunk0 + ll < nch_idx && t < n;
-            valp[m] = valid ? cp.sym[tp[ll * GP + kk]] : 0;
-            valq[m] = valid ? cq.sym[tq[ll * GP + kk]] : 0;
-        }
-#pragma unroll
-        for (int m = 0; m < G; ++m) {
-            const int q = m * C3_NT + tid;
-            const int ll = q >> 4, kk = q & 15;
-            const int t = (task.chunk0 + ll) * C + k0 + kk;
-            const bool valid = ll < task.nchunk && task.chunk0 + ll < nch_idx && t < n;
-            int32_t vp = valp[m], vq = valq[m];
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
-                const int yp = __shfl_up(vp, o, 16), yq = __shfl_up(vq, o, 16);
-                if (lane16 >= o) {
-                    vp += yp;
-                    vq += yq;
-                }
-            }
-            if (ll < task.nchunk) {
-                const int32_t xp = carp[ll] + vp, xq = carq[ll] + vq;
-                if (kk == 15) {
-                    carp[ll] = xp;
-                    carq[ll] = xq;
-                }
-                if (valid) {
-                    int32_t pp = xp, bb = xq;
-                    if ((uint32_t)pp >= npix) {
-                        bad |= C3_ERR_PIX;
-                        pp = 0;
-                    }
-                    if ((uint32_t)bb >= npsi) {
-                        bad |= C3_ERR_PSI;
-                        bb = 0;
-                    }
-                    pix_out[s0 + t] = pp;
-                    psi_out[s0 + t] = (uint16_t)bb;
-                }
+            const int cc = task.chunk0 + ll;
+            const int t = cc * C + k0 + kk;
+            if (ll < task.nchunk && cc < nch_idx && k0 + kk < C && t < n && codes_ok) {
+                pix_out[s0 + t] = tp[ll * GP + kk];
+                psi_out[s0 + t] = tq[ll * GP + kk];
             }
         }
         __syncthreads();
     }
-    // chunk boundary consistency with the side index
-    if (active && c + 1 < nch_idx) {
+    // chunk boundary consistency with the side index: the codes of chunk c end
+    // where chunk c + 1 starts, and the running value meets its stored one
+    if (active && codes_ok && c + 1 < nch_idx) {
         const int64_t gp = hp.seg_chunk_off[seg] + c + 1;
         const int64_t gq = hs.seg_chunk_off[seg] + c + 1;
-        if (rp.consumed != (int64_t)hp.chunk_bit[gp] || carp[l] != hp.chunk_prev[gp]) bad |= C3_ERR_CHUNK;
-        if (rq.consumed != (int64_t)hs.chunk_bit[gq] || carq[l] != hs.chunk_prev[gq]) bad |= C3_ERR_CHUNK;
+        if ((int64_t)start_p + bitp != (int64_t)hp.chunk_bit[gp] || xp != hp.chunk_prev[gp]) bad |= C3_ERR_CHUNK;
+        if ((int64_t)start_q + bitq != (int64_t)hs.chunk_bit[gq] || xq != hs.chunk_prev[gq]) bad |= C3_ERR_CHUNK;
     }
     if (active && ns > 0) {
-        if (rp.consumed > 32 * rp.wend) bad |= C3_ERR_CHUNK;
-        if (rq.consumed > 32 * rq.wend) bad |= C3_ERR_CHUNK;
+        if ((int64_t)start_p + bitp > 32 * nwp) bad |= C3_ERR_CHUNK;
+        if ((int64_t)start_q + bitq > 32 * nwq) bad |= C3_ERR_CHUNK;
     }
     if (bad) atomicOr(&blk_err, bad);
     __syncthreads();
@@ -267,11 +306,12 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
 namespace c3 {
 
 hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
-                         const DecodeTask *tasks, int ntask, int32_t *pix_out, uint16_t *psi_out,
-                         uint32_t *err) {
+                         DecTab *tabs, const DecodeTask *tasks, int ntask, int32_t *pix_out,
+                         uint16_t *psi_out, uint32_t *err) {
     if (ntask <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_decode, dim3(ntask), dim3(C3_NT), 0, st, L, hp, hs, tasks, pix_out, psi_out,
-                       err);
+    hipLaunchKernelGGL(k_tables, dim3(hp.ntable + hs.ntable), dim3(C3_NT), 0, st, hp, hs, tabs);
+    hipLaunchKernelGGL(k_decode, dim3(ntask), dim3(C3_NT), 0, st, L, hp, hs, tabs, tasks, pix_out,
+                       psi_out, err);
     return hipGetLastError();
 }
 
