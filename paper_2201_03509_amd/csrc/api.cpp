@@ -346,7 +346,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     const int esz = mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
     for (const FftPlan &fp : P->h_plans) {
         if (!fp.colreg) P->col_lds = std::max(P->col_lds, 2 * fp.M1 * fp.B * esz);  // ping-pong
-        P->row_lds = std::max(P->row_lds, 4 * fp.M2 * esz);
+        P->row_lds = std::max(P->row_lds, 2 * fp.M2 * esz);  // one in-place buffer, two rows
     }
     std::vector<double> fs(L->nband);
     for (int b = 0; b < L->nband; ++b) fs[b] = L->bands[b].fsamp;

@@ -6,7 +6,8 @@
 #include "../../include/c3tod.h"
 
 #define C3_NT 256            // threads per block of every kernel but the two below
-#define C3_ROW_NT 1024       // threads per block of the FFT row pass
+#define C3_ROW_NT_F32 512    // threads per block of the FFT row pass (two blocks per CU)
+#define C3_ROW_NT_F64 1024
 #define C3_COL_NT 64         // threads (= columns) per block of the register column passes
 #define C3_LDS_MAX 163840    // LDS bytes one workgroup may hold on gfx950
 

@@ -120,6 +120,101 @@ __device__ cx<T> *lds_fft(cx<T> *b0, cx<T> *b1, int L, int lb, int lsi, const in
     return src;
 }
 
+// In-place form for the row pass: every thread reads its butterflies of the
+// stage into registers, the block synchronises, and the results are written
+// back over the inputs; one LDS buffer instead of two, so two row blocks fit
+// on a CU.  KB bounds the butterflies per thread at the longest row pair.
+template <typename T>
+constexpr int row_elems() { return sizeof(T) == 4 ? 2 * 5040 : 2 * 2520; }  // longest row pair
+
+template <int R, int DIR, int NT, typename T>
+__device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, int L, int lb, int lsi, int Ns,
+                                                       const GLBP cx<T> *__restrict__ tw) {
+    constexpr int KB = (row_elems<T>() / R + NT - 1) / NT;
+    const int LR = L / R;
+    const int nb = LR << lb;
+    const int bm = (1 << lb) - 1;
+    const int step = L / (Ns * R);
+    const int in_stride = LR << lsi;
+    const int out_stride = Ns << lsi;
+    const int NsR = Ns * R;
+    const uint32_t magic = 0xFFFFFFFFu / (uint32_t)Ns + 1u;  // j / Ns == umulhi(j, magic)
+    cx<T> v[KB][R];
+    int ob[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int q = (int)threadIdx.x + kb * NT;
+        ob[kb] = -1;
+        if (q < nb) {
+            const int b = q & bm, j = q >> lb;
+            int ia = (j << lsi) + b;
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                v[kb][t] = buf[ia];
+                ia += in_stride;
+            }
+            const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
+            const int k = j - jd * Ns;
+            if (Ns > 1) {
+                const int ks = k * step;
+                const cx<T> w1 = tw[ks];
+                v[kb][1] = DIR < 0 ? cmul(v[kb][1], w1) : cmulc(v[kb][1], w1);
+                if constexpr (R > 2) {
+                    const cx<T> w2 = tw[2 * ks];
+                    v[kb][2] = DIR < 0 ? cmul(v[kb][2], w2) : cmulc(v[kb][2], w2);
+                    cx<T> wa = w1, wb = w2;
+#pragma unroll
+                    for (int t = 3; t < R; ++t) {
+                        const cx<T> w = cmul((t & 1) ? wa : wb, w2);
+                        if (t & 1)
+                            wa = w;
+                        else
+                            wb = w;
+                        v[kb][t] = DIR < 0 ? cmul(v[kb][t], w) : cmulc(v[kb][t], w);
+                    }
+                }
+            }
+            dft<R, DIR>(v[kb]);
+            ob[kb] = ((jd * NsR + k) << lsi) + b;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        if (ob[kb] >= 0) {
+            int o = ob[kb];
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                buf[o] = v[kb][t];
+                o += out_stride;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int DIR, int NT, typename T>
+__device__ void lds_fft_ip(cx<T> *b, int L, int lb, int lsi, const int8_t *rad, int nrad,
+                           const cx<T> *tw_) {
+    const GLBP cx<T> *tw = (const GLBP cx<T> *)tw_;
+    LDSP cx<T> *lb_ = (LDSP cx<T> *)b;
+    int Ns = 1;
+    for (int s = 0; s < nrad; ++s) {
+        const int R = rad[s];
+        if (R == 4)
+            fft_stage_ip<4, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
+        else if (R == 8)
+            fft_stage_ip<8, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
+        else if (R == 2)
+            fft_stage_ip<2, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
+        else if (R == 3)
+            fft_stage_ip<3, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
+        else
+            fft_stage_ip<5, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
+        Ns *= R;
+    }
+}
+
 // ------------------------------------------------------------- pass 1
 extern __shared__ __attribute__((aligned(16))) unsigned char c3_dyn_lds[];
 
@@ -311,10 +406,13 @@ __device__ __forceinline__ void whittle_mode(const ModeCtx &mc, int64_t k, cx<T>
 }
 
 // ------------------------------------------------------------- pass 2
+template <typename T>
+constexpr int row_nt() { return sizeof(T) == 4 ? C3_ROW_NT_F32 : C3_ROW_NT_F64; }
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(C3_ROW_NT) void k_row(FftArgs a) {
-    constexpr int NT = C3_ROW_NT;
-    cx<T> *bufs = (cx<T> *)c3_dyn_lds;  // 2 x (2 * M2) elements (sized per launch)
+__global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
+    constexpr int NT = row_nt<T>();
+    cx<T> *buf = (cx<T> *)c3_dyn_lds;  // 2 * M2 elements (sized per launch)
     __shared__ double red[3][NT / 64];
     const int2 task = a.row_tasks[blockIdx.x];
     const int seg = task.x;
@@ -328,14 +426,12 @@ __global__ __launch_bounds__(C3_ROW_NT) void k_row(FftArgs a) {
     const cx<T> *pool = (const cx<T> *)a.twpool;
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
 
-    const int nel = M2 << two;
     for (int i = threadIdx.x; i < M2; i += NT) {
-        bufs[i * si] = Y[(int64_t)ka * M2 + i];
-        if (two) bufs[i * si + 1] = Y[(int64_t)kb * M2 + i];
+        buf[i * si] = Y[(int64_t)ka * M2 + i];
+        if (two) buf[i * si + 1] = Y[(int64_t)kb * M2 + i];
     }
     __syncthreads();
-    cx<T> *buf = lds_fft<-1, NT>(bufs, bufs + nel, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
-    cx<T> *spare = buf == bufs ? bufs + nel : bufs;
+    lds_fft_ip<-1, NT>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
 
     ModeCtx mc;
     {
@@ -414,10 +510,10 @@ __global__ __launch_bounds__(C3_ROW_NT) void k_row(FftArgs a) {
     }
     if (MODE == 0) {
         __syncthreads();
-        const cx<T> *res = lds_fft<1, NT>(buf, spare, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+        lds_fft_ip<1, NT>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
         for (int i = threadIdx.x; i < M2; i += NT) {
-            Y[(int64_t)ka * M2 + i] = res[i * si];
-            if (two) Y[(int64_t)kb * M2 + i] = res[i * si + 1];
+            Y[(int64_t)ka * M2 + i] = buf[i * si];
+            if (two) Y[(int64_t)kb * M2 + i] = buf[i * si + 1];
         }
     } else {
         // block reduction of the Whittle sums
@@ -470,7 +566,7 @@ hipError_t launch_fft_pass(hipStream_t st, int mixed, const FftArgs &a, int pass
         hipError_t e = fft_init_attributes();
         if (e != hipSuccess) return e;
     }
-    const dim3 b(C3_NT), br(C3_ROW_NT);
+    const dim3 b(C3_NT), br(mixed ? C3_ROW_NT_F32 : C3_ROW_NT_F64);
     const dim3 gc(a.ncol_tasks), gr(a.nrow_tasks);
     if (mixed) {
         if (pass == 0) hipLaunchKernelGGL(k_col_fwd<float>, gc, b, lc, st, a);

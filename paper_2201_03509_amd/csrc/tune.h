@@ -25,8 +25,8 @@ struct FftChoice {
     std::vector<int> r1, r2;
 };
 
-// longest row the row pass holds: two rows, two ping-pong buffers, within the
-// LDS of one workgroup (160 KB), less room for the static reduction array
+// longest row the row pass takes: two rows in one in-place LDS buffer of at
+// most 80 KB, so that two row blocks share a CU (the stage code is sized for it)
 inline int row_cap(int mixed) { return mixed ? 5040 : 2520; }
 // complex elements of one LDS column tile buffer (two buffers per block)
 inline int col_tile(int mixed) { return mixed ? 4096 : 2048; }
