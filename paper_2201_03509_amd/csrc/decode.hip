@@ -164,8 +164,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
                                                   uint16_t *__restrict__ psi_out, uint32_t *err) {
     __shared__ DecTab cp, cq;
     __shared__ int32_t tp[C3_NT * GP];
-    __shared__ uint16_t tq[C3_NT * GP];
-    __shared__ int32_t tqi_[C3_NT * GP];  // psi symbol indices of the round
+    __shared__ uint16_t tq[C3_NT * GP];  // psi symbol indices, then psi values
     __shared__ uint32_t blk_err;
 
     const DecodeTask task = tasks[blockIdx.x];
@@ -192,7 +191,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
         if (tid == 0) blk_err = 0;
     }
     __syncthreads();
-    const bool codes_ok = tabs_ok && cp.ok && cq.ok;
+    const bool codes_ok = tabs_ok && cp.ok && cq.ok && cq.nsym < 65535;
     // symbol arrays as raw buffers of nsym entries: an invalid index reads 0
     const __amdgpu_buffer_rsrc_t symp =
         raw_buffer(hp.tables + hp.table_off[tabs_ok ? tpi : 0] + 34, 4 * cp.nsym);
@@ -212,14 +211,13 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
     int32_t xp = 0, xq = 0;      // running (undifferenced) values
     int32_t bitp = 0, bitq = 0;  // bits consumed by this chunk's codes
     uint32_t start_p = 0, start_q = 0;
-    // the two streams of this segment as raw buffers (at most 2^30 words each)
+    // the two streams of this segment as raw buffers (below 2^29 words each)
     const int64_t wp0 = hp.seg_word_off[seg], wq0 = hs.seg_word_off[seg];
     const int64_t nwp = hp.seg_word_off[seg + 1] - wp0, nwq = hs.seg_word_off[seg + 1] - wq0;
-    if (nwp >= (1ll << 30) || nwq >= (1ll << 30) || nwp < 0 || nwq < 0) bad |= C3_ERR_CHUNK;
-    const __amdgpu_buffer_rsrc_t rsp =
-        raw_buffer(hp.words + wp0, (int32_t)(4 * min(max(nwp, (int64_t)0), (int64_t)(1 << 29))));
-    const __amdgpu_buffer_rsrc_t rsq =
-        raw_buffer(hs.words + wq0, (int32_t)(4 * min(max(nwq, (int64_t)0), (int64_t)(1 << 29))));
+    const bool words_ok = nwp >= 0 && nwq >= 0 && nwp < (1ll << 29) && nwq < (1ll << 29);
+    if (!words_ok) bad |= C3_ERR_CHUNK;
+    const __amdgpu_buffer_rsrc_t rsp = raw_buffer(hp.words + wp0, words_ok ? (int32_t)(4 * nwp) : 0);
+    const __amdgpu_buffer_rsrc_t rsq = raw_buffer(hs.words + wq0, words_ok ? (int32_t)(4 * nwq) : 0);
     if (active) {
         const int64_t gp = hp.seg_chunk_off[seg] + c;
         const int64_t gq = hs.seg_chunk_off[seg] + c;
@@ -229,16 +227,17 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
         rq.init(rsq, start_q);
         xp = hp.chunk_prev[gp];
         xq = hs.chunk_prev[gq];
-        ns = codes_ok ? min(C, n - c * C) : 0;
+        ns = (codes_ok && words_ok) ? min(C, n - c * C) : 0;
     }
     const int nround = (C + G - 1) / G;
 
     for (int rd = 0; rd < nround; ++rd) {
         const int k0 = rd * G;
         if (active && k0 < ns) {
-            // parse: symbol indices into this thread's tile row; codes past the
+            // parse: symbol indices into this thread's tile row (psi tables hold
+            // at most 65535 symbols, checked with the table); codes past the
             // chunk end are parsed but never used
-#pragma unroll
+#pragma unroll 4  // full unrolling runs out of scalar registers
             for (int k = 0; k < G; ++k) {
                 int Lp, Lq;
                 const int32_t ip = rp.next(cp, Lp);
@@ -248,25 +247,28 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
                 bitp += v ? Lp : 0;
                 bitq += v ? Lq : 0;
                 tp[l * GP + k] = ip;
-                tqi_[l * GP + k] = iq;
+                tq[l * GP + k] = (uint16_t)(Lq ? iq : 0xFFFF);
             }
-            // symbol values (gathers issued together), running sums, range checks
-            int32_t gp_[G], gq_[G];
+            // symbol values (gathers issued in groups), running sums, range checks
 #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                gp_[k] = (int32_t)buf_word(symp, (uint32_t)tp[l * GP + k]);
-                gq_[k] = (int32_t)buf_word(symq, (uint32_t)tqi_[l * GP + k]);
-            }
+            for (int h = 0; h < G; h += G / 2) {
+                int32_t gp_[G / 2], gq_[G / 2];
 #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                const bool v = k0 + k < ns;
-                xp += v ? gp_[k] : 0;
-                xq += v ? gq_[k] : 0;
-                const bool okp = (uint32_t)xp < npix, okq = (uint32_t)xq < npsi;
-                bad |= (v && !okp) ? C3_ERR_PIX : 0u;
-                bad |= (v && !okq) ? C3_ERR_PSI : 0u;
-                tp[l * GP + k] = okp ? xp : 0;
-                tq[l * GP + k] = (uint16_t)(okq ? xq : 0);
+                for (int k = 0; k < G / 2; ++k) {
+                    gp_[k] = (int32_t)buf_word(symp, (uint32_t)tp[l * GP + h + k]);
+                    gq_[k] = (int32_t)buf_word(symq, (uint32_t)tq[l * GP + h + k]);
+                }
+#pragma unroll
+                for (int k = 0; k < G / 2; ++k) {
+                    const bool v = k0 + h + k < ns;
+                    xp += v ? gp_[k] : 0;
+                    xq += v ? gq_[k] : 0;
+                    const bool okp = (uint32_t)xp < npix, okq = (uint32_t)xq < npsi;
+                    bad |= (v && !okp) ? C3_ERR_PIX : 0u;
+                    bad |= (v && !okq) ? C3_ERR_PSI : 0u;
+                    tp[l * GP + h + k] = okp ? xp : 0;
+                    tq[l * GP + h + k] = (uint16_t)(okq ? xq : 0);
+                }
             }
         }
         __syncthreads();
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
             const int ll = q >> 4, kk = q & 15;
             const int cc = task.chunk0 + ll;
             const int t = cc * C + k0 + kk;
-            if (ll < task.nchunk && cc < nch_idx && k0 + kk < C && t < n && codes_ok) {
+            if (ll < task.nchunk && cc < nch_idx && k0 + kk < C && t < n && codes_ok && words_ok) {
                 pix_out[s0 + t] = tp[ll * GP + kk];
                 psi_out[s0 + t] = tq[ll * GP + kk];
             }
