@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--fft-batch", type=int, default=None,
                     help="complex elements per FFT batch (0 = all segments at once)")
     ap.add_argument("--bin-stride", type=int, default=None, help="override the binning stride")
+    ap.add_argument("--chunk-len", type=int, default=None,
+                    help="Huffman side-index spacing of the generated inputs (symbols)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -191,7 +193,8 @@ def main():
     from paper_2201_03509_amd import ops
 
     t0 = time.perf_counter()
-    ts = synth.make_cached(args.config, cache_dir=args.cache_dir, nscan=args.nscan)
+    ts = synth.make_cached(args.config, cache_dir=args.cache_dir, nscan=args.nscan,
+                           chunk_len=args.chunk_len)
     log("generated config %d: %d segments, %d samples in %.1fs" %
         (args.config, ts.nseg, ts.nsamp, time.perf_counter() - t0))
     seed = synth.seed32(args.config)
@@ -327,7 +330,8 @@ def main():
         "config": {"workload": workload, "nside": [int(x) for x in ts.band_nside],
                    "segments": ts.nseg, "samples": ts.nsamp,
                    "precision": "FP32 projection/FFT/draws, FP64 pixel accumulation",
-                   "fft_padding": "even 5-smooth >= 2n"},
+                   "fft_padding": "even 5-smooth >= 2n",
+                   "huffman_chunk_len": int(ts.pix_huff.chunk_len)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "graph_ms_per_step": round(ms_graph, 3),

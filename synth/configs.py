@@ -33,10 +33,14 @@ class Config:
     alpha_fixed: float = 0.0
     fknee_range: Tuple[float, float] = (0.05, 0.3)
     alpha_range: Tuple[float, float] = (-1.8, -1.0)
-    chunk_len: int = 256                   # Huffman side-index spacing (symbols)
+    chunk_len: int = 32                    # Huffman side-index spacing (symbols): the
+                                           # densest the format allows; neighbouring
+                                           # chunks then share cache lines in the decoder
 
-    def scaled(self, nscan=None, length=None, bands=None):
+    def scaled(self, nscan=None, length=None, bands=None, chunk_len=None):
         kw = {}
+        if chunk_len is not None:
+            kw["chunk_len"] = int(chunk_len)
         if nscan is not None:
             kw["nscan"] = int(nscan)
         if length is not None:

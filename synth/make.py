@@ -165,8 +165,8 @@ class TodSet:
     """A synthetic TOD set; every array is a numpy array on the host."""
 
 
-def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None):
-    cfg = cfgmod.get(k).scaled(nscan=nscan, length=length, bands=bands)
+def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None, chunk_len=None):
+    cfg = cfgmod.get(k).scaled(nscan=nscan, length=length, bands=bands, chunk_len=chunk_len)
     kk = cfg.index
     nb = len(cfg.bands)
     lengths = _lengths(cfg)
@@ -319,7 +319,7 @@ def load(path):
     for k in _SCALARS:
         setattr(ts, k, meta[k])
     idx, nscan, length = meta["cfg"]
-    ts.cfg = cfgmod.get(idx).scaled(nscan=nscan, length=length)
+    ts.cfg = cfgmod.get(idx).scaled(nscan=nscan, length=length, chunk_len=meta["chunk_len"])
     hs = {"pix_huff": HuffStream(meta["chunk_len"]), "psi_huff": HuffStream(meta["chunk_len"])}
     for f in sorted(os.listdir(path)):
         if not f.endswith(".npy"):
@@ -340,6 +340,8 @@ def make_cached(k, cache_dir=None, **kw):
     if not cache_dir:
         return make(k, **kw)
     tag = "c%d_n%s_l%s" % (k, kw.get("nscan"), "_".join(map(str, kw.get("length") or [])))
+    if kw.get("chunk_len"):
+        tag += "_c%d" % kw["chunk_len"]
     path = os.path.join(cache_dir, tag)
     if os.path.exists(os.path.join(path, "meta.json")):
         return load(path)

@@ -30,11 +30,13 @@ def ctx():
 
 
 def _cases():
-    # (config, nscan, length) -- several chunks, ragged tails, several bands
+    # (config, nscan, length, side-index spacing) -- several chunks, ragged
+    # tails, several bands, the default and a long side-index spacing
     return {
-        "tiny": (0, None, None),
-        "lfi30_small": (1, 3, ("uniform", 9000, 13000)),
-        "mixed_small": (4, 6, ("loguniform2", 11.0, 14.0)),
+        "tiny": (0, None, None, None),
+        "lfi30_small": (1, 3, ("uniform", 9000, 13000), None),
+        "mixed_small": (4, 6, ("loguniform2", 11.0, 14.0), None),
+        "lfi30_c256": (1, 2, ("uniform", 9000, 13000), 256),
     }
 
 
@@ -43,8 +45,8 @@ _CACHE = {}
 
 def dataset(name):
     if name not in _CACHE:
-        k, ns, ln = _cases()[name]
-        ts = synth.make(k, nscan=ns, length=ln, keep_truth=True)
+        k, ns, ln, cl = _cases()[name]
+        ts = synth.make(k, nscan=ns, length=ln, keep_truth=True, chunk_len=cl)
         pix, psi = oh.decode_pointing(ts)
         assert np.array_equal(pix, ts.pix) and np.array_equal(psi, ts.psi)
         _CACHE[name] = (ts, pix, psi)
@@ -70,7 +72,7 @@ def seg_rel(ts, got, ref):
     return max(errs)
 
 
-@pytest.mark.parametrize("name", ["tiny", "lfi30_small", "mixed_small"])
+@pytest.mark.parametrize("name", ["tiny", "lfi30_small", "mixed_small", "lfi30_c256"])
 def test_decode_bit_exact(ctx, name):
     ts, pix, psi = dataset(name)
     tod = dev_tod(ts)
