@@ -29,8 +29,8 @@ def log(*a):
 
 
 def kernel_bytes(ts, tod, prec, sum_m):
-    """Compulsory bytes per launch of each kernel of the sweep: every input
-    array the kernel needs read once, every output written once."""
+    """Compulsory bytes per sweep of each kernel (summed over its launches):
+    every input array the kernel needs read once, every output written once."""
     f = 4 if prec == "mixed" else 8
     ns = ts.nsamp
     dsz = ts.d.dtype.itemsize
@@ -39,12 +39,12 @@ def kernel_bytes(ts, tod, prec, sum_m):
         comp += hs.words.nbytes + hs.chunk_bit.nbytes + hs.chunk_prev.nbytes + hs.tables.nbytes
     npt = ts.npix_total
     return {
-        "decode": comp + ns * dsz + 3 * f * npt + ns * (f + 4 + 2),
+        "decode": comp + ns * (4 + 2),
         "fft_col_fwd": ns * f + 2 * f * sum_m,
         "fft_row": 2 * (2 * f * sum_m),
         "fft_col_inv": 2 * f * sum_m + ns * f,
         "bin": ns * (4 + 2 + dsz + f) + 2 * 80 * npt,
-        "project": ns * (4 + 2 + f) + 3 * f * npt,
+        "project": ns * (4 + 2 + dsz + f) + 3 * f * npt,  # the sweep's residual r = d - g P m
         "solve": 80 * npt + 3 * f * npt + 8 * npt,
         "chisq_time": ns * (4 + 2 + dsz + f) + 3 * f * npt,
     }
@@ -72,8 +72,8 @@ def source_sha():
 
 
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources."""
+    """HBM bytes per sweep (all launches of the kernel) from the committed
+    counter summary, if it was taken on the current kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -84,7 +84,7 @@ def measured_traffic(kernel, workload):
     e = t.get(workload, {}).get(kernel)
     if not e or e.get("source_sha") != source_sha():
         return None
-    return e.get("bytes_per_launch")
+    return e.get("bytes_per_step")
 
 
 # ------------------------------------------------------------- CPU baseline
@@ -273,20 +273,24 @@ def main():
 
     sum_m = sum(next5(int(ts.seg_off[q + 1] - ts.seg_off[q])) for q in range(ts.nseg))
     kb = kernel_bytes(ts, tod, "mixed", sum_m)
-    per = {k: {"ms_per_launch": (v[0] / v[1]) if v[1] else None, "launches": v[1],
-               "compulsory_gb_per_launch": kb[k] / 1e9 if k in kb else None}
+    # a kernel may run as several launches per sweep (one per column length or
+    # occupancy class); its time per sweep is the sum over them
+    per = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
+               "ms_per_launch": (v[0] / v[1]) if v[1] else None,
+               "compulsory_gb_per_step": kb[k] / 1e9 if k in kb else None}
            for k, v in kt.items() if v[1]}
     dom = max(per, key=lambda k: kt[k][0])
-    avg_ms = per[dom]["ms_per_launch"]
+    avg_ms = per[dom]["ms_per_step"]
     ach = kb[dom] / (avg_ms / 1e3) / 1e9
     workload = "lfi70" if args.config == 2 and args.nscan is None else "config%d_nscan%s" % (args.config, args.nscan)
     traffic = measured_traffic(dom, workload)
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "bytes_per_launch": kb[dom], "avg_ms": round(avg_ms, 4)}
+            "bytes_per_step": kb[dom], "ms_per_step": round(avg_ms, 4),
+            "launches_per_step": per[dom]["launches_per_step"]}
     sweep_alg = (2 * (sum(h.words.nbytes for h in (ts.pix_huff, ts.psi_huff))) + ts.nsamp * (4 + 4)
                  + 84 * ts.npix_total)
-    log("dominant kernel %s: %.3f ms, %.0f GB/s compulsory" % (dom, avg_ms, ach))
+    log("dominant kernel %s: %.3f ms per sweep, %.0f GB/s compulsory" % (dom, avg_ms, ach))
 
     plain = None
     if not args.no_plain:

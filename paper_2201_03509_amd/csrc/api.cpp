@@ -88,9 +88,14 @@ struct Plan {
         int m1reg;                        // register column length, 0: LDS tiles
         int t0, nt;                       // range of the column task list
     };
+    struct RowGroup {
+        int lds;                          // dynamic LDS bytes of the launch
+        int t0, nt;                       // range of the row task list
+    };
     struct Batch {
         int col0, ncol, row0, nrow;
         std::vector<ColGroup> groups;     // column tasks of the batch, by kernel
+        std::vector<RowGroup> rgroups;    // row tasks of the batch, by blocks per CU
     };
     std::vector<Batch> batches;
     int col_lds = 0, row_lds = 0;         // dynamic LDS bytes per FFT pass
@@ -310,20 +315,30 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     });
     // batches in LPT order; each batch reuses the workspace from offset 0.
     // Column tasks of a batch are grouped by column kernel (one launch each).
+    // Row tasks are grouped by how many row blocks fit on a CU (their LDS is
+    // two rows of M2), each launch sized to its own longest row.
+    const int esz = mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
     std::vector<int2> col, row;
-    std::map<int, std::vector<int2>> bcol;  // m1reg -> column tasks of the open batch
-    Plan::Batch cur{0, 0, 0, 0, {}};
+    std::map<int, std::vector<int2>> bcol;               // m1reg -> column tasks of the open batch
+    std::map<int, std::pair<int, std::vector<int2>>> brow;  // -blocks per CU -> (lds, row tasks)
+    Plan::Batch cur{0, 0, 0, 0, {}, {}};
     auto close_batch = [&]() {
         cur.col0 = (int)col.size();
         for (auto &kv : bcol) {
             cur.groups.push_back({kv.first, (int)col.size(), (int)kv.second.size()});
             col.insert(col.end(), kv.second.begin(), kv.second.end());
         }
+        cur.row0 = (int)row.size();
+        for (auto &kv : brow) {
+            cur.rgroups.push_back({kv.second.first, (int)row.size(), (int)kv.second.second.size()});
+            row.insert(row.end(), kv.second.second.begin(), kv.second.second.end());
+        }
         cur.ncol = (int)col.size() - cur.col0;
         cur.nrow = (int)row.size() - cur.row0;
         if (cur.ncol > 0 || cur.nrow > 0) P->batches.push_back(cur);
         bcol.clear();
-        cur = Plan::Batch{(int)col.size(), 0, (int)row.size(), 0, {}};
+        brow.clear();
+        cur = Plan::Batch{(int)col.size(), 0, (int)row.size(), 0, {}, {}};
     };
     for (int s : P->seg_order) {
         SegInfo &g = P->h_segs[s];
@@ -338,12 +353,15 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         P->work_elems = std::max(P->work_elems, scr);
         std::vector<int2> &cv = bcol[fp.colreg ? fp.M1 : 0];
         for (int c0 = 0; c0 < fp.M2; c0 += fp.B) cv.push_back(make_int2(s, c0));
-        for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) row.push_back(make_int2(s, k1));
+        const int rl = 2 * fp.M2 * esz;
+        const int per_cu = std::max(1, (C3_LDS_MAX - 1024) / std::max(rl, 1));
+        auto &rg = brow[-per_cu];
+        rg.first = std::max(rg.first, rl);
+        for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) rg.second.push_back(make_int2(s, k1));
     }
     close_batch();
     P->ncol = (int)col.size();
     P->nrow = (int)row.size();
-    const int esz = mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
     for (const FftPlan &fp : P->h_plans) {
         if (!fp.colreg) P->col_lds = std::max(P->col_lds, 2 * fp.M1 * fp.B * esz);  // ping-pong
         P->row_lds = std::max(P->row_lds, 2 * fp.M2 * esz);  // one in-place buffer, two rows
@@ -578,8 +596,14 @@ tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::Ff
         a.nrow_tasks = b.nrow;
         for (int pass = 0; pass < npass; ++pass) {
             if (pass == 1) {
-                KTimer kt(ctx, K_ROW, st);
-                HIPCHK(c3::launch_fft_pass(st, mixed, a, pass, 0));
+                for (const Plan::RowGroup &g : b.rgroups) {
+                    c3::FftArgs ag = a;
+                    ag.row_tasks = (const int2 *)P->row_tasks.p + g.t0;
+                    ag.nrow_tasks = g.nt;
+                    ag.row_lds = g.lds;
+                    KTimer kt(ctx, K_ROW, st);
+                    HIPCHK(c3::launch_fft_pass(st, mixed, ag, pass, 0));
+                }
                 continue;
             }
             for (const Plan::ColGroup &g : b.groups) {
