@@ -156,25 +156,47 @@ __device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, int L, i
             const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
             const int k = j - jd * Ns;
             if (Ns > 1) {
-                const int ks = k * step;
-                const cx<T> w1 = tw[ks];
-                v[kb][1] = DIR < 0 ? cmul(v[kb][1], w1) : cmulc(v[kb][1], w1);
-                if constexpr (R > 2) {
-                    const cx<T> w2 = tw[2 * ks];
-                    v[kb][2] = DIR < 0 ? cmul(v[kb][2], w2) : cmulc(v[kb][2], w2);
-                    cx<T> wa = w1, wb = w2;
+                const int ks = k * step;  // v_t *= w_L^(t ks)
+                if constexpr (R <= 8) {
+                    // w^1 and w^2 from the table, higher powers by products
+                    const cx<T> w1 = tw[ks];
+                    v[kb][1] = DIR < 0 ? cmul(v[kb][1], w1) : cmulc(v[kb][1], w1);
+                    if constexpr (R > 2) {
+                        const cx<T> w2 = tw[2 * ks];
+                        v[kb][2] = DIR < 0 ? cmul(v[kb][2], w2) : cmulc(v[kb][2], w2);
+                        cx<T> wa = w1, wb = w2;
 #pragma unroll
-                    for (int t = 3; t < R; ++t) {
-                        const cx<T> w = cmul((t & 1) ? wa : wb, w2);
-                        if (t & 1)
-                            wa = w;
-                        else
-                            wb = w;
-                        v[kb][t] = DIR < 0 ? cmul(v[kb][t], w) : cmulc(v[kb][t], w);
+                        for (int t = 3; t < R; ++t) {
+                            const cx<T> w = cmul((t & 1) ? wa : wb, w2);
+                            if (t & 1)
+                                wa = w;
+                            else
+                                wb = w;
+                            v[kb][t] = DIR < 0 ? cmul(v[kb][t], w) : cmulc(v[kb][t], w);
+                        }
+                    }
+                } else {
+                    // w^(Q a + b) = w^(Q a) w^b, both factors from the table
+                    constexpr int Q = tw_split(R);
+                    cx<T> wq[Q];
+                    wq[0] = cx<T>{(T)1, (T)0};
+#pragma unroll
+                    for (int q = 1; q < Q; ++q) wq[q] = tw[q * ks];
+#pragma unroll
+                    for (int ai = 0; ai * Q < R; ++ai) {
+                        cx<T> wa = cx<T>{(T)1, (T)0};
+                        if (ai) wa = tw[ai * Q * ks];
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) {
+                            const int t = ai * Q + q;
+                            if (t == 0 || t >= R) continue;
+                            const cx<T> w = ai ? (q ? cmul(wa, wq[q]) : wa) : wq[q];
+                            v[kb][t] = DIR < 0 ? cmul(v[kb][t], w) : cmulc(v[kb][t], w);
+                        }
                     }
                 }
             }
-            dft<R, DIR>(v[kb]);
+            dft_any<R, DIR>(v[kb]);
             ob[kb] = ((jd * NsR + k) << lsi) + b;
         }
     }
@@ -201,16 +223,24 @@ __device__ void lds_fft_ip(cx<T> *b, int L, int lb, int lsi, const int8_t *rad, 
     int Ns = 1;
     for (int s = 0; s < nrad; ++s) {
         const int R = rad[s];
-        if (R == 4)
-            fft_stage_ip<4, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
-        else if (R == 8)
-            fft_stage_ip<8, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
-        else if (R == 2)
-            fft_stage_ip<2, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
-        else if (R == 3)
-            fft_stage_ip<3, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
-        else
-            fft_stage_ip<5, DIR, NT>(lb_, L, lb, lsi, Ns, tw);
+#define C3_RADIX(RR)                                               \
+    case RR:                                                       \
+        fft_stage_ip<RR, DIR, NT>(lb_, L, lb, lsi, Ns, tw);        \
+        break;
+        if constexpr (sizeof(T) == 4) {
+            switch (R) {
+                C3_ROW_RADICES_F32(C3_RADIX)
+            default:
+                break;  // plans hold only the radices above
+            }
+        } else {
+            switch (R) {
+                C3_ROW_RADICES_F64(C3_RADIX)
+            default:
+                break;
+            }
+        }
+#undef C3_RADIX
         Ns *= R;
     }
 }

@@ -19,138 +19,6 @@ namespace {
 using c3::FftArgs;
 using namespace c3fft;
 
-// ------------------------------------------ compile-time twiddle constants
-// cos and sin of 2 pi m / L: the angle is reduced to [0, pi/2) with integer
-// arithmetic (quarter turns are exact), then summed as Taylor series; 14
-// terms at |x| <= pi/2 leave a truncation error below 1e-20.
-constexpr double kQuarterTurn = 1.570796326794896619231321691639751442;
-
-constexpr double taylor_sin(double x) {
-    double t = x, s = x;
-    for (int i = 1; i < 14; ++i) {
-        t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
-        s += t;
-    }
-    return s;
-}
-constexpr double taylor_cos(double x) {
-    double t = 1.0, s = 1.0;
-    for (int i = 1; i < 14; ++i) {
-        t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
-        s += t;
-    }
-    return s;
-}
-struct CS {
-    double c, s;
-};
-constexpr CS cis2pi(long m, long L) {
-    m %= L;
-    if (m < 0) m += L;
-    const long q = (4 * m) / L;      // whole quarter turns
-    const long r = 4 * m - q * L;    // remainder, in units of (pi/2) / L
-    const double th = kQuarterTurn * (double)r / (double)L;
-    double c = taylor_cos(th), s = taylor_sin(th);
-    for (long i = 0; i < q; ++i) {   // rotate by a quarter turn: (c, s) -> (-s, c)
-        const double t = c;
-        c = -s;
-        s = t;
-    }
-    return {c, s};
-}
-
-// ------------------------------------------ radix plan of a 5-smooth length
-struct RadPlan {
-    int n;       // number of stages (-1: not 5-smooth)
-    int r[16];   // radices in stage order
-};
-constexpr RadPlan rad_plan(int L) {
-    RadPlan p{0, {0}};
-    int a = 0, b = 0, c = 0;
-    while (L % 2 == 0) { L /= 2; ++a; }
-    while (L % 3 == 0) { L /= 3; ++b; }
-    while (L % 5 == 0) { L /= 5; ++c; }
-    while (a > 4 || a == 3) { p.r[p.n++] = 8; a -= 3; }
-    if (a == 4) { p.r[p.n++] = 4; p.r[p.n++] = 4; }
-    else if (a == 2) p.r[p.n++] = 4;
-    else if (a == 1) p.r[p.n++] = 2;
-    for (int i = 0; i < b; ++i) p.r[p.n++] = 3;
-    for (int i = 0; i < c; ++i) p.r[p.n++] = 5;
-    if (L != 1) p.n = -1;
-    return p;
-}
-constexpr int stage_ns(int L, int s) {  // product of the radices before stage s
-    const RadPlan p = rad_plan(L);
-    int ns = 1;
-    for (int i = 0; i < s; ++i) ns *= p.r[i];
-    return ns;
-}
-
-// v *= w_NSR^E with w = e^(DIR 2 pi i / NSR); quarter turns as swaps
-template <int DIR, int NSR, int E, typename T>
-__device__ __forceinline__ void twiddle(cx<T> &v) {
-    constexpr int m = ((DIR * E) % NSR + NSR) % NSR;
-    if constexpr (m == 0) {
-    } else if constexpr (4 * m == NSR) {
-        v = cx<T>{-v.y, v.x};
-    } else if constexpr (2 * m == NSR) {
-        v = cx<T>{-v.x, -v.y};
-    } else if constexpr (4 * m == 3 * NSR) {
-        v = cx<T>{v.y, -v.x};
-    } else {
-        constexpr CS w = cis2pi(m, NSR);
-        v = cmul(v, cx<T>{(T)w.c, (T)w.s});
-    }
-}
-
-// butterfly J of a Stockham stage (radix R, NS points already combined):
-// inputs x[J + t L/R], outputs y[(J / NS) NS R + J % NS + t NS]
-template <int L, int DIR, int R, int NS, int J, typename T, int... t>
-__device__ __forceinline__ void butterfly(const cx<T> *x, cx<T> *y, std::integer_sequence<int, t...>) {
-    constexpr int LR = L / R, k = J % NS, jd = J / NS;
-    cx<T> v[R] = {x[J + t * LR]...};
-    (twiddle<DIR, NS * R, t * k>(v[t]), ...);
-    dft<R, DIR>(v);
-    ((y[jd * NS * R + k + t * NS] = v[t]), ...);
-}
-
-template <int L, int DIR, int S, typename T, int... J>
-__device__ __forceinline__ void stage(const cx<T> *x, cx<T> *y, std::integer_sequence<int, J...>) {
-    constexpr RadPlan P = rad_plan(L);
-    constexpr int R = P.r[S];
-    constexpr int NS = stage_ns(L, S);
-    (butterfly<L, DIR, R, NS, J>(x, y, std::make_integer_sequence<int, R>{}), ...);
-}
-
-template <int L, int DIR, int S, typename T>
-__device__ __forceinline__ void stages(cx<T> *x, cx<T> *y) {
-    constexpr RadPlan P = rad_plan(L);
-    if constexpr (S < P.n) {
-        stage<L, DIR, S>(x, y, std::make_integer_sequence<int, L / P.r[S]>{});
-        stages<L, DIR, S + 1>(y, x);
-    }
-}
-
-// in-register FFT of length L (DIR -1 forward, +1 inverse, unnormalised)
-template <int L, int DIR, typename T>
-__device__ __forceinline__ void reg_fft(cx<T> (&x)[L]) {
-    constexpr RadPlan P = rad_plan(L);
-    static_assert(P.n > 0, "column length must be 5-smooth and > 1");
-    cx<T> y[L];
-    stages<L, DIR, 0>(x, y);
-    if constexpr (P.n % 2 == 1) {
-#pragma unroll
-        for (int i = 0; i < L; ++i) x[i] = y[i];
-    }
-}
-
-// split k1 = a Q + b for the four-step twiddle: Q + M1/Q table reads per lane
-constexpr int tw_split(int M1) {
-    int q = 1;
-    while (q * q < M1) ++q;
-    return q;
-}
-
 // word 3 of a raw buffer resource on gfx9-family chips (untyped dword access)
 #define C3_BUF_WORD3 0x00020000
 

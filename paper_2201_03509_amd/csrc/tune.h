@@ -11,6 +11,7 @@
 
 #include "common.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <map>
 #include <string>
@@ -79,6 +80,42 @@ inline std::vector<int> radices(int64_t L, int order) {
     return r;
 }
 
+inline bool row_radix_ok(int mixed, int r) {
+    switch (r) {
+#define C3_TUNE_R(R) case R:
+    C3_ROW_RADICES_F64(C3_TUNE_R)
+        return true;
+    default:
+        break;
+    }
+    if (!mixed) return false;
+    switch (r) {
+        C3_ROW_RADICES_F32(C3_TUNE_R)
+#undef C3_TUNE_R
+        return true;
+    default:
+        return false;
+    }
+}
+
+// row-pass radices: the largest compiled radix dividing what is left, each
+// time (about three stages for rows of a few thousand points in FP32); order
+// 1 runs them smallest first
+inline std::vector<int> row_radices(int64_t L, int mixed, int order) {
+    std::vector<int> r;
+    if (factor235(L).empty()) return r;
+    while (L > 1) {
+        int best = 1;
+        for (int c = 2; c <= 32; ++c)
+            if (L % c == 0 && row_radix_ok(mixed, c)) best = c;
+        if (best == 1) return {};  // cannot happen: 2, 3 and 5 are compiled
+        r.push_back(best);
+        L /= best;
+    }
+    if (order == 1) std::reverse(r.begin(), r.end());
+    return r;
+}
+
 inline int pow2floor(int x) {
     int p = 1;
     while (p * 2 <= x) p *= 2;
@@ -109,7 +146,7 @@ inline bool make_choice(int64_t M, int64_t M2, int mixed, int bmax, int order, i
     }
     c.B = B;
     c.r1 = radices(M1, order);
-    c.r2 = radices(M2, order);
+    c.r2 = row_radices(M2, mixed, order);
     if ((int)c.r1.size() > 16 || (int)c.r2.size() > 16) return false;
     return true;
 }
