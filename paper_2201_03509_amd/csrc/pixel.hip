@@ -139,11 +139,13 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         w = g / (s2 * s2);
         gw = g * w;
         int t = phi;
-        for (; t + 3 * S < n; t += 4 * S) {
-            int p[4], b[4];
-            double v[4];
+        // two revisits in flight: deeper pipelining costs the registers that
+        // bound the occupancy of this latency-bound kernel
+        for (; t + S < n; t += 2 * S) {
+            int p[2], b[2];
+            double v[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 2; ++u) {
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
                 if (ncorr) v[u] -= (double)ncorr[i];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) step(p[u], b[u], v[u]);
+            for (int u = 0; u < 2; ++u) step(p[u], b[u], v[u]);
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
