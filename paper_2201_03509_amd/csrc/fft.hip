@@ -456,9 +456,34 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     const cx<T> *pool = (const cx<T> *)a.twpool;
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
 
-    for (int i = threadIdx.x; i < M2; i += NT) {
-        buf[i * si] = Y[(int64_t)ka * M2 + i];
-        if (two) buf[i * si + 1] = Y[(int64_t)kb * M2 + i];
+    if constexpr (sizeof(T) == 4) {
+        // every load of the thread issued before the first LDS store, so the
+        // HBM latency is paid once per block rather than once per element
+        // (FP32: the FP64 kernel has no registers to spare for it)
+        constexpr int KL = (row_elems<T>() / 2 + NT - 1) / NT;
+        const cx<T> *ya = Y + (int64_t)ka * M2, *yb = Y + (int64_t)kb * M2;
+        cx<T> va[KL], vb[KL];
+#pragma unroll
+        for (int u = 0; u < KL; ++u) {
+            const int i = (int)threadIdx.x + u * NT;
+            if (i < M2) {
+                va[u] = ya[i];
+                if (two) vb[u] = yb[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KL; ++u) {
+            const int i = (int)threadIdx.x + u * NT;
+            if (i < M2) {
+                buf[i * si] = va[u];
+                if (two) buf[i * si + 1] = vb[u];
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < M2; i += NT) {
+            buf[i * si] = Y[(int64_t)ka * M2 + i];
+            if (two) buf[i * si + 1] = Y[(int64_t)kb * M2 + i];
+        }
     }
     __syncthreads();
     lds_fft_ip<-1, NT>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
@@ -541,9 +566,31 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     if (MODE == 0) {
         __syncthreads();
         lds_fft_ip<1, NT>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
-        for (int i = threadIdx.x; i < M2; i += NT) {
-            Y[(int64_t)ka * M2 + i] = buf[i * si];
-            if (two) Y[(int64_t)kb * M2 + i] = buf[i * si + 1];
+        if constexpr (sizeof(T) == 4) {
+            constexpr int KL = (row_elems<T>() / 2 + NT - 1) / NT;
+            cx<T> *ya = Y + (int64_t)ka * M2, *yb = Y + (int64_t)kb * M2;
+            cx<T> va[KL], vb[KL];
+#pragma unroll
+            for (int u = 0; u < KL; ++u) {
+                const int i = (int)threadIdx.x + u * NT;
+                if (i < M2) {
+                    va[u] = buf[i * si];
+                    if (two) vb[u] = buf[i * si + 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < KL; ++u) {
+                const int i = (int)threadIdx.x + u * NT;
+                if (i < M2) {
+                    ya[i] = va[u];
+                    if (two) yb[i] = vb[u];
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < M2; i += NT) {
+                Y[(int64_t)ka * M2 + i] = buf[i * si];
+                if (two) Y[(int64_t)kb * M2 + i] = buf[i * si + 1];
+            }
         }
     } else {
         // block reduction of the Whittle sums
