@@ -510,8 +510,12 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     const T half = (T)0.5;
     const T osc = (T)mc.outscale;
 
-    // pair (element e of row a, its mirror-mode partner)
+    // pair (element e of row a, its mirror-mode partner); w_N^k of the next
+    // iteration is fetched while this one computes
+    cx<T> w_next = twN(pool, p, ka + (int64_t)M1 * min((int)threadIdx.x, M2 - 1));
     for (int k2 = threadIdx.x; k2 < M2; k2 += NT) {
+        const cx<T> w = w_next;  // w_N^k
+        if (k2 + NT < M2) w_next = twN(pool, p, ka + (int64_t)M1 * (k2 + NT));
         int pk2, prow;  // partner position
         if (ka == 0) {
             pk2 = (M2 - k2) % M2;
@@ -537,7 +541,6 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
         }
         const int64_t kp = (int64_t)M - k;
         // A = (Zk + conj Zp)/2, B = -i (Zk - conj Zp)/2, E_k = A + w_N^k B
-        const cx<T> w = twN(pool, p, k);                 // w_N^k
         const cx<T> Ak = {half * (Za.x + Zb.x), half * (Za.y - Zb.y)};
         const cx<T> Dk = {half * (Za.x - Zb.x), half * (Za.y + Zb.y)};
         const cx<T> Bk = {Dk.y, -Dk.x};
