@@ -288,8 +288,11 @@ def main():
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "bytes_per_step": kb[dom], "ms_per_step": round(avg_ms, 4),
             "launches_per_step": per[dom]["launches_per_step"]}
-    sweep_alg = (2 * (sum(h.words.nbytes for h in (ts.pix_huff, ts.psi_huff))) + ts.nsamp * (4 + 4)
-                 + 84 * ts.npix_total)
+    # fused-sweep minimum: the compressed pointing (words, side index, tables)
+    # decoded twice, d read once, n_corr written once, map + accumulators once
+    comp = sum(h.words.nbytes + h.chunk_bit.nbytes + h.chunk_prev.nbytes + h.tables.nbytes
+               for h in (ts.pix_huff, ts.psi_huff))
+    sweep_alg = 2 * comp + ts.nsamp * (4 + 4) + 84 * ts.npix_total
     log("dominant kernel %s: %.3f ms per sweep, %.0f GB/s compulsory" % (dom, avg_ms, ach))
 
     plain = None
