@@ -120,6 +120,7 @@ struct tod_ctx_s {
     uint64_t *d_seed_iter = nullptr;
     DevBuf trig32, trig64, work, seg_sums, seg_whittle, probe_counts, resid;
     DevBuf dec_tabs;                      // decoding tables, rebuilt by every decode
+    DevBuf maps4;                         // the sweep's maps as (T, Q, U, 0) records
     std::map<uint64_t, std::unique_ptr<Plan>> plans;
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
@@ -924,6 +925,7 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     int ndt;
     if ((r = get_decode_tasks(ctx, P, pix->chunk_len, &dt, &ndt)) != TOD_OK) return r;
     HIPCHK(ctx->dec_tabs.ensure(sizeof(DecTab) * (size_t)(pix->ntable + psi->ntable)));
+    HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     hipStream_t st = ctx->stream;
     const LayoutDev Ld = make_layout_dev(lay);
 
@@ -931,7 +933,7 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     uint64_t gk = 1469598103934665603ull;
     const void *ptrs[] = {pix->words, psi->words, pix->tables, psi->tables, d, maps, gain, sigma0,
                           fknee, alpha, ncorr_out, acc, pix_work, psi_work, ctx->work.p,
-                          ctx->resid.p, P->segs.p, ctx->dec_tabs.p};
+                          ctx->resid.p, P->segs.p, ctx->dec_tabs.p, ctx->maps4.p};
     gk = fnv(gk, ptrs, sizeof(ptrs));
     gk = fnv(gk, &P->key, sizeof(P->key));
     gk = fnv(gk, &d_dtype, sizeof(d_dtype));
@@ -962,7 +964,7 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
         {
             KTimer kt(ctx, K_PROJECT, st);
             HIPCHK(c3::launch_resid_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
-                                          d_dtype == TOD_F64, maps, gain,
+                                          d_dtype == TOD_F64, maps, ctx->maps4.p, gain,
                                           mixed ? ctx->trig32.p : ctx->trig64.p, ctx->resid.p));
         }
         {

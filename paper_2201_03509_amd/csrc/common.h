@@ -142,11 +142,13 @@ hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, 
                          DecTab *tabs, const DecodeTask *tasks, int ntask, int32_t *pix_out,
                          uint16_t *psi_out, uint32_t *err);
 
-// r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs)
+// r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs);
+// maps4: workspace of npix_total records of 4 values (T, Q, U, 0), filled from
+// the [3][npix] maps first
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                               int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
-                              int d_f64, const void *maps, const double *gain, const void *trig,
-                              void *r_out);
+                              int d_f64, const void *maps, void *maps4, const double *gain,
+                              const void *trig, void *r_out);
 
 // FFT-based passes.  mode: 0 = n_corr draw, 1 = Whittle sums (chi^2), 2 = chi^2 adjoint sums
 struct FftArgs {

@@ -9,6 +9,8 @@
 // the same pixel, so each thread accumulates its pixel's 3-vector and 3x3 in
 // registers and touches global memory (FP64 atomics) only when the pixel
 // changes.  Any S is correct; only the atomic traffic depends on it.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -170,11 +172,25 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
 // r = d - g (T + Q cos 2psi + U sin 2psi) on strided tiles; the thread keeps
 // the map values of its current pixel in registers across revisits (and
 // across the tile's segments).
+// T, Q, U of one pixel in one aligned record (one load per pixel change)
+template <typename T>
+struct alignas(4 * sizeof(T)) Stokes4 {
+    T t, q, u, pad;
+};
+
+// [3][npix] maps -> [npix] records
+template <typename T>
+__global__ __launch_bounds__(C3_NT) void k_interleave(const T *__restrict__ maps, int64_t npt,
+                                                      Stokes4<T> *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * C3_NT + threadIdx.x; i < npt; i += (int64_t)gridDim.x * C3_NT)
+        out[i] = Stokes4<T>{maps[i], maps[npt + i], maps[2 * npt + i], (T)0};
+}
+
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__restrict__ tiles,
                                                  const int32_t *__restrict__ pix,
                                                  const uint16_t *__restrict__ psi, const void *d,
-                                                 int d_f64, const T *__restrict__ maps,
+                                                 int d_f64, const Stokes4<T> *__restrict__ maps,
                                                  const double *__restrict__ gain,
                                                  const cx<T> *__restrict__ trig,
                                                  T *__restrict__ r_out) {
@@ -189,7 +205,6 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
     const int band = Ld.seg_band[tl.x];
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
-    const int64_t npt = Ld.npix_total;
     const float *df = (const float *)d;
     const double *dd = (const double *)d;
     int cur = -1;
@@ -199,10 +214,10 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
         if (p != cur) {
             cur = p;
             if ((uint32_t)p < npix) {
-                const int64_t gp = poff + p;
-                mT = maps[gp];
-                mQ = maps[npt + gp];
-                mU = maps[2 * npt + gp];
+                const Stokes4<T> m = maps[poff + p];
+                mT = m.t;
+                mQ = m.q;
+                mU = m.u;
             } else {
                 mT = mQ = mU = (T)NAN;
             }
@@ -486,16 +501,24 @@ hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const
 
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                               int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
-                              int d_f64, const void *maps, const double *gain, const void *trig,
-                              void *r_out) {
+                              int d_f64, const void *maps, void *maps4, const double *gain,
+                              const void *trig, void *r_out) {
     if (ntile <= 0) return hipSuccess;
-    if (mixed)
+    const int64_t npt = L.npix_total;
+    const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
+    if (mixed) {
+        hipLaunchKernelGGL(k_interleave<float>, dim3(gi), dim3(C3_NT), 0, st, (const float *)maps, npt,
+                           (Stokes4<float> *)maps4);
         hipLaunchKernelGGL(k_resid<float>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
-                           d_f64, (const float *)maps, gain, (const cx<float> *)trig, (float *)r_out);
-    else
+                           d_f64, (const Stokes4<float> *)maps4, gain, (const cx<float> *)trig,
+                           (float *)r_out);
+    } else {
+        hipLaunchKernelGGL(k_interleave<double>, dim3(gi), dim3(C3_NT), 0, st, (const double *)maps, npt,
+                           (Stokes4<double> *)maps4);
         hipLaunchKernelGGL(k_resid<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
-                           d_f64, (const double *)maps, gain, (const cx<double> *)trig,
+                           d_f64, (const Stokes4<double> *)maps4, gain, (const cx<double> *)trig,
                            (double *)r_out);
+    }
     return hipGetLastError();
 }
 
