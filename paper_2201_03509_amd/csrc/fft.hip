@@ -347,7 +347,9 @@ __device__ __forceinline__ double m2log_u_d(uint32_t x) {
 template <typename T>
 __device__ __forceinline__ void normals4(uint4 w, T *z) {
     if constexpr (sizeof(T) == 4) {
-        const float r0 = __builtin_sqrtf(m2log_u(w.x)), r1 = __builtin_sqrtf(m2log_u(w.z));
+        // -2 ln u >= 2^-32 and q > 0 stay far from denormals: the raw
+        // hardware square root needs no range scaling here
+        const float r0 = __builtin_amdgcn_sqrtf(m2log_u(w.x)), r1 = __builtin_amdgcn_sqrtf(m2log_u(w.z));
         // hardware sine/cosine take their argument in revolutions: sin(2 pi u)
         const float u1 = ((float)w.y + 0.5f) * 2.3283064365386963e-10f;
         const float u3 = ((float)w.w + 0.5f) * 2.3283064365386963e-10f;
@@ -411,7 +413,7 @@ __device__ __forceinline__ cx<T> cr_mode(const ModeCtx &mc, int64_t k, cx<T> E) 
         }
         T sq;
         if constexpr (sizeof(T) == 4)
-            sq = __builtin_sqrtf(q);
+            sq = __builtin_amdgcn_sqrtf(q);
         else
             sq = sqrt(q);
         out.x += s0 * (W1.x + sq * W2.x);
