@@ -127,8 +127,15 @@ __device__ cx<T> *lds_fft(cx<T> *b0, cx<T> *b1, int L, int lb, int lsi, const in
 template <typename T>
 constexpr int row_elems() { return sizeof(T) == 4 ? 2 * 5040 : 2 * 2520; }  // longest row pair
 
-template <int R, int DIR, int NT, typename T>
-__device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, int L, int lb, int lsi, int Ns,
+// IO = 0: LDS -> LDS in place; 1: the first stage (Ns = 1) reads its inputs
+// straight from the two rows in memory (element i of row b at g_b[i]; lanes
+// with consecutive j read consecutive elements); 2: the last stage (Ns R = L)
+// writes its outputs straight to the rows (output i = k + t Ns, again
+// consecutive across lanes).  The global forms skip one LDS round trip each.
+template <int R, int DIR, int NT, int IO, typename T>
+__device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, const GLBP cx<T> *g0,
+                                                       const GLBP cx<T> *g1, GLBP cx<T> *o0,
+                                                       GLBP cx<T> *o1, int L, int lb, int lsi, int Ns,
                                                        const GLBP cx<T> *__restrict__ tw) {
     constexpr int KB = (row_elems<T>() / R + NT - 1) / NT;
     const int LR = L / R;
@@ -147,11 +154,17 @@ __device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, int L, i
         ob[kb] = -1;
         if (q < nb) {
             const int b = q & bm, j = q >> lb;
-            int ia = (j << lsi) + b;
+            if constexpr (IO == 1) {
+                const GLBP cx<T> *g = b ? g1 : g0;
 #pragma unroll
-            for (int t = 0; t < R; ++t) {
-                v[kb][t] = buf[ia];
-                ia += in_stride;
+                for (int t = 0; t < R; ++t) v[kb][t] = g[j + t * LR];
+            } else {
+                int ia = (j << lsi) + b;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    v[kb][t] = buf[ia];
+                    ia += in_stride;
+                }
             }
             const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
             const int k = j - jd * Ns;
@@ -197,10 +210,17 @@ __device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, int L, i
                 }
             }
             dft_any<R, DIR>(v[kb]);
-            ob[kb] = ((jd * NsR + k) << lsi) + b;
+            if constexpr (IO == 2) {
+                GLBP cx<T> *o = b ? o1 : o0;  // jd = 0 in the last stage
+#pragma unroll
+                for (int t = 0; t < R; ++t) o[k + t * Ns] = v[kb][t];
+            } else {
+                ob[kb] = ((jd * NsR + k) << lsi) + b;
+            }
         }
     }
-    __syncthreads();
+    if constexpr (IO == 2) return;  // nothing written to LDS
+    if constexpr (IO == 0) __syncthreads();  // in place: all reads before any write
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         if (ob[kb] >= 0) {
@@ -215,32 +235,47 @@ __device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, int L, i
     __syncthreads();
 }
 
+// Row FFT over the LDS buffer; with g0 set the first stage loads the rows
+// from memory, with o0 set the last stage stores them (both need >= 2 stages)
 template <int DIR, int NT, typename T>
-__device__ void lds_fft_ip(cx<T> *b, int L, int lb, int lsi, const int8_t *rad, int nrad,
-                           const cx<T> *tw_) {
+__device__ void row_fft(cx<T> *b, const cx<T> *g0, const cx<T> *g1, cx<T> *o0, cx<T> *o1, int L,
+                        int lb, int lsi, const int8_t *rad, int nrad, const cx<T> *tw_) {
     const GLBP cx<T> *tw = (const GLBP cx<T> *)tw_;
     LDSP cx<T> *lb_ = (LDSP cx<T> *)b;
+    const GLBP cx<T> *G0 = (const GLBP cx<T> *)g0, *G1 = (const GLBP cx<T> *)g1;
+    GLBP cx<T> *O0 = (GLBP cx<T> *)o0, *O1 = (GLBP cx<T> *)o1;
     int Ns = 1;
     for (int s = 0; s < nrad; ++s) {
         const int R = rad[s];
-#define C3_RADIX(RR)                                               \
-    case RR:                                                       \
-        fft_stage_ip<RR, DIR, NT>(lb_, L, lb, lsi, Ns, tw);        \
+        const int io = (s == 0 && g0) ? 1 : (s == nrad - 1 && o0) ? 2 : 0;
+#define C3_RADIX_IO(RR, IO)                                                          \
+    case RR:                                                                         \
+        fft_stage_ip<RR, DIR, NT, IO>(lb_, G0, G1, O0, O1, L, lb, lsi, Ns, tw);      \
         break;
+#define C3_RADIX0(RR) C3_RADIX_IO(RR, 0)
+#define C3_RADIX1(RR) C3_RADIX_IO(RR, 1)
+#define C3_RADIX2(RR) C3_RADIX_IO(RR, 2)
         if constexpr (sizeof(T) == 4) {
-            switch (R) {
-                C3_ROW_RADICES_F32(C3_RADIX)
-            default:
-                break;  // plans hold only the radices above
+            if (io == 0) {
+                switch (R) { C3_ROW_RADICES_F32(C3_RADIX0) default: break; }
+            } else if (DIR < 0 && io == 1) {
+                switch (R) { C3_ROW_RADICES_F32(C3_RADIX1) default: break; }
+            } else if (DIR > 0 && io == 2) {
+                switch (R) { C3_ROW_RADICES_F32(C3_RADIX2) default: break; }
             }
         } else {
-            switch (R) {
-                C3_ROW_RADICES_F64(C3_RADIX)
-            default:
-                break;
+            if (io == 0) {
+                switch (R) { C3_ROW_RADICES_F64(C3_RADIX0) default: break; }
+            } else if (DIR < 0 && io == 1) {
+                switch (R) { C3_ROW_RADICES_F64(C3_RADIX1) default: break; }
+            } else if (DIR > 0 && io == 2) {
+                switch (R) { C3_ROW_RADICES_F64(C3_RADIX2) default: break; }
             }
         }
-#undef C3_RADIX
+#undef C3_RADIX0
+#undef C3_RADIX1
+#undef C3_RADIX2
+#undef C3_RADIX_IO
         Ns *= R;
     }
 }
@@ -458,37 +493,19 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     const cx<T> *pool = (const cx<T> *)a.twpool;
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
 
-    if constexpr (sizeof(T) == 4) {
-        // every load of the thread issued before the first LDS store, so the
-        // HBM latency is paid once per block rather than once per element
-        // (FP32: the FP64 kernel has no registers to spare for it)
-        constexpr int KL = (row_elems<T>() / 2 + NT - 1) / NT;
-        const cx<T> *ya = Y + (int64_t)ka * M2, *yb = Y + (int64_t)kb * M2;
-        cx<T> va[KL], vb[KL];
-#pragma unroll
-        for (int u = 0; u < KL; ++u) {
-            const int i = (int)threadIdx.x + u * NT;
-            if (i < M2) {
-                va[u] = ya[i];
-                if (two) vb[u] = yb[i];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < KL; ++u) {
-            const int i = (int)threadIdx.x + u * NT;
-            if (i < M2) {
-                buf[i * si] = va[u];
-                if (two) buf[i * si + 1] = vb[u];
-            }
-        }
-    } else {
+    // the first forward stage reads the two rows from memory and the last
+    // inverse stage writes them back (rows of two or more stages)
+    cx<T> *ya = Y + (int64_t)ka * M2, *yb = Y + (int64_t)kb * M2;
+    const bool direct = p.nr2 >= 2;
+    if (!direct) {
         for (int i = threadIdx.x; i < M2; i += NT) {
-            buf[i * si] = Y[(int64_t)ka * M2 + i];
-            if (two) buf[i * si + 1] = Y[(int64_t)kb * M2 + i];
+            buf[i * si] = ya[i];
+            if (two) buf[i * si + 1] = yb[i];
         }
+        __syncthreads();
     }
-    __syncthreads();
-    lds_fft_ip<-1, NT>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+    row_fft<-1, NT>(buf, direct ? ya : nullptr, yb, (cx<T> *)nullptr, (cx<T> *)nullptr, M2, lb, two,
+                    p.r2, p.nr2, pool + p.tw2);
 
     ModeCtx mc;
     {
@@ -570,31 +587,12 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     }
     if (MODE == 0) {
         __syncthreads();
-        lds_fft_ip<1, NT>(buf, M2, lb, two, p.r2, p.nr2, pool + p.tw2);
-        if constexpr (sizeof(T) == 4) {
-            constexpr int KL = (row_elems<T>() / 2 + NT - 1) / NT;
-            cx<T> *ya = Y + (int64_t)ka * M2, *yb = Y + (int64_t)kb * M2;
-            cx<T> va[KL], vb[KL];
-#pragma unroll
-            for (int u = 0; u < KL; ++u) {
-                const int i = (int)threadIdx.x + u * NT;
-                if (i < M2) {
-                    va[u] = buf[i * si];
-                    if (two) vb[u] = buf[i * si + 1];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < KL; ++u) {
-                const int i = (int)threadIdx.x + u * NT;
-                if (i < M2) {
-                    ya[i] = va[u];
-                    if (two) yb[i] = vb[u];
-                }
-            }
-        } else {
+        row_fft<1, NT>(buf, (const cx<T> *)nullptr, (const cx<T> *)nullptr, direct ? ya : nullptr, yb,
+                       M2, lb, two, p.r2, p.nr2, pool + p.tw2);
+        if (!direct) {
             for (int i = threadIdx.x; i < M2; i += NT) {
-                Y[(int64_t)ka * M2 + i] = buf[i * si];
-                if (two) Y[(int64_t)kb * M2 + i] = buf[i * si + 1];
+                ya[i] = buf[i * si];
+                if (two) yb[i] = buf[i * si + 1];
             }
         }
     } else {
