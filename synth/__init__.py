@@ -1,3 +1,3 @@
 """Seeded synthetic input generators (inputs only; no step of the method)."""
-from .make import make, seed32, TodSet, HuffStream, save, load, make_cached  # noqa: F401
+from .make import make, seed32, TodSet, HuffStream, save, load, make_cached, plane_mask, plane_mask_pixels  # noqa: F401
 from . import configs, healpix, huffman_enc  # noqa: F401

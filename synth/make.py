@@ -348,3 +348,27 @@ def make_cached(k, cache_dir=None, **kw):
     ts = make(k, **kw)
     save(ts, path)
     return ts
+
+
+def plane_mask(ts, pix, half_width_deg=10.0):
+    """Processing mask (uint8, 1 = usable) that removes every sample whose
+    pixel centre lies within half_width_deg of the map frame's equator: a
+    stand-in for a Galactic-plane mask, crossed twice per spin period in long
+    contiguous gaps."""
+    out = np.ones(ts.nsamp, dtype=np.uint8)
+    table = {}  # per nside: the mask of every pixel centre
+    for q in range(ts.nseg):
+        a, b = int(ts.seg_off[q]), int(ts.seg_off[q + 1])
+        if b == a:
+            continue
+        nside = int(ts.band_nside[ts.seg_band[q]])
+        if nside not in table:
+            table[nside] = plane_mask_pixels(nside, np.arange(12 * nside * nside), half_width_deg)
+        out[a:b] = table[nside][np.asarray(pix[a:b], dtype=np.int64)]
+    return out
+
+
+def plane_mask_pixels(nside, pix, half_width_deg=10.0):
+    """The same mask for a list of RING pixels of one nside."""
+    theta, _ = healpix.pix2ang_ring(nside, np.asarray(pix, dtype=np.int64))
+    return (np.abs(np.cos(theta)) >= np.sin(np.radians(half_width_deg))).astype(np.uint8)
