@@ -120,11 +120,39 @@ def _oracle_segment(q):
     return q, pix, nc
 
 
-def cpu_baseline(ts, seed, it, maps32, budget_s=15.0):
+MASKED_IT = 7777      # Gibbs iteration number of the masked-draw leg
+MASKED_TOL = 1e-8     # its CG tolerance (FP32 transforms, FP64 Krylov vectors)
+
+
+def _oracle_masked(q):
+    """Masked n_corr draw of segment q (processing mask +-10 deg around the
+    map frame's equator) by the oracle's CG, for the accuracy report."""
+    ts, seed, maps32 = _BASE["ts"], _BASE["seed"], _BASE["maps"]
+    import numpy as np
+    import synth
+    from oracle import gapfill as og
+    from oracle import huffman as oh
+    from oracle import tod as ot
+    n = int(ts.seg_off[q + 1] - ts.seg_off[q])
+    pix = oh.StreamDecoder(ts.pix_huff).segment(q, n)
+    psi = oh.StreamDecoder(ts.psi_huff).segment(q, n)
+    a = ts.seg_off[q]
+    band = ts.seg_band[q]
+    gp = pix + ts.band_pix_off[band]
+    s = ot.project(maps32, gp, psi, ts.gain[q])
+    r = ts.d[a:a + n].astype(np.float64) - s
+    m = synth.plane_mask_pixels(int(ts.band_nside[band]), pix)
+    nc, k = og.cg_ncorr_segment(r, m, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q], ts.alpha[q],
+                                seed, q, MASKED_IT, tol=1e-12)
+    return q, nc, k
+
+
+def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
     """The oracle, as it stands, over a bounded sample of the same workload,
     one segment per worker process.  Runs before the GPU is touched (the
     worker processes are forked)."""
     import multiprocessing as mp
+    import numpy as np
     workers = max(1, min(16, os.cpu_count() or 1))
     _BASE.update(ts=ts, seed=seed, it=it, maps=maps32)
     t0 = time.perf_counter()
@@ -143,6 +171,10 @@ def cpu_baseline(ts, seed, it, maps32, budget_s=15.0):
                 log("  oracle segments done: %d/%d" % (len(res), nseg))
     wall = time.perf_counter() - t0
     nsamp = int(sum(ts.seg_off[q + 1] - ts.seg_off[q] for q in range(nseg)))
+    # masked-draw references (not part of the timed sample)
+    mq = [int(q) for q in np.linspace(0, ts.nseg - 1, masked_segments).round()] if masked_segments else []
+    with ctx.Pool(max(1, min(workers, len(mq)))) as pool:
+        _BASE["masked"] = list(pool.imap_unordered(_oracle_masked, mq)) if mq else []
     return {
         "value": nsamp / wall, "unit": "TOD samples/s", "cores": workers, "kind": "oracle",
         "sample": "%d of %d segments (%d samples): decode+project+n_corr+bin, FP64 numpy/C, "
@@ -162,6 +194,51 @@ def compare_to_oracle(ts, res, gpu_ncorr, gpu_pix):
             "decode_bit_exact": exact, "segments": len(res)}
 
 
+def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix):
+    """The masked n_corr draw (CG gap filling) over the whole workload with a
+    +-10 deg plane mask: one warm-up call, one timed call (HIP events around
+    every launch), iteration counts and the error against the oracle's CG on
+    the sampled segments."""
+    import numpy as np
+    import torch
+    import synth
+    dev = tod.d.device
+    mask_h = synth.plane_mask(ts, gpu_pix)
+    mask = torch.from_numpy(mask_h).to(dev)
+    s = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
+    ctx.project_sky(tod, "mixed", out["pix"], out["psi"], maps32, s)
+    nc = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
+    iters = torch.empty(ts.nseg, dtype=torch.int32, device=dev)
+    ctx.sample_ncorr_masked(tod, "mixed", tod.d, s, mask, seed, MASKED_IT, nc, tol=MASKED_TOL, iters=iters)
+    ctx.sync()
+    ctx.enable_timing(True)
+    ctx.kernel_times()
+    t0 = time.perf_counter()
+    ctx.sample_ncorr_masked(tod, "mixed", tod.d, s, mask, seed, MASKED_IT, nc, tol=MASKED_TOL, iters=iters)
+    ctx.sync()
+    ms = (time.perf_counter() - t0) * 1e3
+    kt = ctx.kernel_times()
+    ctx.enable_timing(False)
+    it_h = iters.cpu().numpy()
+    rep = {"ms_per_call": round(ms, 2), "samples_per_s": ts.nsamp / (ms / 1e3),
+           "masked_fraction": round(float(1.0 - mask_h.mean()), 4), "tol": MASKED_TOL,
+           "iterations": {"min": int(np.abs(it_h).min()), "median": float(np.median(np.abs(it_h))),
+                          "max": int(np.abs(it_h).max()), "unconverged": int((it_h < 0).sum())},
+           "kernels_ms": {k: round(v[0], 2) for k, v in kt.items() if v[1]},
+           "launches": {k: v[1] for k, v in kt.items() if v[1]}}
+    ref = _BASE.get("masked")
+    if ref:
+        g = nc.cpu().numpy()
+        errs = []
+        for q, r, k in ref:
+            a, b = ts.seg_off[q], ts.seg_off[q + 1]
+            errs.append({"segment": q, "rel_l2": float(np.linalg.norm(g[a:b] - r) / np.linalg.norm(r)),
+                         "iterations_gpu": int(it_h[q]), "iterations_oracle": int(k)})
+        rep["accuracy_vs_oracle"] = errs
+    log("masked n_corr: %.1f ms per call, iterations %s" % (ms, rep["iterations"]))
+    return rep
+
+
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -173,6 +250,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cache-dir", default=None, help="reuse generated inputs saved here")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-masked", action="store_true", help="skip the masked n_corr draw leg")
     ap.add_argument("--fft-batch", type=int, default=None,
                     help="complex elements per FFT batch (0 = all segments at once)")
     ap.add_argument("--bin-stride", type=int, default=None, help="override the binning stride")
@@ -311,6 +389,11 @@ def main():
         del outp
         torch.cuda.empty_cache()
 
+    masked = None
+    if not args.no_masked:
+        masked = masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix)
+        torch.cuda.empty_cache()
+
     copy = None
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -349,6 +432,7 @@ def main():
         "fft_splits": plans,
         "bin_stride": tuned.get("bin_stride"),
         "accuracy_vs_oracle": acc_report,
+        "masked_ncorr": masked,
         "copy_probe": copy,
     }
     print(json.dumps(line), flush=True)

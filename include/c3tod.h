@@ -168,6 +168,34 @@ tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                         const double *sigma0, const double *fknee, const double *alpha,
                         uint64_t seed, uint64_t iter, int mean_only, void *ncorr_out);
 
+/* Correlated-noise draw with a processing mask (gap filling: the constrained
+ * realisation needs FFTs inside a CG solver where scans cross masked sky,
+ * section 5 and the correlated-noise row of Table 2).  On the extension and
+ * spectrum of sample_ncorr, with mu = [m, reverse(m), 1 ...] the extended mask
+ * and F the unitary DFT, each segment solves A x = b by preconditioned CG:
+ *   A = F^H diag(1/P) F + diag(mu)/sigma0^2,
+ *   b = mu (e/sigma0^2 + F^H W1/sigma0) + F^H (W2 P^-1/2)   (W as sample_ncorr),
+ *   preconditioner F^H diag(1/(1/sigma0^2 + 1/P)) F, start x = 0, stop when
+ *   ||b - A x|| <= tol ||b|| or after max_iter iterations;  n_corr = x[0:n].
+ * With nothing masked the first iteration returns sample_ncorr's draw.
+ * mask: device [nsamp] uint8, nonzero = sample used.  FFTs run in the
+ * precision's type; the CG vectors and sums are FP64 in both precisions, so
+ * the recursively updated residual keeps falling with FP32 transforms too;
+ * their rounding puts a floor of a few 1e-6 (relative) under the solution's
+ * error.  ||b|| is dominated by the high-frequency draw term, so tol must sit
+ * well below the wanted solution accuracy (1e-8 for the FP32 floor).
+ * iters_out: device [nseg] int32 (may be NULL): iterations per segment,
+ * negated where max_iter stopped it first (0: b = 0 or empty segment).
+ * Workspace: five sweep-wide vectors of the extended length (three FP64, two
+ * of the precision's type), held by the context. */
+tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                               const void *d, tod_dtype d_dtype, const void *s,
+                               const uint8_t *mask,
+                               const double *sigma0, const double *fknee, const double *alpha,
+                               uint64_t seed, uint64_t iter, int mean_only,
+                               double tol, int max_iter,
+                               void *ncorr_out, int32_t *iters_out);
+
 /* Binning into per-pixel P^T N^-1 d and P^T N^-1 P (section 2.4: co-added on
  * the fly during the TOD loop; binning row of the resource table): with
  * w = g/sigma0^2, v = d - n_corr, (c, s) = (cos 2psi, sin 2psi):
@@ -235,13 +263,19 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
 
 /* --------------------------------------------------------- planning/tuning */
 
-/* Measure candidate FFT splits/radix orders for every FFT length the layout
- * needs and candidate binning strides, keep the fastest in the context, and
- * (if cache_path != NULL) merge them into a JSON cache file.  Needs the
- * decoded pointing (pix) for the binning probe; may be NULL to skip it. */
+/* Measure candidate FFT splits for every FFT length the layout needs (section
+ * 4.2's measured cost table, here per length: the split M = M1 x M2, the
+ * column kernel -- whole columns in registers for a compiled M1, or LDS
+ * tiles -- and the radix order) and the binning stride, keep the fastest in
+ * the context, and (if cache_path != NULL) write them to a JSON cache file.
+ * Needs the decoded pointing (pix) for the binning probe; may be NULL to skip
+ * it. */
 tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                         const int32_t *pix, const char *cache_path);
-/* Load plans from a JSON cache written by tod_autotune (missing file: OK). */
+/* Load plans from a JSON cache written by tod_autotune (missing file: OK;
+ * unreadable file: TOD_EINVAL).  A cached split is used only where the
+ * kernels can run it (its factors multiply out, its column kernel exists,
+ * every radix has a compiled stage); otherwise the default split is used. */
 tod_status tod_load_tuning(tod_ctx ctx, const char *cache_path);
 /* Binning stride (samples between revisits of a pixel) per band; 0 = let the
  * library choose.  Correct for any value; only speed depends on it. */
@@ -257,9 +291,11 @@ tod_status tod_set_fft_batch(tod_ctx ctx, int64_t complex_elems);
  * graph capture is bracketed by HIP events on the context stream (the sweep
  * then runs eagerly).  tod_kernel_times synchronises the stream, returns the
  * summed milliseconds and launch counts since the previous read and resets
- * them.  Kernel ids (arrays of 8): 0 decode, 1 projection, 2 FFT forward
- * column pass, 3 FFT row pass (filter + draw, or Whittle sums), 4 FFT inverse
- * column pass, 5 binning, 6 per-pixel solve, 7 chi^2 time-domain terms. */
+ * them.  Kernel ids (arrays of 9): 0 decode, 1 projection, 2 FFT forward
+ * column pass, 3 FFT row pass (filter + draw, Whittle sums, or the masked
+ * draw's Fourier-diagonal products), 4 FFT inverse column pass, 5 binning,
+ * 6 per-pixel solve, 7 chi^2 time-domain terms, 8 the masked draw's CG vector
+ * updates and reductions. */
 tod_status tod_enable_timing(tod_ctx ctx, int enable);
 tod_status tod_kernel_times(tod_ctx ctx, double *total_ms, int32_t *launches);
 

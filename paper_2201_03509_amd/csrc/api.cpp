@@ -100,7 +100,11 @@ struct Plan {
     std::vector<Batch> batches;
     int col_lds = 0, row_lds = 0;         // dynamic LDS bytes per FFT pass
     int64_t work_elems = 0;
+    int64_t ext_elems = 0;                // complex elements of all extended vectors (ext_off)
     DevBuf sample_tiles;
+    // masked n_corr solver: tiles over the extended vectors, per-segment tile ranges
+    DevBuf cg_tiles, cg_seg_tiles;
+    int ncg = 0;
     int nsample_tiles = 0;
     // decode tasks per chunk length
     std::map<int, std::unique_ptr<DevBuf>> dec_tasks;
@@ -121,6 +125,9 @@ struct tod_ctx_s {
     DevBuf trig32, trig64, work, seg_sums, seg_whittle, probe_counts, resid;
     DevBuf dec_tabs;                      // decoding tables, rebuilt by every decode
     DevBuf maps4;                         // the sweep's maps as (T, Q, U, 0) records
+    // masked n_corr solver: FP64 Krylov vectors, FFT in/out vectors, partial
+    // sums, per-segment state, active flags and the active-segment count
+    DevBuf cg_x, cg_res, cg_p, cg_fin, cg_fout, cg_part, cg_state, cg_act, cg_count;
     std::map<uint64_t, std::unique_ptr<Plan>> plans;
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
@@ -262,7 +269,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     const int nseg = L->nseg;
     P->h_segs.resize(nseg);
     Pool pool;
-    int64_t scr = 0;
+    int64_t scr = 0, ext = 0;
     for (int s = 0; s < nseg; ++s) {
         SegInfo &g = P->h_segs[s];
         g.samp_off = L->h_seg_off[s];
@@ -272,16 +279,16 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         g.accept = 1;
         g.pad = 0;
         g.scr_off = scr;
+        g.ext_off = ext;
         g.plan = -1;
         if (g.n <= 0) continue;
         const int64_t M = next_5smooth(g.n);
+        ext += M;
         auto it = P->plan_of_M.find(M);
         if (it == P->plan_of_M.end()) {
-            c3tune::FftChoice ch, chk;
-            // a tuned choice is used only if it is still a valid split here
-            const bool tuned = ctx->tuned.get(mixed, M, ch) &&
-                               c3tune::make_choice(M, ch.M2, mixed, 1 << 30, 0, ch.colreg, chk) &&
-                               (ch.colreg || (ch.B >= 1 && (int64_t)ch.M1 * ch.B <= c3tune::col_tile(mixed)));
+            c3tune::FftChoice ch;
+            // a tuned choice is used only if the kernels here can run it
+            const bool tuned = ctx->tuned.get(mixed, M, ch) && c3tune::choice_ok(ch, M, mixed);
             if (!tuned && !c3tune::default_choice(M, mixed, ch))
                 return fail(ctx, TOD_ENOTSUP, "no FFT plan for M = " + std::to_string(M));
             FftPlan fp;
@@ -308,6 +315,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         }
         g.plan = it->second;
     }
+    P->ext_elems = ext;
     // LPT order: longest FFT first
     P->seg_order.resize(nseg);
     for (int s = 0; s < nseg; ++s) P->seg_order[s] = s;
@@ -553,7 +561,7 @@ tod_status ensure_work(tod_ctx ctx, Plan *P) {
 }
 
 // kernel ids of tod_kernel_times
-enum { K_DECODE = 0, K_PROJECT, K_COLF, K_ROW, K_COLI, K_BIN, K_SOLVE, K_CHISQ, K_NKERNEL };
+enum { K_DECODE = 0, K_PROJECT, K_COLF, K_ROW, K_COLI, K_BIN, K_SOLVE, K_CHISQ, K_CG, K_NKERNEL };
 
 hipEvent_t pool_event(tod_ctx c) {
     if (!c->ev_pool.empty()) {
@@ -588,14 +596,15 @@ struct KTimer {
 };
 
 // the FFT passes over every batch: per batch forward columns, rows, inverse columns
-tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::FftArgs &a0, int npass) {
+tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::FftArgs &a0, int npass,
+                   int first = 0) {
     for (const Plan::Batch &b : P->batches) {
         c3::FftArgs a = a0;
         a.col_tasks = (const int2 *)P->col_tasks.p + b.col0;
         a.ncol_tasks = b.ncol;
         a.row_tasks = (const int2 *)P->row_tasks.p + b.row0;
         a.nrow_tasks = b.nrow;
-        for (int pass = 0; pass < npass; ++pass) {
+        for (int pass = first; pass < npass; ++pass) {
             if (pass == 1) {
                 for (const Plan::RowGroup &g : b.rgroups) {
                     c3::FftArgs ag = a;
@@ -788,6 +797,146 @@ tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
     HIPCHK(c3::launch_set_u64(ctx->stream, ctx->d_seed_iter, seed, iter));
     return ncorr_impl(ctx, lay, mixed, P, d, d_dtype, s, !mixed, sigma0, fknee, alpha, mean_only,
                       ncorr_out);
+}
+
+// tiles of C3_CG_TILE reals over every segment's extended vector, built once per plan
+static tod_status cg_tiles(tod_ctx ctx, Plan *P) {
+    if (P->cg_seg_tiles.p) return TOD_OK;
+    std::vector<int4> t;
+    std::vector<int2> st(P->h_segs.size(), make_int2(0, 0));
+    for (size_t s = 0; s < P->h_segs.size(); ++s) {
+        const SegInfo &g = P->h_segs[s];
+        if (g.plan < 0) continue;
+        const int64_t N = 2 * (int64_t)P->h_plans[g.plan].M;
+        st[s].x = (int)t.size();
+        for (int64_t t0 = 0; t0 < N; t0 += C3_CG_TILE)
+            t.push_back(make_int4((int)s, (int)t0, (int)std::min<int64_t>(C3_CG_TILE, N - t0), 0));
+        st[s].y = (int)t.size() - st[s].x;
+    }
+    if (t.size() > (size_t)INT32_MAX / 2) return fail(ctx, TOD_ENOTSUP, "too many solver tiles");
+    HIPCHK(P->cg_tiles.upload(t, ctx->stream));
+    HIPCHK(P->cg_seg_tiles.upload(st, ctx->stream));
+    P->ncg = (int)t.size();
+    return TOD_OK;
+}
+
+tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const void *d,
+                               tod_dtype d_dtype, const void *s, const uint8_t *mask,
+                               const double *sigma0, const double *fknee, const double *alpha,
+                               uint64_t seed, uint64_t iter, int mean_only, double tol, int max_iter,
+                               void *ncorr_out, int32_t *iters_out) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (!d || !s || !mask || !sigma0 || !fknee || !alpha || !ncorr_out)
+        return fail(ctx, TOD_EINVAL, "NULL argument");
+    if (!(tol >= 0.0) || max_iter < 1) return fail(ctx, TOD_EINVAL, "tol must be >= 0 and max_iter >= 1");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    if ((r = ensure_work(ctx, P)) != TOD_OK) return r;
+    if ((r = cg_tiles(ctx, P)) != TOD_OK) return r;
+    const int nseg = lay->nseg;
+    const size_t NR = 2 * (size_t)P->ext_elems + 64, esz = mixed ? 4 : 8;
+    HIPCHK(ctx->cg_x.ensure(NR * 8));
+    HIPCHK(ctx->cg_res.ensure(NR * 8));
+    HIPCHK(ctx->cg_p.ensure(NR * 8));
+    HIPCHK(ctx->cg_fin.ensure(NR * esz));
+    HIPCHK(ctx->cg_fout.ensure(NR * esz));
+    HIPCHK(ctx->cg_part.ensure((size_t)P->ncg * 8 + 64));
+    HIPCHK(ctx->cg_state.ensure((size_t)nseg * sizeof(c3::CgState) + 64));
+    HIPCHK(ctx->cg_act.ensure((size_t)nseg * 4 + 64));
+    HIPCHK(ctx->cg_count.ensure(64));
+    hipStream_t st = ctx->stream;
+    HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
+    int32_t *act = (int32_t *)ctx->cg_act.p, *count = (int32_t *)ctx->cg_count.p;
+    c3::CgState *cs = (c3::CgState *)ctx->cg_state.p;
+    const int2 *seg_tiles = (const int2 *)P->cg_seg_tiles.p;
+    double *part = (double *)ctx->cg_part.p;
+    const double tol2 = tol * tol;
+
+    c3::FftArgs a = fft_args(ctx, P, lay);
+    a.sigma0 = sigma0;
+    a.fknee = fknee;
+    a.alpha = alpha;
+    a.full_io = 1;
+    if (!mean_only) {  // F^H W1 -> fout, F^H (W2 sqrt(1/P)) -> fin: rows and inverse columns only
+        a.mode = 3;
+        a.which = 0;
+        a.out = ctx->cg_fout.p;
+        if ((r = run_fft(ctx, st, P, mixed, a, 3, 1)) != TOD_OK) return r;
+        a.which = 1;
+        a.out = ctx->cg_fin.p;
+        if ((r = run_fft(ctx, st, P, mixed, a, 3, 1)) != TOD_OK) return r;
+    }
+    c3::CgVecArgs v;
+    memset(&v, 0, sizeof(v));
+    v.tiles = (const int4 *)P->cg_tiles.p;
+    v.ntile = P->ncg;
+    v.segs = (const SegInfo *)P->segs.p;
+    v.act = act;
+    v.cs = cs;
+    v.d = d;
+    v.d_f64 = d_dtype == TOD_F64;
+    v.s = s;
+    v.s_f64 = !mixed;
+    v.mask = mask;
+    v.sigma0 = sigma0;
+    v.w1 = mean_only ? nullptr : ctx->cg_fout.p;
+    v.v2 = mean_only ? nullptr : ctx->cg_fin.p;
+    v.x = (double *)ctx->cg_x.p;
+    v.res = (double *)ctx->cg_res.p;
+    v.p = (double *)ctx->cg_p.p;
+    v.fin = ctx->cg_fin.p;
+    v.fout = ctx->cg_fout.p;
+    v.part = part;
+    // b, x = 0, res = b; then z = M b, rz = res . z, p = z
+    auto vec = [&](int op, const c3::CgVecArgs &va) -> hipError_t {
+        KTimer kt(ctx, K_CG, st);
+        return c3::launch_cg_vec(st, mixed, op, va);
+    };
+    auto fin = [&](int step) -> hipError_t {
+        KTimer kt(ctx, K_CG, st);
+        return c3::launch_cg_finish(st, nseg, seg_tiles, part, cs, act, step, tol2, max_iter, count);
+    };
+    HIPCHK(vec(c3::CG_OP_INIT, v));
+    HIPCHK(fin(c3::CG_INIT));
+    a.mode = 2;
+    a.in_a = ctx->cg_fin.p;
+    a.in_a_f64 = !mixed;
+    a.out = ctx->cg_fout.p;
+    a.active = act;
+    a.which = 1;
+    if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
+    HIPCHK(vec(c3::CG_OP_RZ, v));
+    HIPCHK(fin(c3::CG_RZ0));
+    HIPCHK(vec(c3::CG_OP_P, v));
+    for (int it = 1; it <= max_iter; ++it) {
+        a.which = 0;  // F^H diag(1/P) F p
+        if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
+        HIPCHK(vec(c3::CG_OP_PAP, v));
+        HIPCHK(fin(c3::CG_ALPHA));
+        HIPCHK(vec(c3::CG_OP_XR, v));
+        HIPCHK(fin(c3::CG_RES));
+        int32_t h = 0;
+        HIPCHK(hipMemcpyAsync(&h, count, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (h == 0) break;
+        a.which = 1;  // z = M res
+        if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
+        HIPCHK(vec(c3::CG_OP_RZ, v));
+        HIPCHK(fin(c3::CG_BETA));
+        HIPCHK(vec(c3::CG_OP_P, v));
+    }
+    c3::CgVecArgs c = v;
+    c.tiles = (const int4 *)P->sample_tiles.p;
+    c.ntile = P->nsample_tiles;
+    c.out = ncorr_out;
+    HIPCHK(vec(c3::CG_OP_CROP, c));
+    if (iters_out) HIPCHK(c3::launch_cg_iters(st, nseg, cs, iters_out));
+    return TOD_OK;
 }
 
 tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int32_t *pix,

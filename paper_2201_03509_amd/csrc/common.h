@@ -58,6 +58,8 @@ struct SegInfo {
     int32_t det;
     int32_t accept;
     int32_t pad;
+    int64_t ext_off;     // first complex element of the segment's whole extended vector
+                         // (N = 2M reals) in sweep-wide vectors (masked n_corr solver)
 };
 
 // FFT plan of one complex length M = M1 * M2 (the real length is N = 2M).
@@ -150,7 +152,7 @@ hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, con
                               int d_f64, const void *maps, void *maps4, const double *gain,
                               const void *trig, void *r_out);
 
-// FFT-based passes.  mode: 0 = n_corr draw, 1 = Whittle sums (chi^2), 2 = chi^2 adjoint sums
+// FFT-based passes (modes: see launch_fft_pass)
 struct FftArgs {
     const SegInfo *segs;
     const FftPlan *plans;
@@ -170,12 +172,20 @@ struct FftArgs {
     const uint64_t *seed_iter;  // device {seed, iter}
     int mean_only;
     int mode;
-    double *whittle;            // mode 1/2: per-segment sums [nseg][4]
+    double *whittle;            // mode 1: per-segment sums [nseg][4]
     int col_lds, row_lds;       // dynamic LDS bytes of the column and row passes
+    int full_io;                // 1: pass 1 reads, pass 3 writes whole extended vectors
+                                //    (N reals per segment at real offset 2 ext_off of
+                                //    in_a / out) instead of the mirrored segment / its crop
+    int which;                  // mode 2: 0 filter 1/P, 1 filter 1/(1/sigma0^2 + 1/P);
+                                // mode 3: 0 spectrum W1, 1 spectrum W2 sqrt(1/P)
+    const int32_t *active;      // per segment, 0: skip (NULL: every segment runs)
 };
-// pass 0: forward column FFTs; 1: row pass (mode 0 n_corr draw, 1 Whittle sums);
-// 2: inverse column FFTs.  m1reg > 0 selects the register column kernels for
-// that column length (passes 0 and 2); 0 the LDS column tiles.
+// pass 0: forward column FFTs; 1: row pass (mode 0 n_corr draw, 1 Whittle sums,
+// 2 Fourier-diagonal filter, 3 inverse transform of a drawn spectrum: no
+// forward transform, no input); 2: inverse column FFTs.  m1reg > 0 selects the
+// register column kernels for that column length (passes 0 and 2); 0 the LDS
+// column tiles.
 hipError_t launch_fft_pass(hipStream_t st, int prec_mixed, const FftArgs &a, int pass, int m1reg);
 // register column kernels (fftcol.hip); returns hipErrorInvalidValue for a
 // column length without a compiled kernel
@@ -211,5 +221,44 @@ hipError_t launch_chisq_finish(hipStream_t st, const LayoutDev &L, const double 
                                double *chisq_seg, double *grad_gain, double *grad_sigma0,
                                double *grad_fknee, double *grad_alpha);
 hipError_t launch_set_u64(hipStream_t st, uint64_t *p, uint64_t a, uint64_t b);
+
+// ---- masked n_corr draw (gapfill.hip): per-segment CG state and vector passes
+#define C3_CG_TILE 4096      // reals of a segment's extended vector per elementwise tile
+struct CgState {
+    double rz;       // res . z of the current residual
+    double bb;       // b . b
+    double alpha, beta;
+    double rr;       // res . res after the last update
+    int32_t iters;   // CG iterations done
+    int32_t converged;
+};
+enum CgStep { CG_INIT = 0, CG_RZ0, CG_ALPHA, CG_RES, CG_BETA };
+enum CgOp { CG_OP_INIT = 0, CG_OP_PAP, CG_OP_XR, CG_OP_RZ, CG_OP_P, CG_OP_CROP };
+struct CgVecArgs {
+    const int4 *tiles;          // (seg, first extended index, length, 0); CROP: sample tiles
+    int ntile;
+    const SegInfo *segs;
+    const int32_t *act;
+    const CgState *cs;
+    const void *d;              // INIT: residual d - s and the mask (per sample)
+    int d_f64;
+    const void *s;
+    int s_f64;
+    const uint8_t *mask;        // 1: sample used, 0: masked
+    const double *sigma0;
+    const void *w1, *v2;        // INIT: F^H W1 and F^H (W2 sqrt(1/P)) (NULL: mean only)
+    double *x, *res, *p;        // FP64 Krylov vectors (sweep-wide, 2 ext_off per segment)
+    void *fin;                  // FFT input vector (transform type)
+    const void *fout;           // FFT output vector
+    double *part;               // per-tile partial sums
+    void *out;                  // CROP: n_corr per sample
+};
+hipError_t launch_cg_vec(hipStream_t st, int mixed, int op, const CgVecArgs &a);
+// step: see CgStep; the CG_RES step counts still-active segments into *nactive
+// (zeroed by the CG_ALPHA step of the same iteration)
+hipError_t launch_cg_finish(hipStream_t st, int nseg, const int2 *seg_tiles, const double *part, CgState *cs,
+                            int32_t *act, int step, double tol2, int max_iter, int32_t *nactive);
+// iterations per segment (negative: stopped at max_iter before the tolerance)
+hipError_t launch_cg_iters(hipStream_t st, int nseg, const CgState *cs, int32_t *out);
 
 }  // namespace c3

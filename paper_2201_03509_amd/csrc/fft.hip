@@ -287,6 +287,7 @@ template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
     cx<T> *buf = (cx<T> *)c3_dyn_lds;  // 2 x M1 * B elements (sized per launch)
     const int2 task = a.col_tasks[blockIdx.x];
+    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
     const SegInfo sg = a.segs[task.x];
     const FftPlan &p = a.plans[sg.plan];
     const int M1 = p.M1, M2 = p.M2, B = p.B;
@@ -301,8 +302,12 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
         cx<T> v = {0, 0};
         if (j2 < M2) {
             const int64_t j = (int64_t)M2 * j1 + j2;
-            v.x = ext_at<T>(a, sg.samp_off, sg.n, 2 * j);
-            v.y = ext_at<T>(a, sg.samp_off, sg.n, 2 * j + 1);
+            if (a.full_io) {
+                v = ((const cx<T> *)a.in_a)[sg.ext_off + j];
+            } else {
+                v.x = ext_at<T>(a, sg.samp_off, sg.n, 2 * j);
+                v.y = ext_at<T>(a, sg.samp_off, sg.n, 2 * j + 1);
+            }
         }
         buf[i] = v;
     }
@@ -323,6 +328,7 @@ template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
     cx<T> *buf = (cx<T> *)c3_dyn_lds;
     const int2 task = a.col_tasks[blockIdx.x];
+    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
     const SegInfo sg = a.segs[task.x];
     const FftPlan &p = a.plans[sg.plan];
     const int M1 = p.M1, M2 = p.M2, B = p.B;
@@ -348,8 +354,12 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
         if (j2 < M2) {
             const int64_t t = 2 * ((int64_t)M2 * j1 + j2);
             const cx<T> v = res[i];
-            if (t < n) out[t] = v.x;
-            if (t + 1 < n) out[t + 1] = v.y;
+            if (a.full_io) {
+                ((cx<T> *)a.out)[sg.ext_off + t / 2] = v;
+            } else {
+                if (t < n) out[t] = v.x;
+                if (t + 1 < n) out[t + 1] = v.y;
+            }
         }
     }
 }
@@ -457,6 +467,47 @@ __device__ __forceinline__ cx<T> cr_mode(const ModeCtx &mc, int64_t k, cx<T> E) 
     return cscale(out, inv);
 }
 
+// q_k = (f_k / f_knee)^(-alpha), i.e. 1/P_k = q_k / sigma0^2 (q_0 = 0)
+template <typename T>
+__device__ __forceinline__ T q_of(const ModeCtx &mc, int64_t k) {
+    if (k == 0) return (T)0;
+    if constexpr (sizeof(T) == 4)
+        return __builtin_amdgcn_exp2f((float)mc.malpha * (__builtin_amdgcn_logf((float)k) + (float)mc.lbase2));
+    else
+        return exp(mc.malpha * (log((double)k) + mc.lbase));
+}
+
+// Fourier-diagonal filter of the unitary spectrum E / sqrt(N): 1/P_k
+// (which = 0) or 1 / (1/sigma0^2 + 1/P_k) (which = 1)
+template <typename T>
+__device__ __forceinline__ cx<T> filt_mode(const ModeCtx &mc, int64_t k, cx<T> E, int which) {
+    const T q = q_of<T>(mc, k);
+    const T s2 = (T)(mc.sigma0 * mc.sigma0);
+    const T h = which ? s2 / ((T)1 + q) : q / s2;
+    return cscale(E, (T)mc.invsqrtN * h);
+}
+
+// drawn unitary spectrum: W1 (which = 0) or W2 sqrt(1/P_k) (which = 1), the
+// same Philox modes as the n_corr draw
+template <typename T>
+__device__ __forceinline__ cx<T> draw_mode(const ModeCtx &mc, int64_t k, int which) {
+    T z[4];
+    normals4<T>(philox4x32_10(make_uint4((uint32_t)k, mc.it_lo, mc.it_hi, mc.seed_hi), mc.key), z);
+    const bool real = (k == 0 || k == mc.M);
+    const T h = real ? (T)1 : (T)0.70710678118654752440;
+    cx<T> W = which ? cx<T>{z[2] * h, real ? (T)0 : z[3] * h} : cx<T>{z[0] * h, real ? (T)0 : z[1] * h};
+    if (which) {
+        const T q = q_of<T>(mc, k);
+        T sq;
+        if constexpr (sizeof(T) == 4)
+            sq = __builtin_amdgcn_sqrtf(q);
+        else
+            sq = sqrt(q);
+        W = cscale(W, sq / (T)mc.sigma0);
+    }
+    return W;
+}
+
 // Whittle sums for one mode k >= 1
 struct Wsum {
     double a, b, c;  // sum(I/P + ln P), sum(1 - I/P), sum((1 - I/P) ln(f/fknee))
@@ -482,6 +533,7 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     cx<T> *buf = (cx<T> *)c3_dyn_lds;  // 2 * M2 elements (sized per launch)
     __shared__ double red[3][NT / 64];
     const int2 task = a.row_tasks[blockIdx.x];
+    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
     const int seg = task.x;
     const SegInfo sg = a.segs[seg];
     const FftPlan &p = a.plans[sg.plan];
@@ -497,15 +549,17 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     // inverse stage writes them back (rows of two or more stages)
     cx<T> *ya = Y + (int64_t)ka * M2, *yb = Y + (int64_t)kb * M2;
     const bool direct = p.nr2 >= 2;
-    if (!direct) {
-        for (int i = threadIdx.x; i < M2; i += NT) {
-            buf[i * si] = ya[i];
-            if (two) buf[i * si + 1] = yb[i];
+    if constexpr (MODE != 3) {  // mode 3 synthesises its spectrum: no input
+        if (!direct) {
+            for (int i = threadIdx.x; i < M2; i += NT) {
+                buf[i * si] = ya[i];
+                if (two) buf[i * si + 1] = yb[i];
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        row_fft<-1, NT>(buf, direct ? ya : nullptr, yb, (cx<T> *)nullptr, (cx<T> *)nullptr, M2, lb, two,
+                        p.r2, p.nr2, pool + p.tw2);
     }
-    row_fft<-1, NT>(buf, direct ? ya : nullptr, yb, (cx<T> *)nullptr, (cx<T> *)nullptr, M2, lb, two,
-                    p.r2, p.nr2, pool + p.tw2);
 
     ModeCtx mc;
     {
@@ -546,15 +600,29 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
         if (!two && pk2 < k2) continue;  // single row: each pair once
         const int ea = k2 * si, eb = pk2 * si + prow;
         const int64_t k = ka + (int64_t)M1 * k2;
-        const cx<T> Za = buf[ea], Zb = buf[eb];
+        cx<T> Za = {0, 0}, Zb = {0, 0};
+        if constexpr (MODE != 3) {
+            Za = buf[ea];
+            Zb = buf[eb];
+        }
         if (k == 0) {
             // E_0 = Re Z0 + Im Z0, E_M = Re Z0 - Im Z0 (both real)
             const cx<T> E0 = {Za.x + Za.y, 0}, EM = {Za.x - Za.y, 0};
-            if (MODE == 0) {
-                const cx<T> n0 = cr_mode(mc, 0, E0), nM = cr_mode(mc, M, EM);
-                buf[ea] = cx<T>{half * osc * (n0.x + nM.x), half * osc * (n0.x - nM.x)};
-            } else {
+            if constexpr (MODE == 1) {
                 whittle_mode(mc, M, EM, ws);
+            } else {
+                cx<T> n0, nM;
+                if constexpr (MODE == 0) {
+                    n0 = cr_mode(mc, 0, E0);
+                    nM = cr_mode(mc, M, EM);
+                } else if constexpr (MODE == 2) {
+                    n0 = filt_mode(mc, 0, E0, a.which);
+                    nM = filt_mode(mc, M, EM, a.which);
+                } else {
+                    n0 = draw_mode<T>(mc, 0, a.which);
+                    nM = draw_mode<T>(mc, M, a.which);
+                }
+                buf[ea] = cx<T>{half * osc * (n0.x + nM.x), half * osc * (n0.x - nM.x)};
             }
             continue;
         }
@@ -567,9 +635,18 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
         // partner: A_p = conj A_k, B_p = conj B_k, w_N^p = -conj(w_N^k)
         const cx<T> wp = {-w.x, w.y};
         const cx<T> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
-        if (MODE == 0) {
-            const cx<T> nk = cr_mode(mc, k, Ek);
-            const cx<T> np = (kp == k) ? nk : cr_mode(mc, kp, Ep);
+        if constexpr (MODE != 1) {
+            cx<T> nk, np;
+            if constexpr (MODE == 0) {
+                nk = cr_mode(mc, k, Ek);
+                np = (kp == k) ? nk : cr_mode(mc, kp, Ep);
+            } else if constexpr (MODE == 2) {
+                nk = filt_mode(mc, k, Ek, a.which);
+                np = (kp == k) ? nk : filt_mode(mc, kp, Ep, a.which);
+            } else {
+                nk = draw_mode<T>(mc, k, a.which);
+                np = (kp == k) ? nk : draw_mode<T>(mc, kp, a.which);
+            }
             // Z'_k = (nk + conj np)/2 + i (nk - conj np) conj(w_N^k)/2, scaled
             const cx<T> Ap = {half * (nk.x + np.x), half * (nk.y - np.y)};
             const cx<T> Dp = {half * (nk.x - np.x), half * (nk.y + np.y)};
@@ -585,7 +662,7 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
             if (kp != k) whittle_mode(mc, kp, Ep, ws);
         }
     }
-    if (MODE == 0) {
+    if constexpr (MODE != 1) {
         __syncthreads();
         row_fft<1, NT>(buf, (const cx<T> *)nullptr, (const cx<T> *)nullptr, direct ? ya : nullptr, yb,
                        M2, lb, two, p.r2, p.nr2, pool + p.tw2);
@@ -633,6 +710,10 @@ hipError_t fft_init_attributes() {
     set((const void *)k_row<float, 1>);
     set((const void *)k_row<double, 0>);
     set((const void *)k_row<double, 1>);
+    set((const void *)k_row<float, 2>);
+    set((const void *)k_row<float, 3>);
+    set((const void *)k_row<double, 2>);
+    set((const void *)k_row<double, 3>);
     done = e;
     return e;
 }
@@ -652,12 +733,16 @@ hipError_t launch_fft_pass(hipStream_t st, int mixed, const FftArgs &a, int pass
         if (pass == 0) hipLaunchKernelGGL(k_col_fwd<float>, gc, b, lc, st, a);
         else if (pass == 2) hipLaunchKernelGGL(k_col_inv<float>, gc, b, lc, st, a);
         else if (a.mode == 0) hipLaunchKernelGGL((k_row<float, 0>), gr, br, lr, st, a);
-        else hipLaunchKernelGGL((k_row<float, 1>), gr, br, lr, st, a);
+        else if (a.mode == 1) hipLaunchKernelGGL((k_row<float, 1>), gr, br, lr, st, a);
+        else if (a.mode == 2) hipLaunchKernelGGL((k_row<float, 2>), gr, br, lr, st, a);
+        else hipLaunchKernelGGL((k_row<float, 3>), gr, br, lr, st, a);
     } else {
         if (pass == 0) hipLaunchKernelGGL(k_col_fwd<double>, gc, b, lc, st, a);
         else if (pass == 2) hipLaunchKernelGGL(k_col_inv<double>, gc, b, lc, st, a);
         else if (a.mode == 0) hipLaunchKernelGGL((k_row<double, 0>), gr, br, lr, st, a);
-        else hipLaunchKernelGGL((k_row<double, 1>), gr, br, lr, st, a);
+        else if (a.mode == 1) hipLaunchKernelGGL((k_row<double, 1>), gr, br, lr, st, a);
+        else if (a.mode == 2) hipLaunchKernelGGL((k_row<double, 2>), gr, br, lr, st, a);
+        else hipLaunchKernelGGL((k_row<double, 3>), gr, br, lr, st, a);
     }
     return hipGetLastError();
 }

@@ -54,6 +54,7 @@ __device__ __forceinline__ void col_twiddles(const cx<float> *pool, const FftPla
 template <int M1>
 __global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
     const int2 task = a.col_tasks[blockIdx.x];
+    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
     const SegInfo sg = a.segs[task.x];
     const FftPlan &p = a.plans[sg.plan];
     const int M2 = p.M2;
@@ -61,7 +62,16 @@ __global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
     if (j2 >= M2) return;
     const uint32_t n = (uint32_t)sg.n, n2 = 2u * (uint32_t)sg.n;
     cx<float> x[M1];
-    if (!a.in_b && !a.in_a_f64) {
+    if (a.full_io) {
+        // a whole extended vector (N reals = M complex at the segment's offset)
+        const cx<float> *v = (const cx<float> *)a.in_a + sg.ext_off;
+        const uint32_t lo = 8u * (uint32_t)j2;
+#pragma unroll
+        for (int j1 = 0; j1 < M1; ++j1) {
+            x[j1] = ld_off<cx<float>>(v + (int64_t)j1 * M2, lo);
+            if ((j1 & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        }
+    } else if (!a.in_b && !a.in_a_f64) {
         // r = in_a (FP32): the sweep's residual
         const float *r = (const float *)a.in_a + sg.samp_off;
 #pragma unroll
@@ -106,6 +116,7 @@ __global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
 template <int M1>
 __global__ __launch_bounds__(C3_COL_NT) void k_colr_inv(FftArgs a) {
     const int2 task = a.col_tasks[blockIdx.x];
+    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
     const SegInfo sg = a.segs[task.x];
     const FftPlan &p = a.plans[sg.plan];
     const int M2 = p.M2;
@@ -120,6 +131,14 @@ __global__ __launch_bounds__(C3_COL_NT) void k_colr_inv(FftArgs a) {
         x[k1] = cmulc(x[k1], w);  // times w_M^(-j2 k1)
     });
     reg_fft<M1, 1>(x);
+    if (a.full_io) {
+        // the whole extended vector
+        cx<float> *v = (cx<float> *)a.out + sg.ext_off;
+        const uint32_t lo = 8u * (uint32_t)j2;
+#pragma unroll
+        for (int j1 = 0; j1 < M1; ++j1) st_off(v + (int64_t)j1 * M2, lo, x[j1]);
+        return;
+    }
     // the first n real samples: a raw buffer of n floats, whose hardware range
     // check drops the stores at t >= n (no per-element branch)
     const __amdgpu_buffer_rsrc_t out =

@@ -166,6 +166,28 @@ inline std::vector<int64_t> reg_cols(int64_t M, int mixed) {
     return m1s;
 }
 
+// a choice (e.g. read back from a cache file) that the kernels can run: the
+// split multiplies out, its column kernel exists, and every radix list
+// multiplies to its length using only radices with a compiled stage
+inline bool choice_ok(const FftChoice &c, int64_t M, int mixed) {
+    if (c.M1 < 1 || c.M2 < 1 || (int64_t)c.M1 * c.M2 != M || c.M2 > row_cap(mixed)) return false;
+    if (c.r1.size() > 16 || c.r2.size() > 16) return false;
+    int64_t p2 = 1;
+    for (int r : c.r2) {
+        if (!row_radix_ok(mixed, r)) return false;
+        p2 *= r;
+    }
+    if (p2 != c.M2) return false;
+    if (c.colreg) return colreg_ok(mixed, c.M1);
+    if (c.M1 > col_tile(mixed) || c.B < 1 || (int64_t)c.M1 * c.B > col_tile(mixed)) return false;
+    int64_t p1 = 1;
+    for (int r : c.r1) {
+        if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return false;  // LDS column stages
+        p1 *= r;
+    }
+    return p1 == c.M1;
+}
+
 inline bool default_choice(int64_t M, int mixed, FftChoice &c) {
     // register columns where a compiled M1 fits: the largest M1 up to 64
     // (fewest row-pass stages at two waves per SIMD in the column kernels),

@@ -190,6 +190,15 @@ class Context:
             _ptr(tod.alpha if alpha is None else alpha), ctypes.c_uint64(int(seed)),
             ctypes.c_uint64(int(it)), int(bool(mean_only)), _ptr(out)))
 
+    def sample_ncorr_masked(self, tod, prec, d, s, mask, seed, it, out, mean_only=False, tol=1e-6,
+                            max_iter=500, iters=None, sigma0=None, fknee=None, alpha=None):
+        self._chk(self.lib.sample_ncorr_masked(
+            self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(d), _dt(d), _ptr(s), _ptr(mask),
+            _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(tod.fknee if fknee is None else fknee),
+            _ptr(tod.alpha if alpha is None else alpha), ctypes.c_uint64(int(seed)),
+            ctypes.c_uint64(int(it)), int(bool(mean_only)), float(tol), int(max_iter), _ptr(out),
+            _ptr(iters)))
+
     def bin_tod(self, tod, prec, pix, psi, d, ncorr, acc, accumulate=False, gain=None, sigma0=None):
         self._chk(self.lib.bin_tod(
             self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
@@ -245,12 +254,12 @@ class Context:
         self._chk(self.lib.tod_enable_timing(self.h, int(bool(on))))
 
     KERNELS = ["decode", "project", "fft_col_fwd", "fft_row", "fft_col_inv", "bin", "solve",
-               "chisq_time"]
+               "chisq_time", "cg_vector"]
 
     def kernel_times(self):
         """{kernel: (total_ms, launches)} since the previous read."""
-        t = (ctypes.c_double * 8)()
-        n = (ctypes.c_int32 * 8)()
+        t = (ctypes.c_double * len(self.KERNELS))()
+        n = (ctypes.c_int32 * len(self.KERNELS))()
         self._chk(self.lib.tod_kernel_times(self.h, t, n))
         return {k: (t[i], n[i]) for i, k in enumerate(self.KERNELS)}
 

@@ -1,0 +1,82 @@
+"""Every FFT kernel variant against the oracle's n_corr draw.
+
+The split of each transform length is forced through a tuning file
+(`tod_load_tuning`), so every compiled register column length, every row
+radix (single-stage rows and multi-stage rows, whose first and last stages
+touch memory directly), the LDS column tiles and the FP64 path each run once;
+a file naming a radix without a compiled stage must fall back to a valid split.
+"""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import tod as ot
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"mixed": 1e-5, "fp64": 1e-12}
+
+# (prec, M1, M2, colreg, r1, r2): the register column lengths 16..81 paired with
+# row lengths that use every FP32 row radix; LDS column tiles; the FP64 radices
+CASES = [
+    ("mixed", 16, 27, 1, [], [27]), ("mixed", 18, 25, 1, [], [25]), ("mixed", 20, 24, 1, [], [24]),
+    ("mixed", 24, 20, 1, [], [20]), ("mixed", 25, 18, 1, [], [9, 2]), ("mixed", 27, 12, 1, [], [12]),
+    ("mixed", 30, 10, 1, [], [10]), ("mixed", 32, 9, 1, [], [9]), ("mixed", 36, 8, 1, [], [8]),
+    ("mixed", 40, 6, 1, [], [6]), ("mixed", 45, 5, 1, [], [5]), ("mixed", 48, 4, 1, [], [4]),
+    ("mixed", 50, 3, 1, [], [3]), ("mixed", 54, 2, 1, [], [2]), ("mixed", 60, 30, 1, [], [6, 5]),
+    ("mixed", 64, 36, 1, [], [9, 4]), ("mixed", 72, 40, 1, [], [8, 5]), ("mixed", 75, 48, 1, [], [12, 4]),
+    ("mixed", 80, 50, 1, [], [25, 2]), ("mixed", 81, 54, 1, [], [27, 2]),
+    ("mixed", 60, 600, 1, [], [24, 25]), ("mixed", 81, 729, 1, [], [27, 27]),
+    ("mixed", 96, 45, 0, [8, 4, 3], [9, 5]), ("mixed", 128, 30, 0, [8, 8, 2], [5, 6]),
+    ("fp64", 96, 90, 0, [8, 4, 3], [10, 9]), ("fp64", 40, 36, 0, [8, 5], [6, 6]),
+    ("fp64", 30, 64, 0, [5, 3, 2], [8, 8]),
+]
+
+
+def _case_id(c):
+    return "%s-%dx%d-%s" % (c[0], c[1], c[2], "reg" if c[3] else "lds")
+
+
+def _run(tmp_path, prec, M, choice):
+    from paper_2201_03509_amd import ops
+    ts = synth.make(0, nscan=1, length=("uniform", M, M), keep_truth=True)
+    assert ts.nseg == 1 and int(ts.seg_off[1]) == M
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"fft": [choice], "bin_stride": {}}))
+    c = ops.Context(0)
+    try:
+        c.load_tuning(str(path))
+        tod = ops.DeviceTod(ts, "cuda:0")
+        m = ts.maps.astype(np.float32) if prec == "mixed" else ts.maps
+        s_ref = ot.project_all(ts, m.astype(np.float64), ts.pix, ts.psi)
+        s_in = s_ref.astype(np.float32 if prec == "mixed" else np.float64)
+        seed, it = synth.seed32(ts.config), 7
+        ref = ot.sample_ncorr_all(ts, ts.d, s_in.astype(np.float64), seed, it)
+        out = torch.empty(ts.nsamp, dtype=torch.float32 if prec == "mixed" else torch.float64,
+                          device="cuda")
+        c.sample_ncorr(tod, prec, tod.d, torch.from_numpy(s_in).cuda(), seed, it, out)
+        c.sync()
+        got = out.cpu().numpy().astype(np.float64)
+    finally:
+        c.close()
+    return np.linalg.norm(got - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_case_id)
+def test_forced_split(tmp_path, case):
+    prec, M1, M2, colreg, r1, r2 = case
+    M = M1 * M2
+    choice = {"mixed": int(prec == "mixed"), "M": M, "M1": M1, "M2": M2,
+              "B": 64 if colreg else 16, "colreg": colreg, "r1": r1, "r2": r2}
+    assert _run(tmp_path, prec, M, choice) < TOL[prec]
+
+
+def test_unsupported_radix_falls_back(tmp_path):
+    """A cached split naming radix 16 (no compiled row stage) is ignored."""
+    M1, M2 = 20, 32
+    choice = {"mixed": 1, "M": M1 * M2, "M1": M1, "M2": M2, "B": 64, "colreg": 1, "r1": [],
+              "r2": [16, 2]}
+    assert _run(tmp_path, "mixed", M1 * M2, choice) < TOL["mixed"]

@@ -1,0 +1,160 @@
+"""Masked correlated-noise draw (CG gap filling) on the GPU vs the oracle's CG,
+through the C-ABI.
+
+Inputs: the small synthetic sets of the parity suite with a processing mask
+that removes a band of +-10 degrees around the map frame's equator (about 11%
+of the samples, in long gaps crossed twice per spin period).
+
+Tolerances.  The oracle runs to ||res|| <= 1e-13 ||b||; the FP64 path is asked
+for the same, so both sit within cond(A) x 1e-13 of the exact solution and the
+spec FP64 bar (1e-12 relative per segment) applies.  The mixed path
+applies A and the preconditioner with FP32 transforms (relative error about
+1e-7 per product) while its Krylov vectors and sums stay FP64; it is held to
+the FP32 bar (1e-5 relative per segment) and asked for tol 1e-8.  The stopping
+rule measures the residual against ||b||, which the right-hand side's
+high-frequency draw term F^H(W2 P^-1/2) dominates: at tol 1e-7 CG can stop
+with the solution still ~1e-5 off, in FP64 arithmetic too; at 1e-8 the FP32
+transforms set the floor (a few 1e-6 in a float32 emulation of the solver).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import gapfill as og
+from oracle import tod as ot
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"mixed": 1e-5, "fp64": 1e-12}
+CG_TOL = {"mixed": 1e-8, "fp64": 1e-13}
+ORACLE_TOL = 1e-13
+
+_CASES = {
+    "tiny": (0, None, None),
+    "lfi30_small": (1, 3, ("uniform", 9000, 13000)),
+    "mixed_small": (4, 6, ("loguniform2", 11.0, 14.0)),
+}
+_CACHE = {}
+
+
+def dataset(name):
+    if name not in _CACHE:
+        k, ns, ln = _CASES[name]
+        ts = synth.make(k, nscan=ns, length=ln, keep_truth=True)
+        mask = synth.plane_mask(ts, ts.pix)
+        _CACHE[name] = (ts, mask)
+    return _CACHE[name]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2201_03509_amd import ops
+    c = ops.Context(0)
+    yield c
+    c.close()
+
+
+def _signal(ts, prec):
+    m = ts.maps.astype(np.float32) if prec == "mixed" else ts.maps
+    s = ot.project_all(ts, m.astype(np.float64), ts.pix, ts.psi)
+    return s.astype(np.float32 if prec == "mixed" else np.float64)
+
+
+def _gpu(ctx, ts, prec, d, s_in, mask, seed, it, mean_only=False, tol=None, max_iter=500):
+    from paper_2201_03509_amd import ops
+    tod = ops.DeviceTod(ts, "cuda:0")
+    ft = torch.float32 if prec == "mixed" else torch.float64
+    out = torch.empty(ts.nsamp, dtype=ft, device="cuda")
+    iters = torch.empty(ts.nseg, dtype=torch.int32, device="cuda")
+    d_dev = tod.d if d is None else torch.from_numpy(d).cuda()
+    ctx.sample_ncorr_masked(tod, prec, d_dev, torch.from_numpy(s_in).cuda(),
+                            torch.from_numpy(mask.astype(np.uint8)).cuda(), seed, it, out,
+                            mean_only=mean_only, tol=CG_TOL[prec] if tol is None else tol,
+                            max_iter=max_iter, iters=iters)
+    ctx.sync()
+    return out.cpu().numpy().astype(np.float64), iters.cpu().numpy()
+
+
+def seg_rel(ts, got, ref):
+    errs = []
+    for q in range(ts.nseg):
+        a, b = ts.seg_off[q], ts.seg_off[q + 1]
+        nr = np.linalg.norm(ref[a:b])
+        if b > a:
+            errs.append(np.linalg.norm(got[a:b] - ref[a:b]) / max(nr, 1e-300))
+    return max(errs)
+
+
+@pytest.mark.parametrize("mean_only", [False, True])
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("name", ["tiny", "lfi30_small", "mixed_small"])
+def test_masked_draw(ctx, name, prec, mean_only):
+    ts, mask = dataset(name)
+    s_in = _signal(ts, prec)
+    seed, it = synth.seed32(ts.config), 5
+    ref, ref_it = og.cg_ncorr_all(ts, ts.d, s_in.astype(np.float64), mask, seed, it,
+                                  mean_only=mean_only, tol=ORACLE_TOL)
+    got, iters = _gpu(ctx, ts, prec, None, s_in, mask, seed, it, mean_only)
+    err = seg_rel(ts, got, ref)
+    print("%s %s mean_only=%s: max segment rel L2 %.3e, iterations %d..%d" % (
+        name, prec, mean_only, err, iters.min(), iters.max()))
+    assert err < TOL[prec]
+    assert (iters > 0).all()  # every segment converged
+    if prec == "fp64":  # same recurrence, same stopping rule: counts agree up to rounding
+        for q, k in ref_it.items():
+            assert abs(int(iters[q]) - k) <= 1
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_unmasked_is_one_step_fourier_draw(ctx, prec):
+    """With nothing masked the preconditioner is A^-1: one iteration returns the
+    unmasked constrained realisation (the same Philox modes)."""
+    ts, _ = dataset("lfi30_small")
+    s_in = _signal(ts, prec)
+    seed, it = synth.seed32(ts.config), 8
+    ones = np.ones(ts.nsamp, dtype=np.uint8)
+    # after one step the residual is rounding only: FP32 transforms leave ~1e-7
+    got, iters = _gpu(ctx, ts, prec, None, s_in, ones, seed, it, tol=1e-5 if prec == "mixed" else 1e-12)
+    ref = ot.sample_ncorr_all(ts, ts.d, s_in.astype(np.float64), seed, it)
+    assert seg_rel(ts, got, ref) < TOL[prec]
+    assert (iters == 1).all()
+
+
+def test_masked_samples_do_not_matter(ctx):
+    ts, mask = dataset("lfi30_small")
+    s_in = _signal(ts, "fp64")
+    seed, it = 17, 2
+    d2 = ts.d.astype(np.float64).copy()
+    bad = mask == 0
+    d2[bad] += np.random.default_rng(4).normal(size=int(bad.sum())) * 1e3
+    a, _ = _gpu(ctx, ts, "fp64", ts.d.astype(np.float64), s_in, mask, seed, it)
+    b, _ = _gpu(ctx, ts, "fp64", d2, s_in, mask, seed, it)
+    assert seg_rel(ts, b, a) < 1e-10
+
+
+def test_max_iter_stops_with_the_oracle_iterate(ctx):
+    """max_iter = 3: the GPU returns the third CG iterate, flagged unconverged,
+    equal to the oracle's third iterate."""
+    ts, mask = dataset("tiny")
+    s_in = _signal(ts, "fp64")
+    seed, it = 3, 1
+    ref, _ = og.cg_ncorr_all(ts, ts.d, s_in, mask, seed, it, tol=0.0, maxiter=3)
+    got, iters = _gpu(ctx, ts, "fp64", None, s_in, mask, seed, it, tol=0.0, max_iter=3)
+    assert (iters == -3).all()
+    assert seg_rel(ts, got, ref) < TOL["fp64"]
+
+
+def test_fully_masked_segment(ctx):
+    """A segment with every sample masked: the draw is the prior's, b = F^H W2 P^-1/2
+    plus the observed pad."""
+    ts, mask = dataset("tiny")
+    mask = mask.copy()
+    a, b = int(ts.seg_off[2]), int(ts.seg_off[3])
+    mask[a:b] = 0
+    s_in = _signal(ts, "fp64")
+    seed, it = 9, 4
+    ref, _ = og.cg_ncorr_all(ts, ts.d, s_in, mask, seed, it, tol=ORACLE_TOL)
+    got, iters = _gpu(ctx, ts, "fp64", None, s_in, mask, seed, it)
+    assert (iters > 0).all()
+    assert seg_rel(ts, got, ref) < TOL["fp64"]
