@@ -178,16 +178,17 @@ tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
  *   preconditioner F^H diag(1/(1/sigma0^2 + 1/P)) F, start x = 0, stop when
  *   ||b - A x|| <= tol ||b|| or after max_iter iterations;  n_corr = x[0:n].
  * With nothing masked the first iteration returns sample_ncorr's draw.
- * mask: device [nsamp] uint8, nonzero = sample used.  FFTs run in the
- * precision's type; the CG vectors and sums are FP64 in both precisions, so
- * the recursively updated residual keeps falling with FP32 transforms too;
- * their rounding puts a floor of a few 1e-6 (relative) under the solution's
- * error.  ||b|| is dominated by the high-frequency draw term, so tol must sit
- * well below the wanted solution accuracy (1e-8 for the FP32 floor).
+ * mask: device [nsamp] uint8, nonzero = sample used.  FFTs and the stored
+ * CG vectors use the precision's type; element updates, dot products and the
+ * scalar recurrences are FP64, so the recursively updated residual keeps
+ * falling in the mixed precision too, where FP32 rounding puts a floor of a
+ * few 1e-6 (relative) under the solution's error.  ||b|| is dominated by the
+ * high-frequency draw term, so tol must sit well below the wanted solution
+ * accuracy (1e-8 reaches the FP32 floor).
  * iters_out: device [nseg] int32 (may be NULL): iterations per segment,
  * negated where max_iter stopped it first (0: b = 0 or empty segment).
- * Workspace: five sweep-wide vectors of the extended length (three FP64, two
- * of the precision's type), held by the context. */
+ * Workspace: four sweep-wide vectors of the extended length in the
+ * precision's type, held by the context. */
 tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                                const void *d, tod_dtype d_dtype, const void *s,
                                const uint8_t *mask,

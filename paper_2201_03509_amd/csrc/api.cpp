@@ -125,9 +125,10 @@ struct tod_ctx_s {
     DevBuf trig32, trig64, work, seg_sums, seg_whittle, probe_counts, resid;
     DevBuf dec_tabs;                      // decoding tables, rebuilt by every decode
     DevBuf maps4;                         // the sweep's maps as (T, Q, U, 0) records
-    // masked n_corr solver: FP64 Krylov vectors, FFT in/out vectors, partial
-    // sums, per-segment state, active flags and the active-segment count
-    DevBuf cg_x, cg_res, cg_p, cg_fin, cg_fout, cg_part, cg_state, cg_act, cg_count;
+    // masked n_corr solver: Krylov vectors and the transform output (the
+    // precision's type), partial sums, per-segment state, active flags and the
+    // active-segment count
+    DevBuf cg_x, cg_res, cg_p, cg_fout, cg_part, cg_state, cg_act, cg_count;
     std::map<uint64_t, std::unique_ptr<Plan>> plans;
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
@@ -840,10 +841,9 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     if ((r = cg_tiles(ctx, P)) != TOD_OK) return r;
     const int nseg = lay->nseg;
     const size_t NR = 2 * (size_t)P->ext_elems + 64, esz = mixed ? 4 : 8;
-    HIPCHK(ctx->cg_x.ensure(NR * 8));
-    HIPCHK(ctx->cg_res.ensure(NR * 8));
-    HIPCHK(ctx->cg_p.ensure(NR * 8));
-    HIPCHK(ctx->cg_fin.ensure(NR * esz));
+    HIPCHK(ctx->cg_x.ensure(NR * esz));
+    HIPCHK(ctx->cg_res.ensure(NR * esz));
+    HIPCHK(ctx->cg_p.ensure(NR * esz));
     HIPCHK(ctx->cg_fout.ensure(NR * esz));
     HIPCHK(ctx->cg_part.ensure((size_t)P->ncg * 8 + 64));
     HIPCHK(ctx->cg_state.ensure((size_t)nseg * sizeof(c3::CgState) + 64));
@@ -862,13 +862,13 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     a.fknee = fknee;
     a.alpha = alpha;
     a.full_io = 1;
-    if (!mean_only) {  // F^H W1 -> fout, F^H (W2 sqrt(1/P)) -> fin: rows and inverse columns only
+    if (!mean_only) {  // F^H W1 -> fout, F^H (W2 sqrt(1/P)) -> res: rows and inverse columns only
         a.mode = 3;
         a.which = 0;
         a.out = ctx->cg_fout.p;
         if ((r = run_fft(ctx, st, P, mixed, a, 3, 1)) != TOD_OK) return r;
         a.which = 1;
-        a.out = ctx->cg_fin.p;
+        a.out = ctx->cg_res.p;
         if ((r = run_fft(ctx, st, P, mixed, a, 3, 1)) != TOD_OK) return r;
     }
     c3::CgVecArgs v;
@@ -884,12 +884,11 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     v.s_f64 = !mixed;
     v.mask = mask;
     v.sigma0 = sigma0;
-    v.w1 = mean_only ? nullptr : ctx->cg_fout.p;
-    v.v2 = mean_only ? nullptr : ctx->cg_fin.p;
-    v.x = (double *)ctx->cg_x.p;
-    v.res = (double *)ctx->cg_res.p;
-    v.p = (double *)ctx->cg_p.p;
-    v.fin = ctx->cg_fin.p;
+    v.w1 = ctx->cg_fout.p;
+    v.have_draw = !mean_only;
+    v.x = ctx->cg_x.p;
+    v.res = ctx->cg_res.p;
+    v.p = ctx->cg_p.p;
     v.fout = ctx->cg_fout.p;
     v.part = part;
     // b, x = 0, res = b; then z = M b, rz = res . z, p = z
@@ -904,17 +903,18 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     HIPCHK(vec(c3::CG_OP_INIT, v));
     HIPCHK(fin(c3::CG_INIT));
     a.mode = 2;
-    a.in_a = ctx->cg_fin.p;
     a.in_a_f64 = !mixed;
     a.out = ctx->cg_fout.p;
     a.active = act;
+    a.in_a = ctx->cg_res.p;
     a.which = 1;
     if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
     HIPCHK(vec(c3::CG_OP_RZ, v));
     HIPCHK(fin(c3::CG_RZ0));
     HIPCHK(vec(c3::CG_OP_P, v));
     for (int it = 1; it <= max_iter; ++it) {
-        a.which = 0;  // F^H diag(1/P) F p
+        a.in_a = ctx->cg_p.p;  // F^H diag(1/P) F p
+        a.which = 0;
         if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
         HIPCHK(vec(c3::CG_OP_PAP, v));
         HIPCHK(fin(c3::CG_ALPHA));
@@ -924,7 +924,8 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
         HIPCHK(hipMemcpyAsync(&h, count, sizeof(h), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (h == 0) break;
-        a.which = 1;  // z = M res
+        a.in_a = ctx->cg_res.p;  // z = M res
+        a.which = 1;
         if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
         HIPCHK(vec(c3::CG_OP_RZ, v));
         HIPCHK(fin(c3::CG_BETA));

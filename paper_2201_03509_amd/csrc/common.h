@@ -246,9 +246,9 @@ struct CgVecArgs {
     int s_f64;
     const uint8_t *mask;        // 1: sample used, 0: masked
     const double *sigma0;
-    const void *w1, *v2;        // INIT: F^H W1 and F^H (W2 sqrt(1/P)) (NULL: mean only)
-    double *x, *res, *p;        // FP64 Krylov vectors (sweep-wide, 2 ext_off per segment)
-    void *fin;                  // FFT input vector (transform type)
+    const void *w1;             // INIT: F^H W1 (F^H (W2 sqrt(1/P)) arrives in res)
+    int have_draw;              // INIT: 0 for the mean only (w1 and res not read)
+    void *x, *res, *p;          // Krylov vectors, transform type (sweep-wide, 2 ext_off per segment)
     const void *fout;           // FFT output vector
     double *part;               // per-tile partial sums
     void *out;                  // CROP: n_corr per sample

@@ -14,11 +14,13 @@
 // per-segment reductions and the scalar recurrences.
 //
 // Vectors are sweep-wide: segment s owns reals [2 ext_off, 2 ext_off + N) of
-// each.  The Krylov vectors x, res, p are FP64 in both precisions; the FFT
-// input and output vectors (fin, fout) have the transform's type.  Elementwise
-// kernels walk tiles of C3_CG_TILE reals of one segment; a tile writes one
-// partial sum, and one wave per segment adds its tiles' partials in a fixed
-// order (run-to-run reproducible, no atomics on the sums).
+// each.  The Krylov vectors x, res, p and the transform output fout have the
+// transform's type (FP32 in the mixed precision); every element update and
+// every dot product is evaluated in FP64, and the scalar recurrences (alpha,
+// beta, norms) are FP64.  p and res are the transforms' inputs as they stand.
+// Elementwise kernels walk tiles of C3_CG_TILE reals of one segment; a tile
+// writes one partial sum, and one wave per segment adds its tiles' partials
+// in a fixed order (run-to-run reproducible, no atomics on the sums).
 #include "common.h"
 
 namespace {
@@ -55,33 +57,50 @@ __device__ __forceinline__ void block_sum(double v, double *part) {
     }
 }
 
-// b = mu (e / s0^2 + w1 / s0) + v2; x = 0; res = b; fin = b; partial sums of b^2
+// Elementwise kernels take the extended reals in pairs (t, t+1): N and every
+// tile length are even and each segment's vector starts at an even real, so
+// a pair is one aligned two-element access.
+template <typename T>
+using V2 = cx<T>;
+
+template <typename T>
+__device__ __forceinline__ V2<T> ld2(const T *v, int64_t i) {
+    return *(const V2<T> *)(v + i);
+}
+template <typename T>
+__device__ __forceinline__ void st2(T *v, int64_t i, double a, double b) {
+    *(V2<T> *)(v + i) = V2<T>{(T)a, (T)b};
+}
+
+// b = mu (e / s0^2 + w1 / s0) + v2 -> res (v2 arrives in res); x = 0;
+// partial sums of b^2
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_cg_init(const int4 *__restrict__ tiles, const SegInfo *__restrict__ segs,
                                                    const void *d, int d_f64, const void *s, int s_f64,
                                                    const uint8_t *__restrict__ mask, const T *__restrict__ w1,
-                                                   const T *__restrict__ v2, const double *__restrict__ sigma0,
-                                                   double *__restrict__ x, double *__restrict__ res,
-                                                   T *__restrict__ fin, double *__restrict__ part) {
+                                                   const double *__restrict__ sigma0, int have_draw,
+                                                   T *__restrict__ x, T *__restrict__ res,
+                                                   double *__restrict__ part) {
     const int4 tl = tiles[blockIdx.x];
     const SegInfo sg = segs[tl.x];
     const double s0 = sigma0[tl.x], is2 = 1.0 / (s0 * s0), is1 = 1.0 / s0;
-    const int64_t base = 2 * sg.ext_off;
+    const int64_t base = 2 * sg.ext_off + tl.y;
     double acc = 0;
-    for (int i = threadIdx.x; i < tl.z; i += C3_NT) {
-        const int64_t t = tl.y + i;
-        const int64_t u = mirror(t, sg.n);
-        const int64_t j = sg.samp_off + (u < 0 ? 0 : u);
-        const double e = ldd(d, d_f64, j) - ldd(s, s_f64, j);
-        const double m = u < 0 ? 1.0 : (double)(mask[j] != 0);
-        double b = e * is2;
-        if (w1) b += (double)w1[base + t] * is1;
-        b *= m;
-        if (v2) b += (double)v2[base + t];
-        x[base + t] = 0.0;
-        res[base + t] = b;
-        fin[base + t] = (T)b;
-        acc += b * b;
+    for (int i = 2 * threadIdx.x; i < tl.z; i += 2 * C3_NT) {
+        double b[2];
+        const V2<T> w = have_draw ? ld2(w1, base + i) : V2<T>{0, 0};
+        const V2<T> v = have_draw ? ld2(res, base + i) : V2<T>{0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t u = mirror(tl.y + i + h, sg.n);
+            const int64_t j = sg.samp_off + (u < 0 ? 0 : u);
+            const double e = ldd(d, d_f64, j) - ldd(s, s_f64, j);
+            const double m = u < 0 ? 1.0 : (double)(mask[j] != 0);
+            b[h] = m * (e * is2 + (double)(h ? w.y : w.x) * is1) + (double)(h ? v.y : v.x);
+            acc += b[h] * b[h];
+        }
+        st2(x, base + i, 0.0, 0.0);
+        st2(res, base + i, b[0], b[1]);
     }
     block_sum(acc, part);
 }
@@ -90,47 +109,45 @@ __global__ __launch_bounds__(C3_NT) void k_cg_init(const int4 *__restrict__ tile
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_cg_pap(const int4 *__restrict__ tiles, const SegInfo *__restrict__ segs,
                                                   const int32_t *__restrict__ act, const uint8_t *__restrict__ mask,
-                                                  const double *__restrict__ sigma0, const double *__restrict__ p,
+                                                  const double *__restrict__ sigma0, const T *__restrict__ p,
                                                   const T *__restrict__ fout, double *__restrict__ part) {
     const int4 tl = tiles[blockIdx.x];
     if (!act[tl.x]) return;
     const SegInfo sg = segs[tl.x];
     const double s0 = sigma0[tl.x], is2 = 1.0 / (s0 * s0);
-    const int64_t base = 2 * sg.ext_off;
+    const int64_t base = 2 * sg.ext_off + tl.y;
     double acc = 0;
-    for (int i = threadIdx.x; i < tl.z; i += C3_NT) {
-        const int64_t t = tl.y + i;
-        const double pv = p[base + t];
-        const double ap = (double)fout[base + t] + mu_at(mask, sg.samp_off, sg.n, t) * pv * is2;
-        acc += pv * ap;
+    for (int i = 2 * threadIdx.x; i < tl.z; i += 2 * C3_NT) {
+        const V2<T> pv = ld2(p, base + i), f = ld2(fout, base + i);
+        const double m0 = mu_at(mask, sg.samp_off, sg.n, tl.y + i), m1 = mu_at(mask, sg.samp_off, sg.n, tl.y + i + 1);
+        acc += (double)pv.x * ((double)f.x + m0 * (double)pv.x * is2);
+        acc += (double)pv.y * ((double)f.y + m1 * (double)pv.y * is2);
     }
     block_sum(acc, part);
 }
 
-// x += alpha p; res -= alpha A p; fin = res; partial sums of res^2
+// x += alpha p; res -= alpha A p; partial sums of res^2 (of the stored res)
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_cg_xr(const int4 *__restrict__ tiles, const SegInfo *__restrict__ segs,
                                                  const int32_t *__restrict__ act, const CgState *__restrict__ cs,
                                                  const uint8_t *__restrict__ mask, const double *__restrict__ sigma0,
-                                                 const double *__restrict__ p, const T *__restrict__ fout,
-                                                 double *__restrict__ x, double *__restrict__ res,
-                                                 T *__restrict__ fin, double *__restrict__ part) {
+                                                 const T *__restrict__ p, const T *__restrict__ fout,
+                                                 T *__restrict__ x, T *__restrict__ res, double *__restrict__ part) {
     const int4 tl = tiles[blockIdx.x];
     if (!act[tl.x]) return;
     const SegInfo sg = segs[tl.x];
     const double s0 = sigma0[tl.x], is2 = 1.0 / (s0 * s0);
     const double al = cs[tl.x].alpha;
-    const int64_t base = 2 * sg.ext_off;
+    const int64_t base = 2 * sg.ext_off + tl.y;
     double acc = 0;
-    for (int i = threadIdx.x; i < tl.z; i += C3_NT) {
-        const int64_t t = tl.y + i;
-        const double pv = p[base + t];
-        const double ap = (double)fout[base + t] + mu_at(mask, sg.samp_off, sg.n, t) * pv * is2;
-        x[base + t] += al * pv;
-        const double r = res[base + t] - al * ap;
-        res[base + t] = r;
-        fin[base + t] = (T)r;
-        acc += r * r;
+    for (int i = 2 * threadIdx.x; i < tl.z; i += 2 * C3_NT) {
+        const V2<T> pv = ld2(p, base + i), f = ld2(fout, base + i), xv = ld2(x, base + i), rv = ld2(res, base + i);
+        const double m0 = mu_at(mask, sg.samp_off, sg.n, tl.y + i), m1 = mu_at(mask, sg.samp_off, sg.n, tl.y + i + 1);
+        const double ap0 = (double)f.x + m0 * (double)pv.x * is2, ap1 = (double)f.y + m1 * (double)pv.y * is2;
+        st2(x, base + i, (double)xv.x + al * (double)pv.x, (double)xv.y + al * (double)pv.y);
+        const V2<T> r = {(T)((double)rv.x - al * ap0), (T)((double)rv.y - al * ap1)};
+        *(V2<T> *)(res + base + i) = r;
+        acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
     }
     block_sum(acc, part);
 }
@@ -138,34 +155,32 @@ __global__ __launch_bounds__(C3_NT) void k_cg_xr(const int4 *__restrict__ tiles,
 // partial sums of res . z (z = fout, the preconditioned residual)
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_cg_rz(const int4 *__restrict__ tiles, const SegInfo *__restrict__ segs,
-                                                 const int32_t *__restrict__ act, const double *__restrict__ res,
+                                                 const int32_t *__restrict__ act, const T *__restrict__ res,
                                                  const T *__restrict__ fout, double *__restrict__ part) {
     const int4 tl = tiles[blockIdx.x];
     if (!act[tl.x]) return;
-    const int64_t base = 2 * segs[tl.x].ext_off;
+    const int64_t base = 2 * segs[tl.x].ext_off + tl.y;
     double acc = 0;
-    for (int i = threadIdx.x; i < tl.z; i += C3_NT) {
-        const int64_t t = tl.y + i;
-        acc += res[base + t] * (double)fout[base + t];
+    for (int i = 2 * threadIdx.x; i < tl.z; i += 2 * C3_NT) {
+        const V2<T> r = ld2(res, base + i), z = ld2(fout, base + i);
+        acc += (double)r.x * (double)z.x + (double)r.y * (double)z.y;
     }
     block_sum(acc, part);
 }
 
-// p = z + beta p; fin = p
+// p = z + beta p (beta = 0: p = z, the old p is not read)
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_cg_p(const int4 *__restrict__ tiles, const SegInfo *__restrict__ segs,
                                                 const int32_t *__restrict__ act, const CgState *__restrict__ cs,
-                                                const T *__restrict__ fout, double *__restrict__ p,
-                                                T *__restrict__ fin) {
+                                                const T *__restrict__ fout, T *__restrict__ p) {
     const int4 tl = tiles[blockIdx.x];
     if (!act[tl.x]) return;
-    const int64_t base = 2 * segs[tl.x].ext_off;
+    const int64_t base = 2 * segs[tl.x].ext_off + tl.y;
     const double be = cs[tl.x].beta;
-    for (int i = threadIdx.x; i < tl.z; i += C3_NT) {
-        const int64_t t = tl.y + i;
-        const double v = (double)fout[base + t] + (be != 0.0 ? be * p[base + t] : 0.0);
-        p[base + t] = v;
-        fin[base + t] = (T)v;
+    for (int i = 2 * threadIdx.x; i < tl.z; i += 2 * C3_NT) {
+        const V2<T> z = ld2(fout, base + i);
+        const V2<T> po = be != 0.0 ? ld2(p, base + i) : V2<T>{0, 0};
+        st2(p, base + i, (double)z.x + be * (double)po.x, (double)z.y + be * (double)po.y);
     }
 }
 
@@ -226,13 +241,13 @@ __global__ __launch_bounds__(C3_NT) void k_cg_finish(int nseg, const int2 *__res
 // n_corr = x[0:n] of every segment, in the output type
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_cg_crop(const int4 *__restrict__ tiles, const SegInfo *__restrict__ segs,
-                                                   const double *__restrict__ x, T *__restrict__ out) {
+                                                   const T *__restrict__ x, T *__restrict__ out) {
     const int4 tl = tiles[blockIdx.x];
     const SegInfo sg = segs[tl.x];
     const int64_t base = 2 * sg.ext_off;
     for (int i = threadIdx.x; i < tl.z; i += C3_NT) {
         const int64_t t = tl.y + i;
-        out[sg.samp_off + t] = (T)x[base + t];
+        out[sg.samp_off + t] = x[base + t];
     }
 }
 
@@ -253,26 +268,26 @@ hipError_t launch_cg_vec(hipStream_t st, int mixed, int op, const CgVecArgs &a) 
     switch (op) {                                                                                            \
     case CG_OP_INIT:                                                                                         \
         hipLaunchKernelGGL(k_cg_init<T>, g, b, 0, st, a.tiles, a.segs, a.d, a.d_f64, a.s, a.s_f64, a.mask,    \
-                           (const T *)a.w1, (const T *)a.v2, a.sigma0, a.x, a.res, (T *)a.fin, a.part);       \
+                           (const T *)a.w1, a.sigma0, a.have_draw, (T *)a.x, (T *)a.res, a.part);             \
         break;                                                                                               \
     case CG_OP_PAP:                                                                                          \
-        hipLaunchKernelGGL(k_cg_pap<T>, g, b, 0, st, a.tiles, a.segs, a.act, a.mask, a.sigma0, a.p,          \
-                           (const T *)a.fout, a.part);                                                       \
+        hipLaunchKernelGGL(k_cg_pap<T>, g, b, 0, st, a.tiles, a.segs, a.act, a.mask, a.sigma0,               \
+                           (const T *)a.p, (const T *)a.fout, a.part);                                       \
         break;                                                                                               \
     case CG_OP_XR:                                                                                           \
-        hipLaunchKernelGGL(k_cg_xr<T>, g, b, 0, st, a.tiles, a.segs, a.act, a.cs, a.mask, a.sigma0, a.p,     \
-                           (const T *)a.fout, a.x, a.res, (T *)a.fin, a.part);                               \
+        hipLaunchKernelGGL(k_cg_xr<T>, g, b, 0, st, a.tiles, a.segs, a.act, a.cs, a.mask, a.sigma0,          \
+                           (const T *)a.p, (const T *)a.fout, (T *)a.x, (T *)a.res, a.part);                 \
         break;                                                                                               \
     case CG_OP_RZ:                                                                                           \
-        hipLaunchKernelGGL(k_cg_rz<T>, g, b, 0, st, a.tiles, a.segs, a.act, a.res, (const T *)a.fout,        \
-                           a.part);                                                                          \
+        hipLaunchKernelGGL(k_cg_rz<T>, g, b, 0, st, a.tiles, a.segs, a.act, (const T *)a.res,                \
+                           (const T *)a.fout, a.part);                                                       \
         break;                                                                                               \
     case CG_OP_P:                                                                                            \
-        hipLaunchKernelGGL(k_cg_p<T>, g, b, 0, st, a.tiles, a.segs, a.act, a.cs, (const T *)a.fout, a.p,     \
-                           (T *)a.fin);                                                                      \
+        hipLaunchKernelGGL(k_cg_p<T>, g, b, 0, st, a.tiles, a.segs, a.act, a.cs, (const T *)a.fout,          \
+                           (T *)a.p);                                                                        \
         break;                                                                                               \
     case CG_OP_CROP:                                                                                         \
-        hipLaunchKernelGGL(k_cg_crop<T>, g, b, 0, st, a.tiles, a.segs, a.x, (T *)a.out);                     \
+        hipLaunchKernelGGL(k_cg_crop<T>, g, b, 0, st, a.tiles, a.segs, (const T *)a.x, (T *)a.out);          \
         break;                                                                                               \
     default:                                                                                                 \
         return hipErrorInvalidValue;                                                                         \
