@@ -124,9 +124,13 @@ MASKED_IT = 7777      # Gibbs iteration number of the masked-draw leg
 MASKED_TOL = 1e-8     # its CG tolerance (FP32 transforms, FP64 Krylov vectors)
 
 
-def _oracle_masked(q):
+GAIN_IT = 4242        # Gibbs iteration number of the gain-draw leg
+
+
+def _oracle_next(q):
     """Masked n_corr draw of segment q (processing mask +-10 deg around the
-    map frame's equator) by the oracle's CG, for the accuracy report."""
+    map frame's equator) by the oracle's CG, and its gain draw, for the
+    accuracy reports of those legs."""
     ts, seed, maps32 = _BASE["ts"], _BASE["seed"], _BASE["maps"]
     import numpy as np
     import synth
@@ -144,7 +148,11 @@ def _oracle_masked(q):
     m = synth.plane_mask_pixels(int(ts.band_nside[band]), pix)
     nc, k = og.cg_ncorr_segment(r, m, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q], ts.alpha[q],
                                 seed, q, MASKED_IT, tol=1e-12)
-    return q, nc, k
+    from oracle import gain as ogain
+    t = ot.project(maps32, gp, psi, 1.0)
+    g, sg, _, _ = ogain.sample_gain_segment(ts.d[a:a + n], t, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q],
+                                            ts.alpha[q], seed, q, GAIN_IT)
+    return q, nc, k, g, sg
 
 
 def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
@@ -171,10 +179,10 @@ def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
                 log("  oracle segments done: %d/%d" % (len(res), nseg))
     wall = time.perf_counter() - t0
     nsamp = int(sum(ts.seg_off[q + 1] - ts.seg_off[q] for q in range(nseg)))
-    # masked-draw references (not part of the timed sample)
+    # masked-draw and gain references (not part of the timed sample)
     mq = [int(q) for q in np.linspace(0, ts.nseg - 1, masked_segments).round()] if masked_segments else []
     with ctx.Pool(max(1, min(workers, len(mq)))) as pool:
-        _BASE["masked"] = list(pool.imap_unordered(_oracle_masked, mq)) if mq else []
+        _BASE["next"] = list(pool.imap_unordered(_oracle_next, mq)) if mq else []
     return {
         "value": nsamp / wall, "unit": "TOD samples/s", "cores": workers, "kind": "oracle",
         "sample": "%d of %d segments (%d samples): decode+project+n_corr+bin, FP64 numpy/C, "
@@ -226,16 +234,54 @@ def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix):
                           "max": int(np.abs(it_h).max()), "unconverged": int((it_h < 0).sum())},
            "kernels_ms": {k: round(v[0], 2) for k, v in kt.items() if v[1]},
            "launches": {k: v[1] for k, v in kt.items() if v[1]}}
-    ref = _BASE.get("masked")
+    ref = _BASE.get("next")
     if ref:
         g = nc.cpu().numpy()
         errs = []
-        for q, r, k in ref:
+        for q, r, k, _, _ in ref:
             a, b = ts.seg_off[q], ts.seg_off[q + 1]
             errs.append({"segment": q, "rel_l2": float(np.linalg.norm(g[a:b] - r) / np.linalg.norm(r)),
                          "iterations_gpu": int(it_h[q]), "iterations_oracle": int(k)})
         rep["accuracy_vs_oracle"] = errs
     log("masked n_corr: %.1f ms per call, iterations %s" % (ms, rep["iterations"]))
+    return rep
+
+
+def gain_leg(ctx, ts, tod, out, maps32, seed):
+    """The gain draw over the whole workload: sky template at unit gain, one
+    warm-up call, one timed call (HIP events around every launch), error
+    against the oracle on the sampled segments."""
+    import numpy as np
+    import torch
+    dev = tod.d.device
+    t = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
+    ones = torch.ones(ts.nseg, dtype=torch.float64, device=dev)
+    ctx.project_sky(tod, "mixed", out["pix"], out["psi"], maps32, t, gain=ones)
+    g = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
+    sg = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
+    ctx.sample_gain(tod, "mixed", tod.d, t, seed, GAIN_IT, g, sg)
+    ctx.sync()
+    ctx.enable_timing(True)
+    ctx.kernel_times()
+    t0 = time.perf_counter()
+    ctx.sample_gain(tod, "mixed", tod.d, t, seed, GAIN_IT, g, sg)
+    ctx.sync()
+    ms = (time.perf_counter() - t0) * 1e3
+    kt = ctx.kernel_times()
+    ctx.enable_timing(False)
+    gh, sh = g.cpu().numpy(), sg.cpu().numpy()
+    z = (gh - ts.gain) / sh
+    rep = {"ms_per_call": round(ms, 2), "samples_per_s": ts.nsamp / (ms / 1e3),
+           "kernels_ms": {k: round(v[0], 2) for k, v in kt.items() if v[1]},
+           "launches": {k: v[1] for k, v in kt.items() if v[1]},
+           "sigma_g": {"min": float(sh.min()), "max": float(sh.max())},
+           "draw_minus_true_over_sigma": {"mean": float(z.mean()), "std": float(z.std())}}
+    ref = _BASE.get("next")
+    if ref:
+        rep["accuracy_vs_oracle"] = [{"segment": q, "gain_rel_err": float(abs(gh[q] - gr) / abs(gr)),
+                                      "sigma_rel_err": float(abs(sh[q] - sr) / sr)}
+                                     for q, _, _, gr, sr in ref]
+    log("gain draw: %.1f ms per call" % ms)
     return rep
 
 
@@ -251,6 +297,7 @@ def main():
     ap.add_argument("--cache-dir", default=None, help="reuse generated inputs saved here")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-masked", action="store_true", help="skip the masked n_corr draw leg")
+    ap.add_argument("--no-gain", action="store_true", help="skip the gain draw leg")
     ap.add_argument("--fft-batch", type=int, default=None,
                     help="complex elements per FFT batch (0 = all segments at once)")
     ap.add_argument("--bin-stride", type=int, default=None, help="override the binning stride")
@@ -389,6 +436,11 @@ def main():
         del outp
         torch.cuda.empty_cache()
 
+    gain = None
+    if not args.no_gain:
+        gain = gain_leg(ctx, ts, tod, out, maps32, seed)
+        torch.cuda.empty_cache()
+
     masked = None
     if not args.no_masked:
         masked = masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix)
@@ -432,6 +484,7 @@ def main():
         "fft_splits": plans,
         "bin_stride": tuned.get("bin_stride"),
         "accuracy_vs_oracle": acc_report,
+        "gain_draw": gain,
         "masked_ncorr": masked,
         "copy_probe": copy,
     }

@@ -168,6 +168,28 @@ tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                         const double *sigma0, const double *fknee, const double *alpha,
                         uint64_t seed, uint64_t iter, int mean_only, void *ncorr_out);
 
+/* Gain draw g <- P(g | d, xi_n, sky) per segment (Eq. 3: the gain step comes
+ * before n_corr and does not condition on it, so the correlated noise joins
+ * the white noise in N; section 4.2 counts its FFTs with the n_corr step).
+ * With the sky template t = P m at unit gain and K x = first n samples of
+ * F^H diag(h) F ext(x) on sample_ncorr's extension, h_k = 1/(sigma0^2 + P_k),
+ * h_0 = 0:
+ *   A = t . K t,  B = t . K d  (FP64 sums),  g = B/A + eta/sqrt(A),
+ * eta the Box-Muller z0 of the segment's Philox stream (key as sample_ncorr)
+ * at counter (2^32-1, iter lo, iter hi, seed hi); mean_only != 0: eta = 0.
+ * Flat prior, no smoothing across scans.
+ * t: device [nsamp] (FP32 mixed / FP64 plain), e.g. project_sky with unit
+ * gains; d: device [nsamp] of d_dtype; sigma0/fknee/alpha: device [nseg] FP64.
+ * gain_out: device [nseg] FP64 (NaN where A <= 0, e.g. empty segments);
+ * sigma_out: device [nseg] FP64, 1/sqrt(A) (may be NULL).
+ * Workspace: two [nsamp] vectors of the precision's type, held by the
+ * context. */
+tod_status sample_gain(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                       const void *d, tod_dtype d_dtype, const void *t,
+                       const double *sigma0, const double *fknee, const double *alpha,
+                       uint64_t seed, uint64_t iter, int mean_only,
+                       double *gain_out, double *sigma_out);
+
 /* Correlated-noise draw with a processing mask (gap filling: the constrained
  * realisation needs FFTs inside a CG solver where scans cross masked sky,
  * section 5 and the correlated-noise row of Table 2).  On the extension and
@@ -292,11 +314,11 @@ tod_status tod_set_fft_batch(tod_ctx ctx, int64_t complex_elems);
  * graph capture is bracketed by HIP events on the context stream (the sweep
  * then runs eagerly).  tod_kernel_times synchronises the stream, returns the
  * summed milliseconds and launch counts since the previous read and resets
- * them.  Kernel ids (arrays of 9): 0 decode, 1 projection, 2 FFT forward
+ * them.  Kernel ids (arrays of 10): 0 decode, 1 projection, 2 FFT forward
  * column pass, 3 FFT row pass (filter + draw, Whittle sums, or the masked
- * draw's Fourier-diagonal products), 4 FFT inverse column pass, 5 binning,
- * 6 per-pixel solve, 7 chi^2 time-domain terms, 8 the masked draw's CG vector
- * updates and reductions. */
+ * draw's and the gain draw's Fourier-diagonal filters), 4 FFT inverse column
+ * pass, 5 binning, 6 per-pixel solve, 7 chi^2 time-domain terms, 8 the masked
+ * draw's CG vector updates and reductions, 9 the gain draw's sums and draw. */
 tod_status tod_enable_timing(tod_ctx ctx, int enable);
 tod_status tod_kernel_times(tod_ctx ctx, double *total_ms, int32_t *launches);
 

@@ -102,6 +102,7 @@ struct Plan {
     int64_t work_elems = 0;
     int64_t ext_elems = 0;                // complex elements of all extended vectors (ext_off)
     DevBuf sample_tiles;
+    DevBuf sample_seg_tiles;              // per segment (first sample tile, count)
     // masked n_corr solver: tiles over the extended vectors, per-segment tile ranges
     DevBuf cg_tiles, cg_seg_tiles;
     int ncg = 0;
@@ -129,6 +130,8 @@ struct tod_ctx_s {
     // precision's type), partial sums, per-segment state, active flags and the
     // active-segment count
     DevBuf cg_x, cg_res, cg_p, cg_fout, cg_part, cg_state, cg_act, cg_count;
+    // gain draw: filtered template and data (per sample), per-tile partial sums
+    DevBuf gain_kt, gain_kd, gain_part;
     std::map<uint64_t, std::unique_ptr<Plan>> plans;
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
@@ -380,9 +383,12 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     for (int b = 0; b < L->nband; ++b) fs[b] = L->bands[b].fsamp;
     // sample tiles (projection): 4096 samples per block
     std::vector<int4> tiles;
+    std::vector<int2> seg_tiles(nseg);
     for (int s = 0; s < nseg; ++s) {
         const int n = P->h_segs[s].n;
+        seg_tiles[s].x = (int)tiles.size();
         for (int t0 = 0; t0 < n; t0 += 4096) tiles.push_back(make_int4(s, t0, std::min(4096, n - t0), 0));
+        seg_tiles[s].y = (int)tiles.size() - seg_tiles[s].x;
     }
     P->nsample_tiles = (int)tiles.size();
     hipStream_t st = ctx->stream;
@@ -392,6 +398,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     HIPCHK(P->row_tasks.upload(row, st));
     HIPCHK(P->fsamp.upload(fs, st));
     HIPCHK(P->sample_tiles.upload(tiles, st));
+    HIPCHK(P->sample_seg_tiles.upload(seg_tiles, st));
     if (mixed) {
         std::vector<cx<float>> tw(pool.re.size());
         for (size_t i = 0; i < tw.size(); ++i) tw[i] = {(float)pool.re[i], (float)pool.im[i]};
@@ -562,7 +569,7 @@ tod_status ensure_work(tod_ctx ctx, Plan *P) {
 }
 
 // kernel ids of tod_kernel_times
-enum { K_DECODE = 0, K_PROJECT, K_COLF, K_ROW, K_COLI, K_BIN, K_SOLVE, K_CHISQ, K_CG, K_NKERNEL };
+enum { K_DECODE = 0, K_PROJECT, K_COLF, K_ROW, K_COLI, K_BIN, K_SOLVE, K_CHISQ, K_CG, K_GAIN, K_NKERNEL };
 
 hipEvent_t pool_event(tod_ctx c) {
     if (!c->ev_pool.empty()) {
@@ -937,6 +944,54 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     c.out = ncorr_out;
     HIPCHK(vec(c3::CG_OP_CROP, c));
     if (iters_out) HIPCHK(c3::launch_cg_iters(st, nseg, cs, iters_out));
+    return TOD_OK;
+}
+
+tod_status sample_gain(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const void *d,
+                       tod_dtype d_dtype, const void *t, const double *sigma0, const double *fknee,
+                       const double *alpha, uint64_t seed, uint64_t iter, int mean_only,
+                       double *gain_out, double *sigma_out) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (!d || !t || !sigma0 || !fknee || !alpha || !gain_out) return fail(ctx, TOD_EINVAL, "NULL argument");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    if ((r = ensure_work(ctx, P)) != TOD_OK) return r;
+    const size_t esz = mixed ? 4 : 8;
+    HIPCHK(ctx->gain_kt.ensure((size_t)lay->nsamp * esz + 64));
+    HIPCHK(ctx->gain_kd.ensure((size_t)lay->nsamp * esz + 64));
+    HIPCHK(ctx->gain_part.ensure((size_t)P->nsample_tiles * sizeof(double2) + 64));
+    hipStream_t st = ctx->stream;
+    HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
+    c3::FftArgs a = fft_args(ctx, P, lay);
+    a.sigma0 = sigma0;
+    a.fknee = fknee;
+    a.alpha = alpha;
+    a.mode = 2;
+    a.which = 2;  // 1 / (sigma0^2 + P)
+    a.in_a = t;
+    a.in_a_f64 = !mixed;
+    a.out = ctx->gain_kt.p;
+    if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
+    a.in_a = d;
+    a.in_a_f64 = d_dtype == TOD_F64;
+    a.out = ctx->gain_kd.p;
+    if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
+    {
+        KTimer kt(ctx, K_GAIN, st);
+        HIPCHK(c3::launch_gain_dots(st, mixed, (const int4 *)P->sample_tiles.p, P->nsample_tiles, lay->seg_off, t,
+                                    ctx->gain_kt.p, ctx->gain_kd.p, (double2 *)ctx->gain_part.p));
+    }
+    {
+        KTimer kt(ctx, K_GAIN, st);
+        HIPCHK(c3::launch_gain_finish(st, lay->nseg, (const int2 *)P->sample_seg_tiles.p,
+                                      (const double2 *)ctx->gain_part.p, ctx->d_seed_iter, mean_only, gain_out,
+                                      sigma_out));
+    }
     return TOD_OK;
 }
 

@@ -177,7 +177,8 @@ struct FftArgs {
     int full_io;                // 1: pass 1 reads, pass 3 writes whole extended vectors
                                 //    (N reals per segment at real offset 2 ext_off of
                                 //    in_a / out) instead of the mirrored segment / its crop
-    int which;                  // mode 2: 0 filter 1/P, 1 filter 1/(1/sigma0^2 + 1/P);
+    int which;                  // mode 2: filter 0: 1/P, 1: 1/(1/sigma0^2 + 1/P),
+                                //         2: 1/(sigma0^2 + P);
                                 // mode 3: 0 spectrum W1, 1 spectrum W2 sqrt(1/P)
     const int32_t *active;      // per segment, 0: skip (NULL: every segment runs)
 };
@@ -260,5 +261,13 @@ hipError_t launch_cg_finish(hipStream_t st, int nseg, const int2 *seg_tiles, con
                             int32_t *act, int step, double tol2, int max_iter, int32_t *nactive);
 // iterations per segment (negative: stopped at max_iter before the tolerance)
 hipError_t launch_cg_iters(hipStream_t st, int nseg, const CgState *cs, int32_t *out);
+
+// ---- gain draw (gain.hip): per sample tile the partial sums t . K t and
+// t . K d (kt, kd: the filtered template and data, first n samples of each
+// segment); then per segment g = B/A + eta/sqrt(A)
+hipError_t launch_gain_dots(hipStream_t st, int mixed, const int4 *tiles, int ntile, const int64_t *seg_off,
+                            const void *t, const void *kt, const void *kd, double2 *part);
+hipError_t launch_gain_finish(hipStream_t st, int nseg, const int2 *seg_tiles, const double2 *part,
+                              const uint64_t *seed_iter, int mean_only, double *gain_out, double *sigma_out);
 
 }  // namespace c3

@@ -18,10 +18,12 @@
 // Every sub-transform is an in-LDS Stockham FFT with radix 2/3/4/5 stages.
 #include "common.h"
 #include "fftdev.h"
+#include "rng.h"
 
 namespace {
 using c3::FftArgs;
 using namespace c3fft;
+using namespace c3rng;
 
 // explicit LDS / global address spaces for the out-of-line stage functions
 // (only meaningful in the device compilation pass)
@@ -364,58 +366,6 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
     }
 }
 
-// ------------------------------------------------------------- randomness
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        // full 32x32 -> 64-bit products: one v_mad_u64_u32 each instead of a
-        // separate high and low multiply
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
-        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-        k.x += 0x9E3779B9u;
-        k.y += 0xBB67AE85u;
-    }
-    return c;
-}
-
-// -2 ln u for u = (x + 1/2) 2^-32 with the hardware log2 (FP32 path)
-__device__ __forceinline__ float m2log_u(uint32_t x) {
-    const float u = ((float)x + 0.5f) * 2.3283064365386963e-10f;
-    return -1.3862943611198906f * __builtin_amdgcn_logf(u);  // -2 ln 2 log2(u)
-}
-__device__ __forceinline__ double m2log_u_d(uint32_t x) {
-    return -2.0 * log(((double)x + 0.5) * 2.3283064365386963e-10);
-}
-
-template <typename T>
-__device__ __forceinline__ void normals4(uint4 w, T *z) {
-    if constexpr (sizeof(T) == 4) {
-        // -2 ln u >= 2^-32 and q > 0 stay far from denormals: the raw
-        // hardware square root needs no range scaling here
-        const float r0 = __builtin_amdgcn_sqrtf(m2log_u(w.x)), r1 = __builtin_amdgcn_sqrtf(m2log_u(w.z));
-        // hardware sine/cosine take their argument in revolutions: sin(2 pi u)
-        const float u1 = ((float)w.y + 0.5f) * 2.3283064365386963e-10f;
-        const float u3 = ((float)w.w + 0.5f) * 2.3283064365386963e-10f;
-        const float s0 = __builtin_amdgcn_sinf(u1), c0 = __builtin_amdgcn_cosf(u1);
-        const float s1 = __builtin_amdgcn_sinf(u3), c1 = __builtin_amdgcn_cosf(u3);
-        z[0] = r0 * c0;
-        z[1] = r0 * s0;
-        z[2] = r1 * c1;
-        z[3] = r1 * s1;
-    } else {
-        double r0 = sqrt(m2log_u_d(w.x)), r1 = sqrt(m2log_u_d(w.z));
-        double s0, c0, s1, c1;
-        sincospi(((double)w.y + 0.5) * 4.656612873077392578125e-10, &s0, &c0);
-        sincospi(((double)w.w + 0.5) * 4.656612873077392578125e-10, &s1, &c1);
-        z[0] = r0 * c0;
-        z[1] = r0 * s0;
-        z[2] = r1 * c1;
-        z[3] = r1 * s1;
-    }
-}
-
 struct ModeCtx {
     double sigma0, lbase, lbase2, malpha;      // lbase = ln(fsamp / (N fknee)), lbase2 = log2 of it
     double invsqrtN, outscale;                 // 1/sqrt(N), sqrt(N)/M
@@ -478,12 +428,13 @@ __device__ __forceinline__ T q_of(const ModeCtx &mc, int64_t k) {
 }
 
 // Fourier-diagonal filter of the unitary spectrum E / sqrt(N): 1/P_k
-// (which = 0) or 1 / (1/sigma0^2 + 1/P_k) (which = 1)
+// (which = 0), 1 / (1/sigma0^2 + 1/P_k) (which = 1) or the inverse total
+// noise spectrum 1 / (sigma0^2 + P_k) = q / (sigma0^2 (1 + q)) (which = 2)
 template <typename T>
 __device__ __forceinline__ cx<T> filt_mode(const ModeCtx &mc, int64_t k, cx<T> E, int which) {
     const T q = q_of<T>(mc, k);
     const T s2 = (T)(mc.sigma0 * mc.sigma0);
-    const T h = which ? s2 / ((T)1 + q) : q / s2;
+    const T h = which == 0 ? q / s2 : (which == 1 ? s2 / ((T)1 + q) : q / (s2 * ((T)1 + q)));
     return cscale(E, (T)mc.invsqrtN * h);
 }
 

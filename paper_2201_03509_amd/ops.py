@@ -199,6 +199,14 @@ class Context:
             ctypes.c_uint64(int(it)), int(bool(mean_only)), float(tol), int(max_iter), _ptr(out),
             _ptr(iters)))
 
+    def sample_gain(self, tod, prec, d, t, seed, it, gain_out, sigma_out=None, mean_only=False,
+                    sigma0=None, fknee=None, alpha=None):
+        self._chk(self.lib.sample_gain(
+            self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(d), _dt(d), _ptr(t),
+            _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(tod.fknee if fknee is None else fknee),
+            _ptr(tod.alpha if alpha is None else alpha), ctypes.c_uint64(int(seed)),
+            ctypes.c_uint64(int(it)), int(bool(mean_only)), _ptr(gain_out), _ptr(sigma_out)))
+
     def bin_tod(self, tod, prec, pix, psi, d, ncorr, acc, accumulate=False, gain=None, sigma0=None):
         self._chk(self.lib.bin_tod(
             self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
@@ -254,7 +262,7 @@ class Context:
         self._chk(self.lib.tod_enable_timing(self.h, int(bool(on))))
 
     KERNELS = ["decode", "project", "fft_col_fwd", "fft_row", "fft_col_inv", "bin", "solve",
-               "chisq_time", "cg_vector"]
+               "chisq_time", "cg_vector", "gain"]
 
     def kernel_times(self):
         """{kernel: (total_ms, launches)} since the previous read."""
