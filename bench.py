@@ -125,6 +125,7 @@ MASKED_TOL = 1e-8     # its CG tolerance (FP32 transforms, FP64 Krylov vectors)
 
 
 GAIN_IT = 4242        # Gibbs iteration number of the gain-draw leg
+NOISE_IT = 4343       # Gibbs iteration number of the noise-parameter leg
 
 
 def _oracle_next(q):
@@ -149,10 +150,16 @@ def _oracle_next(q):
     nc, k = og.cg_ncorr_segment(r, m, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q], ts.alpha[q],
                                 seed, q, MASKED_IT, tol=1e-12)
     from oracle import gain as ogain
+    from oracle import noise as onoise
     t = ot.project(maps32, gp, psi, 1.0)
     g, sg, _, _ = ogain.sample_gain_segment(ts.d[a:a + n], t, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q],
                                             ts.alpha[q], seed, q, GAIN_IT)
-    return q, nc, k, g, sg
+    # noise parameters from the oracle's own n_corr of the sweep's last iteration
+    ncs = ot.sample_ncorr_segment(r, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q], ts.alpha[q], seed, q,
+                                  _BASE["it"])
+    xi = onoise.sample_noise_segment(ts.d[a:a + n], t, ts.gain[q], ncs, ts.band_fsamp[band], ts.fknee[q],
+                                     seed, q, NOISE_IT)
+    return q, nc, k, g, sg, xi
 
 
 def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
@@ -238,7 +245,7 @@ def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix):
     if ref:
         g = nc.cpu().numpy()
         errs = []
-        for q, r, k, _, _ in ref:
+        for q, r, k, _, _, _ in ref:
             a, b = ts.seg_off[q], ts.seg_off[q + 1]
             errs.append({"segment": q, "rel_l2": float(np.linalg.norm(g[a:b] - r) / np.linalg.norm(r)),
                          "iterations_gpu": int(it_h[q]), "iterations_oracle": int(k)})
@@ -247,28 +254,65 @@ def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix):
     return rep
 
 
-def gain_leg(ctx, ts, tod, out, maps32, seed):
-    """The gain draw over the whole workload: sky template at unit gain, one
-    warm-up call, one timed call (HIP events around every launch), error
-    against the oracle on the sampled segments."""
-    import numpy as np
+def unit_template(ctx, ts, tod, out, maps32):
     import torch
     dev = tod.d.device
     t = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
     ones = torch.ones(ts.nseg, dtype=torch.float64, device=dev)
     ctx.project_sky(tod, "mixed", out["pix"], out["psi"], maps32, t, gain=ones)
-    g = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
-    sg = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
-    ctx.sample_gain(tod, "mixed", tod.d, t, seed, GAIN_IT, g, sg)
+    return t
+
+
+def timed_call(ctx, fn):
+    """One warm-up call, one timed call with HIP events around every launch:
+    (ms, {kernel: (ms, launches)})."""
+    fn()
     ctx.sync()
     ctx.enable_timing(True)
     ctx.kernel_times()
     t0 = time.perf_counter()
-    ctx.sample_gain(tod, "mixed", tod.d, t, seed, GAIN_IT, g, sg)
+    fn()
     ctx.sync()
     ms = (time.perf_counter() - t0) * 1e3
     kt = ctx.kernel_times()
     ctx.enable_timing(False)
+    return ms, kt
+
+
+def noise_leg(ctx, ts, tod, out, t, seed):
+    """The noise-parameter draw over the whole workload from the sweep's last
+    n_corr; error against the oracle (fed its own n_corr of that iteration)
+    on the sampled segments."""
+    import numpy as np
+    import torch
+    dev = tod.d.device
+    s0, fk, al = (torch.empty(ts.nseg, dtype=torch.float64, device=dev) for _ in range(3))
+    ms, kt = timed_call(ctx, lambda: ctx.sample_noise(tod, "mixed", tod.d, t, out["ncorr"], seed, NOISE_IT,
+                                                      s0, fk, al))
+    xi = np.stack([s0.cpu().numpy(), fk.cpu().numpy(), al.cpu().numpy()])
+    truth = np.stack([ts.sigma0, ts.fknee, ts.alpha])
+    rep = {"ms_per_call": round(ms, 2), "samples_per_s": ts.nsamp / (ms / 1e3),
+           "kernels_ms": {k: round(v[0], 2) for k, v in kt.items() if v[1]},
+           "launches": {k: v[1] for k, v in kt.items() if v[1]},
+           "draw_vs_generator_median_rel": [float(np.median(np.abs(xi[i] / truth[i] - 1))) for i in range(3)]}
+    ref = _BASE.get("next")
+    if ref:
+        rep["vs_oracle_with_its_own_ncorr"] = [
+            {"segment": q, "rel_err": [float(abs(xi[i, q] / x[i] - 1)) for i in range(3)]}
+            for q, _, _, _, _, x in ref]
+    log("noise draw: %.1f ms per call" % ms)
+    return rep
+
+
+def gain_leg(ctx, ts, tod, seed, t):
+    """The gain draw over the whole workload against the unit-gain sky
+    template t; error against the oracle on the sampled segments."""
+    import numpy as np
+    import torch
+    dev = tod.d.device
+    g = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
+    sg = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
+    ms, kt = timed_call(ctx, lambda: ctx.sample_gain(tod, "mixed", tod.d, t, seed, GAIN_IT, g, sg))
     gh, sh = g.cpu().numpy(), sg.cpu().numpy()
     z = (gh - ts.gain) / sh
     rep = {"ms_per_call": round(ms, 2), "samples_per_s": ts.nsamp / (ms / 1e3),
@@ -280,7 +324,7 @@ def gain_leg(ctx, ts, tod, out, maps32, seed):
     if ref:
         rep["accuracy_vs_oracle"] = [{"segment": q, "gain_rel_err": float(abs(gh[q] - gr) / abs(gr)),
                                       "sigma_rel_err": float(abs(sh[q] - sr) / sr)}
-                                     for q, _, _, gr, sr in ref]
+                                     for q, _, _, gr, sr, _ in ref]
     log("gain draw: %.1f ms per call" % ms)
     return rep
 
@@ -298,6 +342,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-masked", action="store_true", help="skip the masked n_corr draw leg")
     ap.add_argument("--no-gain", action="store_true", help="skip the gain draw leg")
+    ap.add_argument("--no-noise", action="store_true", help="skip the noise-parameter draw leg")
     ap.add_argument("--fft-batch", type=int, default=None,
                     help="complex elements per FFT batch (0 = all segments at once)")
     ap.add_argument("--bin-stride", type=int, default=None, help="override the binning stride")
@@ -436,9 +481,14 @@ def main():
         del outp
         torch.cuda.empty_cache()
 
-    gain = None
-    if not args.no_gain:
-        gain = gain_leg(ctx, ts, tod, out, maps32, seed)
+    gain = noise = None
+    if not (args.no_gain and args.no_noise):
+        t_unit = unit_template(ctx, ts, tod, out, maps32)
+        if not args.no_gain:
+            gain = gain_leg(ctx, ts, tod, seed, t_unit)
+        if not args.no_noise:
+            noise = noise_leg(ctx, ts, tod, out, t_unit, seed)
+        del t_unit
         torch.cuda.empty_cache()
 
     masked = None
@@ -485,6 +535,7 @@ def main():
         "bin_stride": tuned.get("bin_stride"),
         "accuracy_vs_oracle": acc_report,
         "gain_draw": gain,
+        "noise_draw": noise,
         "masked_ncorr": masked,
         "copy_probe": copy,
     }

@@ -190,6 +190,35 @@ tod_status sample_gain(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                        uint64_t seed, uint64_t iter, int mean_only,
                        double *gain_out, double *sigma_out);
 
+/* Noise-parameter draw xi_n <- P(xi_n | d, g, n_corr, sky) per segment (Eq. 5:
+ * after n_corr; only low-volume spectrum data are involved, section 5):
+ * 1. sigma0^2 = S / X, S = sum (d - g t - n_corr)^2 (FP64), X the chi^2_n
+ *    variate n (1 - 2/(9n) + z0 sqrt(2/(9n)))^3 (prior flat in ln sigma0);
+ * 2. I_k = |FFT(e(n_corr))_k|^2 / N, k = 1..N/2, on sample_ncorr's extension,
+ *    summed into log-frequency bins b(k) (k < 8: b = k - 1; else with
+ *    e = floor(log2 k): b = 7 + 8 (e - 3) + (k >> (e - 3)) - 8), J_b, count
+ *    c_b, f_b = (f_samp/N) exp(mean ln k); binned Whittle likelihood
+ *    ln L = -sum_b (J_b / P_b + c_b ln P_b), P_b = sigma0^2 (f_b / f_knee)^alpha;
+ * 3. alpha = alpha_hat + z1 / sqrt(H): the maximiser of ln L in alpha at the
+ *    input f_knee and the new sigma0 (ln L is concave in alpha), H = -d2 lnL;
+ * 4. f_knee = u^(1/alpha), u = G sigma0^2 / sum_b J_b f_b^-alpha,
+ *    G = K (1 - 1/(9K) + z2 / (3 sqrt K))^3, K = N/2 (prior flat in ln f_knee).
+ * z0..z2: Box-Muller normals of the segment's Philox stream (key as
+ * sample_ncorr) at counter (2^32-2, iter lo, iter hi, seed hi); mean_only != 0
+ * sets them to 0.  The periodogram's FFT runs in the precision's type, all
+ * sums and the sampler in FP64.
+ * t: device [nsamp] sky template at unit gain (FP32 mixed / FP64 plain);
+ * gain: device [nseg] FP64; ncorr: device [nsamp] (FP32 mixed / FP64 plain);
+ * fknee_in: device [nseg] FP64 (the current f_knee, conditioned on by the
+ * alpha step).  Outputs: device [nseg] FP64 each (may alias fknee_in); NaN for
+ * empty segments.  The bin sums use FP64 atomics: their last bits may vary
+ * from call to call. */
+tod_status sample_noise(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                        const void *d, tod_dtype d_dtype, const void *t,
+                        const double *gain, const void *ncorr, const double *fknee_in,
+                        uint64_t seed, uint64_t iter, int mean_only,
+                        double *sigma0_out, double *fknee_out, double *alpha_out);
+
 /* Correlated-noise draw with a processing mask (gap filling: the constrained
  * realisation needs FFTs inside a CG solver where scans cross masked sky,
  * section 5 and the correlated-noise row of Table 2).  On the extension and
@@ -314,11 +343,12 @@ tod_status tod_set_fft_batch(tod_ctx ctx, int64_t complex_elems);
  * graph capture is bracketed by HIP events on the context stream (the sweep
  * then runs eagerly).  tod_kernel_times synchronises the stream, returns the
  * summed milliseconds and launch counts since the previous read and resets
- * them.  Kernel ids (arrays of 10): 0 decode, 1 projection, 2 FFT forward
- * column pass, 3 FFT row pass (filter + draw, Whittle sums, or the masked
- * draw's and the gain draw's Fourier-diagonal filters), 4 FFT inverse column
- * pass, 5 binning, 6 per-pixel solve, 7 chi^2 time-domain terms, 8 the masked
- * draw's CG vector updates and reductions, 9 the gain draw's sums and draw. */
+ * them.  Kernel ids (arrays of 11): 0 decode, 1 projection, 2 FFT forward
+ * column pass, 3 FFT row pass (filter + draw, Whittle sums, the masked and
+ * gain draws' Fourier-diagonal filters, or periodogram bins), 4 FFT inverse
+ * column pass, 5 binning, 6 per-pixel solve, 7 chi^2 time-domain terms, 8 the
+ * masked draw's CG vector updates and reductions, 9 the gain draw's sums and
+ * draw, 10 the noise-parameter draw's sums and sampler. */
 tod_status tod_enable_timing(tod_ctx ctx, int enable);
 tod_status tod_kernel_times(tod_ctx ctx, double *total_ms, int32_t *launches);
 

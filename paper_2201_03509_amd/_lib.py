@@ -15,7 +15,8 @@ STATUS_NAMES = {0: "TOD_OK", 1: "TOD_EINVAL", 2: "TOD_ENOMEM", 3: "TOD_EHIP",
 # every entry point the header declares
 EXPORTS = [
     "tod_ctx_create", "tod_ctx_destroy", "tod_sync", "tod_clear_error", "tod_last_error",
-    "tod_device_error_bits", "decode_pointing", "project_sky", "sample_ncorr", "sample_ncorr_masked", "sample_gain", "bin_tod",
+    "tod_device_error_bits", "decode_pointing", "project_sky", "sample_ncorr", "sample_ncorr_masked", "sample_gain", "sample_noise",
+    "bin_tod",
     "solve_maps", "tod_chisq", "tod_chisq_backward", "tod_sweep", "tod_autotune",
     "tod_load_tuning", "tod_set_bin_stride", "tod_set_fft_batch", "tod_enable_timing",
     "tod_kernel_times",
@@ -79,6 +80,7 @@ def load():
         "sample_ncorr_masked": [P, LP, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, U64, U64,
                                 ctypes.c_int, D, ctypes.c_int, P, P],
         "sample_gain": [P, LP, ctypes.c_int, P, ctypes.c_int, P, P, P, P, U64, U64, ctypes.c_int, P, P],
+        "sample_noise": [P, LP, ctypes.c_int, P, ctypes.c_int, P, P, P, P, U64, U64, ctypes.c_int, P, P, P],
         "bin_tod": [P, LP, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int],
         "solve_maps": [P, I64, P, D, P, ctypes.c_int, P],
         "tod_chisq": [P, LP, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P, P, P, P],

@@ -132,6 +132,8 @@ struct tod_ctx_s {
     DevBuf cg_x, cg_res, cg_p, cg_fout, cg_part, cg_state, cg_act, cg_count;
     // gain draw: filtered template and data (per sample), per-tile partial sums
     DevBuf gain_kt, gain_kd, gain_part;
+    // noise-parameter draw: periodogram bins per segment, white-residual partials
+    DevBuf xi_bins, xi_part;
     std::map<uint64_t, std::unique_ptr<Plan>> plans;
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
@@ -569,7 +571,7 @@ tod_status ensure_work(tod_ctx ctx, Plan *P) {
 }
 
 // kernel ids of tod_kernel_times
-enum { K_DECODE = 0, K_PROJECT, K_COLF, K_ROW, K_COLI, K_BIN, K_SOLVE, K_CHISQ, K_CG, K_GAIN, K_NKERNEL };
+enum { K_DECODE = 0, K_PROJECT, K_COLF, K_ROW, K_COLI, K_BIN, K_SOLVE, K_CHISQ, K_CG, K_GAIN, K_NOISE, K_NKERNEL };
 
 hipEvent_t pool_event(tod_ctx c) {
     if (!c->ev_pool.empty()) {
@@ -991,6 +993,52 @@ tod_status sample_gain(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const 
         HIPCHK(c3::launch_gain_finish(st, lay->nseg, (const int2 *)P->sample_seg_tiles.p,
                                       (const double2 *)ctx->gain_part.p, ctx->d_seed_iter, mean_only, gain_out,
                                       sigma_out));
+    }
+    return TOD_OK;
+}
+
+tod_status sample_noise(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const void *d,
+                        tod_dtype d_dtype, const void *t, const double *gain, const void *ncorr,
+                        const double *fknee_in, uint64_t seed, uint64_t iter, int mean_only,
+                        double *sigma0_out, double *fknee_out, double *alpha_out) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (!d || !t || !gain || !ncorr || !fknee_in || !sigma0_out || !fknee_out || !alpha_out)
+        return fail(ctx, TOD_EINVAL, "NULL argument");
+    const int mixed = prec == TOD_MIXED;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    if ((r = ensure_work(ctx, P)) != TOD_OK) return r;
+    const size_t nbin = (size_t)lay->nseg * C3_XI_NBIN;
+    HIPCHK(ctx->xi_bins.ensure(nbin * 8 + 64));
+    HIPCHK(ctx->xi_part.ensure((size_t)P->nsample_tiles * 8 + 64));
+    hipStream_t st = ctx->stream;
+    HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
+    {
+        KTimer kt(ctx, K_NOISE, st);
+        HIPCHK(c3::launch_zero(st, ctx->xi_bins.p, (int64_t)(nbin * 8)));
+    }
+    {
+        KTimer kt(ctx, K_NOISE, st);
+        HIPCHK(c3::launch_xi_white(st, mixed, (const int4 *)P->sample_tiles.p, P->nsample_tiles, lay->seg_off, d,
+                                   d_dtype == TOD_F64, t, gain, ncorr, (double *)ctx->xi_part.p));
+    }
+    c3::FftArgs a = fft_args(ctx, P, lay);
+    a.mode = 4;  // periodogram bins: forward passes only
+    a.in_a = ncorr;
+    a.in_a_f64 = !mixed;
+    a.bins = (double *)ctx->xi_bins.p;
+    if ((r = run_fft(ctx, st, P, mixed, a, 2)) != TOD_OK) return r;
+    {
+        KTimer kt(ctx, K_NOISE, st);
+        HIPCHK(c3::launch_xi_sample(st, lay->nseg, (const SegInfo *)P->segs.p, (const FftPlan *)P->plans.p,
+                                    lay->seg_band, (const double *)P->fsamp.p,
+                                    (const int2 *)P->sample_seg_tiles.p, (const double *)ctx->xi_part.p,
+                                    (const double *)ctx->xi_bins.p, fknee_in, ctx->d_seed_iter, mean_only,
+                                    sigma0_out, fknee_out, alpha_out));
     }
     return TOD_OK;
 }

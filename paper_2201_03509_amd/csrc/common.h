@@ -88,6 +88,7 @@ struct BandDev {
 };
 
 #define C3_MAXBAND 16
+#define C3_XI_NBIN 231       // periodogram bins of modes k = 1 .. 2^31 - 1 (noise-parameter draw)
 
 struct LayoutDev {
     const int64_t *seg_off;
@@ -181,10 +182,12 @@ struct FftArgs {
                                 //         2: 1/(sigma0^2 + P);
                                 // mode 3: 0 spectrum W1, 1 spectrum W2 sqrt(1/P)
     const int32_t *active;      // per segment, 0: skip (NULL: every segment runs)
+    double *bins;               // mode 4: periodogram bins [nseg][C3_XI_NBIN], added to
 };
 // pass 0: forward column FFTs; 1: row pass (mode 0 n_corr draw, 1 Whittle sums,
 // 2 Fourier-diagonal filter, 3 inverse transform of a drawn spectrum: no
-// forward transform, no input); 2: inverse column FFTs.  m1reg > 0 selects the
+// forward transform, no input, 4 periodogram summed into log-frequency bins:
+// no inverse transform); 2: inverse column FFTs.  m1reg > 0 selects the
 // register column kernels for that column length (passes 0 and 2); 0 the LDS
 // column tiles.
 hipError_t launch_fft_pass(hipStream_t st, int prec_mixed, const FftArgs &a, int pass, int m1reg);
@@ -267,6 +270,17 @@ hipError_t launch_cg_iters(hipStream_t st, int nseg, const CgState *cs, int32_t 
 // segment); then per segment g = B/A + eta/sqrt(A)
 hipError_t launch_gain_dots(hipStream_t st, int mixed, const int4 *tiles, int ntile, const int64_t *seg_off,
                             const void *t, const void *kt, const void *kd, double2 *part);
+// ---- noise-parameter draw (noise.hip): per sample tile the partial sum of
+// (d - g t - n_corr)^2; then per segment (one wave) sigma0, alpha, f_knee from
+// it and the periodogram bins of the row pass (mode 4)
+hipError_t launch_xi_white(hipStream_t st, int mixed, const int4 *tiles, int ntile, const int64_t *seg_off,
+                           const void *d, int d_f64, const void *t, const double *gain, const void *nc,
+                           double *part);
+hipError_t launch_xi_sample(hipStream_t st, int nseg, const SegInfo *segs, const FftPlan *plans,
+                            const int32_t *seg_band, const double *fsamp_band, const int2 *seg_tiles,
+                            const double *part, const double *bins, const double *fknee_in,
+                            const uint64_t *seed_iter, int mean_only, double *sigma0_out, double *fknee_out,
+                            double *alpha_out);
 hipError_t launch_gain_finish(hipStream_t st, int nseg, const int2 *seg_tiles, const double2 *part,
                               const uint64_t *seed_iter, int mean_only, double *gain_out, double *sigma_out);
 

@@ -474,6 +474,14 @@ __device__ __forceinline__ void whittle_mode(const ModeCtx &mc, int64_t k, cx<T>
     s.c += (1.0 - IP) * lr;
 }
 
+// integer log-frequency bin of mode k >= 1: k = 1..7 one bin each; above,
+// eight bins per octave split by the three bits after the leading one
+__device__ __forceinline__ int xi_bin(int64_t k) {
+    if (k < 8) return (int)k - 1;
+    const int e = 63 - __builtin_clzll((unsigned long long)k);
+    return 7 + 8 * (e - 3) + (int)(k >> (e - 3)) - 8;
+}
+
 // ------------------------------------------------------------- pass 2
 template <typename T>
 constexpr int row_nt() { return sizeof(T) == 4 ? C3_ROW_NT_F32 : C3_ROW_NT_F64; }
@@ -495,6 +503,13 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     const int si = two ? 2 : 1;
     const cx<T> *pool = (const cx<T> *)a.twpool;
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
+    double *hist = nullptr;  // mode 4: per-block periodogram bins
+    if constexpr (MODE == 4) {
+        __shared__ double hist_lds[C3_XI_NBIN];
+        hist = hist_lds;
+        for (int i = threadIdx.x; i < C3_XI_NBIN; i += NT) hist[i] = 0.0;
+        __syncthreads();
+    }
 
     // the first forward stage reads the two rows from memory and the last
     // inverse stage writes them back (rows of two or more stages)
@@ -516,10 +531,12 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     {
         const double fs = a.fsamp_band[sg.band];
         const double N = 2.0 * M;
-        mc.sigma0 = a.sigma0[seg];
-        mc.malpha = -a.alpha[seg];
-        mc.lbase = log(fs / (N * a.fknee[seg]));
-        mc.lbase2 = mc.lbase * 1.4426950408889634;
+        if constexpr (MODE != 4) {  // the periodogram needs no noise parameters
+            mc.sigma0 = a.sigma0[seg];
+            mc.malpha = -a.alpha[seg];
+            mc.lbase = log(fs / (N * a.fknee[seg]));
+            mc.lbase2 = mc.lbase * 1.4426950408889634;
+        }
         mc.invsqrtN = 1.0 / sqrt(N);
         mc.outscale = sqrt(N) / M;
         const uint64_t seed = a.seed_iter ? a.seed_iter[0] : 0, it = a.seed_iter ? a.seed_iter[1] : 0;
@@ -561,6 +578,8 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
             const cx<T> E0 = {Za.x + Za.y, 0}, EM = {Za.x - Za.y, 0};
             if constexpr (MODE == 1) {
                 whittle_mode(mc, M, EM, ws);
+            } else if constexpr (MODE == 4) {  // DC excluded
+                atomicAdd(&hist[xi_bin(M)], (double)EM.x * EM.x * mc.invsqrtN * mc.invsqrtN);
             } else {
                 cx<T> n0, nM;
                 if constexpr (MODE == 0) {
@@ -586,7 +605,11 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
         // partner: A_p = conj A_k, B_p = conj B_k, w_N^p = -conj(w_N^k)
         const cx<T> wp = {-w.x, w.y};
         const cx<T> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
-        if constexpr (MODE != 1) {
+        if constexpr (MODE == 4) {
+            const double s2 = mc.invsqrtN * mc.invsqrtN;
+            atomicAdd(&hist[xi_bin(k)], ((double)Ek.x * Ek.x + (double)Ek.y * Ek.y) * s2);
+            if (kp != k) atomicAdd(&hist[xi_bin(kp)], ((double)Ep.x * Ep.x + (double)Ep.y * Ep.y) * s2);
+        } else if constexpr (MODE != 1) {
             cx<T> nk, np;
             if constexpr (MODE == 0) {
                 nk = cr_mode(mc, k, Ek);
@@ -613,7 +636,11 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
             if (kp != k) whittle_mode(mc, kp, Ep, ws);
         }
     }
-    if constexpr (MODE != 1) {
+    if constexpr (MODE == 4) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < C3_XI_NBIN; i += NT)
+            if (hist[i] != 0.0) atomicAdd(&a.bins[(int64_t)seg * C3_XI_NBIN + i], hist[i]);
+    } else if constexpr (MODE != 1) {
         __syncthreads();
         row_fft<1, NT>(buf, (const cx<T> *)nullptr, (const cx<T> *)nullptr, direct ? ya : nullptr, yb,
                        M2, lb, two, p.r2, p.nr2, pool + p.tw2);
@@ -647,7 +674,9 @@ namespace c3 {
 hipError_t fft_init_attributes() {
     static hipError_t done = hipErrorNotReady;
     if (done == hipSuccess) return done;
-    const int lim = C3_LDS_MAX - 1024;  // room for the static reduction array (384 B)
+    // room for the kernels' static arrays (reduction sums, periodogram bins: under
+    // 2 KB); the largest dynamic request (two rows of 5040 FP32 points) is 80 KB
+    const int lim = C3_LDS_MAX - 4096;
     hipError_t e = hipSuccess;
     auto set = [&](const void *f) {
         hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
@@ -665,6 +694,8 @@ hipError_t fft_init_attributes() {
     set((const void *)k_row<float, 3>);
     set((const void *)k_row<double, 2>);
     set((const void *)k_row<double, 3>);
+    set((const void *)k_row<float, 4>);
+    set((const void *)k_row<double, 4>);
     done = e;
     return e;
 }
@@ -686,14 +717,16 @@ hipError_t launch_fft_pass(hipStream_t st, int mixed, const FftArgs &a, int pass
         else if (a.mode == 0) hipLaunchKernelGGL((k_row<float, 0>), gr, br, lr, st, a);
         else if (a.mode == 1) hipLaunchKernelGGL((k_row<float, 1>), gr, br, lr, st, a);
         else if (a.mode == 2) hipLaunchKernelGGL((k_row<float, 2>), gr, br, lr, st, a);
-        else hipLaunchKernelGGL((k_row<float, 3>), gr, br, lr, st, a);
+        else if (a.mode == 3) hipLaunchKernelGGL((k_row<float, 3>), gr, br, lr, st, a);
+        else hipLaunchKernelGGL((k_row<float, 4>), gr, br, lr, st, a);
     } else {
         if (pass == 0) hipLaunchKernelGGL(k_col_fwd<double>, gc, b, lc, st, a);
         else if (pass == 2) hipLaunchKernelGGL(k_col_inv<double>, gc, b, lc, st, a);
         else if (a.mode == 0) hipLaunchKernelGGL((k_row<double, 0>), gr, br, lr, st, a);
         else if (a.mode == 1) hipLaunchKernelGGL((k_row<double, 1>), gr, br, lr, st, a);
         else if (a.mode == 2) hipLaunchKernelGGL((k_row<double, 2>), gr, br, lr, st, a);
-        else hipLaunchKernelGGL((k_row<double, 3>), gr, br, lr, st, a);
+        else if (a.mode == 3) hipLaunchKernelGGL((k_row<double, 3>), gr, br, lr, st, a);
+        else hipLaunchKernelGGL((k_row<double, 4>), gr, br, lr, st, a);
     }
     return hipGetLastError();
 }

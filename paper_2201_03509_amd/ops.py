@@ -207,6 +207,15 @@ class Context:
             _ptr(tod.alpha if alpha is None else alpha), ctypes.c_uint64(int(seed)),
             ctypes.c_uint64(int(it)), int(bool(mean_only)), _ptr(gain_out), _ptr(sigma_out)))
 
+    def sample_noise(self, tod, prec, d, t, ncorr, seed, it, sigma0_out, fknee_out, alpha_out,
+                     mean_only=False, gain=None, fknee=None):
+        self._chk(self.lib.sample_noise(
+            self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(d), _dt(d), _ptr(t),
+            _ptr(tod.gain if gain is None else gain), _ptr(ncorr),
+            _ptr(tod.fknee if fknee is None else fknee), ctypes.c_uint64(int(seed)),
+            ctypes.c_uint64(int(it)), int(bool(mean_only)), _ptr(sigma0_out), _ptr(fknee_out),
+            _ptr(alpha_out)))
+
     def bin_tod(self, tod, prec, pix, psi, d, ncorr, acc, accumulate=False, gain=None, sigma0=None):
         self._chk(self.lib.bin_tod(
             self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
@@ -262,7 +271,7 @@ class Context:
         self._chk(self.lib.tod_enable_timing(self.h, int(bool(on))))
 
     KERNELS = ["decode", "project", "fft_col_fwd", "fft_row", "fft_col_inv", "bin", "solve",
-               "chisq_time", "cg_vector", "gain"]
+               "chisq_time", "cg_vector", "gain", "noise"]
 
     def kernel_times(self):
         """{kernel: (total_ms, launches)} since the previous read."""
