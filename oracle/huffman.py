@@ -203,3 +203,20 @@ def decode_pointing(ts, segs=None):
         n = int(ts.seg_off[s + 1] - ts.seg_off[s])
         out[s] = (dp.segment(s, n), ds.segment(s, n))
     return out
+
+
+def decode_stream(ts, hs, segs=None):
+    """Undifferenced integers of any stream of the set (TOD, flags), flat."""
+    dec = StreamDecoder(hs)
+    out = np.zeros(ts.nsamp, dtype=np.int64)
+    for q in (range(ts.nseg) if segs is None else segs):
+        a, b = int(ts.seg_off[q]), int(ts.seg_off[q + 1])
+        if b > a:
+            out[a:b] = dec.segment(q, b - a)
+    return out
+
+
+def decode_tod(ts, segs=None):
+    """The TOD of the set from its compressed stream: quantum x the integers
+    (the paper's TOD are ADC integers, differenced and coded like the pointing)."""
+    return ts.tod_quantum * decode_stream(ts, ts.tod_huff, segs).astype(np.float64)

@@ -13,7 +13,14 @@ Recipe (each item is a generator choice, fixed so results are reproducible):
 * gain 1 + 0.01 N(0,1) per segment; sigma0 = 1; f_knee, alpha per detector;
 * correlated noise: Gaussian with PSD sigma0^2 (f/f_knee)^alpha drawn on a
   periodic grid and truncated to the segment, zero mean; white noise N(0, sigma0^2);
-* d = g * (T + Re[(Q - iU) exp(2i psi)]) + n_corr + n_w, stored FP64 or FP32.
+* d = g * (T + Re[(Q - iU) exp(2i psi)]) + n_corr + n_w, quantised to integer
+  multiples of TOD_QUANTUM (the ADC step: the paper's TOD are integers) and
+  stored FP64 or FP32 (exact: |d / TOD_QUANTUM| < 2^24);
+* optional compressed TOD and flag streams (``tod_streams=True``): the
+  integer TOD and a flag word per sample (bit 0: processing mask, the pixel
+  centre within 10 deg of the map frame's equator; bit 1: isolated glitches,
+  probability 1e-4 per sample, stream 7), differenced and Huffman coded per
+  scan exactly like the pointing streams.
 
 A *segment* is one (scan, detector) pair; segments are ordered band, scan,
 detector, and all per-sample arrays are flat with ``seg_off`` offsets.
@@ -28,6 +35,9 @@ from . import healpix
 from . import huffman_enc as H
 
 NPSI = 4096
+TOD_QUANTUM = 0.125        # ADC step of the stored TOD (sigma0 / 8)
+FLAG_PLANE = 1             # flag bits
+FLAG_GLITCH = 2
 OPENING_DEG = 85.0
 HORN_STEP_DEG = 0.5
 SPIN_PERIOD_S = 60.0
@@ -125,7 +135,7 @@ def _scan_worker(args):
             cb, cp = H.chunk_index(vals[j], pos, cfg.chunk_len)
             segs.append((words, cb, cp))
         out["streams"][name] = (blob, segs)
-    dd = []
+    dd, di = [], []
     for j in range(nd):
         seg = seg0 + j
         det = det0 + j
@@ -134,8 +144,26 @@ def _scan_worker(args):
         sig = sky[0, p] + np.real((sky[1, p] - 1j * sky[2, p]) * np.exp(2j * ang))
         nc = _corr_noise(_rng(k, 6, g_scan, j), n, band.fsamp, sig0[det], fkn[det], alp[det])
         nw = _rng(k, 5, g_scan, j).normal(0.0, sig0[det], size=n)
-        dd.append(gains[seg] * sig + nc + nw)
+        x = np.rint((gains[seg] * sig + nc + nw) / TOD_QUANTUM).astype(np.int64)
+        di.append(x)
+        dd.append(x * TOD_QUANTUM)
     out["d"] = dd
+    if _G["tod_streams"]:
+        horn_flag = [FLAG_PLANE * (1 - plane_mask_pixels(band.nside, hp)).astype(np.int64) for hp in horn_pix]
+        flags = []
+        for j in range(nd):
+            fl = horn_flag[min(j // 2, nh - 1)].copy()
+            fl |= FLAG_GLITCH * (_rng(k, 7, g_scan, j).random(n) < 1e-4)
+            flags.append(fl)
+        for name, vals in (("tod", di), ("flag", flags)):
+            diffs = [H.difference(v) for v in vals]
+            blob, lookup = H.build_table(np.concatenate(diffs))
+            segs = []
+            for j in range(nd):
+                words, pos = H.encode_values(diffs[j], lookup)
+                cb, cp = H.chunk_index(vals[j], pos, cfg.chunk_len)
+                segs.append((words, cb, cp))
+            out["streams"][name] = (blob, segs)
     if _G["keep_truth"]:
         out["pix"] = [p.astype(np.int32) for p in pix]
         out["psi"] = [p.astype(np.uint16) for p in psi]
@@ -165,7 +193,8 @@ class TodSet:
     """A synthetic TOD set; every array is a numpy array on the host."""
 
 
-def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None, chunk_len=None):
+def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None, chunk_len=None,
+         tod_streams=False):
     cfg = cfgmod.get(k).scaled(nscan=nscan, length=length, bands=bands, chunk_len=chunk_len)
     kk = cfg.index
     nb = len(cfg.bands)
@@ -213,7 +242,7 @@ def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None,
     sky = [_sky(cfg, b, npix[b]) for b in range(nb)]
     _G.clear()
     _G.update(cfg=cfg, sky=sky, gain=gain, sigma0=sigma0_det, fknee=fknee_det,
-              alpha=alpha_det, keep_truth=keep_truth)
+              alpha=alpha_det, keep_truth=keep_truth, tod_streams=tod_streams)
     if workers is None:
         workers = min(16, os.cpu_count() or 1) if len(jobs) > 8 else 1
     import sys
@@ -257,7 +286,8 @@ def make(k, nscan=None, length=None, workers=None, keep_truth=False, bands=None,
     ts.maps = np.concatenate(sky, axis=1)        # [3][npix_total] FP64 truth
     dt = np.float64 if cfg.tod_f64 else np.float32
     ts.d = np.concatenate([np.concatenate(r["d"]) for r in res]).astype(dt)
-    for name in ("pix", "psi"):
+    ts.tod_quantum = TOD_QUANTUM
+    for name in ("pix", "psi") + (("tod", "flag") if tod_streams else ()):
         hs = HuffStream(cfg.chunk_len)
         blobs, words, cbits, cprevs = [], [], [], []
         seg_table, wlen, clen = [], [], []
@@ -301,10 +331,13 @@ def save(ts, path):
     meta = {k: int(getattr(ts, k)) for k in _SCALARS}
     meta["cfg"] = [ts.cfg.index, ts.cfg.nscan, list(ts.cfg.length)]
     meta["chunk_len"] = ts.pix_huff.chunk_len
+    meta["tod_quantum"] = ts.tod_quantum
+    names = [n for n in ("pix_huff", "psi_huff", "tod_huff", "flag_huff") if hasattr(ts, n)]
+    meta["streams"] = names
     for k, v in vars(ts).items():
         if isinstance(v, np.ndarray):
             np.save(os.path.join(path, k + ".npy"), v)
-    for name in ("pix_huff", "psi_huff"):
+    for name in names:
         for k, v in vars(getattr(ts, name)).items():
             if isinstance(v, np.ndarray):
                 np.save(os.path.join(path, name + "." + k + ".npy"), v)
@@ -320,7 +353,8 @@ def load(path):
         setattr(ts, k, meta[k])
     idx, nscan, length = meta["cfg"]
     ts.cfg = cfgmod.get(idx).scaled(nscan=nscan, length=length, chunk_len=meta["chunk_len"])
-    hs = {"pix_huff": HuffStream(meta["chunk_len"]), "psi_huff": HuffStream(meta["chunk_len"])}
+    ts.tod_quantum = meta["tod_quantum"]
+    hs = {n: HuffStream(meta["chunk_len"]) for n in meta["streams"]}
     for f in sorted(os.listdir(path)):
         if not f.endswith(".npy"):
             continue
@@ -331,7 +365,8 @@ def load(path):
             setattr(hs[a], b, arr)
         else:
             setattr(ts, key, arr)
-    ts.pix_huff, ts.psi_huff = hs["pix_huff"], hs["psi_huff"]
+    for n, h in hs.items():
+        setattr(ts, n, h)
     return ts
 
 
@@ -339,9 +374,11 @@ def make_cached(k, cache_dir=None, **kw):
     """make(), reusing a copy saved under cache_dir when one exists."""
     if not cache_dir:
         return make(k, **kw)
-    tag = "c%d_n%s_l%s" % (k, kw.get("nscan"), "_".join(map(str, kw.get("length") or [])))
+    tag = "c%d_n%s_l%s_q" % (k, kw.get("nscan"), "_".join(map(str, kw.get("length") or [])))
     if kw.get("chunk_len"):
         tag += "_c%d" % kw["chunk_len"]
+    if kw.get("tod_streams"):
+        tag += "_t"
     path = os.path.join(cache_dir, tag)
     if os.path.exists(os.path.join(path, "meta.json")):
         return load(path)
