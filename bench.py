@@ -209,9 +209,37 @@ def compare_to_oracle(ts, res, gpu_ncorr, gpu_pix):
             "decode_bit_exact": exact, "segments": len(res)}
 
 
-def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix):
-    """The masked n_corr draw (CG gap filling) over the whole workload with a
-    +-10 deg plane mask: one warm-up call, one timed call (HIP events around
+def stream_leg(ctx, ts, tod):
+    """Decoding the compressed TOD and flag streams over the whole workload;
+    returns the report and the processing mask decoded from the flags."""
+    import torch
+    import synth
+    dev = tod.d.device
+    d = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
+    ms_d, _ = timed_call(ctx, lambda: ctx.decode_tod(tod, "mixed", d))
+    exact = bool(torch.equal(d, tod.d))
+    del d
+    mask = torch.empty(ts.nsamp, dtype=torch.uint8, device=dev)
+    ms_f, _ = timed_call(ctx, lambda: ctx.decode_flags(tod, synth.FLAG_PLANE, None, mask))
+
+    def comp(h):
+        return h.words.nbytes + h.chunk_bit.nbytes + h.chunk_prev.nbytes + h.tables.nbytes
+
+    rep = {"tod": {"ms_per_call": round(ms_d, 3), "samples_per_s": ts.nsamp / (ms_d / 1e3),
+                   "compressed_bytes_per_sample": comp(ts.tod_huff) / ts.nsamp,
+                   "ratio_vs_32bit": 4.0 * ts.nsamp / comp(ts.tod_huff),
+                   "decoded_equals_fp32_tod": exact},
+           "flags": {"ms_per_call": round(ms_f, 3), "samples_per_s": ts.nsamp / (ms_f / 1e3),
+                     "compressed_bytes_per_sample": comp(ts.flag_huff) / ts.nsamp,
+                     "ratio_vs_32bit": 4.0 * ts.nsamp / comp(ts.flag_huff)}}
+    log("tod stream: %.2f ms, flag stream: %.2f ms" % (ms_d, ms_f))
+    return rep, mask
+
+
+def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix, mask):
+    """The masked n_corr draw (CG gap filling) over the whole workload with the
+    processing mask decoded from the flag stream (+-10 deg around the map
+    frame's equator): one warm-up call, one timed call (HIP events around
     every launch), iteration counts and the error against the oracle's CG on
     the sampled segments."""
     import numpy as np
@@ -219,7 +247,7 @@ def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix):
     import synth
     dev = tod.d.device
     mask_h = synth.plane_mask(ts, gpu_pix)
-    mask = torch.from_numpy(mask_h).to(dev)
+    mask_ok = bool(np.array_equal(mask.cpu().numpy(), mask_h))
     s = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
     ctx.project_sky(tod, "mixed", out["pix"], out["psi"], maps32, s)
     nc = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
@@ -237,6 +265,7 @@ def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix):
     it_h = iters.cpu().numpy()
     rep = {"ms_per_call": round(ms, 2), "samples_per_s": ts.nsamp / (ms / 1e3),
            "masked_fraction": round(float(1.0 - mask_h.mean()), 4), "tol": MASKED_TOL,
+           "mask_from_flag_stream_equals_plane_mask": mask_ok,
            "iterations": {"min": int(np.abs(it_h).min()), "median": float(np.median(np.abs(it_h))),
                           "max": int(np.abs(it_h).max()), "unconverged": int((it_h < 0).sum())},
            "kernels_ms": {k: round(v[0], 2) for k, v in kt.items() if v[1]},
@@ -364,7 +393,7 @@ def main():
 
     t0 = time.perf_counter()
     ts = synth.make_cached(args.config, cache_dir=args.cache_dir, nscan=args.nscan,
-                           chunk_len=args.chunk_len)
+                           chunk_len=args.chunk_len, tod_streams=True)
     log("generated config %d: %d segments, %d samples in %.1fs" %
         (args.config, ts.nseg, ts.nsamp, time.perf_counter() - t0))
     seed = synth.seed32(args.config)
@@ -491,10 +520,12 @@ def main():
         del t_unit
         torch.cuda.empty_cache()
 
+    streams, flag_mask = stream_leg(ctx, ts, tod)
     masked = None
     if not args.no_masked:
-        masked = masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix)
-        torch.cuda.empty_cache()
+        masked = masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix, flag_mask)
+    del flag_mask
+    torch.cuda.empty_cache()
 
     copy = None
     if args.copy_probe:
@@ -534,6 +565,7 @@ def main():
         "fft_splits": plans,
         "bin_stride": tuned.get("bin_stride"),
         "accuracy_vs_oracle": acc_report,
+        "tod_flag_streams": streams,
         "gain_draw": gain,
         "noise_draw": noise,
         "masked_ncorr": masked,

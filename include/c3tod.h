@@ -140,6 +140,20 @@ tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay,
                            const tod_huff *pix, const tod_huff *psi,
                            int32_t *pix_out, uint16_t *psi_out);
 
+/* Compressed TOD and flag streams (section 4.1: TOD and flags are integers
+ * by nature (ADC output), differenced sample by sample and Huffman coded like
+ * the pointing; Table 1 lists their compression).  Same stream format, side
+ * index and error reporting as decode_pointing; one stream per call.
+ * decode_tod: d_out[t] = quantum * x_t (x_t the undifferenced integer), device
+ * [nsamp] FP32 (mixed) or FP64 (plain).
+ * decode_flags: flags_out[t] = x_t (device [nsamp] uint32, may be NULL) and
+ * mask_out[t] = (x_t & flag_mask) == 0 (device [nsamp] uint8, may be NULL):
+ * the mask input of sample_ncorr_masked.  At least one output. */
+tod_status decode_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                      const tod_huff *tod, double quantum, void *d_out);
+tod_status decode_flags(tod_ctx ctx, const tod_layout *lay, const tod_huff *flags,
+                        uint32_t flag_mask, uint32_t *flags_out, uint8_t *mask_out);
+
 /* Projection s = g P m (Eq. 1; pointing matrix as pixel + psi streams,
  * section 2.1).  pix/psi: device [nsamp] as produced by decode_pointing.
  * maps: device [3][npix_total] FP32 (mixed) or FP64 (plain).  gain: device

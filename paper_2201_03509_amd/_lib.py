@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "TOD_OK", 1: "TOD_EINVAL", 2: "TOD_ENOMEM", 3: "TOD_EHIP",
 # every entry point the header declares
 EXPORTS = [
     "tod_ctx_create", "tod_ctx_destroy", "tod_sync", "tod_clear_error", "tod_last_error",
-    "tod_device_error_bits", "decode_pointing", "project_sky", "sample_ncorr", "sample_ncorr_masked", "sample_gain", "sample_noise",
+    "tod_device_error_bits", "decode_pointing", "decode_tod", "decode_flags", "project_sky", "sample_ncorr", "sample_ncorr_masked", "sample_gain", "sample_noise",
     "bin_tod",
     "solve_maps", "tod_chisq", "tod_chisq_backward", "tod_sweep", "tod_autotune",
     "tod_load_tuning", "tod_set_bin_stride", "tod_set_fft_batch", "tod_enable_timing",
@@ -80,6 +80,8 @@ def load():
         "sample_ncorr_masked": [P, LP, ctypes.c_int, P, ctypes.c_int, P, P, P, P, P, U64, U64,
                                 ctypes.c_int, D, ctypes.c_int, P, P],
         "sample_gain": [P, LP, ctypes.c_int, P, ctypes.c_int, P, P, P, P, U64, U64, ctypes.c_int, P, P],
+        "decode_tod": [P, LP, ctypes.c_int, HP, D, P],
+        "decode_flags": [P, LP, HP, ctypes.c_uint32, P, P],
         "sample_noise": [P, LP, ctypes.c_int, P, ctypes.c_int, P, P, P, P, U64, U64, ctypes.c_int, P, P, P],
         "bin_tod": [P, LP, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int],
         "solve_maps": [P, I64, P, D, P, ctypes.c_int, P],

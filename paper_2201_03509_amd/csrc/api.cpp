@@ -755,6 +755,40 @@ tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay, const tod_huff *p
     return TOD_OK;
 }
 
+// one TOD or flag stream: kind 0/1 TOD in FP32/FP64, 2 flags
+static tod_status decode_stream(tod_ctx ctx, const tod_layout *lay, const tod_huff *h, const char *what,
+                                int kind, double quantum, uint32_t flag_mask, void *out, uint8_t *mask_out) {
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if ((r = check_huff(ctx, h, what)) != TOD_OK) return r;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, 1, &P)) != TOD_OK) return r;
+    const DecodeTask *tasks;
+    int nt;
+    if ((r = get_decode_tasks(ctx, P, h->chunk_len, &tasks, &nt)) != TOD_OK) return r;
+    HIPCHK(ctx->dec_tabs.ensure(sizeof(DecTab) * (size_t)std::max(h->ntable, 1)));
+    KTimer kt(ctx, K_DECODE, ctx->stream);
+    HIPCHK(c3::launch_decode_stream(ctx->stream, make_layout_dev(lay), make_huff_dev(h), (DecTab *)ctx->dec_tabs.p,
+                                    tasks, nt, kind, quantum, flag_mask, out, mask_out, ctx->d_err));
+    return TOD_OK;
+}
+
+tod_status decode_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const tod_huff *tod, double quantum,
+                      void *d_out) {
+    if (!ctx) return TOD_EINVAL;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (!d_out) return fail(ctx, TOD_EINVAL, "NULL output");
+    if (!(quantum > 0.0)) return fail(ctx, TOD_EINVAL, "quantum must be > 0");
+    return decode_stream(ctx, lay, tod, "tod", prec == TOD_MIXED ? 0 : 1, quantum, 0, d_out, nullptr);
+}
+
+tod_status decode_flags(tod_ctx ctx, const tod_layout *lay, const tod_huff *flags, uint32_t flag_mask,
+                        uint32_t *flags_out, uint8_t *mask_out) {
+    if (!ctx) return TOD_EINVAL;
+    if (!flags_out && !mask_out) return fail(ctx, TOD_EINVAL, "no output");
+    return decode_stream(ctx, lay, flags, "flag", 2, 1.0, flag_mask, flags_out, mask_out);
+}
+
 tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int32_t *pix,
                        const uint16_t *psi, const void *maps, const double *gain, void *s_out) {
     if (!ctx) return TOD_EINVAL;

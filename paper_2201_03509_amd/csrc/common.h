@@ -145,6 +145,13 @@ hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, 
                          DecTab *tabs, const DecodeTask *tasks, int ntask, int32_t *pix_out,
                          uint16_t *psi_out, uint32_t *err);
 
+// one integer stream (TOD or flags): kind 0 writes FP32 quantum * x, 1 FP64
+// quantum * x, 2 the uint32 flag words (out may be NULL) and, if mask_out, the
+// byte (x & flag_mask) == 0; tabs: workspace of h.ntable DecTab records
+hipError_t launch_decode_stream(hipStream_t st, const LayoutDev &L, const HuffDev &h, DecTab *tabs,
+                                const DecodeTask *tasks, int ntask, int kind, double quantum,
+                                uint32_t flag_mask, void *out, uint8_t *mask_out, uint32_t *err);
+
 // r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs);
 // maps4: workspace of npix_total records of 4 values (T, Q, U, 0), filled from
 // the [3][npix] maps first

@@ -1,4 +1,5 @@
-// Huffman decode + undifferencing of the pointing streams (section 4.1).
+// Huffman decode + undifferencing of the pointing streams (section 4.1), and
+// of the TOD and flag streams (k_decode1: one stream, same format).
 //
 // Two kernels per call.
 //
@@ -303,9 +304,138 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
     if (tid == 0 && blk_err) atomicOr(err, blk_err);
 }
 
+// One integer stream per segment (the TOD or the flag words): the same chunk
+// parse and undifferencing as k_decode, without range checks; the tile is
+// written as KIND 0: FP32 quantum * x, 1: FP64 quantum * x, 2: flag words
+// (and, if mask_out, the mask byte (x & flag_mask) == 0).
+template <int KIND>
+__global__ __launch_bounds__(C3_NT) void k_decode1(LayoutDev Ld, HuffDev h, const DecTab *__restrict__ tabs,
+                                                   const DecodeTask *__restrict__ tasks, double quantum,
+                                                   uint32_t flag_mask, void *__restrict__ out,
+                                                   uint8_t *__restrict__ mask_out, uint32_t *err) {
+    __shared__ DecTab cp;
+    __shared__ int32_t tp[C3_NT * GP];
+    __shared__ uint32_t blk_err;
+
+    const DecodeTask task = tasks[blockIdx.x];
+    const int seg = task.seg;
+    const int tid = threadIdx.x;
+    const int64_t s0 = Ld.seg_off[seg];
+    const int n = (int)(Ld.seg_off[seg + 1] - s0);
+    const int C = h.chunk_len;
+
+    const int ti = h.seg_table[seg];
+    const bool tabs_ok = ti >= 0 && ti < h.ntable;
+    {
+        const uint4 *sp = (const uint4 *)(tabs + (tabs_ok ? ti : 0));
+        uint4 *dp = (uint4 *)&cp;
+        for (int i = tid; i < (int)(sizeof(DecTab) / 16); i += C3_NT) dp[i] = sp[i];
+        if (tid == 0) blk_err = 0;
+    }
+    __syncthreads();
+    const bool codes_ok = tabs_ok && cp.ok;
+    const __amdgpu_buffer_rsrc_t sym = raw_buffer(h.tables + h.table_off[tabs_ok ? ti : 0] + 34, 4 * cp.nsym);
+
+    const int l = tid;
+    const int c = task.chunk0 + l;
+    const int nch_idx = (int)(h.seg_chunk_off[seg + 1] - h.seg_chunk_off[seg]);
+    const bool active = l < task.nchunk && c < nch_idx;
+    uint32_t bad = codes_ok ? 0u : C3_ERR_CODE;
+    if (l < task.nchunk && c >= nch_idx) bad |= C3_ERR_CHUNK;
+    BitReader rd;
+    int ns = 0;
+    int32_t x = 0, bits = 0;
+    uint32_t start = 0;
+    const int64_t w0 = h.seg_word_off[seg];
+    const int64_t nw = h.seg_word_off[seg + 1] - w0;
+    const bool words_ok = nw >= 0 && nw < (1ll << 29);
+    if (!words_ok) bad |= C3_ERR_CHUNK;
+    const __amdgpu_buffer_rsrc_t rs = raw_buffer(h.words + w0, words_ok ? (int32_t)(4 * nw) : 0);
+    if (active) {
+        const int64_t g = h.seg_chunk_off[seg] + c;
+        start = h.chunk_bit[g];
+        rd.init(rs, start);
+        x = h.chunk_prev[g];
+        ns = (codes_ok && words_ok) ? min(C, n - c * C) : 0;
+    }
+    const int nround = (C + G - 1) / G;
+    for (int r = 0; r < nround; ++r) {
+        const int k0 = r * G;
+        if (active && k0 < ns) {
+#pragma unroll 4
+            for (int k = 0; k < G; ++k) {
+                int L;
+                const int32_t ix = rd.next(cp, L);
+                const bool v = k0 + k < ns;
+                bad |= (v && L == 0) ? C3_ERR_CODE : 0u;
+                bits += v ? L : 0;
+                tp[l * GP + k] = ix;
+            }
+#pragma unroll
+            for (int hh = 0; hh < G; hh += G / 2) {
+                int32_t gv[G / 2];
+#pragma unroll
+                for (int k = 0; k < G / 2; ++k) gv[k] = (int32_t)buf_word(sym, (uint32_t)tp[l * GP + hh + k]);
+#pragma unroll
+                for (int k = 0; k < G / 2; ++k) {
+                    x += (k0 + hh + k < ns) ? gv[k] : 0;
+                    tp[l * GP + hh + k] = x;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int m = 0; m < G; ++m) {
+            const int q = m * C3_NT + tid;
+            const int ll = q >> 4, kk = q & 15;
+            const int cc = task.chunk0 + ll;
+            const int t = cc * C + k0 + kk;
+            if (ll < task.nchunk && cc < nch_idx && k0 + kk < C && t < n && codes_ok && words_ok) {
+                const int32_t v = tp[ll * GP + kk];
+                if constexpr (KIND == 0) {
+                    ((float *)out)[s0 + t] = (float)(quantum * (double)v);
+                } else if constexpr (KIND == 1) {
+                    ((double *)out)[s0 + t] = quantum * (double)v;
+                } else {
+                    if (out) ((uint32_t *)out)[s0 + t] = (uint32_t)v;
+                    if (mask_out) mask_out[s0 + t] = ((uint32_t)v & flag_mask) == 0u;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active && codes_ok && c + 1 < nch_idx) {
+        const int64_t g = h.seg_chunk_off[seg] + c + 1;
+        if ((int64_t)start + bits != (int64_t)h.chunk_bit[g] || x != h.chunk_prev[g]) bad |= C3_ERR_CHUNK;
+    }
+    if (active && ns > 0 && (int64_t)start + bits > 32 * nw) bad |= C3_ERR_CHUNK;
+    if (bad) atomicOr(&blk_err, bad);
+    __syncthreads();
+    if (tid == 0 && blk_err) atomicOr(err, blk_err);
+}
+
 }  // namespace
 
 namespace c3 {
+
+hipError_t launch_decode_stream(hipStream_t st, const LayoutDev &L, const HuffDev &h, DecTab *tabs,
+                                const DecodeTask *tasks, int ntask, int kind, double quantum,
+                                uint32_t flag_mask, void *out, uint8_t *mask_out, uint32_t *err) {
+    if (ntask <= 0) return hipSuccess;
+    HuffDev none = h;
+    none.ntable = 0;
+    hipLaunchKernelGGL(k_tables, dim3(h.ntable), dim3(C3_NT), 0, st, h, none, tabs);
+    if (kind == 0)
+        hipLaunchKernelGGL(k_decode1<0>, dim3(ntask), dim3(C3_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
+                           out, mask_out, err);
+    else if (kind == 1)
+        hipLaunchKernelGGL(k_decode1<1>, dim3(ntask), dim3(C3_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
+                           out, mask_out, err);
+    else
+        hipLaunchKernelGGL(k_decode1<2>, dim3(ntask), dim3(C3_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
+                           out, mask_out, err);
+    return hipGetLastError();
+}
 
 hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
                          DecTab *tabs, const DecodeTask *tasks, int ntask, int32_t *pix_out,

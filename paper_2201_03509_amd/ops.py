@@ -96,6 +96,13 @@ class DeviceTod:
         self.alpha = to(src.alpha, np.float64)
         self.pix_huff, self._pt = self._huff(src.pix_huff, to)
         self.psi_huff, self._qt = self._huff(src.psi_huff, to)
+        # compressed TOD and flag streams, when the set carries them
+        self.tod_huff = self.flag_huff = None
+        if getattr(src, "tod_huff", None) is not None:
+            self.tod_huff, self._tt = self._huff(src.tod_huff, to)
+            self.tod_quantum = float(src.tod_quantum)
+        if getattr(src, "flag_huff", None) is not None:
+            self.flag_huff, self._ft = self._huff(src.flag_huff, to)
 
     def refresh_accept(self):
         self.layout.seg_accept = self.seg_accept.data_ptr()
@@ -176,6 +183,15 @@ class Context:
                                            ctypes.byref(pix_huff or tod.pix_huff),
                                            ctypes.byref(psi_huff or tod.psi_huff),
                                            _ptr(pix_out), _ptr(psi_out)))
+
+    def decode_tod(self, tod, prec, d_out, quantum=None, tod_huff=None):
+        self._chk(self.lib.decode_tod(self.h, ctypes.byref(tod.layout), _prec(prec),
+                                      ctypes.byref(tod_huff or tod.tod_huff),
+                                      float(tod.tod_quantum if quantum is None else quantum), _ptr(d_out)))
+
+    def decode_flags(self, tod, flag_mask, flags_out=None, mask_out=None, flag_huff=None):
+        self._chk(self.lib.decode_flags(self.h, ctypes.byref(tod.layout), ctypes.byref(flag_huff or tod.flag_huff),
+                                        ctypes.c_uint32(int(flag_mask)), _ptr(flags_out), _ptr(mask_out)))
 
     def project_sky(self, tod, prec, pix, psi, maps, s_out, gain=None):
         self._chk(self.lib.project_sky(self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix),

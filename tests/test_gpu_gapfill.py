@@ -114,11 +114,16 @@ def test_unmasked_is_one_step_fourier_draw(ctx, prec):
     s_in = _signal(ts, prec)
     seed, it = synth.seed32(ts.config), 8
     ones = np.ones(ts.nsamp, dtype=np.uint8)
-    # after one step the residual is rounding only: FP32 transforms leave ~1e-7
+    # after one step the residual is rounding only; with FP32 transforms and
+    # vectors it sits near 1e-5 ||b|| (b carries the large high-frequency draw
+    # term), so a second step may follow there
     got, iters = _gpu(ctx, ts, prec, None, s_in, ones, seed, it, tol=1e-5 if prec == "mixed" else 1e-12)
     ref = ot.sample_ncorr_all(ts, ts.d, s_in.astype(np.float64), seed, it)
     assert seg_rel(ts, got, ref) < TOL[prec]
-    assert (iters == 1).all()
+    if prec == "fp64":
+        assert (iters == 1).all()
+    else:
+        assert (iters >= 1).all() and (iters <= 2).all()
 
 
 def test_masked_samples_do_not_matter(ctx):
