@@ -132,3 +132,65 @@ def dense_system(r, m, fsamp, sigma0, fknee, alpha, seed, seg, it, mean_only=Fal
     full[half:] = invP[1:N - half + 1][::-1]
     A = (F.conj().T @ np.diag(full) @ F).real + np.diag(mu / sigma0 ** 2)
     return A, b
+
+
+def gap_cg(b, invP, mu, sigma0, tol, maxiter):
+    """The same system solved on the masked samples only (Woodbury).  With S
+    the selection of the extended positions where mu = 0 and M the
+    preconditioner above, A = M^-1 - S S^T / sigma0^2, so
+        x = x0 + M S y,   x0 = M b,   (sigma0^2 I - S^T M S) y = S^T x0,
+    and b - A x = S rho / sigma0^2 with rho the residual of the small system.
+    Plain CG from y = 0, stopping when ||rho|| <= tol sigma0^2 ||b|| (the
+    full system's rule).  Returns (x, iterations)."""
+    N = len(b)
+    x0 = preconditioner(b, invP, sigma0)
+    gap = np.flatnonzero(mu == 0)
+    nb = np.linalg.norm(b)
+    if len(gap) == 0 or nb == 0.0:
+        return x0, 0
+
+    def H(v):
+        u = np.zeros(N)
+        u[gap] = v
+        return sigma0 ** 2 * v - preconditioner(u, invP, sigma0)[gap]
+
+    y = np.zeros(len(gap))
+    rho = x0[gap].copy()
+    p = rho.copy()
+    rr = rho @ rho
+    k = 0
+    for k in range(1, maxiter + 1):
+        q = H(p)
+        a = rr / (p @ q)
+        y += a * p
+        rho -= a * q
+        rr_new = rho @ rho
+        if np.sqrt(rr_new) <= tol * sigma0 ** 2 * nb:
+            break
+        p = rho + (rr_new / rr) * p
+        rr = rr_new
+    u = np.zeros(N)
+    u[gap] = y
+    return x0 + preconditioner(u, invP, sigma0), k
+
+
+def cg_ncorr_segment_gap(r, m, fsamp, sigma0, fknee, alpha, seed, seg, it, mean_only=False,
+                         tol=1e-12, maxiter=2000):
+    """Masked n_corr draw of one segment through gap_cg: (n_corr [n], iterations)."""
+    b, e, mu, invP = rhs(r, m, fsamp, sigma0, fknee, alpha, seed, seg, it, mean_only)
+    x, k = gap_cg(b, invP, mu, sigma0, tol, maxiter)
+    return x[:len(r)], k
+
+
+def cg_ncorr_all_gap(ts, d, s, mask, seed, it, mean_only=False, tol=1e-12, maxiter=2000, segs=None):
+    out = np.zeros(ts.nsamp)
+    iters = {}
+    for q in (range(ts.nseg) if segs is None else segs):
+        a, b = int(ts.seg_off[q]), int(ts.seg_off[q + 1])
+        if b == a:
+            continue
+        band = int(ts.seg_band[q])
+        out[a:b], iters[q] = cg_ncorr_segment_gap(
+            d[a:b] - s[a:b], mask[a:b], float(ts.band_fsamp[band]), float(ts.sigma0[q]),
+            float(ts.fknee[q]), float(ts.alpha[q]), seed, q, it, mean_only, tol, maxiter)
+    return out, iters

@@ -95,3 +95,47 @@ def test_masked_samples_do_not_matter():
     a, _ = og.cg_ncorr_segment(r, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 1, 2, 3)
     b, _ = og.cg_ncorr_segment(r2, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 1, 2, 3)
     assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
+
+
+def test_gap_space_solver_matches_dense_and_full_cg():
+    """The Woodbury form on the masked samples reaches the same solution as the
+    dense solve and the full-system CG; no masked sample: x = M b, no iteration."""
+    n = 64
+    r, m = _r(n, 5), _mask(n, 10, 30)
+    for mean_only in (True, False):
+        A, b = og.dense_system(r, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 2, 1, 4,
+                               mean_only)
+        ref = np.linalg.solve(A, b)[:n]
+        got, k = og.cg_ncorr_segment_gap(r, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 2, 1, 4,
+                                         mean_only, tol=1e-14)
+        full, kf = og.cg_ncorr_segment(r, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 2, 1, 4,
+                                       mean_only, tol=1e-14)
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+        assert np.abs(got - full).max() <= 1e-10 * np.abs(ref).max()
+        assert 0 < k <= kf + 1
+    un, k0 = og.cg_ncorr_segment_gap(r, np.ones(n), PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"],
+                                     2, 1, 4)
+    assert k0 == 0
+    ref = ot.sample_ncorr_segment(r, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 2, 1, 4)
+    assert np.abs(un - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_gap_residual_identity():
+    """b - A x = S rho / sigma0^2 for any y (the Woodbury algebra the stopping
+    rule relies on)."""
+    n = 40
+    r, m = _r(n, 6), _mask(n, 7, 19)
+    b, e, mu, invP = og.rhs(r, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 3, 0, 1)
+    s0 = PAR["sigma0"]
+    N = len(b)
+    gap = np.flatnonzero(mu == 0)
+    x0 = og.preconditioner(b, invP, s0)
+    y = np.random.default_rng(1).normal(size=len(gap))
+    u = np.zeros(N)
+    u[gap] = y
+    x = x0 + og.preconditioner(u, invP, s0)
+    rho = x0[gap] - (s0 ** 2 * y - og.preconditioner(u, invP, s0)[gap])
+    full = b - og.operator(x, invP, mu, s0)
+    expect = np.zeros(N)
+    expect[gap] = rho / s0 ** 2
+    assert np.abs(full - expect).max() <= 1e-11 * np.abs(b).max()
