@@ -237,23 +237,25 @@ tod_status sample_noise(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
  * realisation needs FFTs inside a CG solver where scans cross masked sky,
  * section 5 and the correlated-noise row of Table 2).  On the extension and
  * spectrum of sample_ncorr, with mu = [m, reverse(m), 1 ...] the extended mask
- * and F the unitary DFT, each segment solves A x = b by preconditioned CG:
+ * and F the unitary DFT, each segment's draw is x[0:n], x = A^-1 b:
  *   A = F^H diag(1/P) F + diag(mu)/sigma0^2,
- *   b = mu (e/sigma0^2 + F^H W1/sigma0) + F^H (W2 P^-1/2)   (W as sample_ncorr),
- *   preconditioner F^H diag(1/(1/sigma0^2 + 1/P)) F, start x = 0, stop when
- *   ||b - A x|| <= tol ||b|| or after max_iter iterations;  n_corr = x[0:n].
- * With nothing masked the first iteration returns sample_ncorr's draw.
- * mask: device [nsamp] uint8, nonzero = sample used.  FFTs and the stored
- * CG vectors use the precision's type; element updates, dot products and the
- * scalar recurrences are FP64, so the recursively updated residual keeps
- * falling in the mixed precision too, where FP32 rounding puts a floor of a
- * few 1e-6 (relative) under the solution's error.  ||b|| is dominated by the
- * high-frequency draw term, so tol must sit well below the wanted solution
- * accuracy (1e-8 reaches the FP32 floor).
+ *   b = mu (e/sigma0^2 + F^H W1/sigma0) + F^H (W2 P^-1/2)   (W as sample_ncorr).
+ * Solver: with M = F^H diag(1/(1/sigma0^2 + 1/P)) F and S the masked extended
+ * positions, x = x0 + M S y, x0 = M b, (sigma0^2 I - S^T M S) y = S^T x0
+ * (Woodbury), by CG from y = 0 on the masked positions only; it stops when
+ * the residual (b - A x, which lives on the masked positions) has fallen to
+ * tol times its value at x0, or after max_iter iterations.  With nothing
+ * masked x = x0 is sample_ncorr's draw and no iteration runs.
+ * mask: device [nsamp] uint8, nonzero = sample used (decode_flags writes
+ * one).  Transforms and full-length vectors use the precision's type; the
+ * masked-position vectors, every sum and the recurrences are FP64; x0's
+ * drawn term is added per Fourier mode.  tol 1e-6 reaches the FP32 floor
+ * (about 1e-6 relative).
  * iters_out: device [nseg] int32 (may be NULL): iterations per segment,
- * negated where max_iter stopped it first (0: b = 0 or empty segment).
- * Workspace: four sweep-wide vectors of the extended length in the
- * precision's type, held by the context. */
+ * negated where max_iter stopped it first (0: nothing masked).
+ * Workspace (context): four sweep-wide vectors of the extended length in
+ * the precision's type, and per masked extended position an index and three
+ * FP64 values. */
 tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                                const void *d, tod_dtype d_dtype, const void *s,
                                const uint8_t *mask,

@@ -140,13 +140,13 @@ def gap_cg(b, invP, mu, sigma0, tol, maxiter):
     preconditioner above, A = M^-1 - S S^T / sigma0^2, so
         x = x0 + M S y,   x0 = M b,   (sigma0^2 I - S^T M S) y = S^T x0,
     and b - A x = S rho / sigma0^2 with rho the residual of the small system.
-    Plain CG from y = 0, stopping when ||rho|| <= tol sigma0^2 ||b|| (the
-    full system's rule).  Returns (x, iterations)."""
+    Plain CG from y = 0 (x = x0), stopping when ||rho|| <= tol ||rho_0||: the
+    full residual, which lives on the masked samples, has fallen by tol from
+    its value at x0.  Returns (x, iterations)."""
     N = len(b)
     x0 = preconditioner(b, invP, sigma0)
     gap = np.flatnonzero(mu == 0)
-    nb = np.linalg.norm(b)
-    if len(gap) == 0 or nb == 0.0:
+    if len(gap) == 0:
         return x0, 0
 
     def H(v):
@@ -159,13 +159,16 @@ def gap_cg(b, invP, mu, sigma0, tol, maxiter):
     p = rho.copy()
     rr = rho @ rho
     k = 0
+    stop = tol * np.sqrt(rr)
+    if rr == 0.0:  # x0 is the solution
+        return x0, 0
     for k in range(1, maxiter + 1):
         q = H(p)
         a = rr / (p @ q)
         y += a * p
         rho -= a * q
         rr_new = rho @ rho
-        if np.sqrt(rr_new) <= tol * sigma0 ** 2 * nb:
+        if np.sqrt(rr_new) <= stop:
             break
         p = rho + (rr_new / rr) * p
         rr = rr_new

@@ -129,7 +129,8 @@ struct tod_ctx_s {
     // masked n_corr solver: Krylov vectors and the transform output (the
     // precision's type), partial sums, per-segment state, active flags and the
     // active-segment count
-    DevBuf cg_x, cg_res, cg_p, cg_fout, cg_part, cg_state, cg_act, cg_count;
+    DevBuf cg_x, cg_res, cg_fin, cg_fout, cg_part, cg_state, cg_act, cg_count, cg_has_gap;
+    DevBuf cg_cnt, cg_base, cg_gap_idx, cg_y, cg_rho, cg_p, cg_gap_tiles, cg_seg_gap_tiles;
     // gain draw: filtered template and data (per sample), per-tile partial sums
     DevBuf gain_kt, gain_kd, gain_part;
     // noise-parameter draw: periodogram bins per segment, white-residual partials
@@ -886,9 +887,10 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     const size_t NR = 2 * (size_t)P->ext_elems + 64, esz = mixed ? 4 : 8;
     HIPCHK(ctx->cg_x.ensure(NR * esz));
     HIPCHK(ctx->cg_res.ensure(NR * esz));
-    HIPCHK(ctx->cg_p.ensure(NR * esz));
+    HIPCHK(ctx->cg_fin.ensure(NR * esz));
     HIPCHK(ctx->cg_fout.ensure(NR * esz));
-    HIPCHK(ctx->cg_part.ensure((size_t)P->ncg * 8 + 64));
+    HIPCHK(ctx->cg_cnt.ensure((size_t)P->ncg * 4 + 64));
+    HIPCHK(ctx->cg_base.ensure((size_t)P->ncg * 8 + 64));
     HIPCHK(ctx->cg_state.ensure((size_t)nseg * sizeof(c3::CgState) + 64));
     HIPCHK(ctx->cg_act.ensure((size_t)nseg * 4 + 64));
     HIPCHK(ctx->cg_count.ensure(64));
@@ -896,24 +898,30 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
     int32_t *act = (int32_t *)ctx->cg_act.p, *count = (int32_t *)ctx->cg_count.p;
     c3::CgState *cs = (c3::CgState *)ctx->cg_state.p;
-    const int2 *seg_tiles = (const int2 *)P->cg_seg_tiles.p;
-    double *part = (double *)ctx->cg_part.p;
     const double tol2 = tol * tol;
+    auto fin = [&](int step, const int2 *seg_tiles) -> hipError_t {
+        KTimer kt(ctx, K_CG, st);
+        return c3::launch_cg_finish(st, nseg, seg_tiles, (const double *)ctx->cg_part.p, cs, act, step, tol2,
+                                    max_iter, count);
+    };
+    auto vec = [&](int op, const c3::CgVecArgs &va) -> hipError_t {
+        KTimer kt(ctx, K_CG, st);
+        return c3::launch_cg_vec(st, mixed, op, va);
+    };
+    HIPCHK(ctx->cg_part.ensure((size_t)P->ncg * 8 + 64));
 
     c3::FftArgs a = fft_args(ctx, P, lay);
     a.sigma0 = sigma0;
     a.fknee = fknee;
     a.alpha = alpha;
     a.full_io = 1;
-    if (!mean_only) {  // F^H W1 -> fout, F^H (W2 sqrt(1/P)) -> res: rows and inverse columns only
+    if (!mean_only) {  // F^H W1 -> fout: rows and inverse columns only
         a.mode = 3;
         a.which = 0;
         a.out = ctx->cg_fout.p;
         if ((r = run_fft(ctx, st, P, mixed, a, 3, 1)) != TOD_OK) return r;
-        a.which = 1;
-        a.out = ctx->cg_res.p;
-        if ((r = run_fft(ctx, st, P, mixed, a, 3, 1)) != TOD_OK) return r;
     }
+    // mu u -> res
     c3::CgVecArgs v;
     memset(&v, 0, sizeof(v));
     v.tiles = (const int4 *)P->cg_tiles.p;
@@ -931,52 +939,120 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     v.have_draw = !mean_only;
     v.x = ctx->cg_x.p;
     v.res = ctx->cg_res.p;
-    v.p = ctx->cg_p.p;
+    v.fin = ctx->cg_fin.p;
     v.fout = ctx->cg_fout.p;
-    v.part = part;
-    // b, x = 0, res = b; then z = M b, rz = res . z, p = z
-    auto vec = [&](int op, const c3::CgVecArgs &va) -> hipError_t {
-        KTimer kt(ctx, K_CG, st);
-        return c3::launch_cg_vec(st, mixed, op, va);
-    };
-    auto fin = [&](int step) -> hipError_t {
-        KTimer kt(ctx, K_CG, st);
-        return c3::launch_cg_finish(st, nseg, seg_tiles, part, cs, act, step, tol2, max_iter, count);
-    };
+    v.part = (double *)ctx->cg_part.p;
     HIPCHK(vec(c3::CG_OP_INIT, v));
-    HIPCHK(fin(c3::CG_INIT));
+    // x0 = M b = M (mu u) + M F^H (W2 sqrt(1/P)) over every segment
     a.mode = 2;
+    a.which = 3;
+    a.mean_only = mean_only;
+    a.in_a = ctx->cg_res.p;
     a.in_a_f64 = !mixed;
+    a.out = ctx->cg_x.p;
+    if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
+
+    // the masked extended positions: counts per extended tile, their offsets
+    // and the gap tiles laid out on the host, indices filled on the device
+    v.cnt = (int32_t *)ctx->cg_cnt.p;
+    HIPCHK(vec(c3::CG_OP_GAP_COUNT, v));
+    std::vector<int32_t> cnt(P->ncg);
+    if (P->ncg) {
+        HIPCHK(hipMemcpyAsync(cnt.data(), ctx->cg_cnt.p, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    std::vector<int64_t> base(P->ncg);
+    {
+        int64_t acc = 0;
+        for (int t = 0; t < P->ncg; ++t) {
+            base[t] = acc;
+            acc += cnt[t];
+        }
+    }
+    std::vector<int4> gt;
+    std::vector<int2> seg_gt(nseg, make_int2(0, 0));
+    std::vector<int32_t> has_gap(nseg, 0);
+    int64_t total = 0;
+    {
+        // extended tiles are laid out segment by segment (cg_tiles), so a
+        // segment's masked entries are contiguous from base[first tile]
+        int t = 0;
+        for (int sgi = 0; sgi < nseg; ++sgi) {
+            const SegInfo &g = P->h_segs[sgi];
+            if (g.plan < 0) continue;
+            const int64_t N = 2 * (int64_t)P->h_plans[g.plan].M;
+            const int nt = (int)((N + C3_CG_TILE - 1) / C3_CG_TILE);
+            int64_t m = 0;
+            for (int k = 0; k < nt; ++k) m += cnt[t + k];
+            const int64_t j0 = nt ? base[t] : 0;
+            t += nt;
+            seg_gt[sgi].x = (int)gt.size();
+            for (int64_t o = 0; o < m; o += C3_CG_TILE) {
+                const int64_t j = j0 + o;
+                gt.push_back(make_int4(sgi, (int)(j & 0x7FFFFFFF), (int)std::min<int64_t>(C3_CG_TILE, m - o),
+                                       (int)(j >> 31)));
+            }
+            seg_gt[sgi].y = (int)gt.size() - seg_gt[sgi].x;
+            has_gap[sgi] = m > 0;
+            total += m;
+        }
+        if (t != P->ncg) return fail(ctx, TOD_EHIP, "extended tile layout mismatch");
+    }
+    if (gt.size() > (size_t)INT32_MAX / 2) return fail(ctx, TOD_ENOTSUP, "too many masked samples");
+    HIPCHK(ctx->cg_gap_idx.ensure((size_t)total * 8 + 64));
+    HIPCHK(ctx->cg_y.ensure((size_t)total * 8 + 64));
+    HIPCHK(ctx->cg_rho.ensure((size_t)total * 8 + 64));
+    HIPCHK(ctx->cg_p.ensure((size_t)total * 8 + 64));
+    HIPCHK(ctx->cg_part.ensure(std::max<size_t>(P->ncg, gt.size()) * 8 + 64));
+    v.part = (double *)ctx->cg_part.p;
+    HIPCHK(ctx->cg_gap_tiles.upload(gt, st));
+    HIPCHK(ctx->cg_seg_gap_tiles.upload(seg_gt, st));
+    HIPCHK(ctx->cg_base.upload(base, st));
+    HIPCHK(ctx->cg_has_gap.upload(has_gap, st));
+    v.gap_base = (const int64_t *)ctx->cg_base.p;
+    v.gap_idx = (int64_t *)ctx->cg_gap_idx.p;
+    HIPCHK(vec(c3::CG_OP_GAP_FILL, v));
+    HIPCHK(c3::launch_cg_zero(st, mixed, ctx->cg_fin.p, (int64_t)(2 * P->ext_elems)));
+
+    // CG on the masked positions
+    c3::CgVecArgs gv = v;
+    gv.tiles = (const int4 *)ctx->cg_gap_tiles.p;
+    gv.ntile = (int)gt.size();
+    gv.y = (double *)ctx->cg_y.p;
+    gv.rho = (double *)ctx->cg_rho.p;
+    gv.p = (double *)ctx->cg_p.p;
+    const int2 *gseg = (const int2 *)ctx->cg_seg_gap_tiles.p;
+    HIPCHK(vec(c3::CG_OP_GAP_START, gv));
+    HIPCHK(fin(c3::CG_RZ0, gseg));
+    gv.scatter_src = gv.p;
+    HIPCHK(vec(c3::CG_OP_GAP_SCATTER, gv));
+    a.which = 1;  // M
+    a.in_a = ctx->cg_fin.p;
     a.out = ctx->cg_fout.p;
     a.active = act;
-    a.in_a = ctx->cg_res.p;
-    a.which = 1;
-    if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
-    HIPCHK(vec(c3::CG_OP_RZ, v));
-    HIPCHK(fin(c3::CG_RZ0));
-    HIPCHK(vec(c3::CG_OP_P, v));
     for (int it = 1; it <= max_iter; ++it) {
-        a.in_a = ctx->cg_p.p;  // F^H diag(1/P) F p
-        a.which = 0;
-        if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
-        HIPCHK(vec(c3::CG_OP_PAP, v));
-        HIPCHK(fin(c3::CG_ALPHA));
-        HIPCHK(vec(c3::CG_OP_XR, v));
-        HIPCHK(fin(c3::CG_RES));
+        if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;  // M S p
+        HIPCHK(vec(c3::CG_OP_GAP_PQ, gv));
+        HIPCHK(fin(c3::CG_ALPHA, gseg));
+        HIPCHK(vec(c3::CG_OP_GAP_UPDATE, gv));
+        HIPCHK(fin(c3::CG_RES, gseg));
         int32_t h = 0;
         HIPCHK(hipMemcpyAsync(&h, count, sizeof(h), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (h == 0) break;
-        a.in_a = ctx->cg_res.p;  // z = M res
-        a.which = 1;
-        if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
-        HIPCHK(vec(c3::CG_OP_RZ, v));
-        HIPCHK(fin(c3::CG_BETA));
-        HIPCHK(vec(c3::CG_OP_P, v));
+        HIPCHK(vec(c3::CG_OP_GAP_DIR, gv));
     }
+    // x = x0 + M S y where the segment has masked samples
+    c3::CgVecArgs fv = gv;
+    fv.act = nullptr;
+    fv.scatter_src = gv.y;
+    HIPCHK(vec(c3::CG_OP_GAP_SCATTER, fv));
+    a.active = (const int32_t *)ctx->cg_has_gap.p;
+    if ((r = run_fft(ctx, st, P, mixed, a, 3)) != TOD_OK) return r;
     c3::CgVecArgs c = v;
     c.tiles = (const int4 *)P->sample_tiles.p;
     c.ntile = P->nsample_tiles;
+    c.has_gap = (const int32_t *)ctx->cg_has_gap.p;
     c.out = ncorr_out;
     HIPCHK(vec(c3::CG_OP_CROP, c));
     if (iters_out) HIPCHK(c3::launch_cg_iters(st, nseg, cs, iters_out));

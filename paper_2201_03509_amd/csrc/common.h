@@ -186,7 +186,8 @@ struct FftArgs {
                                 //    (N reals per segment at real offset 2 ext_off of
                                 //    in_a / out) instead of the mirrored segment / its crop
     int which;                  // mode 2: filter 0: 1/P, 1: 1/(1/sigma0^2 + 1/P),
-                                //         2: 1/(sigma0^2 + P);
+                                //         2: 1/(sigma0^2 + P), 3: as 1 plus the drawn
+                                //         term (1/(1/sigma0^2 + 1/P)) W2 sqrt(1/P);
                                 // mode 3: 0 spectrum W1, 1 spectrum W2 sqrt(1/P)
     const int32_t *active;      // per segment, 0: skip (NULL: every segment runs)
     double *bins;               // mode 4: periodogram bins [nseg][C3_XI_NBIN], added to
@@ -234,22 +235,33 @@ hipError_t launch_chisq_finish(hipStream_t st, const LayoutDev &L, const double 
 hipError_t launch_set_u64(hipStream_t st, uint64_t *p, uint64_t a, uint64_t b);
 
 // ---- masked n_corr draw (gapfill.hip): per-segment CG state and vector passes
-#define C3_CG_TILE 4096      // reals of a segment's extended vector per elementwise tile
+#define C3_CG_TILE 4096      // entries per elementwise tile (extended reals or gap entries)
 struct CgState {
-    double rz;       // res . z of the current residual
-    double bb;       // b . b
+    double rz;       // unused (kept for layout)
+    double bb;       // rho_0 . rho_0: the stopping rule's reference
     double alpha, beta;
-    double rr;       // res . res after the last update
+    double rr;       // rho . rho of the current residual
     int32_t iters;   // CG iterations done
     int32_t converged;
 };
-enum CgStep { CG_INIT = 0, CG_RZ0, CG_ALPHA, CG_RES, CG_BETA };
-enum CgOp { CG_OP_INIT = 0, CG_OP_PAP, CG_OP_XR, CG_OP_RZ, CG_OP_P, CG_OP_CROP };
+enum CgStep { CG_RZ0 = 0, CG_ALPHA, CG_RES };
+enum CgOp {
+    CG_OP_INIT = 0,     // mu u -> res (b without its F^H W2 term)     (extended tiles)
+    CG_OP_GAP_COUNT,    // masked positions per extended tile -> cnt  (extended tiles)
+    CG_OP_GAP_FILL,     // their global extended indices -> gap_idx   (extended tiles)
+    CG_OP_GAP_START,    // y = 0, rho = p = x0[gap], partial rho.rho  (gap tiles)
+    CG_OP_GAP_SCATTER,  // fin[gap] = scatter_src                     (gap tiles)
+    CG_OP_GAP_PQ,       // partial p.q, q = sigma0^2 p - fout[gap]    (gap tiles)
+    CG_OP_GAP_UPDATE,   // y += alpha p, rho -= alpha q, partial rho.rho (gap tiles)
+    CG_OP_GAP_DIR,      // p = rho + beta p, fin[gap] = p             (gap tiles)
+    CG_OP_CROP          // out = (x0 + fout)[0:n]                     (sample tiles)
+};
 struct CgVecArgs {
-    const int4 *tiles;          // (seg, first extended index, length, 0); CROP: sample tiles
-    int ntile;
+    const int4 *tiles;          // extended tiles (seg, first real, length, 0), gap tiles
+    int ntile;                  // (seg, first entry low 31 bits, length, high bits) or
+                                // sample tiles, by operation
     const SegInfo *segs;
-    const int32_t *act;
+    const int32_t *act;         // per segment: still iterating
     const CgState *cs;
     const void *d;              // INIT: residual d - s and the mask (per sample)
     int d_f64;
@@ -257,14 +269,24 @@ struct CgVecArgs {
     int s_f64;
     const uint8_t *mask;        // 1: sample used, 0: masked
     const double *sigma0;
-    const void *w1;             // INIT: F^H W1 (F^H (W2 sqrt(1/P)) arrives in res)
-    int have_draw;              // INIT: 0 for the mean only (w1 and res not read)
-    void *x, *res, *p;          // Krylov vectors, transform type (sweep-wide, 2 ext_off per segment)
-    const void *fout;           // FFT output vector
+    const void *w1;             // INIT: F^H W1
+    int have_draw;              // INIT: 0 for the mean only (w1 not read)
+    void *x;                    // full vectors, transform type: x0 = M b
+    void *res;                  //   mu u = mu (e / sigma0^2 + F^H W1 / sigma0)
+    void *fin;                  //   FFT input: zero but at the masked positions
+    const void *fout;           //   FFT output
+    int32_t *cnt;               // masked positions per extended tile
+    const int64_t *gap_base;    // their first entry in gap_idx
+    int64_t *gap_idx;           // global extended index of every masked position
+    double *y, *rho, *p;        // small system (FP64)
+    const double *scatter_src;  // GAP_SCATTER source
+    const int32_t *has_gap;     // CROP: segment has masked samples
     double *part;               // per-tile partial sums
     void *out;                  // CROP: n_corr per sample
 };
 hipError_t launch_cg_vec(hipStream_t st, int mixed, int op, const CgVecArgs &a);
+// zero n elements of a vector of the transform type (a fill kernel)
+hipError_t launch_cg_zero(hipStream_t st, int mixed, void *v, int64_t n);
 // step: see CgStep; the CG_RES step counts still-active segments into *nactive
 // (zeroed by the CG_ALPHA step of the same iteration)
 hipError_t launch_cg_finish(hipStream_t st, int nseg, const int2 *seg_tiles, const double *part, CgState *cs,

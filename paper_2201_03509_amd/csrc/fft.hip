@@ -459,6 +459,22 @@ __device__ __forceinline__ cx<T> draw_mode(const ModeCtx &mc, int64_t k, int whi
     return W;
 }
 
+// x0 = M b of the masked draw without b's large drawn term in the time
+// domain: M (mu u) from the transformed input plus M F^H (W2 sqrt(1/P)) added
+// per mode, h1 W2 sqrt(q) / sigma0 with h1 = sigma0^2 / (1 + q) (which = 3)
+template <typename T>
+__device__ __forceinline__ cx<T> x0_mode(const ModeCtx &mc, int64_t k, cx<T> E) {
+    cx<T> v = filt_mode(mc, k, E, 1);
+    if (!mc.mean_only) {
+        const T q = q_of<T>(mc, k);
+        const T h1 = (T)(mc.sigma0 * mc.sigma0) / ((T)1 + q);
+        const cx<T> w = draw_mode<T>(mc, k, 1);
+        v.x += h1 * w.x;
+        v.y += h1 * w.y;
+    }
+    return v;
+}
+
 // Whittle sums for one mode k >= 1
 struct Wsum {
     double a, b, c;  // sum(I/P + ln P), sum(1 - I/P), sum((1 - I/P) ln(f/fknee))
@@ -586,8 +602,8 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
                     n0 = cr_mode(mc, 0, E0);
                     nM = cr_mode(mc, M, EM);
                 } else if constexpr (MODE == 2) {
-                    n0 = filt_mode(mc, 0, E0, a.which);
-                    nM = filt_mode(mc, M, EM, a.which);
+                    n0 = a.which == 3 ? x0_mode(mc, 0, E0) : filt_mode(mc, 0, E0, a.which);
+                    nM = a.which == 3 ? x0_mode(mc, M, EM) : filt_mode(mc, M, EM, a.which);
                 } else {
                     n0 = draw_mode<T>(mc, 0, a.which);
                     nM = draw_mode<T>(mc, M, a.which);
@@ -615,8 +631,13 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
                 nk = cr_mode(mc, k, Ek);
                 np = (kp == k) ? nk : cr_mode(mc, kp, Ep);
             } else if constexpr (MODE == 2) {
-                nk = filt_mode(mc, k, Ek, a.which);
-                np = (kp == k) ? nk : filt_mode(mc, kp, Ep, a.which);
+                if (a.which == 3) {
+                    nk = x0_mode(mc, k, Ek);
+                    np = (kp == k) ? nk : x0_mode(mc, kp, Ep);
+                } else {
+                    nk = filt_mode(mc, k, Ek, a.which);
+                    np = (kp == k) ? nk : filt_mode(mc, kp, Ep, a.which);
+                }
             } else {
                 nk = draw_mode<T>(mc, k, a.which);
                 np = (kp == k) ? nk : draw_mode<T>(mc, kp, a.which);

@@ -1,20 +1,23 @@
 """Masked correlated-noise draw (CG gap filling) on the GPU vs the oracle's CG,
 through the C-ABI.
 
+The GPU solves the system in its gap-space (Woodbury) form, CG on the masked
+positions only; the reference is the oracle's restatement of that form
+(`gap_cg`), itself pinned against the dense solve and the full-system CG.
+
 Inputs: the small synthetic sets of the parity suite with a processing mask
 that removes a band of +-10 degrees around the map frame's equator (about 11%
 of the samples, in long gaps crossed twice per spin period).
 
-Tolerances.  The oracle runs to ||res|| <= 1e-13 ||b||; the FP64 path is asked
-for the same, so both sit within cond(A) x 1e-13 of the exact solution and the
-spec FP64 bar (1e-12 relative per segment) applies.  The mixed path
-applies A and the preconditioner with FP32 transforms (relative error about
-1e-7 per product) while its Krylov vectors and sums stay FP64; it is held to
-the FP32 bar (1e-5 relative per segment) and asked for tol 1e-8.  The stopping
-rule measures the residual against ||b||, which the right-hand side's
-high-frequency draw term F^H(W2 P^-1/2) dominates: at tol 1e-7 CG can stop
-with the solution still ~1e-5 off, in FP64 arithmetic too; at 1e-8 the FP32
-transforms set the floor (a few 1e-6 in a float32 emulation of the solver).
+Tolerances.  The stopping rule is relative: CG ends when the residual has
+fallen by tol from its value at x0 = M b.  The oracle runs to 1e-13; the FP64
+path is asked for the same and held to the spec FP64 bar (1e-12
+relative per segment).  The mixed path applies M with FP32 transforms while
+the small system's vectors and every sum stay FP64; it is asked for 1e-6 and
+held to the FP32 bar (1e-5 relative per segment).  x0's drawn term
+F^H(W2 P^-1/2), large at high frequencies, is added per mode and never
+rounded to FP32 in the time domain: a float32 emulation of the solver gave
+2.6e-7 this way against 7.7e-6 with b rounded in the time domain.
 """
 import numpy as np
 import pytest
@@ -27,7 +30,7 @@ from oracle import tod as ot
 pytestmark = pytest.mark.gpu
 
 TOL = {"mixed": 1e-5, "fp64": 1e-12}
-CG_TOL = {"mixed": 1e-8, "fp64": 1e-13}
+CG_TOL = {"mixed": 1e-6, "fp64": 1e-13}
 ORACLE_TOL = 1e-13
 
 _CASES = {
@@ -93,8 +96,8 @@ def test_masked_draw(ctx, name, prec, mean_only):
     ts, mask = dataset(name)
     s_in = _signal(ts, prec)
     seed, it = synth.seed32(ts.config), 5
-    ref, ref_it = og.cg_ncorr_all(ts, ts.d, s_in.astype(np.float64), mask, seed, it,
-                                  mean_only=mean_only, tol=ORACLE_TOL)
+    ref, ref_it = og.cg_ncorr_all_gap(ts, ts.d, s_in.astype(np.float64), mask, seed, it,
+                                      mean_only=mean_only, tol=ORACLE_TOL)
     got, iters = _gpu(ctx, ts, prec, None, s_in, mask, seed, it, mean_only)
     err = seg_rel(ts, got, ref)
     print("%s %s mean_only=%s: max segment rel L2 %.3e, iterations %d..%d" % (
@@ -107,23 +110,17 @@ def test_masked_draw(ctx, name, prec, mean_only):
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_unmasked_is_one_step_fourier_draw(ctx, prec):
-    """With nothing masked the preconditioner is A^-1: one iteration returns the
-    unmasked constrained realisation (the same Philox modes)."""
+def test_unmasked_is_the_fourier_draw(ctx, prec):
+    """With nothing masked A^-1 = M: x = M b is the unmasked constrained
+    realisation (the same Philox modes), with no CG iteration."""
     ts, _ = dataset("lfi30_small")
     s_in = _signal(ts, prec)
     seed, it = synth.seed32(ts.config), 8
     ones = np.ones(ts.nsamp, dtype=np.uint8)
-    # after one step the residual is rounding only; with FP32 transforms and
-    # vectors it sits near 1e-5 ||b|| (b carries the large high-frequency draw
-    # term), so a second step may follow there
-    got, iters = _gpu(ctx, ts, prec, None, s_in, ones, seed, it, tol=1e-5 if prec == "mixed" else 1e-12)
+    got, iters = _gpu(ctx, ts, prec, None, s_in, ones, seed, it)
     ref = ot.sample_ncorr_all(ts, ts.d, s_in.astype(np.float64), seed, it)
     assert seg_rel(ts, got, ref) < TOL[prec]
-    if prec == "fp64":
-        assert (iters == 1).all()
-    else:
-        assert (iters >= 1).all() and (iters <= 2).all()
+    assert (iters == 0).all()
 
 
 def test_masked_samples_do_not_matter(ctx):
@@ -144,7 +141,7 @@ def test_max_iter_stops_with_the_oracle_iterate(ctx):
     ts, mask = dataset("tiny")
     s_in = _signal(ts, "fp64")
     seed, it = 3, 1
-    ref, _ = og.cg_ncorr_all(ts, ts.d, s_in, mask, seed, it, tol=0.0, maxiter=3)
+    ref, _ = og.cg_ncorr_all_gap(ts, ts.d, s_in, mask, seed, it, tol=0.0, maxiter=3)
     got, iters = _gpu(ctx, ts, "fp64", None, s_in, mask, seed, it, tol=0.0, max_iter=3)
     assert (iters == -3).all()
     assert seg_rel(ts, got, ref) < TOL["fp64"]
@@ -159,7 +156,9 @@ def test_fully_masked_segment(ctx):
     mask[a:b] = 0
     s_in = _signal(ts, "fp64")
     seed, it = 9, 4
-    ref, _ = og.cg_ncorr_all(ts, ts.d, s_in, mask, seed, it, tol=ORACLE_TOL)
+    ref, _ = og.cg_ncorr_all_gap(ts, ts.d, s_in, mask, seed, it, tol=ORACLE_TOL)
+    full, _ = og.cg_ncorr_all(ts, ts.d, s_in, mask, seed, it, tol=ORACLE_TOL)
     got, iters = _gpu(ctx, ts, "fp64", None, s_in, mask, seed, it)
     assert (iters > 0).all()
+    assert seg_rel(ts, got, full) < 1e-10  # the full-system CG reaches the same draw
     assert seg_rel(ts, got, ref) < TOL["fp64"]
