@@ -372,6 +372,8 @@ def main():
     ap.add_argument("--no-masked", action="store_true", help="skip the masked n_corr draw leg")
     ap.add_argument("--no-gain", action="store_true", help="skip the gain draw leg")
     ap.add_argument("--no-noise", action="store_true", help="skip the noise-parameter draw leg")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the sweep: no stream, gain, noise or masked-draw legs (profiling runs)")
     ap.add_argument("--fft-batch", type=int, default=None,
                     help="complex elements per FFT batch (0 = all segments at once)")
     ap.add_argument("--bin-stride", type=int, default=None, help="override the binning stride")
@@ -380,6 +382,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.sweep_only:
+        args.no_gain = args.no_noise = args.no_masked = True
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -520,12 +524,13 @@ def main():
         del t_unit
         torch.cuda.empty_cache()
 
-    streams, flag_mask = stream_leg(ctx, ts, tod)
-    masked = None
-    if not args.no_masked:
-        masked = masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix, flag_mask)
-    del flag_mask
-    torch.cuda.empty_cache()
+    streams = masked = None
+    if not args.sweep_only:
+        streams, flag_mask = stream_leg(ctx, ts, tod)
+        if not args.no_masked:
+            masked = masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix, flag_mask)
+        del flag_mask
+        torch.cuda.empty_cache()
 
     copy = None
     if args.copy_probe:
