@@ -32,8 +32,17 @@
  *   returns as TOD_ECORRUPT; it stays set until tod_clear_error().
  *   tod_last_error() describes the last failure.
  * Precision: TOD_MIXED runs projection, residuals, FFTs and draws in FP32
- *   and keeps per-pixel accumulation and the 3x3 solve in FP64;
- *   TOD_PLAIN_FP64 runs everything in FP64 (the TOD d may still be FP32).
+ *   and keeps per-pixel accumulation and the 3x3 solve in FP64, as it keeps
+ *   every per-segment sum and scalar recurrence of the gain, noise and masked
+ *   draws; TOD_PLAIN_FP64 runs everything in FP64 (the TOD d may still be
+ *   FP32).
+ *
+ * Entry points by Gibbs step: decode_pointing, decode_tod, decode_flags
+ * (compressed data, section 4.1); project_sky (Eq. 1); sample_gain (Eq. 3);
+ * sample_ncorr and sample_ncorr_masked (Eq. 4); sample_noise (Eq. 5);
+ * bin_tod and solve_maps (binning, section 2.4); tod_chisq and
+ * tod_chisq_backward (the likelihood and its adjoint); tod_sweep (decode,
+ * projection, n_corr draw and binning fused for one Gibbs iteration).
  */
 #ifndef C3TOD_H
 #define C3TOD_H

@@ -237,7 +237,6 @@ hipError_t launch_set_u64(hipStream_t st, uint64_t *p, uint64_t a, uint64_t b);
 // ---- masked n_corr draw (gapfill.hip): per-segment CG state and vector passes
 #define C3_CG_TILE 4096      // entries per elementwise tile (extended reals or gap entries)
 struct CgState {
-    double rz;       // unused (kept for layout)
     double bb;       // rho_0 . rho_0: the stopping rule's reference
     double alpha, beta;
     double rr;       // rho . rho of the current residual

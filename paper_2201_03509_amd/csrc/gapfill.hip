@@ -259,7 +259,7 @@ __global__ __launch_bounds__(C3_NT) void k_cg_finish(int nseg, const int2 *__res
     CgState c = cs[seg];
     switch (step) {
     case CG_RZ0:  // v = rho . rho at y = 0 (gap tiles; none: nothing masked)
-        c.rz = c.alpha = c.beta = 0;
+        c.alpha = c.beta = 0;
         c.rr = c.bb = v;
         c.iters = 0;
         c.converged = (tr.y == 0 || v == 0.0) ? 1 : 0;  // x0 is the solution
