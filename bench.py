@@ -159,19 +159,31 @@ def _oracle_next(q):
     s = ot.project(maps32, gp, psi, ts.gain[q])
     r = ts.d[a:a + n].astype(np.float64) - s
     m = synth.plane_mask_pixels(int(ts.band_nside[band]), pix)
+    sec = {}
+    c0 = time.perf_counter()
     nc, k = og.cg_ncorr_segment(r, m, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q], ts.alpha[q],
                                 seed, q, MASKED_IT, tol=1e-12)
+    sec["masked"] = time.perf_counter() - c0
     from oracle import gain as ogain
     from oracle import noise as onoise
     t = ot.project(maps32, gp, psi, 1.0)
+    c0 = time.perf_counter()
     g, sg, _, _ = ogain.sample_gain_segment(ts.d[a:a + n], t, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q],
                                             ts.alpha[q], seed, q, GAIN_IT)
+    sec["gain"] = time.perf_counter() - c0
     # noise parameters from the oracle's own n_corr of the sweep's last iteration
     ncs = ot.sample_ncorr_segment(r, ts.band_fsamp[band], ts.sigma0[q], ts.fknee[q], ts.alpha[q], seed, q,
                                   _BASE["it"])
+    c0 = time.perf_counter()
     xi = onoise.sample_noise_segment(ts.d[a:a + n], t, ts.gain[q], ncs, ts.band_fsamp[band], ts.fknee[q],
                                      seed, q, NOISE_IT)
-    return q, nc, k, g, sg, xi
+    sec["noise"] = time.perf_counter() - c0
+    if getattr(ts, "tod_huff", None) is not None:
+        c0 = time.perf_counter()
+        oh.StreamDecoder(ts.tod_huff).segment(q, n)
+        oh.StreamDecoder(ts.flag_huff).segment(q, n)
+        sec["streams"] = time.perf_counter() - c0
+    return q, nc, k, g, sg, xi, n, sec
 
 
 def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
@@ -243,7 +255,12 @@ def stream_leg(ctx, ts, tod):
                    "decoded_equals_fp32_tod": exact},
            "flags": {"ms_per_call": round(ms_f, 3), "samples_per_s": ts.nsamp / (ms_f / 1e3),
                      "compressed_bytes_per_sample": comp(ts.flag_huff) / ts.nsamp,
-                     "ratio_vs_32bit": 4.0 * ts.nsamp / comp(ts.flag_huff)}}
+                     "ratio_vs_32bit": 4.0 * ts.nsamp / comp(ts.flag_huff)},
+           "cpu_baseline_tod_and_flags": oracle_rate("streams")}
+    # compulsory: the compressed stream (words, side index, tables) read once,
+    # the FP32 TOD or the mask byte written once
+    rep["tod"]["roofline"] = leg_roofline(comp(ts.tod_huff) + 4 * ts.nsamp, ms_d)
+    rep["flags"]["roofline"] = leg_roofline(comp(ts.flag_huff) + ts.nsamp, ms_f)
     log("tod stream: %.2f ms, flag stream: %.2f ms" % (ms_d, ms_f))
     return rep, mask
 
@@ -286,13 +303,56 @@ def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix, mask):
     if ref:
         g = nc.cpu().numpy()
         errs = []
-        for q, r, k, _, _, _ in ref:
+        for q, r, k, _, _, _, _, _ in ref:
             a, b = ts.seg_off[q], ts.seg_off[q + 1]
             errs.append({"segment": q, "rel_l2": float(np.linalg.norm(g[a:b] - r) / np.linalg.norm(r)),
                          "iterations_gpu": int(it_h[q]), "iterations_oracle": int(k)})
         rep["accuracy_vs_oracle"] = errs
+    # compulsory, estimated per segment from its iteration count: whole-vector
+    # FFT round trips (x0, one per iteration, the final M S y) move 6 N f bytes
+    # each, the F^H W1 transform 3 N f; the right-hand side reads d, s, mask
+    # and F^H W1 and writes mu u (N (4 + 4 + 1 + 4 + 4)); the small system
+    # moves about 108 B per masked extended position per iteration; the crop
+    # reads x0 and M S y and writes n_corr (3 n f)
+    n_s = np.diff(ts.seg_off).astype(np.int64)
+    N_s = np.array([2 * next5(int(x)) for x in n_s], dtype=np.int64)
+    mk = (mask_h == 0).astype(np.int64)
+    cs = np.concatenate([[0], np.cumsum(mk)])
+    m_s = 2 * (cs[ts.seg_off[1:]] - cs[ts.seg_off[:-1]])
+    its = np.abs(it_h).astype(np.int64)
+    f = 4
+    nbytes = float(np.sum((its + 2) * 6 * N_s * f + 3 * N_s * f + 17 * N_s + 108 * m_s * its + 3 * n_s * f))
+    rep["roofline_estimate"] = leg_roofline(nbytes, ms)
+    rep["cpu_baseline"] = oracle_rate("masked")
+    if rep["cpu_baseline"]:
+        rep["cpu_baseline"]["sample"] += "; full-system PCG to tol 1e-12"
     log("masked n_corr: %.1f ms per call, iterations %s" % (ms, rep["iterations"]))
     return rep
+
+
+def oracle_rate(kind):
+    """The oracle timed on the sampled segments of a leg (one process per
+    segment): samples/s of one process."""
+    ref = _BASE.get("next")
+    if not ref or kind not in ref[0][7]:
+        return None
+    n = sum(r[6] for r in ref)
+    sec = sum(r[7][kind] for r in ref)
+    return {"value": n / sec, "unit": "TOD samples/s", "cores": 1, "kind": "oracle",
+            "sample": "%d segments (%d samples), one process each, rate per process" % (len(ref), n)}
+
+
+def fft_round_trip_bytes(ns, sum_m, f):
+    """Compulsory bytes of one forward + inverse FFT round trip over the set
+    from per-sample input to per-sample output (the sweep's column and row
+    passes): read the input, write and read the spectrum twice, write the output."""
+    return 2 * ns * f + 8 * f * sum_m
+
+
+def leg_roofline(nbytes, ms):
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "compulsory_gb": round(nbytes / 1e9, 3), "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def unit_template(ctx, ts, tod, out, maps32):
@@ -340,7 +400,12 @@ def noise_leg(ctx, ts, tod, out, t, seed):
     if ref:
         rep["vs_oracle_with_its_own_ncorr"] = [
             {"segment": q, "rel_err": [float(abs(xi[i, q] / x[i] - 1)) for i in range(3)]}
-            for q, _, _, _, _, x in ref]
+            for q, _, _, _, _, x, _, _ in ref]
+    # compulsory: forward column pass (n_corr read, spectrum written), row
+    # pass (spectrum read), white sums (d, t, n_corr read)
+    sum_m = sum(next5(int(x)) for x in np.diff(ts.seg_off))
+    rep["roofline"] = leg_roofline(4 * ts.nsamp + 8 * sum_m + 8 * sum_m + 12 * ts.nsamp, ms)
+    rep["cpu_baseline"] = oracle_rate("noise")
     log("noise draw: %.1f ms per call" % ms)
     return rep
 
@@ -365,7 +430,11 @@ def gain_leg(ctx, ts, tod, seed, t):
     if ref:
         rep["accuracy_vs_oracle"] = [{"segment": q, "gain_rel_err": float(abs(gh[q] - gr) / abs(gr)),
                                       "sigma_rel_err": float(abs(sh[q] - sr) / sr)}
-                                     for q, _, _, gr, sr, _ in ref]
+                                     for q, _, _, gr, sr, _, _, _ in ref]
+    # compulsory: two FFT round trips (t and d filtered), then t, Kt, Kd read
+    sum_m = sum(next5(int(x)) for x in np.diff(ts.seg_off))
+    rep["roofline"] = leg_roofline(2 * fft_round_trip_bytes(ts.nsamp, sum_m, 4) + 12 * ts.nsamp, ms)
+    rep["cpu_baseline"] = oracle_rate("gain")
     log("gain draw: %.1f ms per call" % ms)
     return rep
 
