@@ -121,18 +121,21 @@ def _oracle_segment(q):
     g = ts.gain[q]
     w = g / ts.sigma0[q] ** 2
     v = ts.d[a:a + n] - nc
-    npt = ts.npix_total
-    b = np.zeros((3, npt))
-    A = np.zeros((6, npt))
+    # binned on the segment's own pixels (the accumulation of section 2.4)
+    up, inv = np.unique(gp, return_inverse=True)
+    b = np.zeros((3, len(up)))
+    A = np.zeros((6, len(up)))
     rows = (np.ones(n), c, sn)
     for i in range(3):
-        np.add.at(b[i], gp, w * v * rows[i])
+        np.add.at(b[i], inv, w * v * rows[i])
     for k, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
-        np.add.at(A[k], gp, g * w * rows[i] * rows[j])
-    return q, pix, nc
+        np.add.at(A[k], inv, g * w * rows[i] * rows[j])
+    hits = np.bincount(inv, minlength=len(up))
+    return q, pix, nc, (up, b, A, hits)
 
 
 MASKED_IT = 7777      # Gibbs iteration number of the masked-draw leg
+RCOND_MIN = 1e-3      # conditioning threshold of the map solve in the accuracy report
 MASKED_TOL = 1e-6     # its CG tolerance (residual reduction from x0 = M b)
 
 
@@ -221,10 +224,45 @@ def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
     }, res
 
 
+def oracle_binned(res):
+    """The oracle's (pixels, b, A, hits) summed over the sampled segments."""
+    import numpy as np
+    up = np.unique(np.concatenate([r[3][0] for r in res]))
+    b = np.zeros((3, len(up)))
+    A = np.zeros((6, len(up)))
+    hits = np.zeros(len(up), dtype=np.int64)
+    for r in res:
+        u, bb, AA, hh = r[3]
+        j = np.searchsorted(up, u)
+        b[:, j] += bb
+        A[:, j] += AA
+        hits[j] += hh
+    return up, b, A, hits
+
+
+def compare_maps(res, acc, gpu_map, rcond_min):
+    """Binned accumulators and solved maps of the sampled segments, GPU vs
+    oracle, on every pixel they touch (maps: where the oracle's solve is
+    conditioned)."""
+    import numpy as np
+    from oracle import tod as ot
+    up, b, A, hits = oracle_binned(res)
+    ga = acc[up]
+    rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+    m_ref, _ = ot.solve_maps(b, A, hits, rcond_min)
+    ok = np.isfinite(m_ref[0])
+    gm = gpu_map[:, up]
+    return {"pixels": int(len(up)), "b_rel_l2": [rel(ga[:, i], b[i]) for i in range(3)],
+            "A_rel_l2": rel(ga[:, 3:9].T, A), "hits_exact": bool(np.array_equal(ga[:, 9], hits)),
+            "conditioned_pixels": int(ok.sum()),
+            "map_rel_l2_TQU": [rel(gm[i, ok], m_ref[i, ok]) for i in range(3)],
+            "gpu_conditioned_same": bool(np.array_equal(np.isfinite(gm[0]), ok))}
+
+
 def compare_to_oracle(ts, res, gpu_ncorr, gpu_pix):
     import numpy as np
     errs, exact = [], True
-    for q, pix, nc in res:
+    for q, pix, nc, _ in res:
         a, b = ts.seg_off[q], ts.seg_off[q + 1]
         g = gpu_ncorr[a:b].astype(np.float64)
         errs.append(float(np.linalg.norm(g - nc) / np.linalg.norm(nc)))
@@ -554,6 +592,21 @@ def main():
     ctx.sync()
     gpu_nc = out["ncorr"].cpu().numpy()
     gpu_pix = out["pix"].cpu().numpy()
+    # binning and solve of the oracle's sampled segments alone (accept flags)
+    map_report = None
+    if oracle_res:
+        keep = np.zeros(ts.nseg, dtype=np.uint8)
+        keep[[r[0] for r in oracle_res]] = 1
+        acc_keep = tod.seg_accept.clone()
+        tod.seg_accept.copy_(torch.from_numpy(keep))
+        ctx.bin_tod(tod, "mixed", out["pix"], out["psi"], tod.d, out["ncorr"], out["acc"])
+        gmap = torch.empty((3, ts.npix_total), dtype=torch.float32, device=dev)
+        ctx.solve_maps(out["acc"], RCOND_MIN, gmap)
+        ctx.sync()
+        tod.seg_accept.copy_(acc_keep)
+        map_report = compare_maps(oracle_res, out["acc"].cpu().numpy(), gmap.cpu().numpy().astype(np.float64),
+                                  RCOND_MIN)
+        del gmap
 
     sum_m = sum(next5(int(ts.seg_off[q + 1] - ts.seg_off[q])) for q in range(ts.nseg))
     kb = kernel_bytes(ts, tod, "mixed", sum_m)
@@ -622,6 +675,8 @@ def main():
         copy = {"bytes": 2 * a.numel() * 4}
 
     acc_report = compare_to_oracle(ts, oracle_res, gpu_nc, gpu_pix) if oracle_res else None
+    if acc_report is not None:
+        acc_report["binned_and_maps"] = map_report
 
     line = {
         "metric": "TOD samples/s (decode+project+n_corr+bin), mixed-FP32 vs FP64 plain, 1 GPU",
