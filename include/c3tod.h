@@ -166,7 +166,12 @@ tod_status decode_flags(tod_ctx ctx, const tod_layout *lay, const tod_huff *flag
 /* Projection s = g P m (Eq. 1; pointing matrix as pixel + psi streams,
  * section 2.1).  pix/psi: device [nsamp] as produced by decode_pointing.
  * maps: device [3][npix_total] FP32 (mixed) or FP64 (plain).  gain: device
- * [nseg] FP64.  s_out: device [nsamp] FP32 (mixed) or FP64 (plain). */
+ * [nseg] FP64.  s_out: device [nsamp] FP32 (mixed) or FP64 (plain); NaN where
+ * pix is out of range for the segment's band.  Samples are visited in strided
+ * tiles of the band's revisit period: a band with no period set
+ * (tod_set_bin_stride) or tuned (tod_autotune) has it probed from pix on the
+ * first call, which waits for the stream.  Workspace: npix_total records of
+ * four values, held by the context. */
 tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                        const int32_t *pix, const uint16_t *psi,
                        const void *maps, const double *gain, void *s_out);

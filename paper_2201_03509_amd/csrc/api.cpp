@@ -800,10 +800,14 @@ tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const 
     const int mixed = prec == TOD_MIXED;
     Plan *P;
     if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
+    // strided tiles (the revisit period is probed from pix on first use)
+    const int4 *tiles;
+    int nt;
+    if ((r = get_bin_tiles(ctx, lay, P, pix, &tiles, &nt)) != TOD_OK) return r;
+    HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     KTimer kt(ctx, K_PROJECT, ctx->stream);
-    HIPCHK(c3::launch_project_tiles(ctx->stream, make_layout_dev(lay), mixed,
-                                    (const int4 *)P->sample_tiles.p, P->nsample_tiles, pix, psi, maps,
-                                    gain, mixed ? ctx->trig32.p : ctx->trig64.p, s_out));
+    HIPCHK(c3::launch_resid_tiles(ctx->stream, make_layout_dev(lay), mixed, tiles, nt, pix, psi, nullptr, 0,
+                                  maps, ctx->maps4.p, gain, mixed ? ctx->trig32.p : ctx->trig64.p, s_out));
     return TOD_OK;
 }
 

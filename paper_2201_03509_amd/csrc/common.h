@@ -152,9 +152,9 @@ hipError_t launch_decode_stream(hipStream_t st, const LayoutDev &L, const HuffDe
                                 const DecodeTask *tasks, int ntask, int kind, double quantum,
                                 uint32_t flag_mask, void *out, uint8_t *mask_out, uint32_t *err);
 
-// r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs);
-// maps4: workspace of npix_total records of 4 values (T, Q, U, 0), filled from
-// the [3][npix] maps first
+// r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs),
+// or s = g P m when d is NULL; maps4: workspace of npix_total records of 4
+// values (T, Q, U, 0), filled from the [3][npix] maps first
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                               int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                               int d_f64, const void *maps, void *maps4, const double *gain,
@@ -206,10 +206,6 @@ bool fft_col_reg_supported(int prec_mixed, int m1);
 // raise the dynamic LDS limit of the FFT kernels (once per process)
 hipError_t fft_init_attributes();
 
-hipError_t launch_project_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
-                                int ntile, const int32_t *pix, const uint16_t *psi,
-                                const void *maps, const double *gain, const void *trig,
-                                void *s_out);
 hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                             int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                             int d_f64, const void *ncorr, const double *gain,

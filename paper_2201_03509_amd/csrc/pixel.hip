@@ -20,39 +20,6 @@ __device__ __forceinline__ T ld(const void *p, int f64, int64_t i) {
     return f64 ? (T)((const double *)p)[i] : (T)((const float *)p)[i];
 }
 
-// ---------------------------------------------------------------- projection
-template <typename T>
-__global__ __launch_bounds__(C3_NT) void k_project(LayoutDev Ld, const int4 *__restrict__ tiles,
-                                                   const int32_t *__restrict__ pix,
-                                                   const uint16_t *__restrict__ psi,
-                                                   const T *__restrict__ maps,
-                                                   const double *__restrict__ gain,
-                                                   const cx<T> *__restrict__ trig,
-                                                   T *__restrict__ s_out) {
-    __shared__ cx<T> tr[2048];
-    for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
-    __syncthreads();
-    const int4 tl = tiles[blockIdx.x];
-    const int seg = tl.x;
-    const int band = Ld.seg_band[seg];
-    const int64_t poff = Ld.band[band].pix_off;
-    const int64_t npix = Ld.band[band].npix;
-    const int64_t npt = Ld.npix_total;
-    const T g = (T)gain[seg];
-    const int64_t base = Ld.seg_off[seg] + tl.y;
-    for (int t = threadIdx.x; t < tl.z; t += C3_NT) {
-        const int64_t i = base + t;
-        const int p = pix[i];
-        if ((uint32_t)p >= (uint32_t)npix) {
-            s_out[i] = (T)NAN;
-            continue;
-        }
-        const int64_t gp = poff + p;
-        const cx<T> cs = tr[psi[i] & 2047];
-        s_out[i] = g * (maps[gp] + maps[npt + gp] * cs.x + maps[2 * npt + gp] * cs.y);
-    }
-}
-
 // ---------------------------------------------------------------- binning
 __device__ __forceinline__ void flush_acc(double *acc, int64_t gp, const double *a) {
     double *dst = acc + gp * 10;
@@ -168,10 +135,11 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     if (old >= 0) flush_acc(acc, poff + old, o);
 }
 
-// ---------------------------------------------------------------- residual
-// r = d - g (T + Q cos 2psi + U sin 2psi) on strided tiles; the thread keeps
-// the map values of its current pixel in registers across revisits (and
-// across the tile's segments).
+// ---------------------------------------------------------------- projection
+// s = g (T + Q cos 2psi + U sin 2psi), or the residual r = d - s, on strided
+// tiles; the thread keeps the map values of its current pixel in registers
+// across revisits (and across the tile's segments), so the map is read once
+// per pixel change instead of once per sample.
 // T, Q, U of one pixel in one aligned record (one load per pixel change)
 template <typename T>
 struct alignas(4 * sizeof(T)) Stokes4 {
@@ -186,7 +154,8 @@ __global__ __launch_bounds__(C3_NT) void k_interleave(const T *__restrict__ maps
         out[i] = Stokes4<T>{maps[i], maps[npt + i], maps[2 * npt + i], (T)0};
 }
 
-template <typename T>
+// SUB: write d - s (d read per sample); otherwise s (d unused)
+template <typename T, bool SUB>
 __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__restrict__ tiles,
                                                  const int32_t *__restrict__ pix,
                                                  const uint16_t *__restrict__ psi, const void *d,
@@ -223,7 +192,8 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
             }
         }
         const cx<T> cs = tr[b & 2047];
-        r_out[i] = dv - g * (mT + mQ * cs.x + mU * cs.y);
+        const T sv = g * (mT + mQ * cs.x + mU * cs.y);
+        r_out[i] = SUB ? dv - sv : sv;
     };
     for (int gi = 0; gi < ngrp; ++gi) {
         const int seg = tl.x + gi;
@@ -239,14 +209,14 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
-                v[u] = d_f64 ? (T)dd[i] : (T)df[i];
+                v[u] = !SUB ? (T)0 : d_f64 ? (T)dd[i] : (T)df[i];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], v[u]);
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
-            step(i, pix[i], psi[i], d_f64 ? (T)dd[i] : (T)df[i]);
+            step(i, pix[i], psi[i], !SUB ? (T)0 : d_f64 ? (T)dd[i] : (T)df[i]);
         }
     }
 }
@@ -469,20 +439,6 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_finish(
 
 namespace c3 {
 
-hipError_t launch_project_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
-                                int ntile, const int32_t *pix, const uint16_t *psi,
-                                const void *maps, const double *gain, const void *trig,
-                                void *s_out) {
-    if (ntile <= 0) return hipSuccess;
-    if (mixed)
-        hipLaunchKernelGGL(k_project<float>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi,
-                           (const float *)maps, gain, (const cx<float> *)trig, (float *)s_out);
-    else
-        hipLaunchKernelGGL(k_project<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi,
-                           (const double *)maps, gain, (const cx<double> *)trig, (double *)s_out);
-    return hipGetLastError();
-}
-
 hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                             int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                             int d_f64, const void *ncorr, const double *gain,
@@ -509,15 +465,25 @@ hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, con
     if (mixed) {
         hipLaunchKernelGGL(k_interleave<float>, dim3(gi), dim3(C3_NT), 0, st, (const float *)maps, npt,
                            (Stokes4<float> *)maps4);
-        hipLaunchKernelGGL(k_resid<float>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
-                           d_f64, (const Stokes4<float> *)maps4, gain, (const cx<float> *)trig,
-                           (float *)r_out);
+        if (d)
+            hipLaunchKernelGGL((k_resid<float, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, (const Stokes4<float> *)maps4, gain,
+                               (const cx<float> *)trig, (float *)r_out);
+        else
+            hipLaunchKernelGGL((k_resid<float, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, (const Stokes4<float> *)maps4, gain,
+                               (const cx<float> *)trig, (float *)r_out);
     } else {
         hipLaunchKernelGGL(k_interleave<double>, dim3(gi), dim3(C3_NT), 0, st, (const double *)maps, npt,
                            (Stokes4<double> *)maps4);
-        hipLaunchKernelGGL(k_resid<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
-                           d_f64, (const Stokes4<double> *)maps4, gain, (const cx<double> *)trig,
-                           (double *)r_out);
+        if (d)
+            hipLaunchKernelGGL((k_resid<double, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, (const Stokes4<double> *)maps4, gain,
+                               (const cx<double> *)trig, (double *)r_out);
+        else
+            hipLaunchKernelGGL((k_resid<double, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, (const Stokes4<double> *)maps4, gain,
+                               (const cx<double> *)trig, (double *)r_out);
     }
     return hipGetLastError();
 }
