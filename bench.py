@@ -186,7 +186,18 @@ def _oracle_next(q):
         oh.StreamDecoder(ts.tod_huff).segment(q, n)
         oh.StreamDecoder(ts.flag_huff).segment(q, n)
         sec["streams"] = time.perf_counter() - c0
-    return q, nc, k, g, sg, xi, n, sec
+    # chi^2 and its gain derivative at that same n_corr
+    c0 = time.perf_counter()
+    rc = r - ncs
+    fs = ts.band_fsamp[band]
+    J = ot.chisq_segment(rc, ncs, fs, ts.sigma0[q], ts.fknee[q], ts.alpha[q])
+    _, dg, _, _, _ = ot.chisq_grad_segment(rc, t, ncs, fs, ts.gain[q], ts.sigma0[q], ts.fknee[q], ts.alpha[q])
+    sec["chisq"] = time.perf_counter() - c0
+    # sizes of the terms summed into J and dJ/dg, to scale their errors by
+    I, P, _ = ot.whittle_parts(ncs, fs, ts.sigma0[q], ts.fknee[q], ts.alpha[q])
+    J_terms = float(np.sum(rc * rc) / ts.sigma0[q] ** 2 + np.sum(I / P) + np.sum(np.abs(np.log(P))))
+    dg_terms = 2.0 * float(np.sum(np.abs(t * rc))) / ts.sigma0[q] ** 2
+    return q, nc, k, g, sg, xi, n, sec, (J, J_terms, dg, dg_terms)
 
 
 def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
@@ -341,7 +352,7 @@ def masked_leg(ctx, ts, tod, out, maps32, seed, gpu_pix, mask):
     if ref:
         g = nc.cpu().numpy()
         errs = []
-        for q, r, k, _, _, _, _, _ in ref:
+        for q, r, k, *_ in ref:
             a, b = ts.seg_off[q], ts.seg_off[q + 1]
             errs.append({"segment": q, "rel_l2": float(np.linalg.norm(g[a:b] - r) / np.linalg.norm(r)),
                          "iterations_gpu": int(it_h[q]), "iterations_oracle": int(k)})
@@ -438,13 +449,54 @@ def noise_leg(ctx, ts, tod, out, t, seed):
     if ref:
         rep["vs_oracle_with_its_own_ncorr"] = [
             {"segment": q, "rel_err": [float(abs(xi[i, q] / x[i] - 1)) for i in range(3)]}
-            for q, _, _, _, _, x, _, _ in ref]
+            for q, _, _, _, _, x, *_ in ref]
     # compulsory: forward column pass (n_corr read, spectrum written), row
     # pass (spectrum read), white sums (d, t, n_corr read)
     sum_m = sum(next5(int(x)) for x in np.diff(ts.seg_off))
     rep["roofline"] = leg_roofline(4 * ts.nsamp + 8 * sum_m + 8 * sum_m + 12 * ts.nsamp, ms)
     rep["cpu_baseline"] = oracle_rate("noise")
     log("noise draw: %.1f ms per call" % ms)
+    return rep
+
+
+def chisq_leg(ctx, ts, tod, out, maps32):
+    """tod_chisq and tod_chisq_backward over the whole workload at the sweep's
+    last n_corr; J and dJ/dg against the oracle (fed its own
+    n_corr of that iteration) on the sampled segments."""
+    import numpy as np
+    import torch
+    dev = tod.d.device
+    J = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
+    ms_f, kt_f = timed_call(ctx, lambda: ctx.tod_chisq(tod, "mixed", out["pix"], out["psi"], tod.d,
+                                                       out["ncorr"], maps32, J))
+    gm = torch.empty((3, ts.npix_total), dtype=torch.float64, device=dev)
+    gg = torch.empty(ts.nseg, dtype=torch.float64, device=dev)
+    gs, gf, ga = (torch.empty(ts.ndet, dtype=torch.float64, device=dev) for _ in range(3))
+    ms_b, kt_b = timed_call(ctx, lambda: ctx.tod_chisq_backward(tod, "mixed", out["pix"], out["psi"], tod.d,
+                                                                out["ncorr"], maps32, 1.0, gm, gg, gs, gf, ga))
+    rep = {"forward_ms_per_call": round(ms_f, 2), "backward_ms_per_call": round(ms_b, 2),
+           "forward_samples_per_s": ts.nsamp / (ms_f / 1e3), "backward_samples_per_s": ts.nsamp / (ms_b / 1e3),
+           "forward_kernels_ms": {k: round(v[0], 2) for k, v in kt_f.items() if v[1]},
+           "backward_kernels_ms": {k: round(v[0], 2) for k, v in kt_b.items() if v[1]},
+           "grad_maps_finite": bool(torch.isfinite(gm).all().item())}
+    ref = _BASE.get("next")
+    if ref:
+        Jh, gh = J.cpu().numpy(), gg.cpu().numpy()
+        acc = []
+        for q, *_, chi in ref:
+            Jr, J_terms, dgr, dg_terms = chi
+            acc.append({"segment": q, "J_err_over_terms": float(abs(Jh[q] - Jr) / J_terms),
+                        "dJdg_err_over_terms": float(abs(gh[q] - dgr) / dg_terms)})
+        rep["accuracy_vs_oracle"] = acc
+    # compulsory: pix, psi, d, n_corr read once per sample; the FP32 map read
+    # once; the n_corr spectrum written and read once; backward adds the FP64
+    # map gradient written once
+    sum_m = sum(next5(int(x)) for x in np.diff(ts.seg_off))
+    fwd = 14 * ts.nsamp + 12 * ts.npix_total + 16 * sum_m
+    rep["forward_roofline"] = leg_roofline(fwd, ms_f)
+    rep["backward_roofline"] = leg_roofline(fwd + 24 * ts.npix_total, ms_b)
+    rep["cpu_baseline"] = oracle_rate("chisq")
+    log("chisq: forward %.1f ms, backward %.1f ms per call" % (ms_f, ms_b))
     return rep
 
 
@@ -468,7 +520,7 @@ def gain_leg(ctx, ts, tod, seed, t):
     if ref:
         rep["accuracy_vs_oracle"] = [{"segment": q, "gain_rel_err": float(abs(gh[q] - gr) / abs(gr)),
                                       "sigma_rel_err": float(abs(sh[q] - sr) / sr)}
-                                     for q, _, _, gr, sr, _, _, _ in ref]
+                                     for q, _, _, gr, sr, *_ in ref]
     # compulsory: two FFT round trips (t and d filtered), then t, Kt, Kd read
     sum_m = sum(next5(int(x)) for x in np.diff(ts.seg_off))
     rep["roofline"] = leg_roofline(2 * fft_round_trip_bytes(ts.nsamp, sum_m, 4) + 12 * ts.nsamp, ms)
@@ -491,6 +543,7 @@ def main():
     ap.add_argument("--no-masked", action="store_true", help="skip the masked n_corr draw leg")
     ap.add_argument("--no-gain", action="store_true", help="skip the gain draw leg")
     ap.add_argument("--no-noise", action="store_true", help="skip the noise-parameter draw leg")
+    ap.add_argument("--no-chisq", action="store_true", help="skip the chi^2 forward/backward leg")
     ap.add_argument("--sweep-only", action="store_true",
                     help="only the sweep: no stream, gain, noise or masked-draw legs (profiling runs)")
     ap.add_argument("--fft-batch", type=int, default=None,
@@ -502,7 +555,7 @@ def main():
                     help="also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.sweep_only:
-        args.no_gain = args.no_noise = args.no_masked = True
+        args.no_gain = args.no_noise = args.no_masked = args.no_chisq = True
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -658,6 +711,11 @@ def main():
         del t_unit
         torch.cuda.empty_cache()
 
+    chisq = None
+    if not args.no_chisq:
+        chisq = chisq_leg(ctx, ts, tod, out, maps32)
+        torch.cuda.empty_cache()
+
     streams = masked = None
     if not args.sweep_only:
         streams, flag_mask = stream_leg(ctx, ts, tod)
@@ -709,6 +767,7 @@ def main():
         "tod_flag_streams": streams,
         "gain_draw": gain,
         "noise_draw": noise,
+        "chisq": chisq,
         "masked_ncorr": masked,
         "copy_probe": copy,
     }

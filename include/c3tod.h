@@ -301,7 +301,12 @@ tod_status solve_maps(tod_ctx ctx, int64_t npix, const double *acc, double rcond
  *   J_s = sum_t r_t^2/sigma0^2 + sum_{k=1}^{N/2} (I_k/P_k + ln P_k),
  *   r = d - g P m - n_corr,  I_k = |FFT(e(n_corr))_k|^2 / N on the same
  *   mirrored extension and N as sample_ncorr.
- * chisq_seg: device [nseg] FP64 (0 for rejected segments). */
+ * chisq_seg: device [nseg] FP64 (0 for rejected segments).  Samples whose
+ * pixel is out of range for their band are left out of the time-domain sum.
+ * The time-domain terms walk strided tiles of the band's revisit period
+ * (probed from pix on the first call when not set or tuned, which waits for
+ * the stream).  Workspace: npix_total records of four values, held by the
+ * context. */
 tod_status tod_chisq(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                      const int32_t *pix, const uint16_t *psi,
                      const void *d, tod_dtype d_dtype, const void *ncorr,

@@ -248,22 +248,30 @@ def chisq_grad_all(ts, maps, pix, psi, d, ncorr, gain=None, sigma0=None, fknee=N
     gs = np.zeros(ts.nseg)
     gf = np.zeros(ts.nseg)
     ga = np.zeros(ts.nseg)
+    m = np.asarray(maps, dtype=np.float64)
     for q in range(ts.nseg):
         a, b = ts.seg_off[q], ts.seg_off[q + 1]
         p, c, s = pointing_rows(gp[a:b], psi[a:b])
-        m = np.asarray(maps, dtype=np.float64)
         Pm = m[0, p] + m[1, p] * c + m[2, p] * s
         nc = np.asarray(ncorr[a:b], dtype=np.float64)
         r = np.asarray(d[a:b], dtype=np.float64) - gain[q] * Pm - nc
-        s0 = sigma0[q]
-        coef = -2.0 * gain[q] * r / s0 ** 2
+        coef, gg[q], gs[q], gf[q], ga[q] = chisq_grad_segment(
+            r, Pm, nc, ts.band_fsamp[ts.seg_band[q]], gain[q], sigma0[q], fknee[q], alpha[q])
         np.add.at(gm[0], p, coef)
         np.add.at(gm[1], p, coef * c)
         np.add.at(gm[2], p, coef * s)
-        gg[q] = -2.0 * np.sum(Pm * r) / s0 ** 2
-        I, P, f = whittle_parts(nc, ts.band_fsamp[ts.seg_band[q]], s0, fknee[q], alpha[q])
-        u = 1.0 - I / P
-        gs[q] = -2.0 * np.sum(r * r) / s0 ** 3 + np.sum(2.0 / s0 * u)
-        gf[q] = np.sum(u * (-alpha[q] / fknee[q]))
-        ga[q] = np.sum(u * np.log(f / fknee[q]))
     return gm, gg, gs, gf, ga
+
+
+def chisq_grad_segment(r, Pm, nc, fsamp, gain, sigma0, fknee, alpha):
+    """One segment's terms of chisq_grad_all, for the residual r = d - g Pm - nc:
+    (coef, dJ/dg, dJ/dsigma0, dJ/df_knee, dJ/dalpha), coef = -2 g r / sigma0^2
+    being the per-sample weight that P^T spreads into the map gradient."""
+    coef = -2.0 * gain * r / sigma0 ** 2
+    gg = -2.0 * np.sum(Pm * r) / sigma0 ** 2
+    I, P, f = whittle_parts(nc, fsamp, sigma0, fknee, alpha)
+    u = 1.0 - I / P
+    gs = -2.0 * np.sum(r * r) / sigma0 ** 3 + np.sum(2.0 / sigma0 * u)
+    gf = np.sum(u * (-alpha / fknee))
+    ga = np.sum(u * np.log(f / fknee))
+    return coef, float(gg), float(gs), float(gf), float(ga)

@@ -1218,11 +1218,12 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     if (gsig) HIPCHK(c3::launch_zero(st, gsig, sizeof(double) * lay->ndet));
     if (gfk) HIPCHK(c3::launch_zero(st, gfk, sizeof(double) * lay->ndet));
     if (galpha) HIPCHK(c3::launch_zero(st, galpha, sizeof(double) * lay->ndet));
+    HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     const LayoutDev Ld = make_layout_dev(lay);
     {
         KTimer kt(ctx, K_CHISQ, st);
         HIPCHK(c3::launch_chisq_time_tiles(st, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64,
-                                           ncorr, maps, gain, sigma0, ctx->trig64.p,
+                                           ncorr, maps, ctx->maps4.p, gain, sigma0, ctx->trig64.p,
                                            (double *)ctx->seg_sums.p, grad_maps, gscale));
     }
     c3::FftArgs a = fft_args(ctx, P, lay);

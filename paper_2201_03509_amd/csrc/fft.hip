@@ -369,6 +369,7 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
 struct ModeCtx {
     double sigma0, lbase, lbase2, malpha;      // lbase = ln(fsamp / (N fknee)), lbase2 = log2 of it
     double invsqrtN, outscale;                 // 1/sqrt(N), sqrt(N)/M
+    double l2s0, iscale;                       // 2 ln sigma0, 1/(N sigma0^2)
     uint2 key;
     uint32_t it_lo, it_hi, seed_hi;
     int M;
@@ -479,12 +480,21 @@ __device__ __forceinline__ cx<T> x0_mode(const ModeCtx &mc, int64_t k, cx<T> E) 
 struct Wsum {
     double a, b, c;  // sum(I/P + ln P), sum(1 - I/P), sum((1 - I/P) ln(f/fknee))
 };
+// (FP32 path: I/P and ln(f_k/f_knee) from the hardware exp2/log2, summed in FP64)
 template <typename T>
 __device__ __forceinline__ void whittle_mode(const ModeCtx &mc, int64_t k, cx<T> E, Wsum &s) {
-    const double I = ((double)E.x * E.x + (double)E.y * E.y) * mc.invsqrtN * mc.invsqrtN;
-    const double lr = log((double)k) + mc.lbase;           // ln(f_k / f_knee)
-    const double lnP = 2.0 * log(mc.sigma0) - mc.malpha * lr;
-    const double IP = I * exp(-lnP);
+    double IP, lr;
+    if constexpr (sizeof(T) == 4) {
+        const float lr2 = __builtin_amdgcn_logf((float)k) + (float)mc.lbase2;  // log2(f_k / f_knee)
+        // I/P = |E|^2 / (N sigma0^2) (f_k/f_knee)^-alpha
+        IP = (double)((E.x * E.x + E.y * E.y) * (float)mc.iscale *
+                      __builtin_amdgcn_exp2f((float)mc.malpha * lr2));
+        lr = (double)lr2 * 0.69314718055994530942;
+    } else {
+        lr = log((double)k) + mc.lbase;  // ln(f_k / f_knee)
+        IP = (E.x * E.x + E.y * E.y) * mc.iscale * exp(mc.malpha * lr);
+    }
+    const double lnP = mc.l2s0 - mc.malpha * lr;
     s.a += IP + lnP;
     s.b += 1.0 - IP;
     s.c += (1.0 - IP) * lr;
@@ -552,6 +562,8 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
             mc.malpha = -a.alpha[seg];
             mc.lbase = log(fs / (N * a.fknee[seg]));
             mc.lbase2 = mc.lbase * 1.4426950408889634;
+            mc.l2s0 = 2.0 * log(mc.sigma0);
+            mc.iscale = 1.0 / (N * mc.sigma0 * mc.sigma0);
         }
         mc.invsqrtN = 1.0 / sqrt(N);
         mc.outscale = sqrt(N) / M;

@@ -321,12 +321,19 @@ __global__ __launch_bounds__(C3_NT) void k_probe(const int32_t *__restrict__ pix
 }
 
 // ---------------------------------------------------------------- chi^2 time part
+// chi^2 time-domain terms on strided tiles, r = d - g P m - n_corr: per
+// segment sum r^2/sigma0^2, sum (P m) r and sum r^2 (block sums, one atomic
+// each); with GRAD the map adjoint -2 g r / sigma0^2 (1, c, s) summed per
+// pixel in registers and added with FP64 atomics when the lane's pixel
+// changes.  The thread keeps its pixel's T, Q, U (interleaved records) in
+// registers across revisits, and keeps four revisits' loads in flight.
+template <typename T, bool GRAD>
 __global__ __launch_bounds__(C3_NT) void k_chisq_time(
-    LayoutDev Ld, const int4 *__restrict__ tiles, int mixed, const int32_t *__restrict__ pix,
-    const uint16_t *__restrict__ psi, const void *d, int d_f64, const void *ncorr,
-    const void *maps, const double *__restrict__ gain, const double *__restrict__ sigma0,
-    const cx<double> *__restrict__ trig, double *__restrict__ seg_sums,
-    double *__restrict__ gmap, double gscale) {
+    LayoutDev Ld, const int4 *__restrict__ tiles, const int32_t *__restrict__ pix,
+    const uint16_t *__restrict__ psi, const void *d, int d_f64, const T *__restrict__ ncorr,
+    const Stokes4<T> *__restrict__ maps, const double *__restrict__ gain,
+    const double *__restrict__ sigma0, const cx<double> *__restrict__ trig,
+    double *__restrict__ seg_sums, double *__restrict__ gmap, double gscale) {
     __shared__ cx<double> tr[2048];
     __shared__ double red[3][C3_NT / 64];
     const int4 tl = tiles[blockIdx.x];
@@ -340,58 +347,68 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
     const int64_t npt = Ld.npix_total;
-    double a0 = 0, a1 = 0, a2 = 0;
+    const float *df = (const float *)d;
+    const double *dd = (const double *)d;
     int cur = -1;
+    double mT = 0, mQ = 0, mU = 0;  // map values of pixel cur
+    double a0 = 0, a1 = 0, a2 = 0;  // its map-adjoint sums
+    double g = 0, cfac = 0, sr2 = 0, spr = 0;
+    auto flush = [&]() {
+        atomicAdd(gmap + poff + cur, a0);
+        atomicAdd(gmap + npt + poff + cur, a1);
+        atomicAdd(gmap + 2 * npt + poff + cur, a2);
+    };
+    auto step = [&](int p, int b, double dv, double nc) {
+        if ((uint32_t)p >= npix) return;  // out-of-range pixels are not in the likelihood
+        if (p != cur) {
+            if (GRAD && cur >= 0) flush();
+            a0 = a1 = a2 = 0;
+            cur = p;
+            const Stokes4<T> m = maps[poff + p];
+            mT = m.t;
+            mQ = m.q;
+            mU = m.u;
+        }
+        const cx<double> cs = tr[b & 2047];
+        const double Pm = mT + mQ * cs.x + mU * cs.y;
+        const double r = dv - g * Pm - nc;
+        sr2 += r * r;
+        spr += Pm * r;
+        if (GRAD) {
+            const double cr = cfac * r;
+            a0 += cr;
+            a1 += cr * cs.x;
+            a2 += cr * cs.y;
+        }
+    };
     for (int gi = 0; gi < ngrp; ++gi) {
         const int seg = tl.x + gi;
         if (Ld.seg_accept && !Ld.seg_accept[seg]) continue;  // uniform over the block
         const int64_t s0 = Ld.seg_off[seg];
         const int n = (int)(Ld.seg_off[seg + 1] - s0);
-        const double g = gain[seg];
+        g = gain[seg];
         const double sg = sigma0[seg];
         const double is2 = 1.0 / (sg * sg);
-        const double cfac = -2.0 * g * is2 * gscale;
-        double sr2 = 0, spr = 0;
-        for (int t = act ? phi : n; t < n; t += S) {
+        cfac = -2.0 * g * is2 * gscale;
+        sr2 = spr = 0;
+        int t = act ? phi : n;
+        for (; t + 3 * S < n; t += 4 * S) {
+            int p[4], b[4];
+            double v[4], c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t i = s0 + t + u * S;
+                p[u] = pix[i];
+                b[u] = psi[i];
+                v[u] = d_f64 ? dd[i] : (double)df[i];
+                c[u] = ncorr ? (double)ncorr[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) step(p[u], b[u], v[u], c[u]);
+        }
+        for (; t < n; t += S) {
             const int64_t i = s0 + t;
-            const int p = pix[i];
-            if ((uint32_t)p >= npix) continue;
-            const int64_t gp = poff + p;
-            const cx<double> cs = tr[psi[i] & 2047];
-            double T, Q, U, nc;
-            if (mixed) {
-                const float *m = (const float *)maps;
-                T = m[gp];
-                Q = m[npt + gp];
-                U = m[2 * npt + gp];
-                nc = ncorr ? (double)((const float *)ncorr)[i] : 0.0;
-            } else {
-                const double *m = (const double *)maps;
-                T = m[gp];
-                Q = m[npt + gp];
-                U = m[2 * npt + gp];
-                nc = ncorr ? ((const double *)ncorr)[i] : 0.0;
-            }
-            const double Pm = T + Q * cs.x + U * cs.y;
-            const double dv = d_f64 ? ((const double *)d)[i] : (double)((const float *)d)[i];
-            const double r = dv - g * Pm - nc;
-            sr2 += r * r;
-            spr += Pm * r;
-            if (gmap) {
-                if (p != cur) {
-                    if (cur >= 0) {
-                        atomicAdd(gmap + poff + cur, a0);
-                        atomicAdd(gmap + npt + poff + cur, a1);
-                        atomicAdd(gmap + 2 * npt + poff + cur, a2);
-                    }
-                    a0 = a1 = a2 = 0;
-                    cur = p;
-                }
-                const double cr = cfac * r;
-                a0 += cr;
-                a1 += cr * cs.x;
-                a2 += cr * cs.y;
-            }
+            step(pix[i], psi[i], d_f64 ? dd[i] : (double)df[i], ncorr ? (double)ncorr[i] : 0.0);
         }
         // per-segment sums: block reduction, one atomic per sum
         double v[3] = {sr2 * is2, spr, sr2};
@@ -408,11 +425,7 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
         }
         __syncthreads();
     }
-    if (gmap && cur >= 0) {
-        atomicAdd(gmap + poff + cur, a0);
-        atomicAdd(gmap + npt + poff + cur, a1);
-        atomicAdd(gmap + 2 * npt + poff + cur, a2);
-    }
+    if (GRAD && cur >= 0) flush();
 }
 
 __global__ __launch_bounds__(C3_NT) void k_chisq_finish(
@@ -530,12 +543,36 @@ hipError_t launch_repeat_probe(hipStream_t st, const int32_t *pix, int64_t off, 
 hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                                    int ntile, const int32_t *pix, const uint16_t *psi,
                                    const void *d, int d_f64, const void *ncorr, const void *maps,
-                                   const double *gain, const double *sigma0, const void *trig64,
-                                   double *seg_sums, double *grad_maps, double grad_scale) {
+                                   void *maps4, const double *gain, const double *sigma0,
+                                   const void *trig64, double *seg_sums, double *grad_maps,
+                                   double grad_scale) {
     if (ntile <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chisq_time, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, mixed, pix, psi, d,
-                       d_f64, ncorr, maps, gain, sigma0, (const cx<double> *)trig64, seg_sums,
-                       grad_maps, grad_scale);
+    const int64_t npt = L.npix_total;
+    const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
+    const cx<double> *tr = (const cx<double> *)trig64;
+    if (mixed) {
+        hipLaunchKernelGGL(k_interleave<float>, dim3(gi), dim3(C3_NT), 0, st, (const float *)maps, npt,
+                           (Stokes4<float> *)maps4);
+        const Stokes4<float> *m4 = (const Stokes4<float> *)maps4;
+        const float *nc = (const float *)ncorr;
+        if (grad_maps)
+            hipLaunchKernelGGL((k_chisq_time<float, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
+        else
+            hipLaunchKernelGGL((k_chisq_time<float, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
+    } else {
+        hipLaunchKernelGGL(k_interleave<double>, dim3(gi), dim3(C3_NT), 0, st, (const double *)maps, npt,
+                           (Stokes4<double> *)maps4);
+        const Stokes4<double> *m4 = (const Stokes4<double> *)maps4;
+        const double *nc = (const double *)ncorr;
+        if (grad_maps)
+            hipLaunchKernelGGL((k_chisq_time<double, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
+        else
+            hipLaunchKernelGGL((k_chisq_time<double, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
+                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
+    }
     return hipGetLastError();
 }
 
