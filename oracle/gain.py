@@ -19,7 +19,9 @@ t = P m (unit gain) and d = g t + n, n ~ N(0, N):
   (K t) . d, so a constant offset of d has no effect);
 * g = B/A + eta / sqrt(A), eta ~ N(0, 1) from the Philox stream of the segment
   at the counter word k = 2^32 - 1 (no Fourier mode uses it); mean_only: eta = 0;
-* a flat prior; no smoothing of the gain across scans.
+* a flat prior; no smoothing of the gain across scans;
+* A <= 0 (the template has no power outside the DC mode, as for a one-sample
+  segment, or the segment is empty): no draw, g = NaN and sigma_g = inf.
 """
 import numpy as np
 
@@ -58,6 +60,8 @@ def sample_gain_segment(d, t, fsamp, sigma0, fknee, alpha, seed, seg, it, mean_o
     t = np.asarray(t, dtype=np.float64)
     A = float(t @ inv_noise(t, fsamp, sigma0, fknee, alpha))
     B = float(t @ inv_noise(d, fsamp, sigma0, fknee, alpha))
+    if not A > 0.0:  # no information outside the DC mode (e.g. one sample): no draw
+        return np.nan, np.inf, A, B
     sig = 1.0 / np.sqrt(A)
     g = B / A
     if not mean_only:

@@ -20,6 +20,9 @@ template t (unit gain), the gain g and the current n_corr:
 3. alpha | f_knee, sigma0 (prior flat in alpha): ln L is strictly concave in
    alpha; alpha = alpha_hat + z1 / sqrt(H) with alpha_hat its maximiser and H
    the negative second derivative there (the Laplace form of the conditional).
+   When ln L has no maximiser (every J_b = 0, as for a one-sample segment,
+   whose mirrored extension is constant) the conditional is improper: no
+   draw, alpha = f_knee = NaN.
 4. f_knee | alpha, sigma0 (prior flat in ln f_knee): u = f_knee^alpha has the
    conditional Gamma(K, rate S_a / sigma0^2), K = sum c_b,
    S_a = sum_b J_b f_b^-alpha; u = G sigma0^2 / S_a with the Wilson-Hilferty
@@ -74,18 +77,28 @@ def periodogram_bins(nc, fsamp):
 
 
 def alpha_mode(J, c, f, sigma0, fknee):
-    """(alpha_hat, H): maximiser of the binned ln L in alpha and -d2 lnL/dalpha2."""
+    """(alpha_hat, H): maximiser of the binned ln L in alpha and -d2 lnL/dalpha2;
+    (nan, nan) when there is none."""
     x = np.log(f / fknee)
     a = J / sigma0 ** 2
 
     def score(al):
-        return float(np.sum(a * x * np.exp(-al * x) - c * x))
+        with np.errstate(over="ignore", invalid="ignore"):  # far bracket ends of a flat ln L
+            return float(np.sum(a * x * np.exp(-al * x) - c * x))
 
+    # bracket the root by doubling, at most 60 times each way; no sign change
+    # means ln L has no maximiser in alpha (all J_b = 0: a constant n_corr)
     lo, hi = -1.0, 1.0
-    while score(lo) < 0:
+    for _ in range(60):
+        if not score(lo) < 0:
+            break
         lo *= 2
-    while score(hi) > 0:
+    for _ in range(60):
+        if not score(hi) > 0:
+            break
         hi *= 2
+    if not (score(lo) >= 0 and score(hi) <= 0):
+        return np.nan, np.nan
     al = optimize.brentq(score, lo, hi, xtol=1e-15, rtol=1e-15, maxiter=500)
     H = float(np.sum(a * x * x * np.exp(-al * x)))
     return al, H

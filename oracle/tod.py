@@ -107,6 +107,8 @@ def inv_psd(N, fsamp, sigma0, fknee, alpha):
 
 def sample_ncorr_segment(r, fsamp, sigma0, fknee, alpha, seed, seg, it, mean_only=False):
     n = len(r)
+    if n == 0:  # an empty segment has nothing to draw
+        return np.zeros(0)
     N = fft_length(n)
     e = extend(r, N)
     R = np.fft.rfft(e) / np.sqrt(N)
@@ -199,8 +201,11 @@ def solve_maps(b, A, hits, rcond_min):
 
 # ---------------------------------------------------------------- chi^2
 def whittle_parts(nc, fsamp, sigma0, fknee, alpha):
-    """(I_k, P_k, f_k) for k = 1..N/2 on the extension of n_corr."""
+    """(I_k, P_k, f_k) for k = 1..N/2 on the extension of n_corr (no modes
+    for an empty segment)."""
     n = len(nc)
+    if n == 0:
+        return np.zeros(0), np.zeros(0), np.zeros(0)
     N = fft_length(n)
     X = np.fft.rfft(extend(nc, N)) / np.sqrt(N)
     k = np.arange(1, N // 2 + 1)

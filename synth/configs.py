@@ -27,7 +27,7 @@ class Config:
     name: str
     bands: Tuple[Band, ...]
     nscan: int
-    length: Tuple[str, float, float]       # ("uniform", lo, hi) or ("loguniform2", e0, e1)
+    length: Tuple                          # ("uniform", lo, hi), ("loguniform2", e0, e1) or ("list", n0, n1, ...)
     tod_f64: bool
     fknee_fixed: float = 0.0               # >0: every detector uses it
     alpha_fixed: float = 0.0

@@ -88,8 +88,12 @@ def canonical_codes(symbols, lengths):
 
 
 def build_table(values):
-    """Table blob + lookup (symbol -> (code, length)) from an int array."""
-    sym, cnt = np.unique(np.asarray(values, dtype=np.int64), return_counts=True)
+    """Table blob + lookup (symbol -> (code, length)) from an int array (an
+    empty array gets the one-symbol table of 0, so every scan has a valid table)."""
+    values = np.asarray(values, dtype=np.int64)
+    if values.size == 0:
+        values = np.zeros(1, dtype=np.int64)
+    sym, cnt = np.unique(values, return_counts=True)
     lens = huffman_lengths(sym, cnt)
     ss, sl, codes = canonical_codes(sym, lens)
     nsym = len(ss)

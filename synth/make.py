@@ -71,6 +71,9 @@ def scan_pointing(nside, t, horn_offset_deg):
 
 def _lengths(cfg):
     r = _rng(cfg.index, 3)
+    if cfg.length[0] == "list":  # ("list", n_0, n_1, ...): given lengths, repeated over the scans
+        ns = np.asarray(cfg.length[1:], dtype=np.int64)
+        return ns[np.arange(cfg.nscan) % len(ns)]
     kind, a, b = cfg.length
     if kind == "uniform":
         return r.integers(int(a), int(b) + 1, size=cfg.nscan).astype(np.int64)
@@ -93,6 +96,8 @@ def _sky(cfg, b, npix):
 
 
 def _corr_noise(rng, n, fsamp, sigma0, fknee, alpha):
+    if n == 0:
+        return np.zeros(0)
     ngrid = scipy.fft.next_fast_len(2 * n, real=True)
     nk = ngrid // 2 + 1
     f = np.arange(nk) * fsamp / ngrid
