@@ -31,11 +31,15 @@ __device__ __forceinline__ void flush_acc(double *acc, int64_t gp, const double 
 // the tile's segments are consecutive and of equal length; a lane visits its
 // phase in each of them in turn, so segments that see the same pixels (the two
 // radiometers of a horn) share one register accumulation and one flush.
-template <typename TN>
+// TD: type of d, TN: type of n_corr (NC = false: no n_corr).  Both are
+// compile-time, so a revisit's loads issue back to back with no branch
+// between them and are converted only once all of them are in flight.
+template <typename TN, typename TD, bool NC>
 __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restrict__ tiles,
                                                const int32_t *__restrict__ pix,
-                                               const uint16_t *__restrict__ psi, const void *d,
-                                               int d_f64, const TN *__restrict__ ncorr,
+                                               const uint16_t *__restrict__ psi,
+                                               const TD *__restrict__ d,
+                                               const TN *__restrict__ ncorr,
                                                const double *__restrict__ gain,
                                                const double *__restrict__ sigma0,
                                                const cx<double> *__restrict__ trig,
@@ -52,8 +56,6 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     const int seg0 = tl.x;
     const int64_t poff = Ld.band[Ld.seg_band[seg0]].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg0]].npix;
-    const float *df = (const float *)d;
-    const double *dd = (const double *)d;
     // two register accumulators: the current pixel and the one before it, so a
     // phase that crosses a pixel edge (or alternates between two segments'
     // pixels) rarely flushes early
@@ -112,22 +114,27 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         // bound the occupancy of this latency-bound kernel
         for (; t + S < n; t += 2 * S) {
             int p[2], b[2];
-            double v[2];
+            TD dv[2];
+            TN nv[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
-                v[u] = d_f64 ? dd[i] : (double)df[i];
-                if (ncorr) v[u] -= (double)ncorr[i];
+                dv[u] = d[i];
+                if constexpr (NC) nv[u] = ncorr[i];
             }
 #pragma unroll
-            for (int u = 0; u < 2; ++u) step(p[u], b[u], v[u]);
+            for (int u = 0; u < 2; ++u) {
+                double v = (double)dv[u];
+                if constexpr (NC) v -= (double)nv[u];
+                step(p[u], b[u], v);
+            }
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
-            double v = d_f64 ? dd[i] : (double)df[i];
-            if (ncorr) v -= (double)ncorr[i];
+            double v = (double)d[i];
+            if constexpr (NC) v -= (double)ncorr[i];
             step(pix[i], psi[i], v);
         }
     }
@@ -154,12 +161,13 @@ __global__ __launch_bounds__(C3_NT) void k_interleave(const T *__restrict__ maps
         out[i] = Stokes4<T>{maps[i], maps[npt + i], maps[2 * npt + i], (T)0};
 }
 
-// SUB: write d - s (d read per sample); otherwise s (d unused)
-template <typename T, bool SUB>
+// SUB: write d - s (d, of type TD, read per sample); otherwise s (d unused)
+template <typename T, typename TD, bool SUB>
 __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__restrict__ tiles,
                                                  const int32_t *__restrict__ pix,
-                                                 const uint16_t *__restrict__ psi, const void *d,
-                                                 int d_f64, const Stokes4<T> *__restrict__ maps,
+                                                 const uint16_t *__restrict__ psi,
+                                                 const TD *__restrict__ d,
+                                                 const Stokes4<T> *__restrict__ maps,
                                                  const double *__restrict__ gain,
                                                  const cx<T> *__restrict__ trig,
                                                  T *__restrict__ r_out) {
@@ -174,8 +182,6 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
     const int band = Ld.seg_band[tl.x];
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
-    const float *df = (const float *)d;
-    const double *dd = (const double *)d;
     int cur = -1;
     T mT = 0, mQ = 0, mU = 0;
     T g = 0;
@@ -209,14 +215,14 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
-                v[u] = !SUB ? (T)0 : d_f64 ? (T)dd[i] : (T)df[i];
+                v[u] = SUB ? (T)d[i] : (T)0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], v[u]);
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
-            step(i, pix[i], psi[i], !SUB ? (T)0 : d_f64 ? (T)dd[i] : (T)df[i]);
+            step(i, pix[i], psi[i], SUB ? (T)d[i] : (T)0);
         }
     }
 }
@@ -326,11 +332,12 @@ __global__ __launch_bounds__(C3_NT) void k_probe(const int32_t *__restrict__ pix
 // each); with GRAD the map adjoint -2 g r / sigma0^2 (1, c, s) summed per
 // pixel in registers and added with FP64 atomics when the lane's pixel
 // changes.  The thread keeps its pixel's T, Q, U (interleaved records) in
-// registers across revisits, and keeps four revisits' loads in flight.
-template <typename T, bool GRAD>
+// registers across revisits, and keeps four revisits' loads in flight (d of
+// type TD; both types compile-time, so the loads issue with no branch between).
+template <typename T, typename TD, bool GRAD>
 __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     LayoutDev Ld, const int4 *__restrict__ tiles, const int32_t *__restrict__ pix,
-    const uint16_t *__restrict__ psi, const void *d, int d_f64, const T *__restrict__ ncorr,
+    const uint16_t *__restrict__ psi, const TD *__restrict__ d, const T *__restrict__ ncorr,
     const Stokes4<T> *__restrict__ maps, const double *__restrict__ gain,
     const double *__restrict__ sigma0, const cx<double> *__restrict__ trig,
     double *__restrict__ seg_sums, double *__restrict__ gmap, double gscale) {
@@ -347,8 +354,6 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
     const int64_t npt = Ld.npix_total;
-    const float *df = (const float *)d;
-    const double *dd = (const double *)d;
     int cur = -1;
     double mT = 0, mQ = 0, mU = 0;  // map values of pixel cur
     double a0 = 0, a1 = 0, a2 = 0;  // its map-adjoint sums
@@ -394,21 +399,22 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
         int t = act ? phi : n;
         for (; t + 3 * S < n; t += 4 * S) {
             int p[4], b[4];
-            double v[4], c[4];
+            TD v[4];
+            T c[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
-                v[u] = d_f64 ? dd[i] : (double)df[i];
-                c[u] = ncorr ? (double)ncorr[i] : 0.0;
+                v[u] = d[i];
+                c[u] = ncorr[i];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) step(p[u], b[u], v[u], c[u]);
+            for (int u = 0; u < 4; ++u) step(p[u], b[u], (double)v[u], (double)c[u]);
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
-            step(pix[i], psi[i], d_f64 ? dd[i] : (double)df[i], ncorr ? (double)ncorr[i] : 0.0);
+            step(pix[i], psi[i], (double)d[i], (double)ncorr[i]);
         }
         // per-segment sums: block reduction, one atomic per sum
         double v[3] = {sr2 * is2, spr, sr2};
@@ -448,6 +454,86 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_finish(
     if (galpha) atomicAdd(galpha + det, gscale * w[2]);
 }
 
+// ---------------------------------------------------------------- launch helpers
+// the strided kernels are compiled per element type of d (and of n_corr), so
+// the launchers pick the instantiation here
+
+template <typename TN>
+void launch_bin_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
+                      const uint16_t *psi, const void *d, int d_f64, const TN *nc, const double *gain,
+                      const double *sigma0, const cx<double> *tr, double *acc) {
+    const dim3 g(ntile), b(C3_NT);
+    if (d_f64) {
+        const double *dd = (const double *)d;
+        if (nc)
+            hipLaunchKernelGGL((k_bin<TN, double, true>), g, b, 0, st, L, tiles, pix, psi, dd, nc, gain, sigma0,
+                               tr, acc);
+        else
+            hipLaunchKernelGGL((k_bin<TN, double, false>), g, b, 0, st, L, tiles, pix, psi, dd, nc, gain, sigma0,
+                               tr, acc);
+    } else {
+        const float *df = (const float *)d;
+        if (nc)
+            hipLaunchKernelGGL((k_bin<TN, float, true>), g, b, 0, st, L, tiles, pix, psi, df, nc, gain, sigma0,
+                               tr, acc);
+        else
+            hipLaunchKernelGGL((k_bin<TN, float, false>), g, b, 0, st, L, tiles, pix, psi, df, nc, gain, sigma0,
+                               tr, acc);
+    }
+}
+
+// maps -> interleaved records, then s = g P m (d == NULL) or r = d - g P m
+template <typename T>
+void launch_resid_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
+                        const uint16_t *psi, const void *d, int d_f64, const void *maps, void *maps4,
+                        const double *gain, const void *trig, void *r_out) {
+    const int64_t npt = L.npix_total;
+    const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
+    hipLaunchKernelGGL(k_interleave<T>, dim3(gi), dim3(C3_NT), 0, st, (const T *)maps, npt, (Stokes4<T> *)maps4);
+    const Stokes4<T> *m4 = (const Stokes4<T> *)maps4;
+    const cx<T> *tr = (const cx<T> *)trig;
+    T *out = (T *)r_out;
+    const dim3 g(ntile), b(C3_NT);
+    if (!d)
+        hipLaunchKernelGGL((k_resid<T, T, false>), g, b, 0, st, L, tiles, pix, psi, (const T *)nullptr, m4, gain,
+                           tr, out);
+    else if (d_f64)
+        hipLaunchKernelGGL((k_resid<T, double, true>), g, b, 0, st, L, tiles, pix, psi, (const double *)d, m4,
+                           gain, tr, out);
+    else
+        hipLaunchKernelGGL((k_resid<T, float, true>), g, b, 0, st, L, tiles, pix, psi, (const float *)d, m4,
+                           gain, tr, out);
+}
+
+template <typename T>
+void launch_chisq_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
+                        const uint16_t *psi, const void *d, int d_f64, const void *ncorr, const void *maps,
+                        void *maps4, const double *gain, const double *sigma0, const void *trig64,
+                        double *seg_sums, double *grad_maps, double grad_scale) {
+    const int64_t npt = L.npix_total;
+    const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
+    hipLaunchKernelGGL(k_interleave<T>, dim3(gi), dim3(C3_NT), 0, st, (const T *)maps, npt, (Stokes4<T> *)maps4);
+    const Stokes4<T> *m4 = (const Stokes4<T> *)maps4;
+    const T *nc = (const T *)ncorr;
+    const cx<double> *tr = (const cx<double> *)trig64;
+    const dim3 g(ntile), b(C3_NT);
+#define C3_CHISQ(TD, GRAD)                                                                              \
+    hipLaunchKernelGGL((k_chisq_time<T, TD, GRAD>), g, b, 0, st, L, tiles, pix, psi, (const TD *)d, nc, m4, \
+                       gain, sigma0, tr, seg_sums, grad_maps, grad_scale)
+    if (d_f64) {
+        if (grad_maps)
+            C3_CHISQ(double, true);
+        else
+            C3_CHISQ(double, false);
+    } else {
+        if (grad_maps)
+            C3_CHISQ(float, true);
+        else
+            C3_CHISQ(float, false);
+    }
+#undef C3_CHISQ
+}
+
 }  // namespace
 
 namespace c3 {
@@ -458,13 +544,11 @@ hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const
                             const double *sigma0, const void *trig64, double *acc) {
     if (ntile <= 0) return hipSuccess;
     if (mixed)
-        hipLaunchKernelGGL(k_bin<float>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
-                           d_f64, (const float *)ncorr, gain, sigma0,
-                           (const cx<double> *)trig64, acc);
+        launch_bin_typed(st, L, tiles, ntile, pix, psi, d, d_f64, (const float *)ncorr, gain, sigma0,
+                         (const cx<double> *)trig64, acc);
     else
-        hipLaunchKernelGGL(k_bin<double>, dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix, psi, d,
-                           d_f64, (const double *)ncorr, gain, sigma0,
-                           (const cx<double> *)trig64, acc);
+        launch_bin_typed(st, L, tiles, ntile, pix, psi, d, d_f64, (const double *)ncorr, gain, sigma0,
+                         (const cx<double> *)trig64, acc);
     return hipGetLastError();
 }
 
@@ -473,31 +557,10 @@ hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, con
                               int d_f64, const void *maps, void *maps4, const double *gain,
                               const void *trig, void *r_out) {
     if (ntile <= 0) return hipSuccess;
-    const int64_t npt = L.npix_total;
-    const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
-    if (mixed) {
-        hipLaunchKernelGGL(k_interleave<float>, dim3(gi), dim3(C3_NT), 0, st, (const float *)maps, npt,
-                           (Stokes4<float> *)maps4);
-        if (d)
-            hipLaunchKernelGGL((k_resid<float, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, (const Stokes4<float> *)maps4, gain,
-                               (const cx<float> *)trig, (float *)r_out);
-        else
-            hipLaunchKernelGGL((k_resid<float, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, (const Stokes4<float> *)maps4, gain,
-                               (const cx<float> *)trig, (float *)r_out);
-    } else {
-        hipLaunchKernelGGL(k_interleave<double>, dim3(gi), dim3(C3_NT), 0, st, (const double *)maps, npt,
-                           (Stokes4<double> *)maps4);
-        if (d)
-            hipLaunchKernelGGL((k_resid<double, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, (const Stokes4<double> *)maps4, gain,
-                               (const cx<double> *)trig, (double *)r_out);
-        else
-            hipLaunchKernelGGL((k_resid<double, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, (const Stokes4<double> *)maps4, gain,
-                               (const cx<double> *)trig, (double *)r_out);
-    }
+    if (mixed)
+        launch_resid_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig, r_out);
+    else
+        launch_resid_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig, r_out);
     return hipGetLastError();
 }
 
@@ -547,32 +610,12 @@ hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed
                                    const void *trig64, double *seg_sums, double *grad_maps,
                                    double grad_scale) {
     if (ntile <= 0) return hipSuccess;
-    const int64_t npt = L.npix_total;
-    const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
-    const cx<double> *tr = (const cx<double> *)trig64;
-    if (mixed) {
-        hipLaunchKernelGGL(k_interleave<float>, dim3(gi), dim3(C3_NT), 0, st, (const float *)maps, npt,
-                           (Stokes4<float> *)maps4);
-        const Stokes4<float> *m4 = (const Stokes4<float> *)maps4;
-        const float *nc = (const float *)ncorr;
-        if (grad_maps)
-            hipLaunchKernelGGL((k_chisq_time<float, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
-        else
-            hipLaunchKernelGGL((k_chisq_time<float, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
-    } else {
-        hipLaunchKernelGGL(k_interleave<double>, dim3(gi), dim3(C3_NT), 0, st, (const double *)maps, npt,
-                           (Stokes4<double> *)maps4);
-        const Stokes4<double> *m4 = (const Stokes4<double> *)maps4;
-        const double *nc = (const double *)ncorr;
-        if (grad_maps)
-            hipLaunchKernelGGL((k_chisq_time<double, true>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
-        else
-            hipLaunchKernelGGL((k_chisq_time<double, false>), dim3(ntile), dim3(C3_NT), 0, st, L, tiles, pix,
-                               psi, d, d_f64, nc, m4, gain, sigma0, tr, seg_sums, grad_maps, grad_scale);
-    }
+    if (mixed)
+        launch_chisq_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, ncorr, maps, maps4, gain, sigma0,
+                                  trig64, seg_sums, grad_maps, grad_scale);
+    else
+        launch_chisq_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, ncorr, maps, maps4, gain, sigma0,
+                                   trig64, seg_sums, grad_maps, grad_scale);
     return hipGetLastError();
 }
 
