@@ -84,6 +84,20 @@ __global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
             // load: 16 rows (32 loads per lane) in flight is plenty
             if ((j1 & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
+    } else if (a.in_b && !a.in_a_f64 && !a.in_b_f64) {
+        // r = in_a - in_b, both FP32 (d and s of a standalone draw): every
+        // load of the column is issued before the first subtraction
+        const float *ra = (const float *)a.in_a + sg.samp_off;
+        const float *rb = (const float *)a.in_b + sg.samp_off;
+#pragma unroll
+        for (int j1 = 0; j1 < M1; ++j1) {
+            const uint32_t t = 2u * (uint32_t)(M2 * j1 + j2);
+            const uint32_t u0 = t < n ? t : (t < n2 ? n2 - 1u - t : 0u);
+            const uint32_t u1 = t + 1u < n ? t + 1u : (t + 1u < n2 ? n2 - 2u - t : 0u);
+            x[j1] = cx<float>{ld_off<float>(ra, 4u * u0) - ld_off<float>(rb, 4u * u0),
+                              ld_off<float>(ra, 4u * u1) - ld_off<float>(rb, 4u * u1)};
+            if ((j1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
     } else {
         // r = in_a - in_b in any input precision, rounded to FP32
         const int64_t s0 = sg.samp_off;
