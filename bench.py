@@ -22,6 +22,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed
+# FP32) x 2.4 GHz.  The kernels here are built without packed FP32
+# instructions, so half of it is the ceiling they can reach.
+FP32_VALU_PEAK_TFLOPS = 157.3
+# families bound by vector-ALU issue rather than by HBM (the counter pass finds
+# the row pass filling about 0.95 of the chip's VALU issue slots)
+ALU_BOUND = {"fft_row"}
 
 
 def log(*a):
@@ -83,20 +90,43 @@ def source_sha(family):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per sweep (all launches of the kernel) from the committed
-    counter summary, if it was taken on the current kernel sources."""
+def measured_counters(kernel, workload):
+    """The committed counter summary of a kernel family (HBM bytes per sweep
+    over all its launches, VALU issue fraction), if it was taken on the
+    current kernel sources; else {}."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
-        return None
+        return {}
     try:
         t = json.load(open(p))
     except ValueError:
-        return None
+        return {}
     e = t.get(workload, {}).get(kernel)
     if not e or kernel not in FAMILY_SOURCES or e.get("source_sha") != source_sha(kernel):
-        return None
-    return e.get("bytes_per_step")
+        return {}
+    return e
+
+
+def row_pass_flops(ts, tuned):
+    """Algorithmic FP32 flops of the row passes of one sweep.  A segment of
+    M = M1 x M2 complex points has M1 rows: each is transformed forward and
+    back (5 M2 log2 M2 flops each, the conventional count), and each of its M
+    modes takes about 30 flops for the real-spectrum split, the
+    constrained-realisation filter and the re-pack.  The Philox and
+    Box-Muller work (integer and transcendental) is not counted."""
+    import math
+    import numpy as np
+    m2_of = {int(e["M"]): int(e["M2"]) for e in tuned.get("fft", []) if e.get("mixed") == 1}
+    fl = 0.0
+    for n in np.diff(ts.seg_off):
+        if n <= 0:
+            continue
+        M = next5(int(n))
+        M2 = m2_of.get(M)
+        if M2 is None:
+            return None
+        fl += 10.0 * M * math.log2(M2) + 30.0 * M
+    return fl
 
 
 # ------------------------------------------------------------- CPU baseline
@@ -673,17 +703,28 @@ def main():
     avg_ms = per[dom]["ms_per_step"]
     ach = kb[dom] / (avg_ms / 1e3) / 1e9
     workload = "lfi70" if args.config == 2 and args.nscan is None else "config%d_nscan%s" % (args.config, args.nscan)
-    traffic = measured_traffic(dom, workload)
-    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-            "bytes_per_step": kb[dom], "ms_per_step": round(avg_ms, 4),
-            "launches_per_step": per[dom]["launches_per_step"]}
+    meas = measured_counters(dom, workload)
+    traffic = meas.get("bytes_per_step")
+    fl = row_pass_flops(ts, tuned) if dom in ALU_BOUND else None
+    if fl is not None:
+        tfs = fl / (avg_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfs / FP32_VALU_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": dom,
+                "flops_per_step": fl, "valu_issue": meas.get("valu_issue"),
+                "hbm_compulsory_gbs": round(ach, 1), "ms_per_step": round(avg_ms, 4),
+                "launches_per_step": per[dom]["launches_per_step"]}
+    else:
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_step": kb[dom], "ms_per_step": round(avg_ms, 4),
+                "launches_per_step": per[dom]["launches_per_step"]}
     # fused-sweep minimum: the compressed pointing (words, side index, tables)
     # decoded twice, d read once, n_corr written once, map + accumulators once
     comp = sum(h.words.nbytes + h.chunk_bit.nbytes + h.chunk_prev.nbytes + h.tables.nbytes
                for h in (ts.pix_huff, ts.psi_huff))
     sweep_alg = 2 * comp + ts.nsamp * (4 + 4) + 84 * ts.npix_total
-    log("dominant kernel %s: %.3f ms per sweep, %.0f GB/s compulsory" % (dom, avg_ms, ach))
+    log("dominant kernel %s: %.3f ms per sweep, %.0f GB/s compulsory, roofline %s %s %s of %s" % (
+        dom, avg_ms, ach, roof["bound"], roof["achieved"], roof["unit"], roof["peak"]))
 
     plain = None
     if not args.no_plain:
