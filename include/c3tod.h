@@ -301,6 +301,9 @@ tod_status solve_maps(tod_ctx ctx, int64_t npix, const double *acc, double rcond
  *   J_s = sum_t r_t^2/sigma0^2 + sum_{k=1}^{N/2} (I_k/P_k + ln P_k),
  *   r = d - g P m - n_corr,  I_k = |FFT(e(n_corr))_k|^2 / N on the same
  *   mirrored extension and N as sample_ncorr.
+ * pix, psi: device [nsamp]; d: device [nsamp] of d_dtype; ncorr: device
+ * [nsamp] (FP32 mixed / FP64 plain, required); maps: device [3][npix_total]
+ * of the precision's type; gain, sigma0, fknee, alpha: device [nseg] FP64.
  * chisq_seg: device [nseg] FP64 (0 for rejected segments).  Samples whose
  * pixel is out of range for their band are left out of the time-domain sum.
  * The time-domain terms walk strided tiles of the band's revisit period
