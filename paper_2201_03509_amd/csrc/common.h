@@ -263,7 +263,7 @@ struct CgVecArgs {
     const void *d;              // INIT: residual d - s and the mask (per sample)
     int d_f64;
     const void *s;
-    int s_f64;
+    int s_f64;                  // must match the precision (FP64 s for the plain path)
     const uint8_t *mask;        // 1: sample used, 0: masked
     const double *sigma0;
     const void *w1;             // INIT: F^H W1

@@ -298,20 +298,40 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
     const cx<T> *pool = (const cx<T> *)a.twpool;
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
     const int tot = M1 * B;
-    for (int i = threadIdx.x; i < tot; i += C3_NT) {
-        const int j1 = i >> lb, c = i & (B - 1);
-        const int j2 = col0 + c;
-        cx<T> v = {0, 0};
-        if (j2 < M2) {
-            const int64_t j = (int64_t)M2 * j1 + j2;
-            if (a.full_io) {
-                v = ((const cx<T> *)a.in_a)[sg.ext_off + j];
-            } else {
-                v.x = ext_at<T>(a, sg.samp_off, sg.n, 2 * j);
-                v.y = ext_at<T>(a, sg.samp_off, sg.n, 2 * j + 1);
+    if (!a.full_io && !a.in_b && a.in_a_f64 == (sizeof(T) == 8)) {
+        // one input of the transform's own type (the sweep's residual): plain
+        // loads with no type branch, several elements' loads in flight
+        const T *r = (const T *)a.in_a + sg.samp_off;
+        const int64_t n = sg.n, n2 = 2 * (int64_t)sg.n;
+#pragma unroll 4
+        for (int i = threadIdx.x; i < tot; i += C3_NT) {
+            const int j1 = i >> lb, c = i & (B - 1);
+            const int j2 = col0 + c;
+            cx<T> v = {0, 0};
+            if (j2 < M2) {
+                const int64_t t = 2 * ((int64_t)M2 * j1 + j2);
+                const int64_t u0 = t < n ? t : (t < n2 ? n2 - 1 - t : 0);
+                const int64_t u1 = t + 1 < n ? t + 1 : (t + 1 < n2 ? n2 - 2 - t : 0);
+                v = cx<T>{r[u0], r[u1]};
             }
+            buf[i] = v;
         }
-        buf[i] = v;
+    } else {
+        for (int i = threadIdx.x; i < tot; i += C3_NT) {
+            const int j1 = i >> lb, c = i & (B - 1);
+            const int j2 = col0 + c;
+            cx<T> v = {0, 0};
+            if (j2 < M2) {
+                const int64_t j = (int64_t)M2 * j1 + j2;
+                if (a.full_io) {
+                    v = ((const cx<T> *)a.in_a)[sg.ext_off + j];
+                } else {
+                    v.x = ext_at<T>(a, sg.samp_off, sg.n, 2 * j);
+                    v.y = ext_at<T>(a, sg.samp_off, sg.n, 2 * j + 1);
+                }
+            }
+            buf[i] = v;
+        }
     }
     __syncthreads();
     const cx<T> *res = lds_fft<-1, C3_NT>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
@@ -508,6 +528,22 @@ __device__ __forceinline__ int xi_bin(int64_t k) {
     return 7 + 8 * (e - 3) + (int)(k >> (e - 3)) - 8;
 }
 
+// hist[b] += v over the lanes of a wave (b < 0: the lane has no value).  When
+// every lane with a value shares lane 0's bin the wave sums them and adds
+// once; otherwise each lane adds its own.  All lanes of the wave call it
+// together.
+__device__ __forceinline__ void hist_add(double *hist, int b, double v) {
+    const int b0 = __builtin_amdgcn_readfirstlane(b);
+    if (b0 >= 0 && __all(b == b0 || b < 0)) {
+        double x = b < 0 ? 0.0 : v;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&hist[b0], x);
+    } else if (b >= 0) {
+        atomicAdd(&hist[b], v);
+    }
+}
+
 // ------------------------------------------------------------- pass 2
 template <typename T>
 constexpr int row_nt() { return sizeof(T) == 4 ? C3_ROW_NT_F32 : C3_ROW_NT_F64; }
@@ -579,96 +615,137 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     const T half = (T)0.5;
     const T osc = (T)mc.outscale;
 
-    // pair (element e of row a, its mirror-mode partner); w_N^k of the next
-    // iteration is fetched while this one computes
-    cx<T> w_next = twN(pool, p, ka + (int64_t)M1 * min((int)threadIdx.x, M2 - 1));
-    for (int k2 = threadIdx.x; k2 < M2; k2 += NT) {
-        const cx<T> w = w_next;  // w_N^k
-        if (k2 + NT < M2) w_next = twN(pool, p, ka + (int64_t)M1 * (k2 + NT));
-        int pk2, prow;  // partner position
-        if (ka == 0) {
-            pk2 = (M2 - k2) % M2;
-            prow = 0;
-        } else {
-            pk2 = M2 - 1 - k2;
-            prow = two;  // row b (or row a when single)
+    if constexpr (MODE == 4) {
+        // periodogram of the spectrum into the block's LDS histogram.  A wave
+        // covers 64 consecutive k2, modes M1 apart: above k ~ 2^15 its lanes
+        // mostly share one bin, and one wave sum replaces 64 colliding atomics
+        const double s2 = mc.invsqrtN * mc.invsqrtN;
+        for (int base = 0; base < M2; base += NT) {
+            const int k2 = base + (int)threadIdx.x;
+            int bk = -1, bp = -1;
+            double vk = 0.0, vp = 0.0;
+            if (k2 < M2) {
+                int pk2, prow;  // partner position
+                if (ka == 0) {
+                    pk2 = (M2 - k2) % M2;
+                    prow = 0;
+                } else {
+                    pk2 = M2 - 1 - k2;
+                    prow = two;
+                }
+                const int ea = k2 * si, eb = pk2 * si + prow;
+                const int64_t k = ka + (int64_t)M1 * k2;
+                const cx<T> Za = buf[ea], Zb = buf[eb];
+                if (k == 0) {  // E_M = Re Z0 - Im Z0 (real); the DC mode is left out
+                    const T em = Za.x - Za.y;
+                    vk = (double)em * em * s2;
+                    bk = xi_bin(M);
+                } else if (two || pk2 >= k2) {  // single row: each pair once
+                    const cx<T> w = twN(pool, p, k);
+                    const cx<T> Ak = {half * (Za.x + Zb.x), half * (Za.y - Zb.y)};
+                    const cx<T> Dk = {half * (Za.x - Zb.x), half * (Za.y + Zb.y)};
+                    const cx<T> Bk = {Dk.y, -Dk.x};
+                    const cx<T> Ek = cadd(Ak, cmul(w, Bk));
+                    const cx<T> wp = {-w.x, w.y};
+                    const cx<T> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
+                    vk = ((double)Ek.x * Ek.x + (double)Ek.y * Ek.y) * s2;
+                    bk = xi_bin(k);
+                    const int64_t kp = (int64_t)M - k;
+                    if (kp != k) {
+                        vp = ((double)Ep.x * Ep.x + (double)Ep.y * Ep.y) * s2;
+                        bp = xi_bin(kp);
+                    }
+                }
+            }
+            hist_add(hist, bk, vk);
+            hist_add(hist, bp, vp);
         }
-        if (!two && pk2 < k2) continue;  // single row: each pair once
-        const int ea = k2 * si, eb = pk2 * si + prow;
-        const int64_t k = ka + (int64_t)M1 * k2;
-        cx<T> Za = {0, 0}, Zb = {0, 0};
-        if constexpr (MODE != 3) {
-            Za = buf[ea];
-            Zb = buf[eb];
-        }
-        if (k == 0) {
-            // E_0 = Re Z0 + Im Z0, E_M = Re Z0 - Im Z0 (both real)
-            const cx<T> E0 = {Za.x + Za.y, 0}, EM = {Za.x - Za.y, 0};
-            if constexpr (MODE == 1) {
-                whittle_mode(mc, M, EM, ws);
-            } else if constexpr (MODE == 4) {  // DC excluded
-                atomicAdd(&hist[xi_bin(M)], (double)EM.x * EM.x * mc.invsqrtN * mc.invsqrtN);
+    } else {
+        // pair (element e of row a, its mirror-mode partner); w_N^k of the next
+        // iteration is fetched while this one computes
+        cx<T> w_next = twN(pool, p, ka + (int64_t)M1 * min((int)threadIdx.x, M2 - 1));
+        for (int k2 = threadIdx.x; k2 < M2; k2 += NT) {
+            const cx<T> w = w_next;  // w_N^k
+            if (k2 + NT < M2) w_next = twN(pool, p, ka + (int64_t)M1 * (k2 + NT));
+            int pk2, prow;  // partner position
+            if (ka == 0) {
+                pk2 = (M2 - k2) % M2;
+                prow = 0;
             } else {
-                cx<T> n0, nM;
+                pk2 = M2 - 1 - k2;
+                prow = two;  // row b (or row a when single)
+            }
+            if (!two && pk2 < k2) continue;  // single row: each pair once
+            const int ea = k2 * si, eb = pk2 * si + prow;
+            const int64_t k = ka + (int64_t)M1 * k2;
+            cx<T> Za = {0, 0}, Zb = {0, 0};
+            if constexpr (MODE != 3) {
+                Za = buf[ea];
+                Zb = buf[eb];
+            }
+            if (k == 0) {
+                // E_0 = Re Z0 + Im Z0, E_M = Re Z0 - Im Z0 (both real)
+                const cx<T> E0 = {Za.x + Za.y, 0}, EM = {Za.x - Za.y, 0};
+                if constexpr (MODE == 1) {
+                    whittle_mode(mc, M, EM, ws);
+                } else {
+                    cx<T> n0, nM;
+                    if constexpr (MODE == 0) {
+                        n0 = cr_mode(mc, 0, E0);
+                        nM = cr_mode(mc, M, EM);
+                    } else if constexpr (MODE == 2) {
+                        n0 = a.which == 3 ? x0_mode(mc, 0, E0) : filt_mode(mc, 0, E0, a.which);
+                        nM = a.which == 3 ? x0_mode(mc, M, EM) : filt_mode(mc, M, EM, a.which);
+                    } else {
+                        n0 = draw_mode<T>(mc, 0, a.which);
+                        nM = draw_mode<T>(mc, M, a.which);
+                    }
+                    buf[ea] = cx<T>{half * osc * (n0.x + nM.x), half * osc * (n0.x - nM.x)};
+                }
+                continue;
+            }
+            const int64_t kp = (int64_t)M - k;
+            // A = (Zk + conj Zp)/2, B = -i (Zk - conj Zp)/2, E_k = A + w_N^k B
+            const cx<T> Ak = {half * (Za.x + Zb.x), half * (Za.y - Zb.y)};
+            const cx<T> Dk = {half * (Za.x - Zb.x), half * (Za.y + Zb.y)};
+            const cx<T> Bk = {Dk.y, -Dk.x};
+            const cx<T> Ek = cadd(Ak, cmul(w, Bk));
+            // partner: A_p = conj A_k, B_p = conj B_k, w_N^p = -conj(w_N^k)
+            const cx<T> wp = {-w.x, w.y};
+            const cx<T> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
+            if constexpr (MODE != 1) {
+                cx<T> nk, np;
                 if constexpr (MODE == 0) {
-                    n0 = cr_mode(mc, 0, E0);
-                    nM = cr_mode(mc, M, EM);
+                    nk = cr_mode(mc, k, Ek);
+                    np = (kp == k) ? nk : cr_mode(mc, kp, Ep);
                 } else if constexpr (MODE == 2) {
-                    n0 = a.which == 3 ? x0_mode(mc, 0, E0) : filt_mode(mc, 0, E0, a.which);
-                    nM = a.which == 3 ? x0_mode(mc, M, EM) : filt_mode(mc, M, EM, a.which);
+                    if (a.which == 3) {
+                        nk = x0_mode(mc, k, Ek);
+                        np = (kp == k) ? nk : x0_mode(mc, kp, Ep);
+                    } else {
+                        nk = filt_mode(mc, k, Ek, a.which);
+                        np = (kp == k) ? nk : filt_mode(mc, kp, Ep, a.which);
+                    }
                 } else {
-                    n0 = draw_mode<T>(mc, 0, a.which);
-                    nM = draw_mode<T>(mc, M, a.which);
+                    nk = draw_mode<T>(mc, k, a.which);
+                    np = (kp == k) ? nk : draw_mode<T>(mc, kp, a.which);
                 }
-                buf[ea] = cx<T>{half * osc * (n0.x + nM.x), half * osc * (n0.x - nM.x)};
-            }
-            continue;
-        }
-        const int64_t kp = (int64_t)M - k;
-        // A = (Zk + conj Zp)/2, B = -i (Zk - conj Zp)/2, E_k = A + w_N^k B
-        const cx<T> Ak = {half * (Za.x + Zb.x), half * (Za.y - Zb.y)};
-        const cx<T> Dk = {half * (Za.x - Zb.x), half * (Za.y + Zb.y)};
-        const cx<T> Bk = {Dk.y, -Dk.x};
-        const cx<T> Ek = cadd(Ak, cmul(w, Bk));
-        // partner: A_p = conj A_k, B_p = conj B_k, w_N^p = -conj(w_N^k)
-        const cx<T> wp = {-w.x, w.y};
-        const cx<T> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
-        if constexpr (MODE == 4) {
-            const double s2 = mc.invsqrtN * mc.invsqrtN;
-            atomicAdd(&hist[xi_bin(k)], ((double)Ek.x * Ek.x + (double)Ek.y * Ek.y) * s2);
-            if (kp != k) atomicAdd(&hist[xi_bin(kp)], ((double)Ep.x * Ep.x + (double)Ep.y * Ep.y) * s2);
-        } else if constexpr (MODE != 1) {
-            cx<T> nk, np;
-            if constexpr (MODE == 0) {
-                nk = cr_mode(mc, k, Ek);
-                np = (kp == k) ? nk : cr_mode(mc, kp, Ep);
-            } else if constexpr (MODE == 2) {
-                if (a.which == 3) {
-                    nk = x0_mode(mc, k, Ek);
-                    np = (kp == k) ? nk : x0_mode(mc, kp, Ep);
-                } else {
-                    nk = filt_mode(mc, k, Ek, a.which);
-                    np = (kp == k) ? nk : filt_mode(mc, kp, Ep, a.which);
-                }
+                // Z'_k = (nk + conj np)/2 + i (nk - conj np) conj(w_N^k)/2, scaled
+                const cx<T> Ap = {half * (nk.x + np.x), half * (nk.y - np.y)};
+                const cx<T> Dp = {half * (nk.x - np.x), half * (nk.y + np.y)};
+                const cx<T> Bp = cmulc(Dp, w);
+                const cx<T> Zk = {osc * (Ap.x - Bp.y), osc * (Ap.y + Bp.x)};
+                // partner: A'_p = conj A'_k, B'_p = -conj(D') conj(w_N^p) = conj(D') w_N^k
+                const cx<T> Bq = cmul(cconj(Dp), w);
+                const cx<T> Zq = {osc * (Ap.x - Bq.y), osc * (-Ap.y + Bq.x)};
+                buf[ea] = Zk;
+                if (eb != ea) buf[eb] = Zq;
             } else {
-                nk = draw_mode<T>(mc, k, a.which);
-                np = (kp == k) ? nk : draw_mode<T>(mc, kp, a.which);
+                whittle_mode(mc, k, Ek, ws);
+                if (kp != k) whittle_mode(mc, kp, Ep, ws);
             }
-            // Z'_k = (nk + conj np)/2 + i (nk - conj np) conj(w_N^k)/2, scaled
-            const cx<T> Ap = {half * (nk.x + np.x), half * (nk.y - np.y)};
-            const cx<T> Dp = {half * (nk.x - np.x), half * (nk.y + np.y)};
-            const cx<T> Bp = cmulc(Dp, w);
-            const cx<T> Zk = {osc * (Ap.x - Bp.y), osc * (Ap.y + Bp.x)};
-            // partner: A'_p = conj A'_k, B'_p = -conj(D') conj(w_N^p) = conj(D') w_N^k
-            const cx<T> Bq = cmul(cconj(Dp), w);
-            const cx<T> Zq = {osc * (Ap.x - Bq.y), osc * (-Ap.y + Bq.x)};
-            buf[ea] = Zk;
-            if (eb != ea) buf[eb] = Zq;
-        } else {
-            whittle_mode(mc, k, Ek, ws);
-            if (kp != k) whittle_mode(mc, kp, Ep, ws);
         }
-    }
+    }  // MODE != 4
     if constexpr (MODE == 4) {
         __syncthreads();
         for (int i = threadIdx.x; i < C3_XI_NBIN; i += NT)

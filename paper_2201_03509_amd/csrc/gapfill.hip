@@ -32,10 +32,6 @@
 namespace {
 using namespace c3;
 
-__device__ __forceinline__ double ldd(const void *p, int f64, int64_t i) {
-    return f64 ? ((const double *)p)[i] : (double)((const float *)p)[i];
-}
-
 // position of extended index t in the segment: the mirror of the extension;
 // -1 in the pad (mask 1, value r_0)
 __device__ __forceinline__ int64_t mirror(int64_t t, int n) {
@@ -67,26 +63,38 @@ __device__ __forceinline__ void block_sum(double v, double *part) {
 __device__ __forceinline__ int64_t gap_first(int4 tl) { return ((int64_t)tl.w << 31) | (uint32_t)tl.y; }
 
 // mu u = mu (e / s0^2 + w1 / s0) -> res.  Extended reals in pairs: N and
-// every tile length are even.
-template <typename T>
+// every tile length are even.  d of type TD, s of the precision's type T and
+// the presence of the drawn term are compile-time, so a pair's loads issue
+// together.
+template <typename T, typename TD, bool DRAW>
 __global__ __launch_bounds__(C3_NT) void k_cg_init(const int4 *__restrict__ tiles, const SegInfo *__restrict__ segs,
-                                                   const void *d, int d_f64, const void *s, int s_f64,
+                                                   const TD *__restrict__ d, const T *__restrict__ s,
                                                    const uint8_t *__restrict__ mask, const T *__restrict__ w1,
-                                                   const double *__restrict__ sigma0, int have_draw,
-                                                   T *__restrict__ res) {
+                                                   const double *__restrict__ sigma0, T *__restrict__ res) {
     const int4 tl = tiles[blockIdx.x];
     const SegInfo sg = segs[tl.x];
     const double s0 = sigma0[tl.x], is2 = 1.0 / (s0 * s0), is1 = 1.0 / s0;
     const int64_t base = 2 * sg.ext_off + tl.y;
     for (int i = 2 * threadIdx.x; i < tl.z; i += 2 * C3_NT) {
-        double b[2];
-        const cx<T> w = have_draw ? *(const cx<T> *)(w1 + base + i) : cx<T>{0, 0};
+        cx<T> w = {0, 0};
+        if constexpr (DRAW) w = *(const cx<T> *)(w1 + base + i);
+        int64_t u[2], j[2];
+        TD dv[2];
+        T sv[2];
+        uint8_t mk[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int64_t u = mirror(tl.y + i + h, sg.n);
-            const int64_t j = sg.samp_off + (u < 0 ? 0 : u);
-            const double e = ldd(d, d_f64, j) - ldd(s, s_f64, j);
-            const double m = u < 0 ? 1.0 : (double)(mask[j] != 0);
+            u[h] = mirror(tl.y + i + h, sg.n);
+            j[h] = sg.samp_off + (u[h] < 0 ? 0 : u[h]);
+            dv[h] = d[j[h]];
+            sv[h] = s[j[h]];
+            mk[h] = mask[j[h]];
+        }
+        double b[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double e = (double)dv[h] - (double)sv[h];
+            const double m = u[h] < 0 ? 1.0 : (double)(mk[h] != 0);
             b[h] = m * (e * is2 + (double)(h ? w.y : w.x) * is1);
         }
         *(cx<T> *)(res + base + i) = cx<T>{(T)b[0], (T)b[1]};
@@ -313,18 +321,32 @@ __global__ __launch_bounds__(C3_NT) void k_fill_zero(T *__restrict__ v, int64_t 
     for (int64_t i = (int64_t)blockIdx.x * C3_NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * C3_NT) v[i] = (T)0;
 }
 
+// s is of the precision's type (the entry point passes it so)
+template <typename T, typename TD>
+void launch_cg_init(hipStream_t st, dim3 g, dim3 b, const c3::CgVecArgs &a) {
+    if (a.have_draw)
+        hipLaunchKernelGGL((k_cg_init<T, TD, true>), g, b, 0, st, a.tiles, a.segs, (const TD *)a.d, (const T *)a.s,
+                           a.mask, (const T *)a.w1, a.sigma0, (T *)a.res);
+    else
+        hipLaunchKernelGGL((k_cg_init<T, TD, false>), g, b, 0, st, a.tiles, a.segs, (const TD *)a.d,
+                           (const T *)a.s, a.mask, (const T *)a.w1, a.sigma0, (T *)a.res);
+}
+
 }  // namespace
 
 namespace c3 {
 
 hipError_t launch_cg_vec(hipStream_t st, int mixed, int op, const CgVecArgs &a) {
     if (a.ntile <= 0) return hipSuccess;
+    if (op == CG_OP_INIT && a.s_f64 != (mixed ? 0 : 1)) return hipErrorInvalidValue;  // s: the precision's type
     const dim3 g((unsigned)a.ntile), b(C3_NT);
 #define C3_CG_OPS(T)                                                                                          \
     switch (op) {                                                                                             \
     case CG_OP_INIT:                                                                                          \
-        hipLaunchKernelGGL(k_cg_init<T>, g, b, 0, st, a.tiles, a.segs, a.d, a.d_f64, a.s, a.s_f64, a.mask,     \
-                           (const T *)a.w1, a.sigma0, a.have_draw, (T *)a.res);                                \
+        if (a.d_f64)                                                                                          \
+            launch_cg_init<T, double>(st, g, b, a);                                                           \
+        else                                                                                                  \
+            launch_cg_init<T, float>(st, g, b, a);                                                            \
         break;                                                                                                \
     case CG_OP_GAP_COUNT:                                                                                     \
         hipLaunchKernelGGL(k_gap_count, g, b, 0, st, a.tiles, a.segs, a.mask, a.cnt);                         \

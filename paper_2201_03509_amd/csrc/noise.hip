@@ -21,19 +21,20 @@ namespace {
 using namespace c3;
 using namespace c3rng;
 
-// per sample tile: partial sum of (d - g t - n_corr)^2
-template <typename T>
+// per sample tile: partial sum of (d - g t - n_corr)^2 (d of type TD, fixed at
+// compile time so that the loads of several samples issue together)
+template <typename T, typename TD>
 __global__ __launch_bounds__(C3_NT) void k_xi_white(const int4 *__restrict__ tiles, const int64_t *__restrict__ seg_off,
-                                                    const void *d, int d_f64, const T *__restrict__ t,
+                                                    const TD *__restrict__ d, const T *__restrict__ t,
                                                     const double *__restrict__ gain, const T *__restrict__ nc,
                                                     double *__restrict__ part) {
     const int4 tl = tiles[blockIdx.x];
     const int64_t base = seg_off[tl.x] + tl.y;
     const double g = gain[tl.x];
     double acc = 0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < tl.z; i += C3_NT) {
-        const double dv = d_f64 ? ((const double *)d)[base + i] : (double)((const float *)d)[base + i];
-        const double r = dv - g * (double)t[base + i] - (double)nc[base + i];
+        const double r = (double)d[base + i] - g * (double)t[base + i] - (double)nc[base + i];
         acc += r * r;
     }
     __shared__ double red[C3_NT / 64];
@@ -192,12 +193,22 @@ hipError_t launch_xi_white(hipStream_t st, int mixed, const int4 *tiles, int nti
                            const void *d, int d_f64, const void *t, const double *gain, const void *nc,
                            double *part) {
     if (ntile <= 0) return hipSuccess;
-    if (mixed)
-        hipLaunchKernelGGL(k_xi_white<float>, dim3((unsigned)ntile), dim3(C3_NT), 0, st, tiles, seg_off, d, d_f64,
-                           (const float *)t, gain, (const float *)nc, part);
-    else
-        hipLaunchKernelGGL(k_xi_white<double>, dim3((unsigned)ntile), dim3(C3_NT), 0, st, tiles, seg_off, d,
-                           d_f64, (const double *)t, gain, (const double *)nc, part);
+    const dim3 g((unsigned)ntile), b(C3_NT);
+#define C3_XIW(T, TD)                                                                                    \
+    hipLaunchKernelGGL((k_xi_white<T, TD>), g, b, 0, st, tiles, seg_off, (const TD *)d, (const T *)t, gain, \
+                       (const T *)nc, part)
+    if (mixed) {
+        if (d_f64)
+            C3_XIW(float, double);
+        else
+            C3_XIW(float, float);
+    } else {
+        if (d_f64)
+            C3_XIW(double, double);
+        else
+            C3_XIW(double, float);
+    }
+#undef C3_XIW
     return hipGetLastError();
 }
 

@@ -15,11 +15,6 @@
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ T ld(const void *p, int f64, int64_t i) {
-    return f64 ? (T)((const double *)p)[i] : (T)((const float *)p)[i];
-}
-
 // ---------------------------------------------------------------- binning
 __device__ __forceinline__ void flush_acc(double *acc, int64_t gp, const double *a) {
     double *dst = acc + gp * 10;
