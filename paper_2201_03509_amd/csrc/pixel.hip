@@ -51,18 +51,21 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     const int seg0 = tl.x;
     const int64_t poff = Ld.band[Ld.seg_band[seg0]].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg0]].npix;
-    // two register accumulators: the current pixel and the one before it, so a
-    // phase that crosses a pixel edge (or alternates between two segments'
-    // pixels) rarely flushes early
-    double a[10], o[10];
+    // three register accumulators, the current pixel and the two before it
+    // (most recent first), so a phase that crosses pixel edges or alternates
+    // between pixels rarely flushes before its tile ends.  A flush inside the
+    // loop is costly beyond its atomics: loads and atomics share one in-order
+    // completion counter, so the next revisit's loads also wait for them.  On
+    // the 70 GHz-like set no lane meets a fourth pixel within a tile.
+    double a[10], o[10], q[10];
 #pragma unroll
-    for (int j = 0; j < 10; ++j) a[j] = o[j] = 0.0;
-    int cur = -1, old = -1;
+    for (int j = 0; j < 10; ++j) a[j] = o[j] = q[j] = 0.0;
+    int cur = -1, old = -1, older = -1;
     double w = 0, gw = 0;
     auto step = [&](int p, int b, double v) {
         if ((uint32_t)p >= npix) return;  // out-of-range pixels are not binned
         if (p != cur) {
-            if (p == old) {
+            if (p == old) {  // a <-> o
 #pragma unroll
                 for (int j = 0; j < 10; ++j) {
                     const double x = a[j];
@@ -71,13 +74,26 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
                 }
                 old = cur;
                 cur = p;
-            } else {
-                if (old >= 0) flush_acc(acc, poff + old, o);
+            } else if (p == older) {  // q -> a -> o -> q
 #pragma unroll
                 for (int j = 0; j < 10; ++j) {
+                    const double x = q[j];
+                    q[j] = o[j];
+                    o[j] = a[j];
+                    a[j] = x;
+                }
+                older = old;
+                old = cur;
+                cur = p;
+            } else {  // a new pixel: the least recent one leaves
+                if (older >= 0) flush_acc(acc, poff + older, q);
+#pragma unroll
+                for (int j = 0; j < 10; ++j) {
+                    q[j] = o[j];
                     o[j] = a[j];
                     a[j] = 0.0;
                 }
+                older = old;
                 old = cur;
                 cur = p;
             }
@@ -135,6 +151,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     }
     if (cur >= 0) flush_acc(acc, poff + cur, a);
     if (old >= 0) flush_acc(acc, poff + old, o);
+    if (older >= 0) flush_acc(acc, poff + older, q);
 }
 
 // ---------------------------------------------------------------- projection
@@ -349,20 +366,52 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
     const int64_t npt = Ld.npix_total;
-    int cur = -1;
+    // map-adjoint sums of the current pixel and the two before it (most
+    // recent first), flushed when a fourth pixel arrives or the tile ends (as
+    // in the binning: a flush inside the loop also delays the next loads)
+    int cur = -1, old = -1, older = -1;
     double mT = 0, mQ = 0, mU = 0;  // map values of pixel cur
-    double a0 = 0, a1 = 0, a2 = 0;  // its map-adjoint sums
+    double a[3] = {0, 0, 0}, o[3] = {0, 0, 0}, q[3] = {0, 0, 0};
     double g = 0, cfac = 0, sr2 = 0, spr = 0;
-    auto flush = [&]() {
-        atomicAdd(gmap + poff + cur, a0);
-        atomicAdd(gmap + npt + poff + cur, a1);
-        atomicAdd(gmap + 2 * npt + poff + cur, a2);
+    auto flush = [&](int pp, const double *x) {
+        atomicAdd(gmap + poff + pp, x[0]);
+        atomicAdd(gmap + npt + poff + pp, x[1]);
+        atomicAdd(gmap + 2 * npt + poff + pp, x[2]);
     };
     auto step = [&](int p, int b, double dv, double nc) {
         if ((uint32_t)p >= npix) return;  // out-of-range pixels are not in the likelihood
         if (p != cur) {
-            if (GRAD && cur >= 0) flush();
-            a0 = a1 = a2 = 0;
+            if constexpr (GRAD) {
+                if (p == old) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const double x = a[j];
+                        a[j] = o[j];
+                        o[j] = x;
+                    }
+                    old = cur;
+                } else if (p == older) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const double x = q[j];
+                        q[j] = o[j];
+                        o[j] = a[j];
+                        a[j] = x;
+                    }
+                    older = old;
+                    old = cur;
+                } else {
+                    if (older >= 0) flush(older, q);
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        q[j] = o[j];
+                        o[j] = a[j];
+                        a[j] = 0.0;
+                    }
+                    older = old;
+                    old = cur;
+                }
+            }
             cur = p;
             const Stokes4<T> m = maps[poff + p];
             mT = m.t;
@@ -374,11 +423,11 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
         const double r = dv - g * Pm - nc;
         sr2 += r * r;
         spr += Pm * r;
-        if (GRAD) {
+        if constexpr (GRAD) {
             const double cr = cfac * r;
-            a0 += cr;
-            a1 += cr * cs.x;
-            a2 += cr * cs.y;
+            a[0] += cr;
+            a[1] += cr * cs.x;
+            a[2] += cr * cs.y;
         }
     };
     for (int gi = 0; gi < ngrp; ++gi) {
@@ -426,7 +475,11 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
         }
         __syncthreads();
     }
-    if (GRAD && cur >= 0) flush();
+    if constexpr (GRAD) {
+        if (cur >= 0) flush(cur, a);
+        if (old >= 0) flush(old, o);
+        if (older >= 0) flush(older, q);
+    }
 }
 
 __global__ __launch_bounds__(C3_NT) void k_chisq_finish(
