@@ -109,38 +109,45 @@ __device__ __forceinline__ uint32_t buf_word(__amdgpu_buffer_rsrc_t r, uint32_t 
 }
 
 // MSB-first bit reader over one segment's stream (a raw buffer, so reads
-// past the end give zero bits), two doublewords of look-ahead in registers
+// past the end give zero bits).  Look-ahead: three pairs of words in stream
+// order, kept as loaded (no reordering at load time).  A pair is loaded two
+// pair-lengths before its first word is used, so the wait for it falls long
+// after the load was issued.
 struct BitReader {
     __amdgpu_buffer_rsrc_t rs;
-    unsigned long long buf, n0, n1;
-    uint32_t wp;
-    int nbits, nh;
+    unsigned long long buf;  // next bits, MSB first; nbits of them valid
+    uint2 n0, n1, n2;        // look-ahead words n0.x, n0.y, n1.x, ... in stream order
+    uint32_t wp;             // next word to load
+    int nbits, nh;           // nh: words of n0 not yet taken (2, 1 or 0)
 
-    __device__ __forceinline__ unsigned long long load2(uint32_t p) const {
-        return ((unsigned long long)buf_word(rs, p) << 32) | buf_word(rs, p + 1u);
+    __device__ __forceinline__ uint2 load2(uint32_t p) const {
+        return make_uint2(buf_word(rs, p), buf_word(rs, p + 1u));
     }
     __device__ void init(__amdgpu_buffer_rsrc_t r, uint32_t bit) {
         rs = r;
         const uint32_t p = bit >> 5;
         const int s = bit & 31;
-        buf = load2(p) << s;
+        const uint2 w = load2(p);
+        buf = (((unsigned long long)w.x << 32) | w.y) << s;
         nbits = 64 - s;
         n0 = load2(p + 2u);
         n1 = load2(p + 4u);
+        n2 = load2(p + 6u);
         nh = 2;
-        wp = p + 6u;
+        wp = p + 8u;
     }
     __device__ __forceinline__ void refill() {
         const bool need = nbits < 32;
+        const uint32_t word = nh == 2 ? n0.x : n0.y;
         const int sh = need ? 32 - nbits : 0;
-        buf |= need ? (n0 >> 32) << sh : 0ull;
+        buf |= need ? (unsigned long long)word << sh : 0ull;
         nbits += need ? 32 : 0;
-        n0 = need ? n0 << 32 : n0;
         nh -= need ? 1 : 0;
-        if (nh == 0) {  // every second refill: next doubleword from memory
+        if (nh == 0) {  // every second refill: the pairs move up, one more is loaded
             n0 = n1;
+            n1 = n2;
             nh = 2;
-            n1 = load2(wp);
+            n2 = load2(wp);
             wp += 2u;
         }
     }
