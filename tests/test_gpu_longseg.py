@@ -7,9 +7,10 @@ points.  The FP32 plans split them into LDS column tiles of 128, 600 and
 1200 points with rows of 4096 and 5000.  The FP64 plans reach
 2048 x 2520 complex points, so the 6e6-sample segment has no FP64 plan: that
 call fails on the host with TOD_ENOTSUP, before any launch.  The two shorter
-segments run in FP64 on a layout without it.  Bars: 1e-5 relative per segment
-(FP32 path) and 1e-12 (FP64); the fused sweep's n_corr 3e-5 (its residual
-d - s is rounded to FP32 before the transforms).
+segments run in FP64 on a layout without it, and carry the gain and
+noise-parameter draws too.  Bars: 1e-5 relative per segment (FP32 path) and
+1e-12 (FP64); the fused sweep's n_corr 3e-5 (its residual d - s is rounded to
+FP32 before the transforms).
 """
 import types
 
@@ -131,3 +132,35 @@ def test_long_sweep_mixed():
     b, A, hits = ot.bin_tod(ts, ts.pix, ts.psi, ts.d, got)
     assert np.array_equal(acc[:, 9], hits)
     assert np.abs(acc[:, 0:3].T - b).max() <= 1e-11 * np.abs(b).max()
+
+
+def test_long_gain_noise_mixed():
+    """Gain and noise-parameter draws on the long segments.  At these lengths
+    the periodogram's high-frequency bins are wider than the 64 modes a wave
+    covers, so the per-wave bin sums take their one-atomic path."""
+    from paper_2201_03509_amd import ops
+    from oracle import gain as og
+    from oracle import noise as on
+    ts = first_segments(data(), 2)
+    t = ot.project(ts.maps, ot.global_pix(ts, ts.pix), ts.psi, 1.0).astype(np.float32)
+    s = t.astype(np.float64) * np.repeat(ts.gain, np.diff(ts.seg_off))
+    nc = ot.sample_ncorr_all(ts, ts.d, s, 41, 5).astype(np.float32)
+    seed, it = 29, 3
+    g_ref, _ = og.sample_gain_all(ts, ts.d, t.astype(np.float64), seed, it)
+    xi_ref = on.sample_noise_all(ts, ts.d, t.astype(np.float64), ts.gain, nc.astype(np.float64), ts.fknee,
+                                 seed, it)
+    c = ops.Context(0)
+    try:
+        tod = ops.DeviceTod(ts, "cuda:0")
+        g = torch.empty(ts.nseg, dtype=torch.float64, device="cuda")
+        c.sample_gain(tod, "mixed", tod.d, torch.from_numpy(t).cuda(), seed, it, g)
+        xi = [torch.empty(ts.nseg, dtype=torch.float64, device="cuda") for _ in range(3)]
+        c.sample_noise(tod, "mixed", tod.d, torch.from_numpy(t).cuda(), torch.from_numpy(nc).cuda(), seed, it,
+                       *xi)
+        c.sync()
+    finally:
+        c.close()
+    eg = np.abs(g.cpu().numpy() - g_ref) / np.abs(g_ref)
+    ex = np.stack([np.abs(x.cpu().numpy() - r) / np.abs(r) for x, r in zip(xi, xi_ref)])
+    print("long segments: gain rel err %.2e, noise rel err %.2e" % (eg.max(), ex.max()))
+    assert eg.max() < TOL["mixed"] and ex.max() < TOL["mixed"]
