@@ -121,8 +121,8 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         w = g / (s2 * s2);
         gw = g * w;
         int t = phi;
-        // two revisits in flight: deeper pipelining costs the registers that
-        // bound the occupancy of this latency-bound kernel
+        // two revisits in flight (four measured no faster; their registers
+        // cost occupancy)
         for (; t + S < n; t += 2 * S) {
             int p[2], b[2];
             TD dv[2];
