@@ -587,7 +587,7 @@ def main():
     if args.sweep_only:
         args.no_gain = args.no_noise = args.no_masked = args.no_chisq = True
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
