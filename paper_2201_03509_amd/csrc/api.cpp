@@ -379,7 +379,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     P->ncol = (int)col.size();
     P->nrow = (int)row.size();
     for (const FftPlan &fp : P->h_plans) {
-        if (!fp.colreg) P->col_lds = std::max(P->col_lds, 2 * fp.M1 * fp.B * esz);  // ping-pong
+        if (!fp.colreg) P->col_lds = std::max(P->col_lds, fp.M1 * fp.B * esz);  // one in-place buffer
         P->row_lds = std::max(P->row_lds, 2 * fp.M2 * esz);  // one in-place buffer, two rows
     }
     std::vector<double> fs(L->nband);

@@ -35,97 +35,13 @@ using namespace c3rng;
 #define GLBP
 #endif
 
-// One Stockham stage of radix R on B = 1 << lb transforms of length L, from
-// src to dst in LDS; element i of transform b lives at [(i << lsi) + b].
-// Twiddles: w^k and w^2k from the table, higher powers by multiplication.
-template <int R, int DIR, int NT, typename T>
-__device__ __attribute__((noinline)) void fft_stage(const LDSP cx<T> *src, LDSP cx<T> *dst, int L,
-                                                    int lb, int lsi, int Ns,
-                                                    const GLBP cx<T> *__restrict__ tw) {
-    const int LR = L / R;
-    const int nb = LR << lb;
-    const int bm = (1 << lb) - 1;
-    const int step = L / (Ns * R);
-    const int in_stride = LR << lsi;   // between the R inputs of a butterfly
-    const int out_stride = Ns << lsi;  // between its R outputs
-    const int NsR = Ns * R;
-    const uint32_t magic = 0xFFFFFFFFu / (uint32_t)Ns + 1u;  // j / Ns == umulhi(j, magic)
-#pragma unroll 2
-    for (int q = threadIdx.x; q < nb; q += NT) {
-        const int b = q & bm, j = q >> lb;
-        cx<T> v[R];
-        int ia = (j << lsi) + b;
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            v[t] = src[ia];
-            ia += in_stride;
-        }
-        const int jd = (Ns == 1) ? j : (int)__umulhi((uint32_t)j, magic);
-        const int k = j - jd * Ns;
-        if (Ns > 1) {
-            const int ks = k * step;
-            const cx<T> w1 = tw[ks];
-            v[1] = DIR < 0 ? cmul(v[1], w1) : cmulc(v[1], w1);
-            if constexpr (R > 2) {
-                const cx<T> w2 = tw[2 * ks];
-                v[2] = DIR < 0 ? cmul(v[2], w2) : cmulc(v[2], w2);
-                cx<T> wa = w1, wb = w2;
-#pragma unroll
-                for (int t = 3; t < R; ++t) {
-                    const cx<T> w = cmul((t & 1) ? wa : wb, w2);
-                    if (t & 1)
-                        wa = w;
-                    else
-                        wb = w;
-                    v[t] = DIR < 0 ? cmul(v[t], w) : cmulc(v[t], w);
-                }
-            }
-        }
-        dft<R, DIR>(v);
-        int ob = ((jd * NsR + k) << lsi) + b;
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            dst[ob] = v[t];
-            ob += out_stride;
-        }
-    }
-    __syncthreads();
-}
-
-// In-LDS Stockham FFT between two buffers of the same size; returns the one
-// holding the result.
-template <int DIR, int NT, typename T>
-__device__ cx<T> *lds_fft(cx<T> *b0, cx<T> *b1, int L, int lb, int lsi, const int8_t *rad, int nrad,
-                          const cx<T> *tw_) {
-    const GLBP cx<T> *tw = (const GLBP cx<T> *)tw_;
-    int Ns = 1;
-    cx<T> *src = b0, *dst = b1;
-    for (int s = 0; s < nrad; ++s) {
-        const int R = rad[s];
-        const LDSP cx<T> *ls = (const LDSP cx<T> *)src;
-        LDSP cx<T> *ld = (LDSP cx<T> *)dst;
-        if (R == 4)
-            fft_stage<4, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
-        else if (R == 8)
-            fft_stage<8, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
-        else if (R == 2)
-            fft_stage<2, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
-        else if (R == 3)
-            fft_stage<3, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
-        else
-            fft_stage<5, DIR, NT>(ls, ld, L, lb, lsi, Ns, tw);
-        Ns *= R;
-        cx<T> *x = src;
-        src = dst;
-        dst = x;
-    }
-    return src;
-}
-
-// In-place form for the row pass: every thread reads its butterflies of the
-// stage into registers, the block synchronises, and the results are written
-// back over the inputs; one LDS buffer instead of two, so two row blocks fit
-// on a CU.  KB bounds the butterflies per thread at the longest row pair.
+// One Stockham stage of radix R on B = 1 << lb transforms of length L in LDS;
+// element i of transform b lives at [(i << lsi) + b].  Twiddles: w^k and w^2k
+// from the table, higher powers by multiplication (R <= 8), or products of
+// table entries w^(Q a) w^b (R > 8).  In place: every thread reads its
+// butterflies of the stage into registers, the block synchronises, and the
+// results are written back over the inputs, so one LDS buffer serves (two
+// row blocks fit on a CU).  KB bounds the butterflies per thread.
 template <typename T>
 constexpr int row_elems() { return sizeof(T) == 4 ? 2 * 5040 : 2 * 2520; }  // longest row pair
 
@@ -134,12 +50,13 @@ constexpr int row_elems() { return sizeof(T) == 4 ? 2 * 5040 : 2 * 2520; }  // l
 // with consecutive j read consecutive elements); 2: the last stage (Ns R = L)
 // writes its outputs straight to the rows (output i = k + t Ns, again
 // consecutive across lanes).  The global forms skip one LDS round trip each.
-template <int R, int DIR, int NT, int IO, typename T>
+// E: the most elements a call holds (fixes KB, the butterflies per thread).
+template <int R, int DIR, int NT, int IO, typename T, int E = row_elems<T>()>
 __device__ __attribute__((noinline)) void fft_stage_ip(LDSP cx<T> *buf, const GLBP cx<T> *g0,
                                                        const GLBP cx<T> *g1, GLBP cx<T> *o0,
                                                        GLBP cx<T> *o1, int L, int lb, int lsi, int Ns,
                                                        const GLBP cx<T> *__restrict__ tw) {
-    constexpr int KB = (row_elems<T>() / R + NT - 1) / NT;
+    constexpr int KB = (E / R + NT - 1) / NT;
     const int LR = L / R;
     const int nb = LR << lb;
     const int bm = (1 << lb) - 1;
@@ -282,12 +199,37 @@ __device__ void row_fft(cx<T> *b, const cx<T> *g0, const cx<T> *g1, cx<T> *o0, c
     }
 }
 
+// Column FFT of B interleaved columns of L points in one LDS buffer, in place
+// with the row pass's stage form; radices 2, 3, 4, 5 and 8 (the LDS column
+// plans' radices), at most col_elems elements per block
+template <typename T>
+constexpr int col_elems() { return sizeof(T) == 4 ? 4096 : 2048; }
+
+template <int DIR, int NT, typename T>
+__device__ void col_fft(cx<T> *b, int L, int lb, const int8_t *rad, int nrad, const cx<T> *tw_) {
+    const GLBP cx<T> *tw = (const GLBP cx<T> *)tw_;
+    LDSP cx<T> *lb_ = (LDSP cx<T> *)b;
+    constexpr int E = col_elems<T>();
+    int Ns = 1;
+    for (int s = 0; s < nrad; ++s) {
+        const int R = rad[s];
+        switch (R) {
+        case 2: fft_stage_ip<2, DIR, NT, 0, T, E>(lb_, nullptr, nullptr, nullptr, nullptr, L, lb, lb, Ns, tw); break;
+        case 3: fft_stage_ip<3, DIR, NT, 0, T, E>(lb_, nullptr, nullptr, nullptr, nullptr, L, lb, lb, Ns, tw); break;
+        case 4: fft_stage_ip<4, DIR, NT, 0, T, E>(lb_, nullptr, nullptr, nullptr, nullptr, L, lb, lb, Ns, tw); break;
+        case 5: fft_stage_ip<5, DIR, NT, 0, T, E>(lb_, nullptr, nullptr, nullptr, nullptr, L, lb, lb, Ns, tw); break;
+        default: fft_stage_ip<8, DIR, NT, 0, T, E>(lb_, nullptr, nullptr, nullptr, nullptr, L, lb, lb, Ns, tw); break;
+        }
+        Ns *= R;
+    }
+}
+
 // ------------------------------------------------------------- pass 1
 extern __shared__ __attribute__((aligned(16))) unsigned char c3_dyn_lds[];
 
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
-    cx<T> *buf = (cx<T> *)c3_dyn_lds;  // 2 x M1 * B elements (sized per launch)
+    cx<T> *buf = (cx<T> *)c3_dyn_lds;  // M1 * B elements (sized per launch)
     const int2 task = a.col_tasks[blockIdx.x];
     if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
     const SegInfo sg = a.segs[task.x];
@@ -334,7 +276,8 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
         }
     }
     __syncthreads();
-    const cx<T> *res = lds_fft<-1, C3_NT>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
+    col_fft<-1, C3_NT>(buf, M1, lb, p.r1, p.nr1, pool + p.tw1);  // in place
+    const cx<T> *res = buf;
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
         const int k1 = i >> lb, c = i & (B - 1);
         const int j2 = col0 + c;
@@ -367,7 +310,8 @@ __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
                          : cx<T>{0, 0};
     }
     __syncthreads();
-    const cx<T> *res = lds_fft<1, C3_NT>(buf, buf + tot, M1, lb, lb, p.r1, p.nr1, pool + p.tw1);
+    col_fft<1, C3_NT>(buf, M1, lb, p.r1, p.nr1, pool + p.tw1);  // in place
+    const cx<T> *res = buf;
     T *out = (T *)a.out + sg.samp_off;
     const int n = sg.n;
     for (int i = threadIdx.x; i < tot; i += C3_NT) {
