@@ -288,13 +288,13 @@ def compare_maps(res, acc, gpu_map, rcond_min):
     import numpy as np
     from oracle import tod as ot
     up, b, A, hits = oracle_binned(res)
-    ga = acc[up]
+    ga = acc[:, up]
     rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
     m_ref, _ = ot.solve_maps(b, A, hits, rcond_min)
     ok = np.isfinite(m_ref[0])
     gm = gpu_map[:, up]
-    return {"pixels": int(len(up)), "b_rel_l2": [rel(ga[:, i], b[i]) for i in range(3)],
-            "A_rel_l2": rel(ga[:, 3:9].T, A), "hits_exact": bool(np.array_equal(ga[:, 9], hits)),
+    return {"pixels": int(len(up)), "b_rel_l2": [rel(ga[i], b[i]) for i in range(3)],
+            "A_rel_l2": rel(ga[3:9], A), "hits_exact": bool(np.array_equal(ga[9], hits)),
             "conditioned_pixels": int(ok.sum()),
             "map_rel_l2_TQU": [rel(gm[i, ok], m_ref[i, ok]) for i in range(3)],
             "gpu_conditioned_same": bool(np.array_equal(np.isfinite(gm[0]), ok))}

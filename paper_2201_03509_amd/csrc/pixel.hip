@@ -16,10 +16,11 @@
 namespace {
 
 // ---------------------------------------------------------------- binning
-__device__ __forceinline__ void flush_acc(double *acc, int64_t gp, const double *a) {
-    double *dst = acc + gp * 10;
+// acc is component-major, [10][npt]: a wave's flushes of one component land
+// on nearby pixels of one block instead of ten words of each pixel's record.
+__device__ __forceinline__ void flush_acc(double *acc, int64_t npt, int64_t gp, const double *a) {
 #pragma unroll
-    for (int j = 0; j < 10; ++j) atomicAdd(dst + j, a[j]);
+    for (int j = 0; j < 10; ++j) atomicAdd(acc + j * npt + gp, a[j]);
 }
 
 // Bin tile (x = first segment, y = first phase, z = stride S, w = phases | nseg << 16):
@@ -51,6 +52,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     const int seg0 = tl.x;
     const int64_t poff = Ld.band[Ld.seg_band[seg0]].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg0]].npix;
+    const int64_t npt = Ld.npix_total;
     // three register accumulators, the current pixel and the two before it
     // (most recent first), so a phase that crosses pixel edges or alternates
     // between pixels rarely flushes before its tile ends.  A flush inside the
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
                 old = cur;
                 cur = p;
             } else {  // a new pixel: the least recent one leaves
-                if (older >= 0) flush_acc(acc, poff + older, q);
+                if (older >= 0) flush_acc(acc, npt, poff + older, q);
 #pragma unroll
                 for (int j = 0; j < 10; ++j) {
                     q[j] = o[j];
@@ -149,9 +151,9 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
             step(pix[i], psi[i], v);
         }
     }
-    if (cur >= 0) flush_acc(acc, poff + cur, a);
-    if (old >= 0) flush_acc(acc, poff + old, o);
-    if (older >= 0) flush_acc(acc, poff + older, q);
+    if (cur >= 0) flush_acc(acc, npt, poff + cur, a);
+    if (old >= 0) flush_acc(acc, npt, poff + old, o);
+    if (older >= 0) flush_acc(acc, npt, poff + older, q);
 }
 
 // ---------------------------------------------------------------- projection
@@ -280,7 +282,9 @@ __global__ __launch_bounds__(C3_NT) void k_solve(int64_t npix, const double *__r
                                                  double *__restrict__ rc_out) {
     const int64_t p = (int64_t)blockIdx.x * C3_NT + threadIdx.x;
     if (p >= npix) return;
-    const double *a = acc + p * 10;
+    double a[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) a[j] = acc[j * npix + p];
     const double b0 = a[0], b1 = a[1], b2 = a[2];
     double A[3][3] = {{a[3], a[4], a[5]}, {a[4], a[6], a[7]}, {a[5], a[7], a[8]}};
     const double hits = a[9];

@@ -239,7 +239,9 @@ class Context:
             _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(acc), int(bool(accumulate))))
 
     def solve_maps(self, acc, rcond_min, map_out, rcond_out=None):
-        npix = acc.shape[0]
+        if acc.dim() != 2 or acc.shape[0] != 10:
+            raise ValueError("acc must be [10][npix] (component-major)")
+        npix = acc.shape[1]
         self._chk(self.lib.solve_maps(self.h, int(npix), _ptr(acc), float(rcond_min), _ptr(map_out),
                                       _dt(map_out), _ptr(rcond_out)))
 
@@ -305,5 +307,5 @@ def new_outputs(tod, prec):
         "pix": torch.empty(tod.nsamp, dtype=torch.int32, device=dev),
         "psi": torch.empty(tod.nsamp, dtype=torch.uint16, device=dev),
         "ncorr": torch.empty(tod.nsamp, dtype=ft, device=dev),
-        "acc": torch.empty((tod.npix_total, 10), dtype=torch.float64, device=dev),
+        "acc": torch.empty((10, tod.npix_total), dtype=torch.float64, device=dev),
     }

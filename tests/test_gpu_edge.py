@@ -126,7 +126,7 @@ def test_edge_project_bin_chisq(prec, stride):
         tod = ops.DeviceTod(ts, "cuda:0")
         s = torch.empty(ts.nsamp, dtype=tf, device="cuda")
         c.project_sky(tod, prec, pix, psi, _dev(m), s)
-        acc = torch.empty((ts.npix_total, 10), dtype=torch.float64, device="cuda")
+        acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
         c.bin_tod(tod, prec, pix, psi, tod.d, _dev(nc), acc)
         J = torch.empty(ts.nseg, dtype=torch.float64, device="cuda")
         c.tod_chisq(tod, prec, pix, psi, tod.d, _dev(nc), _dev(m), J)
@@ -140,9 +140,9 @@ def test_edge_project_bin_chisq(prec, stride):
     assert seg_rel(ts, s.cpu().numpy().astype(np.float64), s_ref) < TOL[prec]
     b, A, hits = ot.bin_tod(ts, ts.pix, ts.psi, ts.d, nc.astype(np.float64))
     a = acc.cpu().numpy()
-    assert np.array_equal(a[:, 9], hits)
-    assert np.abs(a[:, 0:3].T - b).max() <= 1e-11 * np.abs(b).max()
-    assert np.abs(a[:, 3:9].T - A).max() <= 1e-11 * np.abs(A).max()
+    assert np.array_equal(a[9], hits)
+    assert np.abs(a[0:3] - b).max() <= 1e-11 * np.abs(b).max()
+    assert np.abs(a[3:9] - A).max() <= 1e-11 * np.abs(A).max()
     J_ref = ot.chisq_all(ts, m_ref, ts.pix, ts.psi, ts.d, nc.astype(np.float64))
     Jg = J.cpu().numpy()
     gm_ref, gg_ref, _, _, _ = ot.chisq_grad_all(ts, m_ref, ts.pix, ts.psi, ts.d, nc.astype(np.float64))
@@ -293,5 +293,5 @@ def test_edge_sweep(prec):
     assert seg_rel(ts, got, nc) < TOL[prec] * (3 if prec == "mixed" else 1)
     b, A, hits = ot.bin_tod(ts, ts.pix, ts.psi, ts.d, got)
     a = out["acc"].cpu().numpy()
-    assert np.array_equal(a[:, 9], hits)
-    assert np.abs(a[:, 0:3].T - b).max() <= 1e-11 * np.abs(b).max()
+    assert np.array_equal(a[9], hits)
+    assert np.abs(a[0:3] - b).max() <= 1e-11 * np.abs(b).max()

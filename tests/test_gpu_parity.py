@@ -163,17 +163,17 @@ def test_bin_and_solve(ctx, name, prec):
     rng = np.random.default_rng(5)
     nc = (rng.normal(size=ts.nsamp) * 0.3).astype(np.float32 if prec == "mixed" else np.float64)
     b, A, hits = ot.bin_tod(ts, pix, psi, ts.d, nc.astype(np.float64))
-    acc = torch.empty((ts.npix_total, 10), dtype=torch.float64, device="cuda")
+    acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
     ctx.bin_tod(tod, prec, torch.from_numpy(pix.astype(np.int32)).cuda(),
                 torch.from_numpy(psi.astype(np.uint16)).cuda(), tod.d,
                 torch.from_numpy(nc).cuda(), acc)
     ctx.sync()
     a = acc.cpu().numpy()
-    assert np.array_equal(a[:, 9], hits)
+    assert np.array_equal(a[9], hits)
     scale_b = np.abs(b).max()
     scale_A = np.abs(A).max()
-    assert np.abs(a[:, 0:3].T - b).max() <= 1e-12 * scale_b * 10
-    assert np.abs(a[:, 3:9].T - A).max() <= 1e-12 * scale_A * 10
+    assert np.abs(a[0:3] - b).max() <= 1e-12 * scale_b * 10
+    assert np.abs(a[3:9] - A).max() <= 1e-12 * scale_A * 10
     # solve
     tau = 1e-3
     m_ref, rc_ref = ot.solve_maps(b, A, hits, tau)
@@ -199,7 +199,7 @@ def test_noiseless_round_trip(ctx, prec):
     ts, pix, psi = dataset("tiny")
     tod = dev_tod(ts)
     d = ot.project_all(ts, ts.maps, pix, psi)
-    acc = torch.empty((ts.npix_total, 10), dtype=torch.float64, device="cuda")
+    acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
     ctx.bin_tod(tod, prec, torch.from_numpy(pix.astype(np.int32)).cuda(),
                 torch.from_numpy(psi.astype(np.uint16)).cuda(), torch.from_numpy(d).cuda(), None,
                 acc)
@@ -230,8 +230,8 @@ def test_sweep_matches_steps(ctx, name, prec):
     assert seg_rel(ts, got, nc) < TOL[prec] * (3 if prec == "mixed" else 1)
     b, A, hits = ot.bin_tod(ts, pix, psi, ts.d, got)
     a = out["acc"].cpu().numpy()
-    assert np.array_equal(a[:, 9], hits)
-    assert np.abs(a[:, 0:3].T - b).max() <= 1e-11 * np.abs(b).max()
+    assert np.array_equal(a[9], hits)
+    assert np.abs(a[0:3] - b).max() <= 1e-11 * np.abs(b).max()
 
 
 def test_sweep_graph_replays(ctx):
@@ -254,5 +254,5 @@ def test_sweep_graph_replays(ctx):
         ctx.sync()
         assert np.array_equal(graph["ncorr"].cpu().numpy(), e_nc)
         ga = graph["acc"].cpu().numpy()
-        assert np.array_equal(ga[:, 9], e_acc[:, 9])
-        assert np.allclose(ga[:, :9], e_acc[:, :9], rtol=1e-12, atol=1e-9)
+        assert np.array_equal(ga[9], e_acc[9])
+        assert np.allclose(ga[:9], e_acc[:9], rtol=1e-12, atol=1e-9)
