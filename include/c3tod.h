@@ -29,8 +29,9 @@
  *   serves one stream and one host thread at a time.
  * Errors: host-detectable problems return a status before any device work
  *   is queued.  Device-detected problems (corrupt Huffman stream, decoded
- *   value out of range) raise a sticky device error word that tod_sync()
- *   returns as TOD_ECORRUPT; it stays set until tod_clear_error().
+ *   value out of range, noise parameters outside their domain, non-finite
+ *   data) raise a sticky device error word that tod_sync() returns as
+ *   TOD_ECORRUPT; it stays set until tod_clear_error().
  *   tod_last_error() describes the last failure.
  * Precision: TOD_MIXED runs projection, residuals, FFTs and draws in FP32
  *   and keeps per-pixel accumulation and the 3x3 solve in FP64, as it keeps
@@ -137,7 +138,13 @@ tod_status tod_clear_error(tod_ctx ctx);
 /* Text of the last failure on this context ("" if none).  Owned by the ctx. */
 const char *tod_last_error(tod_ctx ctx);
 /* Device error word bits (after tod_sync): 1 = invalid code, 2 = chunk
- * boundary mismatch, 4 = pixel out of range, 8 = psi bin out of range. */
+ * boundary mismatch, 4 = pixel out of range, 8 = psi bin out of range,
+ * 16 = a non-empty segment's sigma0 is not finite and > 0, 32 = its f_knee is
+ * not finite and > 0, 64 = its alpha is not finite and < 0 (the PSD
+ * P(f) = sigma0^2 (f/f_knee)^alpha of Eq. 4 needs all three; every call that
+ * reads them checks them on the device, and its kernels still run, giving
+ * inf/NaN outputs), 128 = non-finite data: a residual d - g P m (tod_sweep)
+ * or a binned d - n_corr (bin_tod, tod_sweep) at an in-range pixel. */
 uint32_t tod_device_error_bits(tod_ctx ctx);
 
 /* ------------------------------------------------------------- hot path */
@@ -189,8 +196,8 @@ tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
  *   u = (x + 1/2) 2^-32 and Box-Muller on (u0,u1), (u2,u3).  mean_only != 0
  *   sets W = 0 (the Wiener-filter mean).
  * d: device [nsamp] of d_dtype; s: device [nsamp] (FP32 mixed / FP64 plain);
- * sigma0, fknee, alpha: device [nseg] FP64 (sigma0 > 0, fknee > 0, alpha < 0
- * is the caller's responsibility: they are not read on the host).
+ * sigma0, fknee, alpha: device [nseg] FP64 with sigma0 > 0, fknee > 0,
+ * alpha < 0 (device memory, so checked on the device: error bits 16/32/64).
  * ncorr_out: device [nsamp] (FP32 mixed / FP64 plain). */
 tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                         const void *d, tod_dtype d_dtype, const void *s,
@@ -318,7 +325,9 @@ tod_status tod_chisq(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                      const double *sigma0, const double *fknee, const double *alpha,
                      double *chisq_seg);
 
-/* Adjoint of tod_chisq, scaled by grad_scale (dL/dJ):
+/* Adjoint of tod_chisq, scaled by dL/dJ = grad_scale * (*grad_scale_dev)
+ * (grad_scale_dev: device FP64 scalar, may be NULL = 1; read by the kernels,
+ * so an autograd caller passes its incoming gradient without a host sync):
  *   dJ/dm = -2 P^T (g r / sigma0^2)                       -> grad_maps [3][npix_total] FP64
  *   dJ/dg_s = -2 sum_t (P m)_t r_t / sigma0^2             -> grad_gain [nseg]
  *   dJ/dsigma0 = -2 sum r^2/sigma0^3 + sum_k (2/sigma0)(1 - I_k/P_k)
@@ -331,7 +340,7 @@ tod_status tod_chisq_backward(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                               const void *d, tod_dtype d_dtype, const void *ncorr,
                               const void *maps, const double *gain,
                               const double *sigma0, const double *fknee, const double *alpha,
-                              double grad_scale,
+                              double grad_scale, const double *grad_scale_dev,
                               double *grad_maps, double *grad_gain,
                               double *grad_sigma0, double *grad_fknee, double *grad_alpha);
 
@@ -354,6 +363,15 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
 
 /* --------------------------------------------------------- planning/tuning */
 
+/* Plan a layout ahead of its first call (the measured-cost-table step of
+ * section 4.2, done once per data set): load FFT choices and binning strides
+ * from tune_cache when it is given (a file written by tod_autotune; missing
+ * file: defaults), then build the layout's FFT plans, task lists and twiddle
+ * tables and size the FFT workspace in the context.  Later calls with the same
+ * layout and precision reuse them.  Every entry point plans on first use
+ * anyway; this call moves that host work and its allocations up front. */
+tod_status tod_plan(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const char *tune_cache);
+
 /* Measure candidate FFT splits for every FFT length the layout needs (section
  * 4.2's measured cost table, here per length: the split M = M1 x M2, the
  * column kernel -- whole columns in registers for a compiled M1, or LDS
@@ -369,7 +387,8 @@ tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
  * every radix has a compiled stage); otherwise the default split is used. */
 tod_status tod_load_tuning(tod_ctx ctx, const char *cache_path);
 /* Binning stride (samples between revisits of a pixel) per band; 0 = let the
- * library choose.  Correct for any value; only speed depends on it. */
+ * library choose, at most 2^26.  Correct for any value; only speed depends on
+ * it.  A stride longer than a segment acts as the segment's length. */
 tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride);
 
 /* FFT work batching: the column/row passes run batch by batch over groups of

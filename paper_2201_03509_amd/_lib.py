@@ -19,7 +19,7 @@ EXPORTS = [
     "bin_tod",
     "solve_maps", "tod_chisq", "tod_chisq_backward", "tod_sweep", "tod_autotune",
     "tod_load_tuning", "tod_set_bin_stride", "tod_set_fft_batch", "tod_enable_timing",
-    "tod_kernel_times",
+    "tod_kernel_times", "tod_plan",
 ]
 
 
@@ -87,11 +87,12 @@ def load():
         "solve_maps": [P, I64, P, D, P, ctypes.c_int, P],
         "tod_chisq": [P, LP, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P, P, P, P],
         "tod_chisq_backward": [P, LP, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P, P, P,
-                               D, P, P, P, P, P],
+                               D, P, P, P, P, P, P],
         "tod_sweep": [P, LP, ctypes.c_int, HP, HP, P, ctypes.c_int, P, P, P, P, P, U64, U64,
                       P, P, P, P, ctypes.c_int],
         "tod_autotune": [P, LP, ctypes.c_int, P, ctypes.c_char_p],
         "tod_load_tuning": [P, ctypes.c_char_p],
+        "tod_plan": [P, LP, ctypes.c_int, ctypes.c_char_p],
         "tod_set_bin_stride": [P, I32, I32],
         "tod_set_fft_batch": [P, I64],
         "tod_enable_timing": [P, ctypes.c_int],

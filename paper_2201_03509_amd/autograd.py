@@ -37,7 +37,9 @@ class TodChisq(torch.autograd.Function):
         gs = torch.empty(tod.ndet, dtype=torch.float64, device=dev)
         gf = torch.empty(tod.ndet, dtype=torch.float64, device=dev)
         ga = torch.empty(tod.ndet, dtype=torch.float64, device=dev)
-        c.tod_chisq_backward(tod, prec, pix, psi, tod.d, ncorr, m, float(gJ.item()), gm, gg, gs, gf,
+        # the incoming gradient stays on the device: the adjoint kernels read it
+        gj = gJ.detach().to(device=dev, dtype=torch.float64).reshape(1).contiguous()
+        c.tod_chisq_backward(tod, prec, pix, psi, tod.d, ncorr, m, gj, gm, gg, gs, gf,
                              ga, gain=g, sigma0=s0, fknee=fk, alpha=al)
         return gm.to(fctx.maps_dtype), gg, gs, gf, ga, None
 

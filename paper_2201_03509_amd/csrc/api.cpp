@@ -75,6 +75,7 @@ int64_t next_5smooth(int64_t n) {
 
 struct Plan {
     uint64_t key = 0;
+    uint64_t gen = 0;                     // context-unique; renewed when bin tiles change
     int mixed = 0;
     std::vector<SegInfo> h_segs;
     std::vector<int32_t> seg_order;       // LPT order
@@ -156,6 +157,7 @@ struct tod_ctx_s {
     };
     std::map<uint64_t, GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;     // capture-only stream (default priority)
+    uint64_t gen_counter = 0;             // source of Plan::gen
 };
 
 namespace {
@@ -184,7 +186,8 @@ tod_status check_layout(tod_ctx ctx, const tod_layout *L) {
     for (int s = 0; s < L->nseg; ++s) {
         const int64_t n = L->h_seg_off[s + 1] - L->h_seg_off[s];
         if (n < 0) return fail(ctx, TOD_EINVAL, "seg_off is not non-decreasing");
-        if (n > (1 << 30)) return fail(ctx, TOD_ENOTSUP, "segment longer than 2^30 samples");
+        // the strided kernels step t + 4 S with t, S <= n in 32-bit arithmetic
+        if (n > (1 << 28)) return fail(ctx, TOD_ENOTSUP, "segment longer than 2^28 samples");
         if (L->h_seg_band[s] < 0 || L->h_seg_band[s] >= L->nband)
             return fail(ctx, TOD_EINVAL, "seg_band out of range");
     }
@@ -237,6 +240,7 @@ LayoutDev make_layout_dev(const tod_layout *L) {
 
 HuffDev make_huff_dev(const tod_huff *h) {
     HuffDev d;
+    memset(&d, 0, sizeof(d));
     d.words = h->words;
     d.seg_word_off = h->seg_word_off;
     d.seg_table = h->seg_table;
@@ -272,6 +276,7 @@ struct Pool {
 tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key, Plan **out) {
     auto P = std::make_unique<Plan>();
     P->key = key;
+    P->gen = ++ctx->gen_counter;
     P->mixed = mixed;
     const int nseg = L->nseg;
     P->h_segs.resize(nseg);
@@ -416,6 +421,14 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     return TOD_OK;
 }
 
+void drop_graphs(tod_ctx ctx) {
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
+        if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+    }
+    ctx->graphs.clear();
+}
+
 uint64_t layout_key(const tod_layout *L, int mixed, uint64_t salt) {
     uint64_t h = 1469598103934665603ull;
     h = fnv(h, &salt, sizeof(salt));
@@ -435,7 +448,11 @@ tod_status get_plan(tod_ctx ctx, const tod_layout *L, int mixed, Plan **out) {
         *out = it->second.get();
         return TOD_OK;
     }
-    if (ctx->plans.size() > 16) ctx->plans.clear();
+    if (ctx->plans.size() > 16) {
+        // captured sweeps bake in the plans' buffers: they go with them
+        drop_graphs(ctx);
+        ctx->plans.clear();
+    }
     return build_plan(ctx, L, mixed, key, out);
 }
 
@@ -506,6 +523,8 @@ tod_status get_bin_tiles(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_
             st[b] = it->second;
         } else if (kt != ctx->stride_by_key.end() && kt->second > 0) {
             st[b] = kt->second;
+        } else if ((int)P->bin_stride.size() == L->nband && P->bin_stride[b] > 0) {
+            st[b] = P->bin_stride[b];  // the one this plan's tiles already use
         } else if (pix) {
             tod_status r = probe_stride(ctx, L, P, pix, b, &st[b]);
             if (r != TOD_OK) return r;
@@ -532,7 +551,8 @@ tod_status get_bin_tiles(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_
             }
             for (int g = 0; g < grp; ++g) done[first + g] = 1;
             const int n = P->h_segs[first].n;
-            const int S = st[P->h_segs[first].band];
+            // a period beyond the segment visits each sample once, as S = n does
+            const int S = std::max(1, std::min(st[P->h_segs[first].band], std::max(n, 1)));
             const int nph = std::min(S, n);
             for (int p0 = 0; p0 < nph; p0 += C3_NT)
                 v.push_back(make_int4(first, p0, S, std::min(C3_NT, nph - p0) | (grp << 16)));
@@ -540,6 +560,7 @@ tod_status get_bin_tiles(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_
         HIPCHK(P->bin_tiles.upload(v, ctx->stream));
         P->nbin = (int)v.size();
         P->bin_stride = st;
+        P->gen = ++ctx->gen_counter;  // graphs captured with the old tiles no longer match
     }
     *tiles = (const int4 *)P->bin_tiles.p;
     *ntile = P->nbin;
@@ -714,8 +735,10 @@ tod_status tod_sync(tod_ctx ctx) {
     HIPCHK(hipMemcpy(&e, ctx->d_err, sizeof(e), hipMemcpyDeviceToHost));
     ctx->last_err_bits = e;
     if (e) {
-        char buf[160];
-        snprintf(buf, sizeof(buf), "device error bits 0x%x (1 invalid code, 2 chunk mismatch, 4 pixel range, 8 psi range)", e);
+        char buf[256];
+        snprintf(buf, sizeof(buf),
+                 "device error bits 0x%x (1 invalid code, 2 chunk mismatch, 4 pixel range, 8 psi range, "
+                 "16 sigma0, 32 f_knee, 64 alpha, 128 non-finite data)", e);
         return fail(ctx, TOD_ECORRUPT, buf);
     }
     return TOD_OK;
@@ -807,7 +830,7 @@ tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const 
     HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     KTimer kt(ctx, K_PROJECT, ctx->stream);
     HIPCHK(c3::launch_resid_tiles(ctx->stream, make_layout_dev(lay), mixed, tiles, nt, pix, psi, nullptr, 0,
-                                  maps, ctx->maps4.p, gain, mixed ? ctx->trig32.p : ctx->trig64.p, s_out));
+                                  maps, ctx->maps4.p, gain, ctx->trig64.p, s_out, nullptr));
     return TOD_OK;
 }
 
@@ -844,6 +867,7 @@ tod_status sample_ncorr(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
     Plan *P;
     if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
     HIPCHK(c3::launch_set_u64(ctx->stream, ctx->d_seed_iter, seed, iter));
+    HIPCHK(c3::launch_check_params(ctx->stream, make_layout_dev(lay), sigma0, fknee, alpha, ctx->d_err));
     return ncorr_impl(ctx, lay, mixed, P, d, d_dtype, s, !mixed, sigma0, fknee, alpha, mean_only,
                       ncorr_out);
 }
@@ -900,6 +924,7 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     HIPCHK(ctx->cg_count.ensure(64));
     hipStream_t st = ctx->stream;
     HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
+    HIPCHK(c3::launch_check_params(st, make_layout_dev(lay), sigma0, fknee, alpha, ctx->d_err));
     int32_t *act = (int32_t *)ctx->cg_act.p, *count = (int32_t *)ctx->cg_count.p;
     c3::CgState *cs = (c3::CgState *)ctx->cg_state.p;
     const double tol2 = tol * tol;
@@ -1083,6 +1108,7 @@ tod_status sample_gain(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const 
     HIPCHK(ctx->gain_part.ensure((size_t)P->nsample_tiles * sizeof(double2) + 64));
     hipStream_t st = ctx->stream;
     HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
+    HIPCHK(c3::launch_check_params(st, make_layout_dev(lay), sigma0, fknee, alpha, ctx->d_err));
     c3::FftArgs a = fft_args(ctx, P, lay);
     a.sigma0 = sigma0;
     a.fknee = fknee;
@@ -1131,6 +1157,7 @@ tod_status sample_noise(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
     HIPCHK(ctx->xi_part.ensure((size_t)P->nsample_tiles * 8 + 64));
     hipStream_t st = ctx->stream;
     HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
+    HIPCHK(c3::launch_check_params(st, make_layout_dev(lay), nullptr, fknee_in, nullptr, ctx->d_err));
     {
         KTimer kt(ctx, K_NOISE, st);
         HIPCHK(c3::launch_zero(st, ctx->xi_bins.p, (int64_t)(nbin * 8)));
@@ -1172,10 +1199,12 @@ tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int3
     const int4 *tiles;
     int nt;
     if ((r = get_bin_tiles(ctx, lay, P, pix, &tiles, &nt)) != TOD_OK) return r;
+    const LayoutDev Ld = make_layout_dev(lay);
+    HIPCHK(c3::launch_check_params(ctx->stream, Ld, sigma0, nullptr, nullptr, ctx->d_err));
     if (!accumulate) HIPCHK(c3::launch_zero(ctx->stream, acc, lay->npix_total * 10 * sizeof(double)));
     KTimer kt(ctx, K_BIN, ctx->stream);
-    HIPCHK(c3::launch_bin_tiles(ctx->stream, make_layout_dev(lay), mixed, tiles, nt, pix, psi, d,
-                                d_dtype == TOD_F64, ncorr, gain, sigma0, ctx->trig64.p, acc));
+    HIPCHK(c3::launch_bin_tiles(ctx->stream, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64, ncorr, gain,
+                                sigma0, ctx->trig64.p, acc, ctx->d_err));
     return TOD_OK;
 }
 
@@ -1193,7 +1222,7 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
                                const uint16_t *psi, const void *d, tod_dtype d_dtype,
                                const void *ncorr, const void *maps, const double *gain,
                                const double *sigma0, const double *fknee, const double *alpha,
-                               double gscale, double *grad_maps, double *chisq_seg,
+                               double gscale, const double *gscale_dev, double *grad_maps, double *chisq_seg,
                                double *grad_gain, double *gsig, double *gfk, double *galpha) {
     tod_status r;
     if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
@@ -1220,11 +1249,12 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     if (galpha) HIPCHK(c3::launch_zero(st, galpha, sizeof(double) * lay->ndet));
     HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     const LayoutDev Ld = make_layout_dev(lay);
+    HIPCHK(c3::launch_check_params(st, Ld, sigma0, fknee, alpha, ctx->d_err));
     {
         KTimer kt(ctx, K_CHISQ, st);
         HIPCHK(c3::launch_chisq_time_tiles(st, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64,
                                            ncorr, maps, ctx->maps4.p, gain, sigma0, ctx->trig64.p,
-                                           (double *)ctx->seg_sums.p, grad_maps, gscale));
+                                           (double *)ctx->seg_sums.p, grad_maps, gscale, gscale_dev));
     }
     c3::FftArgs a = fft_args(ctx, P, lay);
     a.in_a = ncorr;
@@ -1241,7 +1271,7 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     }
     HIPCHK(c3::launch_chisq_finish(st, Ld, (const double *)ctx->seg_sums.p,
                                    (const double *)ctx->seg_whittle.p, gain, sigma0, fknee, alpha,
-                                   gscale, chisq_seg, grad_gain, gsig, gfk, galpha));
+                                   gscale, gscale_dev, chisq_seg, grad_gain, gsig, gfk, galpha));
     return TOD_OK;
 }
 
@@ -1252,19 +1282,20 @@ tod_status tod_chisq(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const in
     if (!ctx) return TOD_EINVAL;
     if (!chisq_seg) return fail(ctx, TOD_EINVAL, "NULL chisq_seg");
     return chisq_common(ctx, lay, prec, pix, psi, d, d_dtype, ncorr, maps, gain, sigma0, fknee, alpha,
-                        1.0, nullptr, chisq_seg, nullptr, nullptr, nullptr, nullptr);
+                        1.0, nullptr, nullptr, chisq_seg, nullptr, nullptr, nullptr, nullptr);
 }
 
 tod_status tod_chisq_backward(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                               const int32_t *pix, const uint16_t *psi, const void *d,
                               tod_dtype d_dtype, const void *ncorr, const void *maps,
                               const double *gain, const double *sigma0, const double *fknee,
-                              const double *alpha, double grad_scale, double *grad_maps,
+                              const double *alpha, double grad_scale, const double *grad_scale_dev,
+                              double *grad_maps,
                               double *grad_gain, double *grad_sigma0, double *grad_fknee,
                               double *grad_alpha) {
     if (!ctx) return TOD_EINVAL;
     return chisq_common(ctx, lay, prec, pix, psi, d, d_dtype, ncorr, maps, gain, sigma0, fknee, alpha,
-                        grad_scale, grad_maps, nullptr, grad_gain, grad_sigma0, grad_fknee,
+                        grad_scale, grad_scale_dev, grad_maps, nullptr, grad_gain, grad_sigma0, grad_fknee,
                         grad_alpha);
 }
 
@@ -1296,15 +1327,32 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     hipStream_t st = ctx->stream;
     const LayoutDev Ld = make_layout_dev(lay);
+    if (P->nbin > 0) {
+        // tiles exist: rebuild them if a band's stride has been set or tuned
+        // since (no probe: the pointing of this call is not decoded yet)
+        const int4 *t0;
+        int n0;
+        if ((r = get_bin_tiles(ctx, lay, P, nullptr, &t0, &n0)) != TOD_OK) return r;
+    }
 
-    // graph key: every pointer and size the captured kernels bake in
+    // graph key: every pointer and size the captured kernels bake in -- the
+    // layout and stream structs as the kernels receive them, the caller's
+    // buffers, the context's scratch and the plan (its generation changes
+    // whenever its task lists or tiles are rebuilt)
+    const HuffDev Hp = make_huff_dev(pix), Hs = make_huff_dev(psi);
     uint64_t gk = 1469598103934665603ull;
-    const void *ptrs[] = {pix->words, psi->words, pix->tables, psi->tables, d, maps, gain, sigma0,
-                          fknee, alpha, ncorr_out, acc, pix_work, psi_work, ctx->work.p,
-                          ctx->resid.p, P->segs.p, ctx->dec_tabs.p, ctx->maps4.p};
+    gk = fnv(gk, &Ld, sizeof(Ld));
+    gk = fnv(gk, &Hp, sizeof(Hp));
+    gk = fnv(gk, &Hs, sizeof(Hs));
+    const void *ptrs[] = {d, maps, gain, sigma0, fknee, alpha, ncorr_out, acc, pix_work, psi_work,
+                          ctx->work.p, ctx->resid.p, ctx->dec_tabs.p, ctx->maps4.p, ctx->trig32.p,
+                          ctx->trig64.p, ctx->d_err, ctx->d_seed_iter, dt};
     gk = fnv(gk, ptrs, sizeof(ptrs));
+    gk = fnv(gk, &ndt, sizeof(ndt));
     gk = fnv(gk, &P->key, sizeof(P->key));
+    gk = fnv(gk, &P->gen, sizeof(P->gen));
     gk = fnv(gk, &d_dtype, sizeof(d_dtype));
+    gk = fnv(gk, &mixed, sizeof(mixed));
 
     HIPCHK(c3::launch_set_u64(st, ctx->d_seed_iter, seed, iter));
     const bool have_tiles = P->nbin > 0;
@@ -1317,6 +1365,7 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     }
     // eager (or capture) sequence
     auto run = [&](bool capture) -> tod_status {
+        HIPCHK(c3::launch_check_params(st, Ld, sigma0, fknee, alpha, ctx->d_err));
         {
             KTimer kt(ctx, K_DECODE, st);
             HIPCHK(c3::launch_decode(st, Ld, make_huff_dev(pix), make_huff_dev(psi),
@@ -1332,8 +1381,8 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
         {
             KTimer kt(ctx, K_PROJECT, st);
             HIPCHK(c3::launch_resid_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
-                                          d_dtype == TOD_F64, maps, ctx->maps4.p, gain,
-                                          mixed ? ctx->trig32.p : ctx->trig64.p, ctx->resid.p));
+                                          d_dtype == TOD_F64, maps, ctx->maps4.p, gain, ctx->trig64.p,
+                                          ctx->resid.p, ctx->d_err));
         }
         {
             c3::FftArgs a = fft_args(ctx, P, lay);
@@ -1352,7 +1401,8 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
             HIPCHK(c3::launch_zero(st, acc, lay->npix_total * 10 * sizeof(double)));
             KTimer kt(ctx, K_BIN, st);
             HIPCHK(c3::launch_bin_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
-                                        d_dtype == TOD_F64, ncorr_out, gain, sigma0, ctx->trig64.p, acc));
+                                        d_dtype == TOD_F64, ncorr_out, gain, sigma0, ctx->trig64.p, acc,
+                                        ctx->d_err));
         }
         return TOD_OK;
     };
@@ -1381,7 +1431,8 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
 
 tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride) {
     if (!ctx) return TOD_EINVAL;
-    if (band < 0 || band >= C3_MAXBAND || stride < 0) return fail(ctx, TOD_EINVAL, "bad band/stride");
+    if (band < 0 || band >= C3_MAXBAND || stride < 0 || stride > c3tune::kMaxStride)
+        return fail(ctx, TOD_EINVAL, "bad band/stride (stride must be in [0, 2^26])");
     if (stride == 0)
         ctx->band_stride.erase(band);
     else
@@ -1573,6 +1624,17 @@ tod_status tod_autotune(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const
         fclose(f);
     }
     return TOD_OK;
+}
+
+tod_status tod_plan(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const char *tune_cache) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
+    if (tune_cache && (r = tod_load_tuning(ctx, tune_cache)) != TOD_OK) return r;
+    Plan *P;
+    if ((r = get_plan(ctx, lay, prec == TOD_MIXED, &P)) != TOD_OK) return r;
+    return ensure_work(ctx, P);
 }
 
 }  // extern "C"

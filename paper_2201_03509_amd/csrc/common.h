@@ -25,6 +25,10 @@
 #define C3_ERR_CHUNK 2u      // chunk end does not meet the next chunk's start
 #define C3_ERR_PIX 4u        // decoded pixel outside [0, npix)
 #define C3_ERR_PSI 8u        // decoded psi bin outside [0, npsi)
+#define C3_ERR_SIGMA0 16u    // a non-empty segment's sigma0 is not finite and > 0
+#define C3_ERR_FKNEE 32u     // a non-empty segment's f_knee is not finite and > 0
+#define C3_ERR_ALPHA 64u     // a non-empty segment's alpha is not finite and < 0
+#define C3_ERR_NONFINITE 128u  // a residual d - g P m or a binned d - n_corr is not finite
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
@@ -155,10 +159,18 @@ hipError_t launch_decode_stream(hipStream_t st, const LayoutDev &L, const HuffDe
 // r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs),
 // or s = g P m when d is NULL; maps4: workspace of npix_total records of 4
 // values (T, Q, U, 0), filled from the [3][npix] maps first
+// trig: the FP64 cos/sin 2psi table (the projection is summed in FP64 and
+// rounded once to the output type); err: sticky word that receives
+// C3_ERR_NONFINITE where d - s is not finite at an in-range pixel (may be NULL)
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                               int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                               int d_f64, const void *maps, void *maps4, const double *gain,
-                              const void *trig, void *r_out);
+                              const void *trig64, void *r_out, uint32_t *err);
+// per non-empty segment: sigma0 > 0, f_knee > 0, alpha < 0, all finite (any
+// pointer may be NULL: not checked); failures set C3_ERR_SIGMA0 / _FKNEE /
+// _ALPHA in the sticky word.  The kernels that use them still run.
+hipError_t launch_check_params(hipStream_t st, const LayoutDev &L, const double *sigma0,
+                               const double *fknee, const double *alpha, uint32_t *err);
 
 // FFT-based passes (modes: see launch_fft_pass)
 struct FftArgs {
@@ -209,7 +221,7 @@ hipError_t fft_init_attributes();
 hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                             int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                             int d_f64, const void *ncorr, const double *gain,
-                            const double *sigma0, const void *trig64, double *acc);
+                            const double *sigma0, const void *trig64, double *acc, uint32_t *err);
 hipError_t launch_zero(hipStream_t st, void *p, int64_t bytes);
 hipError_t launch_solve(hipStream_t st, int64_t npix, const double *acc, double rcond_min,
                         void *map_out, int map_f64, double *rcond_out);
@@ -224,11 +236,11 @@ hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed
                                    const void *d, int d_f64, const void *ncorr, const void *maps,
                                    void *maps4, const double *gain, const double *sigma0,
                                    const void *trig64, double *seg_sums, double *grad_maps,
-                                   double grad_scale);
+                                   double grad_scale, const double *gscale_dev);
 hipError_t launch_chisq_finish(hipStream_t st, const LayoutDev &L, const double *seg_time,
                                const double *seg_whittle, const double *gain, const double *sigma0,
                                const double *fknee, const double *alpha, double grad_scale,
-                               double *chisq_seg, double *grad_gain, double *grad_sigma0,
+                               const double *gscale_dev, double *chisq_seg, double *grad_gain, double *grad_sigma0,
                                double *grad_fknee, double *grad_alpha);
 hipError_t launch_set_u64(hipStream_t st, uint64_t *p, uint64_t a, uint64_t b);
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
                                                const double *__restrict__ gain,
                                                const double *__restrict__ sigma0,
                                                const cx<double> *__restrict__ trig,
-                                               double *__restrict__ acc) {
+                                               double *__restrict__ acc, uint32_t *__restrict__ err) {
     // cos/sin 2psi repeat every 2048 psi bins
     __shared__ cx<double> tr[2048];
     const int4 tl = tiles[blockIdx.x];
@@ -64,8 +64,10 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     for (int j = 0; j < 10; ++j) a[j] = o[j] = q[j] = 0.0;
     int cur = -1, old = -1, older = -1;
     double w = 0, gw = 0;
+    bool bad = false;  // a binned d - n_corr is not finite
     auto step = [&](int p, int b, double v) {
         if ((uint32_t)p >= npix) return;  // out-of-range pixels are not binned
+        bad |= !isfinite(v);
         if (p != cur) {
             if (p == old) {  // a <-> o
 #pragma unroll
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     if (cur >= 0) flush_acc(acc, npt, poff + cur, a);
     if (old >= 0) flush_acc(acc, npt, poff + old, o);
     if (older >= 0) flush_acc(acc, npt, poff + older, q);
+    if (bad && err) atomicOr(err, C3_ERR_NONFINITE);
 }
 
 // ---------------------------------------------------------------- projection
@@ -175,7 +178,12 @@ __global__ __launch_bounds__(C3_NT) void k_interleave(const T *__restrict__ maps
         out[i] = Stokes4<T>{maps[i], maps[npt + i], maps[2 * npt + i], (T)0};
 }
 
-// SUB: write d - s (d, of type TD, read per sample); otherwise s (d unused)
+// SUB: write d - s (d, of type TD, read per sample); otherwise s (d unused).
+// The projection and the subtraction are summed in FP64 from the stored map
+// values and rounded once to the output type T: a residual of a few noise
+// units is the difference of two numbers a hundred times larger, so forming
+// s in FP32 first would cost it about 1e-5 of its own size.  With SUB a lane
+// that meets a non-finite d - s at an in-range pixel raises C3_ERR_NONFINITE.
 template <typename T, typename TD, bool SUB>
 __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__restrict__ tiles,
                                                  const int32_t *__restrict__ pix,
@@ -183,9 +191,9 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
                                                  const TD *__restrict__ d,
                                                  const Stokes4<T> *__restrict__ maps,
                                                  const double *__restrict__ gain,
-                                                 const cx<T> *__restrict__ trig,
-                                                 T *__restrict__ r_out) {
-    __shared__ cx<T> tr[2048];
+                                                 const cx<double> *__restrict__ trig,
+                                                 T *__restrict__ r_out, uint32_t *__restrict__ err) {
+    __shared__ cx<double> tr[2048];
     const int4 tl = tiles[blockIdx.x];
     for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
@@ -197,48 +205,79 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
     int cur = -1;
-    T mT = 0, mQ = 0, mU = 0;
-    T g = 0;
-    auto step = [&](int64_t i, int p, int b, T dv) {
+    double mT = 0, mQ = 0, mU = 0;
+    double g = 0;
+    bool bad = false;
+    auto step = [&](int64_t i, int p, int b, double dv) {
         if (p != cur) {
             cur = p;
             if ((uint32_t)p < npix) {
                 const Stokes4<T> m = maps[poff + p];
-                mT = m.t;
-                mQ = m.q;
-                mU = m.u;
+                mT = (double)m.t;
+                mQ = (double)m.q;
+                mU = (double)m.u;
             } else {
-                mT = mQ = mU = (T)NAN;
+                mT = mQ = mU = (double)NAN;
             }
         }
-        const cx<T> cs = tr[b & 2047];
-        const T sv = g * (mT + mQ * cs.x + mU * cs.y);
-        r_out[i] = SUB ? dv - sv : sv;
+        const cx<double> cs = tr[b & 2047];
+        const double sv = g * (mT + mQ * cs.x + mU * cs.y);
+        if constexpr (SUB) {
+            const double rv = dv - sv;
+            bad |= (uint32_t)p < npix && !isfinite(rv);
+            r_out[i] = (T)rv;
+        } else {
+            r_out[i] = (T)sv;
+        }
     };
     for (int gi = 0; gi < ngrp; ++gi) {
         const int seg = tl.x + gi;
         const int64_t s0 = Ld.seg_off[seg];
         const int n = (int)(Ld.seg_off[seg + 1] - s0);
-        g = (T)gain[seg];
+        g = gain[seg];
         int t = phi;
         for (; t + 3 * S < n; t += 4 * S) {
             int p[4], b[4];
-            T v[4];
+            TD v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
-                v[u] = SUB ? (T)d[i] : (T)0;
+                v[u] = SUB ? d[i] : (TD)0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], v[u]);
+            for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], (double)v[u]);
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
-            step(i, pix[i], psi[i], SUB ? (T)d[i] : (T)0);
+            step(i, pix[i], psi[i], SUB ? (double)d[i] : 0.0);
         }
     }
+    if (SUB && bad && err) atomicOr(err, C3_ERR_NONFINITE);
+}
+
+// per non-empty segment: the noise parameters the draws and weights divide by
+__global__ __launch_bounds__(C3_NT) void k_check_params(LayoutDev Ld, const double *__restrict__ sigma0,
+                                                        const double *__restrict__ fknee,
+                                                        const double *__restrict__ alpha,
+                                                        uint32_t *__restrict__ err) {
+    const int s = blockIdx.x * C3_NT + threadIdx.x;
+    if (s >= Ld.nseg || Ld.seg_off[s + 1] <= Ld.seg_off[s]) return;
+    uint32_t e = 0;
+    if (sigma0) {
+        const double v = sigma0[s];
+        if (!(v > 0.0) || !isfinite(v)) e |= C3_ERR_SIGMA0;
+    }
+    if (fknee) {
+        const double v = fknee[s];
+        if (!(v > 0.0) || !isfinite(v)) e |= C3_ERR_FKNEE;
+    }
+    if (alpha) {
+        const double v = alpha[s];
+        if (!(v < 0.0) || !isfinite(v)) e |= C3_ERR_ALPHA;
+    }
+    if (e) atomicOr(err, e);
 }
 
 // ---------------------------------------------------------------- solve
@@ -356,7 +395,11 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     const uint16_t *__restrict__ psi, const TD *__restrict__ d, const T *__restrict__ ncorr,
     const Stokes4<T> *__restrict__ maps, const double *__restrict__ gain,
     const double *__restrict__ sigma0, const cx<double> *__restrict__ trig,
-    double *__restrict__ seg_sums, double *__restrict__ gmap, double gscale) {
+    double *__restrict__ seg_sums, double *__restrict__ gmap, double gscale0,
+    const double *__restrict__ gscale_dev) {
+    // dL/dJ: a host factor times an optional device scalar (read here, so the
+    // caller's autograd never waits for it)
+    const double gscale = gscale_dev ? gscale0 * *gscale_dev : gscale0;
     __shared__ cx<double> tr[2048];
     __shared__ double red[3][C3_NT / 64];
     const int4 tl = tiles[blockIdx.x];
@@ -489,8 +532,10 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
 __global__ __launch_bounds__(C3_NT) void k_chisq_finish(
     LayoutDev Ld, const double *__restrict__ st, const double *__restrict__ sw,
     const double *__restrict__ gain, const double *__restrict__ sigma0,
-    const double *__restrict__ fknee, const double *__restrict__ alpha, double gscale,
-    double *chisq, double *ggain, double *gsig, double *gfk, double *galpha) {
+    const double *__restrict__ fknee, const double *__restrict__ alpha, double gscale0,
+    const double *__restrict__ gscale_dev, double *chisq, double *ggain, double *gsig, double *gfk,
+    double *galpha) {
+    const double gscale = gscale_dev ? gscale0 * *gscale_dev : gscale0;
     const int s = blockIdx.x * C3_NT + threadIdx.x;
     if (s >= Ld.nseg) return;
     const bool ok = !Ld.seg_accept || Ld.seg_accept[s];
@@ -513,24 +558,24 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_finish(
 template <typename TN>
 void launch_bin_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
                       const uint16_t *psi, const void *d, int d_f64, const TN *nc, const double *gain,
-                      const double *sigma0, const cx<double> *tr, double *acc) {
+                      const double *sigma0, const cx<double> *tr, double *acc, uint32_t *err) {
     const dim3 g(ntile), b(C3_NT);
     if (d_f64) {
         const double *dd = (const double *)d;
         if (nc)
             hipLaunchKernelGGL((k_bin<TN, double, true>), g, b, 0, st, L, tiles, pix, psi, dd, nc, gain, sigma0,
-                               tr, acc);
+                               tr, acc, err);
         else
             hipLaunchKernelGGL((k_bin<TN, double, false>), g, b, 0, st, L, tiles, pix, psi, dd, nc, gain, sigma0,
-                               tr, acc);
+                               tr, acc, err);
     } else {
         const float *df = (const float *)d;
         if (nc)
             hipLaunchKernelGGL((k_bin<TN, float, true>), g, b, 0, st, L, tiles, pix, psi, df, nc, gain, sigma0,
-                               tr, acc);
+                               tr, acc, err);
         else
             hipLaunchKernelGGL((k_bin<TN, float, false>), g, b, 0, st, L, tiles, pix, psi, df, nc, gain, sigma0,
-                               tr, acc);
+                               tr, acc, err);
     }
 }
 
@@ -538,30 +583,30 @@ void launch_bin_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int
 template <typename T>
 void launch_resid_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
                         const uint16_t *psi, const void *d, int d_f64, const void *maps, void *maps4,
-                        const double *gain, const void *trig, void *r_out) {
+                        const double *gain, const void *trig, void *r_out, uint32_t *err) {
     const int64_t npt = L.npix_total;
     const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
     hipLaunchKernelGGL(k_interleave<T>, dim3(gi), dim3(C3_NT), 0, st, (const T *)maps, npt, (Stokes4<T> *)maps4);
     const Stokes4<T> *m4 = (const Stokes4<T> *)maps4;
-    const cx<T> *tr = (const cx<T> *)trig;
+    const cx<double> *tr = (const cx<double> *)trig;
     T *out = (T *)r_out;
     const dim3 g(ntile), b(C3_NT);
     if (!d)
         hipLaunchKernelGGL((k_resid<T, T, false>), g, b, 0, st, L, tiles, pix, psi, (const T *)nullptr, m4, gain,
-                           tr, out);
+                           tr, out, err);
     else if (d_f64)
         hipLaunchKernelGGL((k_resid<T, double, true>), g, b, 0, st, L, tiles, pix, psi, (const double *)d, m4,
-                           gain, tr, out);
+                           gain, tr, out, err);
     else
         hipLaunchKernelGGL((k_resid<T, float, true>), g, b, 0, st, L, tiles, pix, psi, (const float *)d, m4,
-                           gain, tr, out);
+                           gain, tr, out, err);
 }
 
 template <typename T>
 void launch_chisq_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
                         const uint16_t *psi, const void *d, int d_f64, const void *ncorr, const void *maps,
                         void *maps4, const double *gain, const double *sigma0, const void *trig64,
-                        double *seg_sums, double *grad_maps, double grad_scale) {
+                        double *seg_sums, double *grad_maps, double grad_scale, const double *gscale_dev) {
     const int64_t npt = L.npix_total;
     const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
     hipLaunchKernelGGL(k_interleave<T>, dim3(gi), dim3(C3_NT), 0, st, (const T *)maps, npt, (Stokes4<T> *)maps4);
@@ -571,7 +616,7 @@ void launch_chisq_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, i
     const dim3 g(ntile), b(C3_NT);
 #define C3_CHISQ(TD, GRAD)                                                                              \
     hipLaunchKernelGGL((k_chisq_time<T, TD, GRAD>), g, b, 0, st, L, tiles, pix, psi, (const TD *)d, nc, m4, \
-                       gain, sigma0, tr, seg_sums, grad_maps, grad_scale)
+                       gain, sigma0, tr, seg_sums, grad_maps, grad_scale, gscale_dev)
     if (d_f64) {
         if (grad_maps)
             C3_CHISQ(double, true);
@@ -593,26 +638,34 @@ namespace c3 {
 hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                             int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                             int d_f64, const void *ncorr, const double *gain,
-                            const double *sigma0, const void *trig64, double *acc) {
+                            const double *sigma0, const void *trig64, double *acc, uint32_t *err) {
     if (ntile <= 0) return hipSuccess;
     if (mixed)
         launch_bin_typed(st, L, tiles, ntile, pix, psi, d, d_f64, (const float *)ncorr, gain, sigma0,
-                         (const cx<double> *)trig64, acc);
+                         (const cx<double> *)trig64, acc, err);
     else
         launch_bin_typed(st, L, tiles, ntile, pix, psi, d, d_f64, (const double *)ncorr, gain, sigma0,
-                         (const cx<double> *)trig64, acc);
+                         (const cx<double> *)trig64, acc, err);
     return hipGetLastError();
 }
 
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                               int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                               int d_f64, const void *maps, void *maps4, const double *gain,
-                              const void *trig, void *r_out) {
+                              const void *trig64, void *r_out, uint32_t *err) {
     if (ntile <= 0) return hipSuccess;
     if (mixed)
-        launch_resid_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig, r_out);
+        launch_resid_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig64, r_out, err);
     else
-        launch_resid_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig, r_out);
+        launch_resid_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig64, r_out, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_params(hipStream_t st, const LayoutDev &L, const double *sigma0, const double *fknee,
+                               const double *alpha, uint32_t *err) {
+    if (L.nseg <= 0 || (!sigma0 && !fknee && !alpha)) return hipSuccess;
+    const int nb = (L.nseg + C3_NT - 1) / C3_NT;
+    hipLaunchKernelGGL(k_check_params, dim3(nb), dim3(C3_NT), 0, st, L, sigma0, fknee, alpha, err);
     return hipGetLastError();
 }
 
@@ -660,26 +713,26 @@ hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed
                                    const void *d, int d_f64, const void *ncorr, const void *maps,
                                    void *maps4, const double *gain, const double *sigma0,
                                    const void *trig64, double *seg_sums, double *grad_maps,
-                                   double grad_scale) {
+                                   double grad_scale, const double *gscale_dev) {
     if (ntile <= 0) return hipSuccess;
     if (mixed)
         launch_chisq_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, ncorr, maps, maps4, gain, sigma0,
-                                  trig64, seg_sums, grad_maps, grad_scale);
+                                  trig64, seg_sums, grad_maps, grad_scale, gscale_dev);
     else
         launch_chisq_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, ncorr, maps, maps4, gain, sigma0,
-                                   trig64, seg_sums, grad_maps, grad_scale);
+                                   trig64, seg_sums, grad_maps, grad_scale, gscale_dev);
     return hipGetLastError();
 }
 
 hipError_t launch_chisq_finish(hipStream_t st, const LayoutDev &L, const double *seg_time,
                                const double *seg_whittle, const double *gain, const double *sigma0,
                                const double *fknee, const double *alpha, double grad_scale,
-                               double *chisq_seg, double *grad_gain, double *grad_sigma0,
+                               const double *gscale_dev, double *chisq_seg, double *grad_gain, double *grad_sigma0,
                                double *grad_fknee, double *grad_alpha) {
     if (L.nseg <= 0) return hipSuccess;
     const int nb = (L.nseg + C3_NT - 1) / C3_NT;
     hipLaunchKernelGGL(k_chisq_finish, dim3(nb), dim3(C3_NT), 0, st, L, seg_time, seg_whittle,
-                       gain, sigma0, fknee, alpha, grad_scale, chisq_seg, grad_gain, grad_sigma0,
+                       gain, sigma0, fknee, alpha, grad_scale, gscale_dev, chisq_seg, grad_gain, grad_sigma0,
                        grad_fknee, grad_alpha);
     return hipGetLastError();
 }

@@ -20,6 +20,9 @@
 
 namespace c3tune {
 
+// largest binning stride (revisit period, samples) the strided kernels take
+constexpr long kMaxStride = 1l << 26;
+
 struct FftChoice {
     int M1 = 1, M2 = 1, B = 1;
     int colreg = 0;  // 1: register column kernels (M1 compiled in)
@@ -179,7 +182,9 @@ inline bool choice_ok(const FftChoice &c, int64_t M, int mixed) {
     }
     if (p2 != c.M2) return false;
     if (c.colreg) return colreg_ok(mixed, c.M1);
-    if (c.M1 > col_tile(mixed) || c.B < 1 || (int64_t)c.M1 * c.B > col_tile(mixed)) return false;
+    // the LDS column kernels index a tile by shifts and masks of B
+    if (c.M1 > col_tile(mixed) || c.B < 1 || (c.B & (c.B - 1)) != 0 || (int64_t)c.M1 * c.B > col_tile(mixed))
+        return false;
     int64_t p1 = 1;
     for (int r : c.r1) {
         if (r != 2 && r != 3 && r != 4 && r != 5 && r != 8) return false;  // LDS column stages
@@ -280,11 +285,13 @@ inline bool from_json(const std::string &s, Table &t, std::map<std::string, int>
         if (q == std::string::npos) return std::string::npos;
         size_t a = s.find('[', q), b = s.find(']', q);
         v.clear();
+        if (a == std::string::npos || b == std::string::npos || b < a) return std::string::npos;
         const char *c = s.c_str() + a + 1;
         while (c < s.c_str() + b) {
             char *e;
             long x = strtol(c, &e, 10);
             if (e == c) { ++c; continue; }
+            if (v.size() >= 64) return std::string::npos;  // no plan has that many stages
             v.push_back((int)x);
             c = e;
         }
@@ -307,11 +314,13 @@ inline bool from_json(const std::string &s, Table &t, std::map<std::string, int>
         num_after(o, "\"M1\"", M1);
         num_after(o, "\"M2\"", M2);
         num_after(o, "\"B\"", B);
+        // out-of-range numbers make a choice that choice_ok rejects later
+        auto clip = [](long long x) { return (int)std::max<long long>(-1, std::min<long long>(x, 1 << 30)); };
         FftChoice c;
-        c.M1 = (int)M1;
-        c.M2 = (int)M2;
-        c.B = (int)B;
-        c.colreg = (int)colreg;
+        c.M1 = clip(M1);
+        c.M2 = clip(M2);
+        c.B = clip(B);
+        c.colreg = colreg != 0;
         list_after(o, "\"r1\"", c.r1);
         q = list_after(o, "\"r2\"", c.r2);
         if (q == std::string::npos) break;
@@ -320,13 +329,19 @@ inline bool from_json(const std::string &s, Table &t, std::map<std::string, int>
     ++t.version;
     if (fend != std::string::npos) {
         size_t a = s.find('{', fend), b = s.find('}', fend);
+        if (a == std::string::npos || b == std::string::npos || b < a) return false;
         size_t c = a;
         while (c != std::string::npos && c < b) {
             size_t k0 = s.find('"', c + 1);
             if (k0 == std::string::npos || k0 > b) break;
             size_t k1 = s.find('"', k0 + 1);
+            if (k1 == std::string::npos || k1 > b) return false;
             size_t col = s.find(':', k1);
-            strides[s.substr(k0 + 1, k1 - k0 - 1)] = (int)strtol(s.c_str() + col + 1, nullptr, 10);
+            if (col == std::string::npos || col > b) return false;
+            const long v = strtol(s.c_str() + col + 1, nullptr, 10);
+            // a revisit period is a positive sample count; keep those the
+            // strided kernels can step through in 32-bit arithmetic
+            if (v > 0 && v <= kMaxStride) strides[s.substr(k0 + 1, k1 - k0 - 1)] = (int)v;
             c = s.find(',', col);
         }
     }

@@ -256,18 +256,25 @@ class Context:
     def tod_chisq_backward(self, tod, prec, pix, psi, d, ncorr, maps, grad_scale, grad_maps=None,
                            grad_gain=None, grad_sigma0=None, grad_fknee=None, grad_alpha=None,
                            gain=None, sigma0=None, fknee=None, alpha=None):
+        """grad_scale: a number, or a one-element FP64 device tensor read by the kernels."""
+        if torch.is_tensor(grad_scale):
+            if grad_scale.dtype != torch.float64 or grad_scale.numel() != 1 or not grad_scale.is_cuda:
+                raise ValueError("a tensor grad_scale must be one FP64 value on the device")
+            gs_host, gs_dev = 1.0, _ptr(grad_scale)
+        else:
+            gs_host, gs_dev = float(grad_scale), None
         self._chk(self.lib.tod_chisq_backward(
             self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
             _ptr(ncorr), _ptr(maps), _ptr(tod.gain if gain is None else gain),
             _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(tod.fknee if fknee is None else fknee),
-            _ptr(tod.alpha if alpha is None else alpha), float(grad_scale), _ptr(grad_maps),
+            _ptr(tod.alpha if alpha is None else alpha), gs_host, gs_dev, _ptr(grad_maps),
             _ptr(grad_gain), _ptr(grad_sigma0), _ptr(grad_fknee), _ptr(grad_alpha)))
 
     def tod_sweep(self, tod, prec, maps, seed, it, ncorr_out, acc, pix_work, psi_work,
-                  use_graph=False):
+                  use_graph=False, pix_huff=None, psi_huff=None):
         self._chk(self.lib.tod_sweep(
-            self.h, ctypes.byref(tod.layout), _prec(prec), ctypes.byref(tod.pix_huff),
-            ctypes.byref(tod.psi_huff), _ptr(tod.d), _dt(tod.d), _ptr(maps), _ptr(tod.gain),
+            self.h, ctypes.byref(tod.layout), _prec(prec), ctypes.byref(pix_huff or tod.pix_huff),
+            ctypes.byref(psi_huff or tod.psi_huff), _ptr(tod.d), _dt(tod.d), _ptr(maps), _ptr(tod.gain),
             _ptr(tod.sigma0), _ptr(tod.fknee), _ptr(tod.alpha), ctypes.c_uint64(int(seed)),
             ctypes.c_uint64(int(it)), _ptr(ncorr_out), _ptr(acc), _ptr(pix_work), _ptr(psi_work),
             int(bool(use_graph))))
@@ -275,6 +282,10 @@ class Context:
     def autotune(self, tod, prec, pix=None, cache_path=None):
         self._chk(self.lib.tod_autotune(self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix),
                                         cache_path.encode() if cache_path else None))
+
+    def plan(self, tod, prec, tune_cache=None):
+        self._chk(self.lib.tod_plan(self.h, ctypes.byref(tod.layout), _prec(prec),
+                                    tune_cache.encode() if tune_cache else None))
 
     def load_tuning(self, path):
         self._chk(self.lib.tod_load_tuning(self.h, path.encode()))

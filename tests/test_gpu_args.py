@@ -45,3 +45,101 @@ def test_bad_arguments_rejected(env):
     c.decode_tod(tod, "fp64", out)
     c.sync()
     assert np.array_equal(out.cpu().numpy(), ts.d.astype(np.float64))
+
+
+def _tod_with(ts, **arrays):
+    """A device copy of the tiny set with some per-segment arrays replaced."""
+    from paper_2201_03509_amd import ops
+    tod = ops.DeviceTod(ts, "cuda:0")
+    for k, v in arrays.items():
+        getattr(tod, k).copy_(torch.from_numpy(np.asarray(v, dtype=np.float64)))
+    return tod
+
+
+@pytest.mark.parametrize("which,value,bit", [
+    ("sigma0", 0.0, 16), ("sigma0", -1.0, 16), ("sigma0", np.nan, 16),
+    ("fknee", 0.0, 32), ("fknee", np.inf, 32),
+    ("alpha", 0.0, 64), ("alpha", 0.5, 64), ("alpha", np.nan, 64),
+])
+def test_noise_parameter_domain_sets_sticky_bit(env, which, value, bit):
+    """sigma0 > 0, f_knee > 0, alpha < 0 (the PSD of Eq. 4) are checked on the
+    device by every call that reads them; the kernels still finish and the
+    sticky word carries the bit until it is cleared."""
+    from paper_2201_03509_amd import ops
+    c, ts, _ = env
+    vals = getattr(ts, which).astype(np.float64).copy()
+    vals[3] = value
+    tod = _tod_with(ts, **{which: vals})
+    s = torch.zeros(ts.nsamp, dtype=torch.float64, device="cuda")
+    out = torch.empty(ts.nsamp, dtype=torch.float64, device="cuda")
+    calls = [lambda: c.sample_ncorr(tod, "fp64", tod.d, s, 1, 0, out)]
+    if which == "sigma0":
+        acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+        calls.append(lambda: c.bin_tod(tod, "fp64", torch.from_numpy(ts.pix.astype(np.int32)).cuda(),
+                                       torch.from_numpy(ts.psi.astype(np.uint16)).cuda(), tod.d, None, acc))
+    maps = torch.from_numpy(ts.maps).cuda()
+    o = ops.new_outputs(tod, "fp64")
+    calls.append(lambda: c.tod_sweep(tod, "fp64", maps, 1, 0, o["ncorr"], o["acc"], o["pix"], o["psi"]))
+    for f in calls:
+        f()
+        with pytest.raises(ops.CorruptStream):
+            c.sync()
+        # a NaN parameter may also make the sweep's n_corr, hence its binned
+        # d - n_corr, non-finite (bit 128); nothing else may be raised
+        bits = c.device_error_bits()
+        assert bits & bit and not bits & ~(bit | 128), bits
+        c.clear_error()
+        c.sync()
+    # valid parameters: no bit
+    c.sample_ncorr(env[2], "fp64", env[2].d, s, 1, 0, out)
+    c.sync()
+
+
+def test_non_finite_data_sets_sticky_bit(env):
+    """A non-finite TOD sample raises bit 128 in the sweep's residual and in
+    the binning; a finite set raises nothing."""
+    from paper_2201_03509_amd import ops
+    c, ts, _ = env
+    tod = ops.DeviceTod(ts, "cuda:0")
+    maps = torch.from_numpy(ts.maps).cuda()
+    o = ops.new_outputs(tod, "fp64")
+    c.tod_sweep(tod, "fp64", maps, 1, 0, o["ncorr"], o["acc"], o["pix"], o["psi"])
+    c.sync()
+    d = tod.d.clone()
+    d[int(ts.seg_off[2]) + 7] = float("nan")
+    tod.d = d
+    c.tod_sweep(tod, "fp64", maps, 1, 0, o["ncorr"], o["acc"], o["pix"], o["psi"])
+    with pytest.raises(ops.CorruptStream):
+        c.sync()
+    assert c.device_error_bits() == 128
+    c.clear_error()
+    acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+    c.bin_tod(tod, "fp64", o["pix"], o["psi"], d, None, acc)
+    with pytest.raises(ops.CorruptStream):
+        c.sync()
+    assert c.device_error_bits() == 128
+    c.clear_error()
+    c.sync()
+
+
+def test_plan_ahead_and_stride_bounds(env, tmp_path):
+    """tod_plan builds a layout's plans up front (optionally from a tuning
+    cache); strides outside [0, 2^26] are rejected."""
+    from paper_2201_03509_amd import ops
+    c, ts, tod = env
+    c.plan(tod, "mixed")
+    c.plan(tod, "fp64", tune_cache=str(tmp_path / "missing.json"))
+    with pytest.raises(ops.InvalidArgument):
+        c.set_bin_stride(0, -1)
+    with pytest.raises(ops.InvalidArgument):
+        c.set_bin_stride(0, (1 << 26) + 1)
+    c.set_bin_stride(0, 0)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"fft": [ {"mixed": 1, "M": 4096, "M1": 64, "M2": 64, "B": 3, "colreg": 0, '
+                   '"r1": [8, 8], "r2": [8, 8]} ], "bin_stride": {"16:32.5": 2147483647}}')
+    c.load_tuning(str(bad))   # B = 3 and the stride are not taken
+    s = torch.zeros(ts.nsamp, dtype=torch.float64, device="cuda")
+    out = torch.empty(ts.nsamp, dtype=torch.float64, device="cuda")
+    c.sample_ncorr(tod, "fp64", tod.d, s, 1, 0, out)
+    c.sync()
+    assert torch.isfinite(out).all().item()

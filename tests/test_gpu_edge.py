@@ -141,8 +141,8 @@ def test_edge_project_bin_chisq(prec, stride):
     b, A, hits = ot.bin_tod(ts, ts.pix, ts.psi, ts.d, nc.astype(np.float64))
     a = acc.cpu().numpy()
     assert np.array_equal(a[9], hits)
-    assert np.abs(a[0:3] - b).max() <= 1e-11 * np.abs(b).max()
-    assert np.abs(a[3:9] - A).max() <= 1e-11 * np.abs(A).max()
+    assert np.abs(a[0:3] - b).max() <= 1e-12 * np.abs(b).max()
+    assert np.abs(a[3:9] - A).max() <= 1e-12 * np.abs(A).max()
     J_ref = ot.chisq_all(ts, m_ref, ts.pix, ts.psi, ts.d, nc.astype(np.float64))
     Jg = J.cpu().numpy()
     gm_ref, gg_ref, _, _, _ = ot.chisq_grad_all(ts, m_ref, ts.pix, ts.psi, ts.d, nc.astype(np.float64))
@@ -244,8 +244,8 @@ def test_edge_masked(prec, mean_only):
     mask[ts.seg_off[2]], mask[ts.seg_off[3]] = 0, 1  # one-sample segments: masked, kept
     s = ot.project_all(ts, ts.maps, ts.pix, ts.psi).astype(nf)
     seed, it = 5, 2
-    ref, ref_it = gf.cg_ncorr_all_gap(ts, ts.d, s.astype(np.float64), mask, seed, it, mean_only=mean_only,
-                                      tol=1e-13)
+    # the plain definition: the full extended system by preconditioned CG
+    ref, _ = gf.cg_ncorr_all(ts, ts.d, s.astype(np.float64), mask, seed, it, mean_only=mean_only, tol=1e-14)
     c = _ctx()
     try:
         from paper_2201_03509_amd import ops
@@ -253,15 +253,24 @@ def test_edge_masked(prec, mean_only):
         out = torch.empty(ts.nsamp, dtype=tf, device="cuda")
         iters = torch.empty(ts.nseg, dtype=torch.int32, device="cuda")
         c.sample_ncorr_masked(tod, prec, tod.d, _dev(s), _dev(mask), seed, it, out, mean_only=mean_only,
-                              tol=1e-6 if prec == "mixed" else 1e-13, iters=iters)
+                              tol=1e-6 if prec == "mixed" else 1e-15, iters=iters)
         c.sync()
     finally:
         c.close()
-    assert seg_rel(ts, out.cpu().numpy().astype(np.float64), ref) < TOL[prec]
-    if prec == "fp64":
-        ig = iters.cpu().numpy()
-        for q, k in ref_it.items():
-            assert abs(int(ig[q]) - k) <= 1, (q, int(ig[q]), k)
+    got = out.cpu().numpy().astype(np.float64)
+    assert seg_rel(ts, got, ref) < TOL[prec]
+    # segments short enough for the dense system: numpy.linalg.solve (a
+    # segment masked whole leaves its DC mode free, A singular: no unique x)
+    for q in range(ts.nseg):
+        a, b = int(ts.seg_off[q]), int(ts.seg_off[q + 1])
+        if not 0 < b - a <= 64 or not mask[a:b].any():
+            continue
+        band = int(ts.seg_band[q])
+        A, rhs = gf.dense_system(ts.d[a:b] - s[a:b].astype(np.float64), mask[a:b], float(ts.band_fsamp[band]),
+                                 float(ts.sigma0[q]), float(ts.fknee[q]), float(ts.alpha[q]), seed, q, it,
+                                 mean_only)
+        x = np.linalg.solve(A, rhs)[:b - a]
+        assert np.linalg.norm(got[a:b] - x) <= TOL[prec] * max(np.linalg.norm(x), 1e-300), q
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
@@ -290,8 +299,8 @@ def test_edge_sweep(prec):
     s = ot.project_all(ts, m.astype(np.float64), ts.pix, ts.psi)
     nc = ot.sample_ncorr_all(ts, ts.d, s, seed, 1)
     got = out["ncorr"].cpu().numpy().astype(np.float64)
-    assert seg_rel(ts, got, nc) < TOL[prec] * (3 if prec == "mixed" else 1)
+    assert seg_rel(ts, got, nc) < TOL[prec]
     b, A, hits = ot.bin_tod(ts, ts.pix, ts.psi, ts.d, got)
     a = out["acc"].cpu().numpy()
     assert np.array_equal(a[9], hits)
-    assert np.abs(a[0:3] - b).max() <= 1e-11 * np.abs(b).max()
+    assert np.abs(a[0:3] - b).max() <= 1e-12 * np.abs(b).max()

@@ -46,7 +46,7 @@ def test_cg_matches_dense_solve():
         ref = np.linalg.solve(A, b)[:n]
         got, k = og.cg_ncorr_segment(r, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 11, 3, 5,
                                      mean_only, tol=1e-14)
-        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
         assert k < 200
 
 
@@ -110,8 +110,8 @@ def test_gap_space_solver_matches_dense_and_full_cg():
                                          mean_only, tol=1e-14)
         full, kf = og.cg_ncorr_segment(r, m, PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"], 2, 1, 4,
                                        mean_only, tol=1e-14)
-        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
-        assert np.abs(got - full).max() <= 1e-10 * np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert np.abs(got - full).max() <= 1e-12 * np.abs(ref).max()
         assert 0 < k <= kf + 1
     un, k0 = og.cg_ncorr_segment_gap(r, np.ones(n), PAR["fsamp"], PAR["sigma0"], PAR["fknee"], PAR["alpha"],
                                      2, 1, 4)
