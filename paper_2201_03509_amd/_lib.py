@@ -19,7 +19,7 @@ EXPORTS = [
     "bin_tod",
     "solve_maps", "tod_chisq", "tod_chisq_backward", "tod_sweep", "tod_autotune",
     "tod_load_tuning", "tod_set_bin_stride", "tod_set_fft_batch", "tod_enable_timing",
-    "tod_kernel_times", "tod_plan",
+    "tod_kernel_times", "tod_plan", "decode_pointing_noalloc",
 ]
 
 
@@ -74,6 +74,7 @@ def load():
         "tod_last_error": [P],
         "tod_device_error_bits": [P],
         "decode_pointing": [P, LP, HP, HP, P, P],
+        "decode_pointing_noalloc": [P, LP, HP, HP, P, P],
         "project_sky": [P, LP, ctypes.c_int, P, P, P, P, P],
         "sample_ncorr": [P, LP, ctypes.c_int, P, ctypes.c_int, P, P, P, P, U64, U64,
                          ctypes.c_int, P],

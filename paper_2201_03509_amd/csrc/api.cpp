@@ -158,6 +158,7 @@ struct tod_ctx_s {
     std::map<uint64_t, GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;     // capture-only stream (default priority)
     uint64_t gen_counter = 0;             // source of Plan::gen
+    void *noalloc = nullptr;              // this device's static scratch (decode_pointing_noalloc)
 };
 
 namespace {
@@ -698,6 +699,10 @@ tod_status tod_ctx_create(tod_ctx *out, int device, void *hip_stream) {
         return TOD_EHIP;
     }
     for (auto &e : ctx->ev) (void)hipEventCreate(&e);
+    if (c3::noalloc_scratch(&ctx->noalloc) != hipSuccess) {  // device is current here
+        delete ctx;
+        return TOD_EHIP;
+    }
     if (c3::fft_init_attributes() != hipSuccess) {
         delete ctx;
         return TOD_EHIP;
@@ -776,6 +781,39 @@ tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay, const tod_huff *p
     KTimer kt(ctx, K_DECODE, ctx->stream);
     HIPCHK(c3::launch_decode(ctx->stream, make_layout_dev(lay), make_huff_dev(pix), make_huff_dev(psi),
                              (DecTab *)ctx->dec_tabs.p, tasks, nt, pix_out, psi_out, ctx->d_err));
+    return TOD_OK;
+}
+
+tod_status decode_pointing_noalloc(tod_ctx ctx, const tod_layout *lay, const tod_huff *pix,
+                                   const tod_huff *psi, int32_t *pix_out, uint16_t *psi_out) {
+    if (!ctx) return TOD_EINVAL;
+    tod_status r;
+    if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
+    if ((r = check_huff(ctx, pix, "pix")) != TOD_OK) return r;
+    if ((r = check_huff(ctx, psi, "psi")) != TOD_OK) return r;
+    if (pix->chunk_len != psi->chunk_len) return fail(ctx, TOD_EINVAL, "pix and psi chunk_len differ");
+    if (!pix_out || !psi_out) return fail(ctx, TOD_EINVAL, "NULL output");
+    if (!ctx->noalloc) return fail(ctx, TOD_EHIP, "no static scratch on this device");
+    // the work list is counted from the host mirror and built on the device:
+    // no plan, no device allocation
+    const int C = pix->chunk_len;
+    int64_t ntask = 0;
+    for (int s = 0; s < lay->nseg; ++s) {
+        const int64_t n = lay->h_seg_off[s + 1] - lay->h_seg_off[s];
+        const int64_t nch = n > 0 ? (n + C - 1) / C : 0;
+        ntask += (nch + C3_NT - 1) / C3_NT;
+    }
+    const int64_t need = c3::noalloc_task_offset((int64_t)pix->ntable + psi->ntable) +
+                         ntask * (int64_t)sizeof(DecodeTask);
+    if (need > (int64_t)C3_NOALLOC_BYTES || ntask > INT32_MAX) {
+        char buf[160];
+        snprintf(buf, sizeof(buf), "decode_pointing_noalloc needs %lld bytes of its %u-byte static scratch",
+                 (long long)need, (unsigned)C3_NOALLOC_BYTES);
+        return fail(ctx, TOD_ENOTSUP, buf);
+    }
+    KTimer kt(ctx, K_DECODE, ctx->stream);
+    HIPCHK(c3::launch_decode_noalloc(ctx->stream, make_layout_dev(lay), make_huff_dev(pix), make_huff_dev(psi),
+                                     ctx->noalloc, (int)ntask, pix_out, psi_out, ctx->d_err));
     return TOD_OK;
 }
 

@@ -144,6 +144,22 @@ struct DecodeTask {
 // Implemented in the .hip files; all return hipError_t of the launch.
 namespace c3 {
 
+// Static device scratch of decode_pointing_noalloc (bytes per device), laid
+// out as ntable DecTab records then the DecodeTask list
+#define C3_NOALLOC_BYTES (16u << 20)
+#define C3_MAX_DEVICES 64
+inline int64_t noalloc_task_offset(int64_t ntable) {
+    return (ntable * (int64_t)sizeof(DecTab) + 255) / 256 * 256;
+}
+// address of this device's static scratch (the current device); looked up
+// once per device with hipGetSymbolAddress
+hipError_t noalloc_scratch(void **ptr);
+// decode_pointing's kernels with the tables and a device-built work list of
+// ntask entries in the static scratch at scratch_ptr
+hipError_t launch_decode_noalloc(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
+                                 void *scratch_ptr, int ntask, int32_t *pix_out, uint16_t *psi_out,
+                                 uint32_t *err);
+
 // tabs: workspace of hp.ntable + hs.ntable DecTab records (pixel tables first)
 hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
                          DecTab *tabs, const DecodeTask *tasks, int ntask, int32_t *pix_out,

@@ -17,6 +17,8 @@
 // round, adds the symbol values to its running value (x_i = x_{i-1} + d_i),
 // range-checks, and leaves the samples in an LDS tile; the block then writes
 // the tile in rows of 16 consecutive samples of a chunk.
+#include <mutex>
+
 #include "common.h"
 
 namespace {
@@ -311,6 +313,51 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
     if (tid == 0 && blk_err) atomicOr(err, blk_err);
 }
 
+// ------------------------------------------------------- allocation-free variant
+// Scratch of decode_pointing_noalloc: the decoding tables of both streams,
+// then the work list, in one static array per device (held until the process
+// ends).  Host code uses only the address hipGetSymbolAddress returns for it.
+static __device__ __align__(256) unsigned char scratch[C3_NOALLOC_BYTES];
+
+// The work list of k_decode in segment order: segment s takes
+// ceil(ceil(n_s / C) / C3_NT) tasks, starting at the sum of the counts before
+// it.  One block scans the counts 1024 segments at a time.  Exactly ntask
+// entries are written: the host counts them from its mirror of the offsets;
+// entries the device offsets do not fill are empty tasks (no chunk), and
+// none is written past ntask, whatever the device offsets hold.
+__global__ __launch_bounds__(1024) void k_decode_tasks(const int64_t *__restrict__ seg_off, int nseg, int C,
+                                                       int ntask, DecodeTask *__restrict__ tasks) {
+    __shared__ int32_t pre[1024];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nseg; base += 1024) {
+        const int s = base + tid;
+        int nch = 0, cnt = 0;
+        if (s < nseg) {
+            const int64_t n = seg_off[s + 1] - seg_off[s];
+            nch = n > 0 ? (int)((n + C - 1) / C) : 0;
+            cnt = (nch + C3_NT - 1) / C3_NT;
+        }
+        pre[tid] = cnt;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {  // inclusive scan
+            const int v = tid >= o ? pre[tid - o] : 0;
+            __syncthreads();
+            pre[tid] += v;
+            __syncthreads();
+        }
+        const int64_t start = carry + pre[tid] - cnt;
+        for (int j = 0; j < cnt && start + j < ntask; ++j)
+            tasks[start + j] = DecodeTask{s, j * C3_NT, min(C3_NT, nch - j * C3_NT), 0};
+        __syncthreads();
+        if (tid == 1023) carry += pre[1023];
+        __syncthreads();
+    }
+    for (int64_t i = carry + tid; i < ntask; i += 1024) tasks[i] = DecodeTask{0, 0, 0, 0};
+}
+
 // One integer stream per segment (the TOD or the flag words): the same chunk
 // parse and undifferencing as k_decode, without range checks; the tile is
 // written as KIND 0: FP32 quantum * x, 1: FP64 quantum * x, 2: flag words
@@ -442,6 +489,35 @@ hipError_t launch_decode_stream(hipStream_t st, const LayoutDev &L, const HuffDe
         hipLaunchKernelGGL(k_decode1<2>, dim3(ntask), dim3(C3_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
                            out, mask_out, err);
     return hipGetLastError();
+}
+
+hipError_t noalloc_scratch(void **ptr) {
+    // one address per device, looked up once with that device current
+    static std::mutex mu;
+    static void *addr[C3_MAX_DEVICES] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= C3_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_decode_noalloc(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,
+                                 void *scratch_ptr, int ntask, int32_t *pix_out, uint16_t *psi_out,
+                                 uint32_t *err) {
+    if (ntask <= 0) return hipSuccess;
+    DecTab *tabs = (DecTab *)scratch_ptr;
+    DecodeTask *tasks = (DecodeTask *)((char *)scratch_ptr + noalloc_task_offset(hp.ntable + hs.ntable));
+    hipLaunchKernelGGL(k_decode_tasks, dim3(1), dim3(1024), 0, st, L.seg_off, L.nseg, hp.chunk_len, ntask, tasks);
+    return launch_decode(st, L, hp, hs, tabs, tasks, ntask, pix_out, psi_out, err);
 }
 
 hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, const HuffDev &hs,

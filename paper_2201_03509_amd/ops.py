@@ -184,6 +184,12 @@ class Context:
                                            ctypes.byref(psi_huff or tod.psi_huff),
                                            _ptr(pix_out), _ptr(psi_out)))
 
+    def decode_pointing_noalloc(self, tod, pix_out, psi_out, pix_huff=None, psi_huff=None):
+        self._chk(self.lib.decode_pointing_noalloc(self.h, ctypes.byref(tod.layout),
+                                                   ctypes.byref(pix_huff or tod.pix_huff),
+                                                   ctypes.byref(psi_huff or tod.psi_huff),
+                                                   _ptr(pix_out), _ptr(psi_out)))
+
     def decode_tod(self, tod, prec, d_out, quantum=None, tod_huff=None):
         self._chk(self.lib.decode_tod(self.h, ctypes.byref(tod.layout), _prec(prec),
                                       ctypes.byref(tod_huff or tod.tod_huff),
