@@ -579,6 +579,8 @@ def main():
     ap.add_argument("--fft-batch", type=int, default=None,
                     help="complex elements per FFT batch (0 = all segments at once)")
     ap.add_argument("--bin-stride", type=int, default=None, help="override the binning stride")
+    ap.add_argument("--bin-runs", type=int, default=None,
+                    help="scans per binning run (0 = chosen per layout)")
     ap.add_argument("--chunk-len", type=int, default=None,
                     help="Huffman side-index spacing of the generated inputs (symbols)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -631,6 +633,8 @@ def main():
     if args.bin_stride:
         for b in range(ts.nband):
             ctx.set_bin_stride(b, args.bin_stride)
+    if args.bin_runs is not None:
+        ctx.set_bin_runs(args.bin_runs)
     plans = {}
     for e in tuned.get("fft", []):
         if e["mixed"] == 1:

@@ -96,6 +96,11 @@ typedef struct {
     const int64_t *h_seg_off;    /* host mirror [nseg+1] */
     const int32_t *h_seg_band;   /* host mirror [nseg] */
     const tod_band *bands;       /* host [nband] */
+    const int32_t *h_seg_det;    /* host mirror [nseg] of seg_det; may be NULL.  With it the
+                                    binning chains a detector's segments, taken in index order
+                                    as consecutive in time, over several scans (see
+                                    tod_set_bin_runs); without it each segment (or pair of
+                                    equal neighbours) is binned alone */
 } tod_layout;
 
 /* One Huffman-coded, sample-differenced pointing stream kind (section 4.1):
@@ -406,6 +411,15 @@ tod_status tod_load_tuning(tod_ctx ctx, const char *cache_path);
  * library choose, at most 2^26.  Correct for any value; only speed depends on
  * it.  A stride longer than a segment acts as the segment's length. */
 tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride);
+
+/* Binning runs: the binning kernel gives each lane one phase of the revisit
+ * period (the spin phase, counted from the start of a detector's first segment)
+ * and walks it through `scans` consecutive scans of one detector pair before
+ * flushing its per-pixel sums, so the nearly coinciding rings of consecutive
+ * scans share the flushes (section 2.4: binned on the fly, synchronised once).
+ * Needs h_seg_det in the layout.  scans = 0: chosen per layout (as many as keep
+ * about 4096 blocks), 1..16: fixed.  Correct for any value. */
+tod_status tod_set_bin_runs(tod_ctx ctx, int32_t scans);
 
 /* FFT work batching: the column/row passes run batch by batch over groups of
  * segments whose complex workspace totals at most complex_elems (0 = all

@@ -19,7 +19,7 @@ EXPORTS = [
     "bin_tod",
     "solve_maps", "tod_chisq", "tod_chisq_backward", "tod_sweep", "tod_autotune",
     "tod_load_tuning", "tod_set_bin_stride", "tod_set_fft_batch", "tod_enable_timing",
-    "tod_kernel_times", "tod_plan", "decode_pointing_noalloc",
+    "tod_kernel_times", "tod_plan", "decode_pointing_noalloc", "tod_set_bin_runs",
 ]
 
 
@@ -35,7 +35,7 @@ class tod_layout(ctypes.Structure):
                 ("seg_off", ctypes.c_void_p), ("seg_band", ctypes.c_void_p),
                 ("seg_det", ctypes.c_void_p), ("seg_accept", ctypes.c_void_p),
                 ("h_seg_off", ctypes.c_void_p), ("h_seg_band", ctypes.c_void_p),
-                ("bands", ctypes.POINTER(tod_band))]
+                ("bands", ctypes.POINTER(tod_band)), ("h_seg_det", ctypes.c_void_p)]
 
 
 class tod_huff(ctypes.Structure):
@@ -95,6 +95,7 @@ def load():
         "tod_load_tuning": [P, ctypes.c_char_p],
         "tod_plan": [P, LP, ctypes.c_int, ctypes.c_char_p],
         "tod_set_bin_stride": [P, I32, I32],
+        "tod_set_bin_runs": [P, I32],
         "tod_set_fft_batch": [P, I64],
         "tod_enable_timing": [P, ctypes.c_int],
         "tod_kernel_times": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],

@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -115,6 +116,12 @@ struct Plan {
     DevBuf bin_tiles;
     int nbin = 0;
     std::vector<int> bin_stride;          // per band, as used for bin_tiles
+    // binning runs: tiles over chains of one detector pair's segments across
+    // consecutive scans, and the (segment, phase offset) list they index
+    DevBuf run_tiles, run_segs;
+    int nrun_tiles = 0;
+    int run_want = -1;                    // tod_set_bin_runs value the runs were built for
+    std::vector<int> run_stride;          // strides the runs were built for
 };
 
 }  // namespace
@@ -140,6 +147,7 @@ struct tod_ctx_s {
     std::map<int, int> band_stride;       // band index -> stride (tuned or set)
     std::map<std::string, int> stride_by_key;  // "nside:fsamp" -> stride (cache file)
     int64_t fft_batch = 0;                // complex elements per FFT batch (0: all segments)
+    int bin_runs = 0;                     // scans per binning run (0: chosen per layout)
     c3tune::Table tuned;                  // FFT choices
     std::string last_error;
     uint32_t last_err_bits = 0;
@@ -439,6 +447,7 @@ uint64_t layout_key(const tod_layout *L, int mixed, uint64_t salt) {
     h = fnv(h, L->h_seg_off, sizeof(int64_t) * (L->nseg + 1));
     h = fnv(h, L->h_seg_band, sizeof(int32_t) * L->nseg);
     h = fnv(h, L->bands, sizeof(tod_band) * L->nband);
+    if (L->h_seg_det) h = fnv(h, L->h_seg_det, sizeof(int32_t) * L->nseg);  // binning runs
     return h;
 }
 
@@ -565,6 +574,117 @@ tod_status get_bin_tiles(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_
     }
     *tiles = (const int4 *)P->bin_tiles.p;
     *ntile = P->nbin;
+    return TOD_OK;
+}
+
+// Binning runs.  Segments pair as in get_bin_tiles (a horn's two radiometers,
+// equal neighbours in index order); a detector pair's pairs, in index order,
+// are taken as consecutive scans contiguous in time, and G of them form a run
+// that one tile's lanes walk in turn.  Lane phase Phi of a multi-pair run
+// visits t = (Phi - A_s) mod S, phi + S, ... of each segment s, A_s being the
+// samples of the detector's earlier segments in the band: the same spin phase
+// in every scan, so a lane meets nearly the same pixels scan after scan (the
+// spin axis drifts by less than a pixel per scan) and its register sums are
+// flushed once per run.  Every residue mod S is one lane's, so every sample is
+// binned once whatever the pointing does.  Pairs shorter than the stride, and
+// every pair when the layout has no detector mirror, are runs of one pair with
+// phases [0, min(S, n)), as before.
+tod_status get_bin_runs(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_t *pix,
+                        const int4 **tiles, int *ntile, const int2 **runs) {
+    const int4 *pt;
+    int np;
+    tod_status r = get_bin_tiles(ctx, L, P, pix, &pt, &np);
+    if (r != TOD_OK) return r;
+    if (P->run_want != ctx->bin_runs || P->run_stride != P->bin_stride || (P->nrun_tiles == 0 && np > 0)) {
+        const int nseg = L->nseg;
+        const std::vector<int> &st = P->bin_stride;
+        auto n_of = [&](int s) { return P->h_segs[s].n; };
+        auto band_of = [&](int s) { return P->h_segs[s].band; };
+        auto det_of = [&](int s) { return L->h_seg_det ? L->h_seg_det[s] : -1; };
+        struct Pr {
+            int first, grp;
+        };
+        std::vector<Pr> pairs;
+        for (int s = 0; s < nseg;) {
+            if (s % 2 == 0 && s + 1 < nseg && n_of(s) == n_of(s + 1) && band_of(s) == band_of(s + 1)) {
+                pairs.push_back({s, 2});
+                s += 2;
+            } else {
+                pairs.push_back({s, 1});
+                s += 1;
+            }
+        }
+        // samples of each detector's earlier segments in its band
+        std::vector<int64_t> A(nseg, 0);
+        {
+            std::map<std::pair<int, int>, int64_t> tsum;
+            for (int s = 0; s < nseg; ++s) {
+                int64_t &t = tsum[{band_of(s), det_of(s)}];
+                A[s] = t;
+                t += n_of(s);
+            }
+        }
+        auto S_of = [&](int s) { return std::max(1, std::min(st[band_of(s)], std::max(n_of(s), 1))); };
+        int G = ctx->bin_runs;
+        if (!L->h_seg_det) {
+            G = 1;
+        } else if (G <= 0) {
+            int64_t t1 = 0;
+            for (const Pr &q : pairs) t1 += (std::min(S_of(q.first), std::max(n_of(q.first), 0)) + C3_NT - 1) / C3_NT;
+            G = (int)std::max<int64_t>(1, std::min<int64_t>(16, t1 / 4096));
+        }
+        // chains of pairs of one detector pair (long pairs only), in index order
+        std::map<std::tuple<int, int, int>, std::vector<int>> chains;
+        std::vector<std::vector<int>> runs_of_pairs;
+        for (int i = 0; i < (int)pairs.size(); ++i) {
+            const Pr &q = pairs[i];
+            const int s = q.first;
+            if (G > 1 && n_of(s) >= st[band_of(s)])
+                chains[{band_of(s), det_of(s), q.grp == 2 ? det_of(s + 1) : -1}].push_back(i);
+            else
+                runs_of_pairs.push_back({i});
+        }
+        for (auto &kv : chains)
+            for (size_t a = 0; a < kv.second.size(); a += G)
+                runs_of_pairs.emplace_back(kv.second.begin() + a,
+                                           kv.second.begin() + std::min(kv.second.size(), a + G));
+        // longest runs first
+        auto run_samples = [&](const std::vector<int> &rp) {
+            int64_t t = 0;
+            for (int i : rp) t += (int64_t)pairs[i].grp * n_of(pairs[i].first);
+            return t;
+        };
+        std::stable_sort(runs_of_pairs.begin(), runs_of_pairs.end(),
+                         [&](const std::vector<int> &a, const std::vector<int> &b) {
+                             return run_samples(a) > run_samples(b);
+                         });
+        std::vector<int2> segs;
+        std::vector<int4> tl;
+        for (const std::vector<int> &rp : runs_of_pairs) {
+            const int first = (int)segs.size();
+            const int s0 = pairs[rp[0]].first;
+            const int S = S_of(s0);
+            const bool multi = rp.size() > 1;
+            int nph = multi ? S : std::min(S, n_of(s0));
+            for (int i : rp)
+                for (int g = 0; g < pairs[i].grp; ++g) {
+                    const int sg = pairs[i].first + g;
+                    segs.push_back(make_int2(sg, multi ? (int)(A[sg] % S) : 0));
+                }
+            const int nsg = (int)segs.size() - first;
+            for (int p0 = 0; p0 < nph; p0 += C3_NT)
+                tl.push_back(make_int4(first, p0, S, std::min(C3_NT, nph - p0) | (nsg << 16)));
+        }
+        HIPCHK(P->run_tiles.upload(tl, ctx->stream));
+        HIPCHK(P->run_segs.upload(segs, ctx->stream));
+        P->nrun_tiles = (int)tl.size();
+        P->run_want = ctx->bin_runs;
+        P->run_stride = st;
+        P->gen = ++ctx->gen_counter;
+    }
+    *tiles = (const int4 *)P->run_tiles.p;
+    *ntile = P->nrun_tiles;
+    *runs = (const int2 *)P->run_segs.p;
     return TOD_OK;
 }
 
@@ -1235,14 +1355,15 @@ tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const int3
     Plan *P;
     if ((r = get_plan(ctx, lay, mixed, &P)) != TOD_OK) return r;
     const int4 *tiles;
+    const int2 *runs;
     int nt;
-    if ((r = get_bin_tiles(ctx, lay, P, pix, &tiles, &nt)) != TOD_OK) return r;
+    if ((r = get_bin_runs(ctx, lay, P, pix, &tiles, &nt, &runs)) != TOD_OK) return r;
     const LayoutDev Ld = make_layout_dev(lay);
     HIPCHK(c3::launch_check_params(ctx->stream, Ld, sigma0, nullptr, nullptr, ctx->d_err));
     if (!accumulate) HIPCHK(c3::launch_zero(ctx->stream, acc, lay->npix_total * 10 * sizeof(double)));
     KTimer kt(ctx, K_BIN, ctx->stream);
-    HIPCHK(c3::launch_bin_tiles(ctx->stream, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64, ncorr, gain,
-                                sigma0, ctx->trig64.p, acc, ctx->d_err));
+    HIPCHK(c3::launch_bin_tiles(ctx->stream, Ld, mixed, tiles, nt, runs, pix, psi, d, d_dtype == TOD_F64, ncorr,
+                                gain, sigma0, ctx->trig64.p, acc, ctx->d_err));
     return TOD_OK;
 }
 
@@ -1366,11 +1487,13 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     hipStream_t st = ctx->stream;
     const LayoutDev Ld = make_layout_dev(lay);
     if (P->nbin > 0) {
-        // tiles exist: rebuild them if a band's stride has been set or tuned
-        // since (no probe: the pointing of this call is not decoded yet)
+        // tiles exist: rebuild them if a band's stride or the run length has
+        // been set or tuned since (no probe: the pointing of this call is not
+        // decoded yet)
         const int4 *t0;
+        const int2 *r0;
         int n0;
-        if ((r = get_bin_tiles(ctx, lay, P, nullptr, &t0, &n0)) != TOD_OK) return r;
+        if ((r = get_bin_runs(ctx, lay, P, nullptr, &t0, &n0, &r0)) != TOD_OK) return r;
     }
 
     // graph key: every pointer and size the captured kernels bake in -- the
@@ -1384,7 +1507,8 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     gk = fnv(gk, &Hs, sizeof(Hs));
     const void *ptrs[] = {d, maps, gain, sigma0, fknee, alpha, ncorr_out, acc, pix_work, psi_work,
                           ctx->work.p, ctx->resid.p, ctx->dec_tabs.p, ctx->maps4.p, ctx->trig32.p,
-                          ctx->trig64.p, ctx->d_err, ctx->d_seed_iter, dt};
+                          ctx->trig64.p, ctx->d_err, ctx->d_seed_iter, dt, P->bin_tiles.p, P->run_tiles.p,
+                          P->run_segs.p};
     gk = fnv(gk, ptrs, sizeof(ptrs));
     gk = fnv(gk, &ndt, sizeof(ndt));
     gk = fnv(gk, &P->key, sizeof(P->key));
@@ -1412,9 +1536,14 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
         }
         const int4 *tiles = (const int4 *)P->bin_tiles.p;
         int nt = P->nbin;
+        const int4 *rtiles = (const int4 *)P->run_tiles.p;
+        const int2 *runs = (const int2 *)P->run_segs.p;
+        int nrt = P->nrun_tiles;
         if (!capture && !have_tiles) {
-            tod_status rr = get_bin_tiles(ctx, lay, P, pix_work, &tiles, &nt);
+            tod_status rr = get_bin_runs(ctx, lay, P, pix_work, &rtiles, &nrt, &runs);
             if (rr != TOD_OK) return rr;
+            tiles = (const int4 *)P->bin_tiles.p;
+            nt = P->nbin;
         }
         {
             KTimer kt(ctx, K_PROJECT, st);
@@ -1438,7 +1567,7 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
         {
             HIPCHK(c3::launch_zero(st, acc, lay->npix_total * 10 * sizeof(double)));
             KTimer kt(ctx, K_BIN, st);
-            HIPCHK(c3::launch_bin_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
+            HIPCHK(c3::launch_bin_tiles(st, Ld, mixed, rtiles, nrt, runs, pix_work, psi_work, d,
                                         d_dtype == TOD_F64, ncorr_out, gain, sigma0, ctx->trig64.p, acc,
                                         ctx->d_err));
         }
@@ -1475,6 +1604,13 @@ tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride) {
         ctx->band_stride.erase(band);
     else
         ctx->band_stride[band] = stride;
+    return TOD_OK;
+}
+
+tod_status tod_set_bin_runs(tod_ctx ctx, int32_t scans) {
+    if (!ctx) return TOD_EINVAL;
+    if (scans < 0 || scans > 16) return fail(ctx, TOD_EINVAL, "scans per binning run must be in [0, 16]");
+    ctx->bin_runs = scans;
     return TOD_OK;
 }
 

@@ -234,9 +234,10 @@ bool fft_col_reg_supported(int prec_mixed, int m1);
 // raise the dynamic LDS limit of the FFT kernels (once per process)
 hipError_t fft_init_attributes();
 
+// tiles and runs: the binning runs (get_bin_runs); err receives C3_ERR_NONFINITE
 hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
-                            int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
-                            int d_f64, const void *ncorr, const double *gain,
+                            int ntile, const int2 *runs, const int32_t *pix, const uint16_t *psi,
+                            const void *d, int d_f64, const void *ncorr, const double *gain,
                             const double *sigma0, const void *trig64, double *acc, uint32_t *err);
 hipError_t launch_zero(hipStream_t st, void *p, int64_t bytes);
 hipError_t launch_solve(hipStream_t st, int64_t npix, const double *acc, double rcond_min,

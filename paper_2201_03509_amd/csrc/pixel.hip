@@ -23,15 +23,18 @@ __device__ __forceinline__ void flush_acc(double *acc, int64_t npt, int64_t gp, 
     for (int j = 0; j < 10; ++j) atomicAdd(acc + j * npt + gp, a[j]);
 }
 
-// Bin tile (x = first segment, y = first phase, z = stride S, w = phases | nseg << 16):
-// the tile's segments are consecutive and of equal length; a lane visits its
-// phase in each of them in turn, so segments that see the same pixels (the two
-// radiometers of a horn) share one register accumulation and one flush.
+// Bin tile (x = first entry of the run list, y = first phase, z = stride S,
+// w = phases | entries << 16); run entry = (segment, phase offset o).  Lane
+// phase Phi visits t = (Phi - o) mod S, + S, ... of each of the run's
+// segments in turn, so segments that see the same pixels (the two radiometers
+// of a horn, and the same horn's consecutive scans at equal spin phase) share
+// one register accumulation and its flushes.
 // TD: type of d, TN: type of n_corr (NC = false: no n_corr).  Both are
 // compile-time, so a revisit's loads issue back to back with no branch
 // between them and are converted only once all of them are in flight.
 template <typename TN, typename TD, bool NC>
 __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restrict__ tiles,
+                                               const int2 *__restrict__ runs,
                                                const int32_t *__restrict__ pix,
                                                const uint16_t *__restrict__ psi,
                                                const TD *__restrict__ d,
@@ -49,7 +52,7 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
     const int nph = tl.w & 0xFFFF, ngrp = tl.w >> 16;
     const int phi = tl.y + threadIdx.x;
     if ((int)threadIdx.x >= nph) return;
-    const int seg0 = tl.x;
+    const int seg0 = runs[tl.x].x;
     const int64_t poff = Ld.band[Ld.seg_band[seg0]].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[Ld.seg_band[seg0]].npix;
     const int64_t npt = Ld.npix_total;
@@ -116,7 +119,8 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         a[9] += 1.0;
     };
     for (int gi = 0; gi < ngrp; ++gi) {
-        const int seg = seg0 + gi;
+        const int2 re = runs[tl.x + gi];
+        const int seg = re.x;
         if (Ld.seg_accept && !Ld.seg_accept[seg]) continue;
         const int64_t s0 = Ld.seg_off[seg];
         const int n = (int)(Ld.seg_off[seg + 1] - s0);
@@ -124,7 +128,8 @@ __global__ __launch_bounds__(C3_NT) void k_bin(LayoutDev Ld, const int4 *__restr
         const double s2 = sigma0[seg];
         w = g / (s2 * s2);
         gw = g * w;
-        int t = phi;
+        int t = phi - re.y;  // the offset is in [0, S): one wrap at most
+        if (t < 0) t += S;
         // two revisits in flight (four measured no faster; their registers
         // cost occupancy)
         for (; t + S < n; t += 2 * S) {
@@ -556,25 +561,26 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_finish(
 // the launchers pick the instantiation here
 
 template <typename TN>
-void launch_bin_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
+void launch_bin_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int2 *runs,
+                      const int32_t *pix,
                       const uint16_t *psi, const void *d, int d_f64, const TN *nc, const double *gain,
                       const double *sigma0, const cx<double> *tr, double *acc, uint32_t *err) {
     const dim3 g(ntile), b(C3_NT);
     if (d_f64) {
         const double *dd = (const double *)d;
         if (nc)
-            hipLaunchKernelGGL((k_bin<TN, double, true>), g, b, 0, st, L, tiles, pix, psi, dd, nc, gain, sigma0,
+            hipLaunchKernelGGL((k_bin<TN, double, true>), g, b, 0, st, L, tiles, runs, pix, psi, dd, nc, gain, sigma0,
                                tr, acc, err);
         else
-            hipLaunchKernelGGL((k_bin<TN, double, false>), g, b, 0, st, L, tiles, pix, psi, dd, nc, gain, sigma0,
+            hipLaunchKernelGGL((k_bin<TN, double, false>), g, b, 0, st, L, tiles, runs, pix, psi, dd, nc, gain, sigma0,
                                tr, acc, err);
     } else {
         const float *df = (const float *)d;
         if (nc)
-            hipLaunchKernelGGL((k_bin<TN, float, true>), g, b, 0, st, L, tiles, pix, psi, df, nc, gain, sigma0,
+            hipLaunchKernelGGL((k_bin<TN, float, true>), g, b, 0, st, L, tiles, runs, pix, psi, df, nc, gain, sigma0,
                                tr, acc, err);
         else
-            hipLaunchKernelGGL((k_bin<TN, float, false>), g, b, 0, st, L, tiles, pix, psi, df, nc, gain, sigma0,
+            hipLaunchKernelGGL((k_bin<TN, float, false>), g, b, 0, st, L, tiles, runs, pix, psi, df, nc, gain, sigma0,
                                tr, acc, err);
     }
 }
@@ -636,15 +642,15 @@ void launch_chisq_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, i
 namespace c3 {
 
 hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
-                            int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
-                            int d_f64, const void *ncorr, const double *gain,
+                            int ntile, const int2 *runs, const int32_t *pix, const uint16_t *psi,
+                            const void *d, int d_f64, const void *ncorr, const double *gain,
                             const double *sigma0, const void *trig64, double *acc, uint32_t *err) {
     if (ntile <= 0) return hipSuccess;
     if (mixed)
-        launch_bin_typed(st, L, tiles, ntile, pix, psi, d, d_f64, (const float *)ncorr, gain, sigma0,
+        launch_bin_typed(st, L, tiles, ntile, runs, pix, psi, d, d_f64, (const float *)ncorr, gain, sigma0,
                          (const cx<double> *)trig64, acc, err);
     else
-        launch_bin_typed(st, L, tiles, ntile, pix, psi, d, d_f64, (const double *)ncorr, gain, sigma0,
+        launch_bin_typed(st, L, tiles, ntile, runs, pix, psi, d, d_f64, (const double *)ncorr, gain, sigma0,
                          (const cx<double> *)trig64, acc, err);
     return hipGetLastError();
 }

@@ -69,7 +69,7 @@ class DeviceTod:
         self.seg_band = to(self.h_seg_band)
         self.seg_det = to(src.seg_det, np.int32)
         self.seg_accept = to(src.seg_accept, np.uint8)
-        self.seg_det_h = np.asarray(src.seg_det, dtype=np.int32)
+        self.seg_det_h = np.ascontiguousarray(src.seg_det, dtype=np.int32)
         bands = (L.tod_band * self.nband)()
         for b in range(self.nband):
             bands[b].nside = int(src.band_nside[b])
@@ -88,6 +88,7 @@ class DeviceTod:
         lay.h_seg_off = self.h_seg_off.ctypes.data
         lay.h_seg_band = self.h_seg_band.ctypes.data
         lay.bands = bands
+        lay.h_seg_det = self.seg_det_h.ctypes.data
         self.layout = lay
         self.d = to(src.d)
         self.gain = to(src.gain, np.float64)
@@ -298,6 +299,9 @@ class Context:
 
     def set_bin_stride(self, band, stride):
         self._chk(self.lib.tod_set_bin_stride(self.h, int(band), int(stride)))
+
+    def set_bin_runs(self, scans):
+        self._chk(self.lib.tod_set_bin_runs(self.h, int(scans)))
 
     def set_fft_batch(self, complex_elems):
         self._chk(self.lib.tod_set_fft_batch(self.h, int(complex_elems)))

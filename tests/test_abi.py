@@ -44,5 +44,5 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 def test_struct_layouts():
     from paper_2201_03509_amd import _lib
     assert ctypes.sizeof(_lib.tod_band) == 32
-    assert ctypes.sizeof(_lib.tod_layout) == 4 * 4 + 8 * 2 + 7 * 8
+    assert ctypes.sizeof(_lib.tod_layout) == 4 * 4 + 8 * 2 + 8 * 8
     assert ctypes.sizeof(_lib.tod_huff) == 8 * 8 + 4 * 2 + 8 * 2

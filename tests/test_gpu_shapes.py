@@ -72,6 +72,7 @@ def test_lfi70_shape_autotuned(lfi70, tmp_path):
         print("autotuned splits:", sorted({(e["M1"], e["M2"]) for e in plans}))
         assert all(e["colreg"] == 1 and 50 <= e["M1"] <= 81 for e in plans)
         maps = torch.from_numpy(m32).cuda()
+        c.set_bin_runs(2)  # binning walks both scans of a detector pair per run
         c.tod_sweep(tod, "mixed", maps, seed, 4, out["ncorr"], out["acc"], out["pix"], out["psi"])
         c.sync()
         nc_e = out["ncorr"].cpu().numpy().astype(np.float64)
