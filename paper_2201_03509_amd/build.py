@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libc3tod.so")
-SOURCES = ["fftcol.hip", "api.cpp", "decode.hip", "fft.hip", "gain.hip", "gapfill.hip", "noise.hip", "pixel.hip"]
+SOURCES = ["rowc.hip", "fftcol.hip", "api.cpp", "decode.hip", "fft.hip", "gain.hip", "gapfill.hip", "noise.hip", "pixel.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "common.h"
+#include "rowc.h"
 #include "tune.h"
 
 namespace {
@@ -93,6 +94,7 @@ struct Plan {
     struct RowGroup {
         int lds;                          // dynamic LDS bytes of the launch
         int t0, nt;                       // range of the row task list
+        int rowc;                         // row length of a compiled row kernel, 0: generic
     };
     struct Batch {
         int col0, ncol, row0, nrow;
@@ -330,6 +332,20 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
             for (int64_t m = 0; m < 1024; ++m) pool.push(m, N);
             fp.twhi = (int64_t)pool.re.size();
             for (int64_t h = 0; h <= N / 1024 + 1; ++h) pool.push(h * 1024, N);
+            fp.twr = fp.twh = -1;
+            if (mixed && c3rowc::compiled(ch.M2)) {
+                // the compiled row kernel's stage twiddles (rowc.h layout) and w_2L^j
+                const int L = ch.M2;
+                const c3rowc::Plan3 rp = c3rowc::plan(L);
+                fp.twr = (int64_t)pool.re.size();
+                for (int st = 1; st < 3; ++st) {
+                    const int R = rp.r[st], NS = c3rowc::row_ns(L, st);
+                    for (int k = 0; k < NS; ++k)
+                        for (int t = 1; t < R; ++t) pool.push((int64_t)t * k, (int64_t)NS * R);
+                }
+                fp.twh = (int64_t)pool.re.size();
+                for (int j = 0; j < L; ++j) pool.push(j, 2 * (int64_t)L);
+            }
             P->plan_of_M[M] = (int)P->h_plans.size();
             P->h_plans.push_back(fp);
             it = P->plan_of_M.find(M);
@@ -351,6 +367,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     std::vector<int2> col, row;
     std::map<int, std::vector<int2>> bcol;               // m1reg -> column tasks of the open batch
     std::map<int, std::pair<int, std::vector<int2>>> brow;  // -blocks per CU -> (lds, row tasks)
+    std::map<int, std::vector<int2>> browc;              // compiled row length -> two-row tasks
     Plan::Batch cur{0, 0, 0, 0, {}, {}};
     auto close_batch = [&]() {
         cur.col0 = (int)col.size();
@@ -359,8 +376,12 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
             col.insert(col.end(), kv.second.begin(), kv.second.end());
         }
         cur.row0 = (int)row.size();
+        for (auto &kv : browc) {
+            cur.rgroups.push_back({2 * kv.first * esz, (int)row.size(), (int)kv.second.size(), kv.first});
+            row.insert(row.end(), kv.second.begin(), kv.second.end());
+        }
         for (auto &kv : brow) {
-            cur.rgroups.push_back({kv.second.first, (int)row.size(), (int)kv.second.second.size()});
+            cur.rgroups.push_back({kv.second.first, (int)row.size(), (int)kv.second.second.size(), 0});
             row.insert(row.end(), kv.second.second.begin(), kv.second.second.end());
         }
         cur.ncol = (int)col.size() - cur.col0;
@@ -368,6 +389,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         if (cur.ncol > 0 || cur.nrow > 0) P->batches.push_back(cur);
         bcol.clear();
         brow.clear();
+        browc.clear();
         cur = Plan::Batch{(int)col.size(), 0, (int)row.size(), 0, {}, {}};
     };
     for (int s : P->seg_order) {
@@ -386,8 +408,15 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         const int rl = 2 * fp.M2 * esz;
         const int per_cu = std::max(1, (C3_LDS_MAX - 1024) / std::max(rl, 1));
         auto &rg = brow[-per_cu];
-        rg.first = std::max(rg.first, rl);
-        for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) rg.second.push_back(make_int2(s, k1));
+        for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) {
+            // rows k1 and M1 - k1 distinct: the compiled kernel of the row length
+            if (fp.twr >= 0 && k1 > 0 && 2 * k1 != fp.M1) {
+                browc[fp.M2].push_back(make_int2(s, k1));
+            } else {
+                rg.first = std::max(rg.first, rl);
+                rg.second.push_back(make_int2(s, k1));
+            }
+        }
     }
     close_batch();
     P->ncol = (int)col.size();
@@ -760,12 +789,16 @@ tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::Ff
         for (int pass = first; pass < npass; ++pass) {
             if (pass == 1) {
                 for (const Plan::RowGroup &g : b.rgroups) {
+                    if (g.nt <= 0) continue;
                     c3::FftArgs ag = a;
                     ag.row_tasks = (const int2 *)P->row_tasks.p + g.t0;
                     ag.nrow_tasks = g.nt;
                     ag.row_lds = g.lds;
                     KTimer kt(ctx, K_ROW, st);
-                    HIPCHK(c3::launch_fft_pass(st, mixed, ag, pass, 0));
+                    if (g.rowc && c3::rowc_supported(mixed, g.rowc, a.mode))
+                        HIPCHK(c3::launch_rowc(st, ag, g.rowc));
+                    else
+                        HIPCHK(c3::launch_fft_pass(st, mixed, ag, pass, 0));
                 }
                 continue;
             }

@@ -80,6 +80,8 @@ struct FftPlan {
     int64_t tw2;                 // offset of w_M2^m (m < M2)
     int64_t twlo;                // w_N^m, m < 1024           (N = 2M)
     int64_t twhi;                // w_N^(1024 h), h < N/1024 + 1
+    int64_t twr;                 // compiled row length M2 (rowc.h): its stage twiddles, -1 if none
+    int64_t twh;                 //   and w_(2 M2)^j, j < M2 (the mode loop's twiddle), -1 if none
 };
 
 // Context-side view of the layout kept on the device.
@@ -231,6 +233,11 @@ hipError_t launch_fft_pass(hipStream_t st, int prec_mixed, const FftArgs &a, int
 // column length without a compiled kernel
 hipError_t launch_fft_col_reg(hipStream_t st, int prec_mixed, const FftArgs &a, int pass, int m1);
 bool fft_col_reg_supported(int prec_mixed, int m1);
+// row kernels compiled per row length (rowc.hip): FP32, modes 0 and 2, the
+// two-row tasks (0 < k1 < M1/2) of plans whose M2 is compiled
+bool rowc_supported(int prec_mixed, int L, int mode);
+hipError_t launch_rowc(hipStream_t st, const FftArgs &a, int L);
+hipError_t rowc_init_attributes();
 // raise the dynamic LDS limit of the FFT kernels (once per process)
 hipError_t fft_init_attributes();
 

@@ -1,0 +1,229 @@
+// FFT row pass (pass 2 of the n_corr transform, section 4.2) compiled per row
+// length L: FP32, the rows k1 and M1 - k1 of one segment (0 < k1 < M1/2, the
+// rows holding each other's mirror modes) in one block of 512 threads.
+//
+// Everything the generic row kernel (fft.hip) decides at run time is fixed
+// here at compile time: the three stage radices (rowc.h), each thread's
+// butterflies, the LDS strides and the index arithmetic; the stage
+// twiddles are loaded whole from a per-length table (one base address per
+// butterfly) instead of being built by chained products, and the mode loop
+// takes w_N^k = w_N^k1 w_2L^k2 from a block constant and a table of L values.
+// The first forward stage reads the two rows from memory and the last inverse
+// stage writes them back.  Modes: 0 (n_corr constrained realisation) and 2
+// (Fourier-diagonal filters); the other modes, and the rows k1 = 0 and
+// k1 = M1/2, run on the generic kernel.
+#include "fftmode.h"
+#include "rowc.h"
+
+namespace {
+using c3::FftArgs;
+using namespace c3fft;
+using namespace c3rowc;
+
+constexpr int NT = C3_ROW_NT_F32;
+
+extern __shared__ __attribute__((aligned(16))) unsigned char c3_rowc_lds[];
+
+// one Stockham stage of the two interleaved rows (row b's element i at LDS
+// index 2 i + b).  IO 1: inputs from the rows in memory (first forward
+// stage); IO 2: outputs to the rows in memory (last inverse stage).
+template <int L, int S, int DIR, int IO>
+__device__ __forceinline__ void rstage(cx<float> *buf, const cx<float> *g0, const cx<float> *g1, cx<float> *o0,
+                                       cx<float> *o1, const cx<float> *__restrict__ tw) {
+    constexpr Plan3 P = plan(L);
+    constexpr int R = P.r[S];
+    constexpr int NS = row_ns(L, S);
+    constexpr int LR = L / R;
+    constexpr int NB = 2 * LR;  // butterflies of both rows
+    constexpr int KB = (NB + NT - 1) / NT;
+    constexpr long TOFF = S > 0 ? stage_off(L, S) : 0;
+    cx<float> v[KB][R];
+    int ob[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int q = (int)threadIdx.x + kb * NT;
+        ob[kb] = -1;
+        if (NB % NT == 0 || q < NB) {
+            const int b = q & 1, j = q >> 1;
+            if constexpr (IO == 1) {
+                const cx<float> *g = b ? g1 : g0;
+#pragma unroll
+                for (int t = 0; t < R; ++t) v[kb][t] = g[j + t * LR];
+            } else {
+#pragma unroll
+                for (int t = 0; t < R; ++t) v[kb][t] = buf[2 * (j + t * LR) + b];
+            }
+            const int jd = j / NS, k = j - jd * NS;
+            if constexpr (S > 0) {
+                const cx<float> *w = tw + TOFF + k * (R - 1);
+#pragma unroll
+                for (int t = 1; t < R; ++t) {
+                    const cx<float> wt = w[t - 1];
+                    v[kb][t] = DIR < 0 ? cmul(v[kb][t], wt) : cmulc(v[kb][t], wt);
+                }
+            }
+            dft_any<R, DIR>(v[kb]);
+            if constexpr (IO == 2) {
+                cx<float> *o = b ? o1 : o0;  // last stage: jd = 0
+#pragma unroll
+                for (int t = 0; t < R; ++t) o[k + t * NS] = v[kb][t];
+            } else {
+                ob[kb] = 2 * (jd * NS * R + k) + b;
+            }
+        }
+    }
+    if constexpr (IO == 2) return;
+    if constexpr (IO == 0) __syncthreads();  // in place: every read before any write
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+        if (ob[kb] >= 0) {
+#pragma unroll
+            for (int t = 0; t < R; ++t) buf[ob[kb] + 2 * t * NS] = v[kb][t];
+        }
+    __syncthreads();
+}
+
+// nhat_k of the n_corr draw (the same value as cr_mode) with the draw's
+// constants folded: s0 W1 = sqrt(c log2 u0) (cos 2 pi u1, sin 2 pi u1) with
+// c = -sigma0^2 ln 2 (Box-Muller radius sqrt(-2 ln u0) times 1/sqrt 2 and
+// sigma0), and s0 sqrt(q) W2 = sqrt(c q log2 u2) (cos 2 pi u3, sin 2 pi u3).
+// k > 0 and k < M here, so both draws are complex.
+struct FastCtx {
+    float c;        // -sigma0^2 ln 2
+    float isq;      // 1 / sqrt(N)
+    float malpha, lbase2;
+};
+
+__device__ __forceinline__ cx<float> cr_fast(const ModeCtx &mc, const FastCtx &fc, uint32_t k, cx<float> E) {
+    const float x = fc.malpha * (__builtin_amdgcn_logf((float)k) + fc.lbase2);
+    const float q = __builtin_amdgcn_exp2f(x);  // (f_k / f_knee)^-alpha = sigma0^2 / P_k
+    const float inv = __builtin_amdgcn_rcpf(1.0f + q);
+    cx<float> out = {E.x * fc.isq, E.y * fc.isq};
+    if (!mc.mean_only) {
+        const uint4 w = philox4x32_10(make_uint4(k, mc.it_lo, mc.it_hi, mc.seed_hi), mc.key);
+        const float sc = 2.3283064365386963e-10f, off = 1.1641532182693481e-10f;  // (x + 1/2) 2^-32
+        const float u0 = fmaf((float)w.x, sc, off), u1 = fmaf((float)w.y, sc, off);
+        const float u2 = fmaf((float)w.z, sc, off), u3 = fmaf((float)w.w, sc, off);
+        const float a0 = __builtin_amdgcn_sqrtf(fc.c * __builtin_amdgcn_logf(u0));
+        const float a1 = __builtin_amdgcn_sqrtf(fc.c * q * __builtin_amdgcn_logf(u2));
+        out.x = fmaf(a0, __builtin_amdgcn_cosf(u1), fmaf(a1, __builtin_amdgcn_cosf(u3), out.x));
+        out.y = fmaf(a0, __builtin_amdgcn_sinf(u1), fmaf(a1, __builtin_amdgcn_sinf(u3), out.y));
+    }
+    return {out.x * inv, out.y * inv};
+}
+
+template <int L, int MODE>
+__global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
+    static_assert(plan(L).r[0] > 0, "row length without a three-stage plan");
+    cx<float> *buf = (cx<float> *)c3_rowc_lds;  // 2 L elements
+    const int2 task = a.row_tasks[blockIdx.x];
+    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
+    const int seg = task.x;
+    const SegInfo sg = a.segs[seg];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M1 = p.M1, M = p.M;
+    const int ka = task.y, kb = M1 - ka;  // 0 < ka < M1 / 2: two distinct rows
+    const cx<float> *pool = (const cx<float> *)a.twpool;
+    const cx<float> *tws = pool + p.twr;
+    const cx<float> *twh = pool + p.twh;
+    cx<float> *Y = (cx<float> *)a.work + sg.scr_off;
+    cx<float> *ya = Y + (int64_t)ka * L, *yb = Y + (int64_t)kb * L;
+
+    rstage<L, 0, -1, 1>(buf, ya, yb, nullptr, nullptr, tws);
+    rstage<L, 1, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+    rstage<L, 2, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+
+    const ModeCtx mc = mode_ctx<MODE>(a, seg, sg.band, M);
+    FastCtx fc;
+    fc.c = (float)(-mc.sigma0 * mc.sigma0 * 0.69314718055994530942);
+    fc.isq = (float)mc.invsqrtN;
+    fc.malpha = (float)mc.malpha;
+    fc.lbase2 = (float)mc.lbase2;
+    const cx<float> wa = twN(pool, p, ka);  // w_N^k1; w_N^(k1 + M1 k2) = w_N^k1 w_2L^k2
+    const float half = 0.5f;
+    const float osc = (float)mc.outscale;
+    for (int k2 = threadIdx.x; k2 < L; k2 += NT) {
+        const int pk2 = L - 1 - k2;  // the partner mode M - k sits in row kb
+        const cx<float> Za = buf[2 * k2], Zb = buf[2 * pk2 + 1];
+        const cx<float> w = cmul(wa, twh[k2]);
+        const int64_t k = ka + (int64_t)M1 * k2, kp = (int64_t)M - k;
+        // A = (Zk + conj Zp)/2, B = -i (Zk - conj Zp)/2, E_k = A + w_N^k B
+        const cx<float> Ak = {half * (Za.x + Zb.x), half * (Za.y - Zb.y)};
+        const cx<float> Dk = {half * (Za.x - Zb.x), half * (Za.y + Zb.y)};
+        const cx<float> Bk = {Dk.y, -Dk.x};
+        const cx<float> Ek = cadd(Ak, cmul(w, Bk));
+        const cx<float> wp = {-w.x, w.y};  // w_N^(M-k) = -conj(w_N^k)
+        const cx<float> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
+        cx<float> nk, np;
+        if constexpr (MODE == 0) {
+            nk = cr_fast(mc, fc, (uint32_t)k, Ek);
+            np = cr_fast(mc, fc, (uint32_t)kp, Ep);
+        } else {
+            if (a.which == 3) {
+                nk = x0_mode(mc, k, Ek);
+                np = x0_mode(mc, kp, Ep);
+            } else {
+                nk = filt_mode(mc, k, Ek, a.which);
+                np = filt_mode(mc, kp, Ep, a.which);
+            }
+        }
+        // Z'_k = (nk + conj np)/2 + i (nk - conj np) conj(w_N^k)/2, scaled
+        const cx<float> Ap = {half * (nk.x + np.x), half * (nk.y - np.y)};
+        const cx<float> Dp = {half * (nk.x - np.x), half * (nk.y + np.y)};
+        const cx<float> Bp = cmulc(Dp, w);
+        buf[2 * k2] = cx<float>{osc * (Ap.x - Bp.y), osc * (Ap.y + Bp.x)};
+        const cx<float> Bq = cmul(cconj(Dp), w);
+        buf[2 * pk2 + 1] = cx<float>{osc * (Ap.x - Bq.y), osc * (-Ap.y + Bq.x)};
+    }
+    __syncthreads();
+
+    rstage<L, 0, 1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+    rstage<L, 1, 1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+    rstage<L, 2, 1, 2>(buf, nullptr, nullptr, ya, yb, tws);
+}
+
+}  // namespace
+
+namespace c3 {
+
+bool rowc_supported(int mixed, int L, int mode) {
+    return mixed && (mode == 0 || mode == 2) && c3rowc::compiled(L);
+}
+
+hipError_t rowc_init_attributes() {
+    hipError_t e = hipSuccess;
+    auto set = [&](const void *f) {
+        hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, C3_LDS_MAX - 4096);
+        if (r != hipSuccess) e = r;
+    };
+#define C3_ROWC_ATTR(LL)                       \
+    set((const void *)k_rowc<LL, 0>);          \
+    set((const void *)k_rowc<LL, 2>);
+    C3_ROWC_LIST(C3_ROWC_ATTR)
+#undef C3_ROWC_ATTR
+    return e;
+}
+
+hipError_t launch_rowc(hipStream_t st, const FftArgs &a, int L) {
+    if (a.nrow_tasks <= 0) return hipSuccess;
+    const dim3 g(a.nrow_tasks), b(NT);
+    const unsigned lds = 2u * (unsigned)L * (unsigned)sizeof(cx<float>);
+    switch (L) {
+#define C3_ROWC_LAUNCH(LL)                                                    \
+    case LL:                                                                  \
+        if (a.mode == 0)                                                      \
+            hipLaunchKernelGGL((k_rowc<LL, 0>), g, b, lds, st, a);            \
+        else if (a.mode == 2)                                                 \
+            hipLaunchKernelGGL((k_rowc<LL, 2>), g, b, lds, st, a);            \
+        else                                                                  \
+            return hipErrorInvalidValue;                                      \
+        break;
+        C3_ROWC_LIST(C3_ROWC_LAUNCH)
+#undef C3_ROWC_LAUNCH
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace c3

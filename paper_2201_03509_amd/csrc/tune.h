@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "common.h"
+#include "rowc.h"
 
 #include <algorithm>
 #include <cstdio>
@@ -202,6 +203,11 @@ inline bool default_choice(int64_t M, int mixed, FftChoice &c) {
         int64_t pick = m1s.back();
         for (int64_t m1 : m1s)
             if (m1 <= 64) pick = m1;
+        // a row length with a compiled row kernel first (the same rule)
+        int64_t pc = 0;
+        for (int64_t m1 : m1s)
+            if (c3rowc::compiled((int)(M / m1)) && (pc == 0 || m1 <= 64)) pc = m1;
+        if (pc) pick = pc;
         return make_choice(M, M / pick, mixed, 64, 0, 1, c);
     }
     const std::vector<int64_t> m2s = lds_rows(M, mixed);

@@ -80,3 +80,64 @@ def test_unsupported_radix_falls_back(tmp_path):
     choice = {"mixed": 1, "M": M1 * M2, "M1": M1, "M2": M2, "B": 64, "colreg": 1, "r1": [],
               "r2": [16, 2]}
     assert _run(tmp_path, "mixed", M1 * M2, choice) < TOL["mixed"]
+
+
+# row lengths with a compiled row kernel: every 5-smooth length in [2000, 5040]
+def _smooth(n):
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+ROWC = [L for L in range(2000, 5041) if _smooth(L)]
+F32_ROW_RADICES = [2, 3, 4, 5, 6, 8, 9, 10, 12, 20, 24, 25, 27]
+
+
+def _generic_radices(L):
+    r = []
+    while L > 1:
+        best = max(c for c in F32_ROW_RADICES if L % c == 0)
+        r.append(best)
+        L //= best
+    return r
+
+
+@pytest.mark.parametrize("L", ROWC)
+def test_compiled_row_lengths(tmp_path, L):
+    """Every compiled row length, as M = 16 x L: the n_corr draw (mode 0, with
+    and without the draw) and the gain draw's filter (mode 2) against the
+    oracle.  The rows 0 and M1/2 of each transform take the generic kernel."""
+    from paper_2201_03509_amd import ops
+    from oracle import gain as og
+    M = 16 * L
+    choice = {"mixed": 1, "M": M, "M1": 16, "M2": L, "B": 64, "colreg": 1, "r1": [],
+              "r2": _generic_radices(L)}
+    ts = synth.make(1, nscan=1, length=("uniform", M, M), keep_truth=True)
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"fft": [choice], "bin_stride": {}}))
+    t = ot.project(ts.maps.astype(np.float32).astype(np.float64), ot.global_pix(ts, ts.pix), ts.psi, 1.0)
+    s_in = (t * np.repeat(ts.gain, np.diff(ts.seg_off))).astype(np.float32)
+    seed, it = 31, 2
+    c = ops.Context(0)
+    try:
+        c.load_tuning(str(path))
+        tod = ops.DeviceTod(ts, "cuda:0")
+        outs = []
+        for mo in (False, True):
+            out = torch.empty(ts.nsamp, dtype=torch.float32, device="cuda")
+            c.sample_ncorr(tod, "mixed", tod.d, torch.from_numpy(s_in).cuda(), seed, it, out, mean_only=mo)
+            outs.append(out)
+        g = torch.empty(ts.nseg, dtype=torch.float64, device="cuda")
+        c.sample_gain(tod, "mixed", tod.d, torch.from_numpy(t.astype(np.float32)).cuda(), seed, it, g)
+        c.sync()
+    finally:
+        c.close()
+    for mo, out in zip((False, True), outs):
+        ref = ot.sample_ncorr_all(ts, ts.d, s_in.astype(np.float64), seed, it, mean_only=mo)
+        got = out.cpu().numpy().astype(np.float64)
+        for q in range(ts.nseg):
+            a, b = ts.seg_off[q], ts.seg_off[q + 1]
+            assert np.linalg.norm(got[a:b] - ref[a:b]) / np.linalg.norm(ref[a:b]) < TOL["mixed"], (L, mo, q)
+    g_ref, _ = og.sample_gain_all(ts, ts.d, t.astype(np.float32).astype(np.float64), seed, it)
+    assert np.all(np.abs(g.cpu().numpy() - g_ref) <= TOL["mixed"] * np.abs(g_ref))
