@@ -1021,7 +1021,8 @@ tod_status project_sky(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const 
     HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     KTimer kt(ctx, K_PROJECT, ctx->stream);
     HIPCHK(c3::launch_resid_tiles(ctx->stream, make_layout_dev(lay), mixed, tiles, nt, pix, psi, nullptr, 0,
-                                  maps, ctx->maps4.p, gain, ctx->trig64.p, s_out, nullptr));
+                                  maps, ctx->maps4.p, gain, mixed ? ctx->trig32.p : ctx->trig64.p, s_out,
+                                  nullptr));
     return TOD_OK;
 }
 
@@ -1581,8 +1582,8 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
         {
             KTimer kt(ctx, K_PROJECT, st);
             HIPCHK(c3::launch_resid_tiles(st, Ld, mixed, tiles, nt, pix_work, psi_work, d,
-                                          d_dtype == TOD_F64, maps, ctx->maps4.p, gain, ctx->trig64.p,
-                                          ctx->resid.p, ctx->d_err));
+                                          d_dtype == TOD_F64, maps, ctx->maps4.p, gain,
+                                          mixed ? ctx->trig32.p : ctx->trig64.p, ctx->resid.p, ctx->d_err));
         }
         {
             c3::FftArgs a = fft_args(ctx, P, lay);

@@ -177,13 +177,13 @@ hipError_t launch_decode_stream(hipStream_t st, const LayoutDev &L, const HuffDe
 // r = d - g P m on strided tiles (the sweep's residual, input of the n_corr FFTs),
 // or s = g P m when d is NULL; maps4: workspace of npix_total records of 4
 // values (T, Q, U, 0), filled from the [3][npix] maps first
-// trig: the FP64 cos/sin 2psi table (the projection is summed in FP64 and
-// rounded once to the output type); err: sticky word that receives
-// C3_ERR_NONFINITE where d - s is not finite at an in-range pixel (may be NULL)
+// trig: the cos/sin 2psi table of the precision's type; err: sticky word that
+// receives C3_ERR_NONFINITE where d - s is not finite at an in-range pixel
+// (may be NULL)
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                               int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                               int d_f64, const void *maps, void *maps4, const double *gain,
-                              const void *trig64, void *r_out, uint32_t *err);
+                              const void *trig, void *r_out, uint32_t *err);
 // per non-empty segment: sigma0 > 0, f_knee > 0, alpha < 0, all finite (any
 // pointer may be NULL: not checked); failures set C3_ERR_SIGMA0 / _FKNEE /
 // _ALPHA in the sticky word.  The kernels that use them still run.

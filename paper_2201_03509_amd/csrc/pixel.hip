@@ -184,10 +184,12 @@ __global__ __launch_bounds__(C3_NT) void k_interleave(const T *__restrict__ maps
 }
 
 // SUB: write d - s (d, of type TD, read per sample); otherwise s (d unused).
-// The projection and the subtraction are summed in FP64 from the stored map
-// values and rounded once to the output type T: a residual of a few noise
-// units is the difference of two numbers a hundred times larger, so forming
-// s in FP32 first would cost it about 1e-5 of its own size.  With SUB a lane
+// A residual of a few noise units is the difference of two numbers a hundred
+// times larger (d and g T), so its rounding is ordered by size.  FP32: the
+// gain as a sum of two floats g_hi + g_lo, then r = d - g_hi T - g_lo T -
+// g_hi (Q cos 2psi + U sin 2psi), each step one fused multiply-add whose
+// result is already residual-sized (about 2e-6 of r against 2e-5 for r =
+// d - g (T + Q c + U s) in float).  FP64: the plain sum.  With SUB a lane
 // that meets a non-finite d - s at an in-range pixel raises C3_ERR_NONFINITE.
 template <typename T, typename TD, bool SUB>
 __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__restrict__ tiles,
@@ -196,9 +198,9 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
                                                  const TD *__restrict__ d,
                                                  const Stokes4<T> *__restrict__ maps,
                                                  const double *__restrict__ gain,
-                                                 const cx<double> *__restrict__ trig,
+                                                 const cx<T> *__restrict__ trig,
                                                  T *__restrict__ r_out, uint32_t *__restrict__ err) {
-    __shared__ cx<double> tr[2048];
+    __shared__ cx<T> tr[2048];
     const int4 tl = tiles[blockIdx.x];
     for (int b = threadIdx.x; b < 2048; b += C3_NT) tr[b] = trig[b];
     __syncthreads();
@@ -210,53 +212,62 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
     int cur = -1;
-    double mT = 0, mQ = 0, mU = 0;
-    double g = 0;
+    T mT = 0, mQ = 0, mU = 0;
+    T ghi = 0, glo = 0;
     bool bad = false;
-    auto step = [&](int64_t i, int p, int b, double dv) {
+    auto step = [&](int64_t i, int p, int b, T dv) {
         if (p != cur) {
             cur = p;
             if ((uint32_t)p < npix) {
                 const Stokes4<T> m = maps[poff + p];
-                mT = (double)m.t;
-                mQ = (double)m.q;
-                mU = (double)m.u;
+                mT = m.t;
+                mQ = m.q;
+                mU = m.u;
             } else {
-                mT = mQ = mU = (double)NAN;
+                mT = mQ = mU = (T)NAN;
             }
         }
-        const cx<double> cs = tr[b & 2047];
-        const double sv = g * (mT + mQ * cs.x + mU * cs.y);
+        const cx<T> cs = tr[b & 2047];
         if constexpr (SUB) {
-            const double rv = dv - sv;
+            T rv;
+            if constexpr (sizeof(T) == 4) {
+                const float pu = fmaf(mQ, cs.x, mU * cs.y);
+                rv = fmaf(-ghi, mT, dv);
+                rv = fmaf(-glo, mT, rv);
+                rv = fmaf(-ghi, pu, rv);
+            } else {
+                rv = dv - ghi * (mT + mQ * cs.x + mU * cs.y);
+            }
             bad |= (uint32_t)p < npix && !isfinite(rv);
-            r_out[i] = (T)rv;
+            r_out[i] = rv;
         } else {
-            r_out[i] = (T)sv;
+            r_out[i] = ghi * (mT + mQ * cs.x + mU * cs.y);
         }
     };
     for (int gi = 0; gi < ngrp; ++gi) {
         const int seg = tl.x + gi;
         const int64_t s0 = Ld.seg_off[seg];
         const int n = (int)(Ld.seg_off[seg + 1] - s0);
-        g = gain[seg];
+        const double g = gain[seg];
+        ghi = (T)g;
+        glo = (T)(g - (double)ghi);
         int t = phi;
         for (; t + 3 * S < n; t += 4 * S) {
             int p[4], b[4];
-            TD v[4];
+            T v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
-                v[u] = SUB ? d[i] : (TD)0;
+                v[u] = SUB ? (T)d[i] : (T)0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], (double)v[u]);
+            for (int u = 0; u < 4; ++u) step(s0 + t + u * S, p[u], b[u], v[u]);
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
-            step(i, pix[i], psi[i], SUB ? (double)d[i] : 0.0);
+            step(i, pix[i], psi[i], SUB ? (T)d[i] : (T)0);
         }
     }
     if (SUB && bad && err) atomicOr(err, C3_ERR_NONFINITE);
@@ -594,7 +605,7 @@ void launch_resid_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, i
     const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
     hipLaunchKernelGGL(k_interleave<T>, dim3(gi), dim3(C3_NT), 0, st, (const T *)maps, npt, (Stokes4<T> *)maps4);
     const Stokes4<T> *m4 = (const Stokes4<T> *)maps4;
-    const cx<double> *tr = (const cx<double> *)trig;
+    const cx<T> *tr = (const cx<T> *)trig;
     T *out = (T *)r_out;
     const dim3 g(ntile), b(C3_NT);
     if (!d)
@@ -658,12 +669,12 @@ hipError_t launch_bin_tiles(hipStream_t st, const LayoutDev &L, int mixed, const
 hipError_t launch_resid_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                               int ntile, const int32_t *pix, const uint16_t *psi, const void *d,
                               int d_f64, const void *maps, void *maps4, const double *gain,
-                              const void *trig64, void *r_out, uint32_t *err) {
+                              const void *trig, void *r_out, uint32_t *err) {
     if (ntile <= 0) return hipSuccess;
     if (mixed)
-        launch_resid_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig64, r_out, err);
+        launch_resid_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig, r_out, err);
     else
-        launch_resid_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig64, r_out, err);
+        launch_resid_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, maps, maps4, gain, trig, r_out, err);
     return hipGetLastError();
 }
 
