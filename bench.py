@@ -674,6 +674,26 @@ def main():
     sweeps("mixed", maps32, out, args.steps, 1000, graph=True)
     torch.cuda.synchronize()
     ms_graph = (time.perf_counter() - g0) * 1e3 / args.steps
+    # the same sweep with the TOD decoded from its compressed stream in the
+    # sweep (tod_sweep_stream); its n_corr must equal the d-reading sweep's
+    stream_sweep = None
+    if tod.tod_huff is not None:
+        dw = torch.empty(ts.nsamp, dtype=torch.float32, device=dev)
+        os_ = ops.new_outputs(tod, "mixed")
+        ctx.tod_sweep_stream(tod, "mixed", maps32, seed, last_it, os_["ncorr"], os_["acc"], os_["pix"],
+                             os_["psi"], dw)
+        ctx.sync()
+        s0 = time.perf_counter()
+        for i in range(args.steps):
+            ctx.tod_sweep_stream(tod, "mixed", maps32, seed, args.warmup + i, os_["ncorr"], os_["acc"],
+                                 os_["pix"], os_["psi"], dw)
+        ctx.sync()
+        ms_stream = (time.perf_counter() - s0) * 1e3 / args.steps
+        tod_bytes = sum(getattr(ts.tod_huff, k).nbytes for k in ("words", "chunk_bit", "chunk_prev", "tables"))
+        stream_sweep = {"ms_per_step": round(ms_stream, 3), "value": ts.nsamp / (ms_stream / 1e3),
+                        "tod_compressed_bytes_per_sample": round(tod_bytes / ts.nsamp, 3)}
+        log("sweep from the compressed TOD: %.3f ms/step" % ms_stream)
+        del dw, os_
     # restore the eager last iteration's n_corr for the accuracy check
     sweeps("mixed", maps32, out, 1, last_it)
     ctx.sync()
@@ -802,6 +822,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "graph_ms_per_step": round(ms_graph, 3),
+        "sweep_from_compressed_tod": stream_sweep,
         "plain_fp64": plain,
         "sweep_algorithmic_gb": round(sweep_alg / 1e9, 3),
         "sweep_algorithmic_frac": round(sweep_alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

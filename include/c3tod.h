@@ -382,6 +382,21 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                      void *ncorr_out, double *acc,
                      int32_t *pix_work, uint16_t *psi_work, int use_graph);
 
+/* tod_sweep with the TOD taken from its Huffman-compressed stream (section
+ * 4.1: TOD samples are integers, differenced and coded like the pointing;
+ * Table 1): the sweep decodes it right after the pointing into d_work as
+ * quantum * x (device [nsamp], FP32 mixed / FP64 plain; bit-exact, as
+ * decode_tod), and the residual and the binning read it there.  Other
+ * arguments, outputs and graph capture as tod_sweep. */
+tod_status tod_sweep_stream(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
+                            const tod_huff *pix, const tod_huff *psi,
+                            const tod_huff *tod, double quantum, void *d_work,
+                            const void *maps, const double *gain, const double *sigma0,
+                            const double *fknee, const double *alpha,
+                            uint64_t seed, uint64_t iter,
+                            void *ncorr_out, double *acc,
+                            int32_t *pix_work, uint16_t *psi_work, int use_graph);
+
 /* --------------------------------------------------------- planning/tuning */
 
 /* Plan a layout ahead of its first call (the measured-cost-table step of

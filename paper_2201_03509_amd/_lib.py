@@ -20,6 +20,7 @@ EXPORTS = [
     "solve_maps", "tod_chisq", "tod_chisq_backward", "tod_sweep", "tod_autotune",
     "tod_load_tuning", "tod_set_bin_stride", "tod_set_fft_batch", "tod_enable_timing",
     "tod_kernel_times", "tod_plan", "decode_pointing_noalloc", "tod_set_bin_runs",
+    "tod_sweep_stream",
 ]
 
 
@@ -91,6 +92,8 @@ def load():
                                D, P, P, P, P, P, P],
         "tod_sweep": [P, LP, ctypes.c_int, HP, HP, P, ctypes.c_int, P, P, P, P, P, U64, U64,
                       P, P, P, P, ctypes.c_int],
+        "tod_sweep_stream": [P, LP, ctypes.c_int, HP, HP, HP, D, P, P, P, P, P, P, U64, U64,
+                             P, P, P, P, ctypes.c_int],
         "tod_autotune": [P, LP, ctypes.c_int, P, ctypes.c_char_p],
         "tod_load_tuning": [P, ctypes.c_char_p],
         "tod_plan": [P, LP, ctypes.c_int, ctypes.c_char_p],

@@ -135,6 +135,7 @@ struct tod_ctx_s {
     uint64_t *d_seed_iter = nullptr;
     DevBuf trig32, trig64, work, seg_sums, seg_whittle, probe_counts, resid;
     DevBuf dec_tabs;                      // decoding tables, rebuilt by every decode
+    DevBuf dec_tabs2;                     // the TOD stream's decoding tables (tod_sweep_stream)
     DevBuf maps4;                         // the sweep's maps as (T, Q, U, 0) records
     // masked n_corr solver: Krylov vectors and the transform output (the
     // precision's type), partial sums, per-segment state, active flags and the
@@ -1492,12 +1493,14 @@ tod_status tod_chisq_backward(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                         grad_alpha);
 }
 
-tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const tod_huff *pix,
-                     const tod_huff *psi, const void *d, tod_dtype d_dtype, const void *maps,
-                     const double *gain, const double *sigma0, const double *fknee,
-                     const double *alpha, uint64_t seed, uint64_t iter, void *ncorr_out,
-                     double *acc, int32_t *pix_work, uint16_t *psi_work, int use_graph) {
-    if (!ctx) return TOD_EINVAL;
+// The fused sweep; with tod != NULL the TOD comes from its compressed stream,
+// decoded into d_work (the precision's type) right after the pointing.
+static tod_status sweep_impl(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const tod_huff *pix,
+                             const tod_huff *psi, const tod_huff *tod, double quantum, void *d_work,
+                             const void *d, tod_dtype d_dtype, const void *maps, const double *gain,
+                             const double *sigma0, const double *fknee, const double *alpha, uint64_t seed,
+                             uint64_t iter, void *ncorr_out, double *acc, int32_t *pix_work,
+                             uint16_t *psi_work, int use_graph) {
     tod_status r;
     if ((r = check_layout(ctx, lay)) != TOD_OK) return r;
     if ((r = check_huff(ctx, pix, "pix")) != TOD_OK) return r;
@@ -1505,6 +1508,13 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     if (pix->chunk_len != psi->chunk_len) return fail(ctx, TOD_EINVAL, "pix and psi chunk_len differ");
     if (prec != TOD_MIXED && prec != TOD_PLAIN_FP64) return fail(ctx, TOD_EINVAL, "bad precision");
     if (d_dtype != TOD_F32 && d_dtype != TOD_F64) return fail(ctx, TOD_EINVAL, "bad d dtype");
+    if (tod) {
+        if ((r = check_huff(ctx, tod, "tod")) != TOD_OK) return r;
+        if (!(quantum > 0.0)) return fail(ctx, TOD_EINVAL, "quantum must be > 0");
+        if (!d_work) return fail(ctx, TOD_EINVAL, "NULL d_work");
+        d = d_work;
+        d_dtype = prec == TOD_MIXED ? TOD_F32 : TOD_F64;
+    }
     if (!d || !maps || !gain || !sigma0 || !fknee || !alpha || !ncorr_out || !acc || !pix_work || !psi_work)
         return fail(ctx, TOD_EINVAL, "NULL argument");
     const int mixed = prec == TOD_MIXED;
@@ -1517,6 +1527,12 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     int ndt;
     if ((r = get_decode_tasks(ctx, P, pix->chunk_len, &dt, &ndt)) != TOD_OK) return r;
     HIPCHK(ctx->dec_tabs.ensure(sizeof(DecTab) * (size_t)(pix->ntable + psi->ntable)));
+    const DecodeTask *dtt = nullptr;
+    int ndtt = 0;
+    if (tod) {
+        if ((r = get_decode_tasks(ctx, P, tod->chunk_len, &dtt, &ndtt)) != TOD_OK) return r;
+        HIPCHK(ctx->dec_tabs2.ensure(sizeof(DecTab) * (size_t)tod->ntable));
+    }
     HIPCHK(ctx->maps4.ensure((size_t)lay->npix_total * 4 * (mixed ? 4 : 8)));
     hipStream_t st = ctx->stream;
     const LayoutDev Ld = make_layout_dev(lay);
@@ -1535,14 +1551,19 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     // buffers, the context's scratch and the plan (its generation changes
     // whenever its task lists or tiles are rebuilt)
     const HuffDev Hp = make_huff_dev(pix), Hs = make_huff_dev(psi);
+    HuffDev Ht;
+    memset(&Ht, 0, sizeof(Ht));
+    if (tod) Ht = make_huff_dev(tod);
     uint64_t gk = 1469598103934665603ull;
     gk = fnv(gk, &Ld, sizeof(Ld));
     gk = fnv(gk, &Hp, sizeof(Hp));
     gk = fnv(gk, &Hs, sizeof(Hs));
+    gk = fnv(gk, &Ht, sizeof(Ht));
+    gk = fnv(gk, &quantum, sizeof(quantum));
     const void *ptrs[] = {d, maps, gain, sigma0, fknee, alpha, ncorr_out, acc, pix_work, psi_work,
                           ctx->work.p, ctx->resid.p, ctx->dec_tabs.p, ctx->maps4.p, ctx->trig32.p,
                           ctx->trig64.p, ctx->d_err, ctx->d_seed_iter, dt, P->bin_tiles.p, P->run_tiles.p,
-                          P->run_segs.p};
+                          P->run_segs.p, ctx->dec_tabs2.p, dtt};
     gk = fnv(gk, ptrs, sizeof(ptrs));
     gk = fnv(gk, &ndt, sizeof(ndt));
     gk = fnv(gk, &P->key, sizeof(P->key));
@@ -1567,6 +1588,11 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
             HIPCHK(c3::launch_decode(st, Ld, make_huff_dev(pix), make_huff_dev(psi),
                                      (DecTab *)ctx->dec_tabs.p, dt, ndt, pix_work, psi_work,
                                      ctx->d_err));
+        }
+        if (tod) {  // d = quantum x (the undifferenced integers), bit-exact as decode_tod
+            KTimer kt(ctx, K_DECODE, st);
+            HIPCHK(c3::launch_decode_stream(st, Ld, Ht, (DecTab *)ctx->dec_tabs2.p, dtt, ndtt, mixed ? 0 : 1,
+                                            quantum, 0, d_work, nullptr, ctx->d_err));
         }
         const int4 *tiles = (const int4 *)P->bin_tiles.p;
         int nt = P->nbin;
@@ -1628,6 +1654,28 @@ tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const to
     ctx->graphs[gk] = ge;
     HIPCHK(hipGraphLaunch(ge.ex, st));
     return TOD_OK;
+}
+
+tod_status tod_sweep(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const tod_huff *pix,
+                     const tod_huff *psi, const void *d, tod_dtype d_dtype, const void *maps,
+                     const double *gain, const double *sigma0, const double *fknee,
+                     const double *alpha, uint64_t seed, uint64_t iter, void *ncorr_out,
+                     double *acc, int32_t *pix_work, uint16_t *psi_work, int use_graph) {
+    if (!ctx) return TOD_EINVAL;
+    return sweep_impl(ctx, lay, prec, pix, psi, nullptr, 0.0, nullptr, d, d_dtype, maps, gain, sigma0, fknee,
+                      alpha, seed, iter, ncorr_out, acc, pix_work, psi_work, use_graph);
+}
+
+tod_status tod_sweep_stream(tod_ctx ctx, const tod_layout *lay, tod_prec prec, const tod_huff *pix,
+                            const tod_huff *psi, const tod_huff *tod, double quantum, void *d_work,
+                            const void *maps, const double *gain, const double *sigma0,
+                            const double *fknee, const double *alpha, uint64_t seed, uint64_t iter,
+                            void *ncorr_out, double *acc, int32_t *pix_work, uint16_t *psi_work,
+                            int use_graph) {
+    if (!ctx) return TOD_EINVAL;
+    if (!tod) return fail(ctx, TOD_EINVAL, "NULL tod stream");
+    return sweep_impl(ctx, lay, prec, pix, psi, tod, quantum, d_work, nullptr, TOD_F32, maps, gain, sigma0,
+                      fknee, alpha, seed, iter, ncorr_out, acc, pix_work, psi_work, use_graph);
 }
 
 tod_status tod_set_bin_stride(tod_ctx ctx, int32_t band, int32_t stride) {

@@ -286,6 +286,16 @@ class Context:
             ctypes.c_uint64(int(it)), _ptr(ncorr_out), _ptr(acc), _ptr(pix_work), _ptr(psi_work),
             int(bool(use_graph))))
 
+    def tod_sweep_stream(self, tod, prec, maps, seed, it, ncorr_out, acc, pix_work, psi_work, d_work,
+                         use_graph=False):
+        """The fused sweep with the TOD decoded from tod.tod_huff into d_work."""
+        self._chk(self.lib.tod_sweep_stream(
+            self.h, ctypes.byref(tod.layout), _prec(prec), ctypes.byref(tod.pix_huff),
+            ctypes.byref(tod.psi_huff), ctypes.byref(tod.tod_huff), float(tod.tod_quantum), _ptr(d_work),
+            _ptr(maps), _ptr(tod.gain), _ptr(tod.sigma0), _ptr(tod.fknee), _ptr(tod.alpha),
+            ctypes.c_uint64(int(seed)), ctypes.c_uint64(int(it)), _ptr(ncorr_out), _ptr(acc), _ptr(pix_work),
+            _ptr(psi_work), int(bool(use_graph))))
+
     def autotune(self, tod, prec, pix=None, cache_path=None):
         self._chk(self.lib.tod_autotune(self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix),
                                         cache_path.encode() if cache_path else None))

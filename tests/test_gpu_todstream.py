@@ -9,6 +9,7 @@ import torch
 
 import synth
 from oracle import huffman as oh
+from oracle import tod as ot
 
 pytestmark = pytest.mark.gpu
 
@@ -110,3 +111,45 @@ def test_flag_mask_drives_the_masked_draw(ctx):
         ctx.sync()
         outs.append(o.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_sweep_from_compressed_tod(prec):
+    """tod_sweep_stream decodes the TOD inside the sweep: its d is the FP32 TOD
+    bit for bit, and n_corr, hits and the binned sums equal those of the
+    sweep that reads d (eager and graph-replayed), and the oracle's."""
+    from paper_2201_03509_amd import ops
+    ts = synth.make(1, nscan=2, length=("uniform", 9000, 13000), keep_truth=True, tod_streams=True)
+    m = ts.maps.astype(np.float32 if prec == "mixed" else np.float64)
+    seed = 21
+    c = ops.Context(0)
+    try:
+        tod = ops.DeviceTod(ts, "cuda:0")
+        maps = torch.from_numpy(m).cuda()
+        a = ops.new_outputs(tod, prec)
+        c.tod_sweep(tod, prec, maps, seed, 3, a["ncorr"], a["acc"], a["pix"], a["psi"])
+        ft = torch.float32 if prec == "mixed" else torch.float64
+        res = []
+        for graph in (False, True, True):
+            b = ops.new_outputs(tod, prec)
+            dw = torch.empty(ts.nsamp, dtype=ft, device="cuda")
+            c.tod_sweep_stream(tod, prec, maps, seed, 3, b["ncorr"], b["acc"], b["pix"], b["psi"], dw,
+                               use_graph=graph)
+            c.sync()
+            res.append((b, dw))
+        ea = a["acc"].cpu().numpy()
+        for b, dw in res:
+            assert np.array_equal(dw.cpu().numpy().astype(np.float64), ts.d.astype(np.float64))
+            assert np.array_equal(b["ncorr"].cpu().numpy(), a["ncorr"].cpu().numpy())
+            ba = b["acc"].cpu().numpy()
+            assert np.array_equal(ba[9], ea[9])
+            assert np.abs(ba[:9] - ea[:9]).max() <= 1e-12 * np.abs(ea[:9]).max()
+        got = a["ncorr"].cpu().numpy().astype(np.float64)
+    finally:
+        c.close()
+    s = ot.project_all(ts, m.astype(np.float64), ts.pix, ts.psi)
+    ref = ot.sample_ncorr_all(ts, ts.d, s, seed, 3)
+    tol = 1e-5 if prec == "mixed" else 1e-12
+    for q in range(ts.nseg):
+        lo, hi = ts.seg_off[q], ts.seg_off[q + 1]
+        assert np.linalg.norm(got[lo:hi] - ref[lo:hi]) / np.linalg.norm(ref[lo:hi]) < tol
