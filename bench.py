@@ -76,9 +76,9 @@ FAMILY_SOURCES = {
     "project": ["pixel.hip", "common.h"],
     "bin": ["pixel.hip", "common.h"],
     "zero": ["pixel.hip", "common.h"],
-    "fft_col_fwd": ["fftcol.hip", "fft.hip", "fftdev.h", "rng.h", "common.h"],
-    "fft_row": ["fft.hip", "fftdev.h", "rng.h", "common.h"],
-    "fft_col_inv": ["fftcol.hip", "fft.hip", "fftdev.h", "rng.h", "common.h"],
+    "fft_col_fwd": ["fftcol.hip", "fft.hip", "fftdev.h", "fftmode.h", "rng.h", "common.h"],
+    "fft_row": ["fft.hip", "rowc.hip", "rowc.h", "fftdev.h", "fftmode.h", "rng.h", "common.h"],
+    "fft_col_inv": ["fftcol.hip", "fft.hip", "fftdev.h", "fftmode.h", "rng.h", "common.h"],
 }
 
 
@@ -139,14 +139,18 @@ def _oracle_segment(q):
     from oracle import huffman as oh
     from oracle import tod as ot
     n = int(ts.seg_off[q + 1] - ts.seg_off[q])
+    tm = [time.perf_counter()]
     pix = oh.StreamDecoder(ts.pix_huff).segment(q, n)
     psi = oh.StreamDecoder(ts.psi_huff).segment(q, n)
+    tm.append(time.perf_counter())
     a = ts.seg_off[q]
     gp = pix + ts.band_pix_off[ts.seg_band[q]]
     s = ot.project(maps32, gp, psi, ts.gain[q])
     r = ts.d[a:a + n].astype(np.float64) - s
+    tm.append(time.perf_counter())
     fs = ts.band_fsamp[ts.seg_band[q]]
     nc = ot.sample_ncorr_segment(r, fs, ts.sigma0[q], ts.fknee[q], ts.alpha[q], seed, q, it)
+    tm.append(time.perf_counter())
     _, c, sn = ot.pointing_rows(gp, psi)
     g = ts.gain[q]
     w = g / ts.sigma0[q] ** 2
@@ -161,7 +165,9 @@ def _oracle_segment(q):
     for k, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
         np.add.at(A[k], inv, g * w * rows[i] * rows[j])
     hits = np.bincount(inv, minlength=len(up))
-    return q, pix, nc, (up, b, A, hits)
+    tm.append(time.perf_counter())
+    steps = dict(zip(("decode", "project", "n_corr", "bin"), np.diff(tm)))
+    return q, pix, nc, (up, b, A, hits), steps
 
 
 MASKED_IT = 7777      # Gibbs iteration number of the masked-draw leg
@@ -241,6 +247,7 @@ def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
     t0 = time.perf_counter()
     _oracle_segment(0)
     t1 = time.perf_counter() - t0
+    single = int(ts.seg_off[1] - ts.seg_off[0]) / t1   # one process alone on the host
     nseg = int(max(workers, min(ts.nseg, budget_s * workers / max(t1, 1e-3))))
     nseg = min(nseg, ts.nseg)
     log("cpu baseline: %.2fs per segment, sampling %d segments on %d processes" % (t1, nseg, workers))
@@ -258,11 +265,25 @@ def cpu_baseline(ts, seed, it, maps32, budget_s=15.0, masked_segments=2):
     mq = [int(q) for q in np.linspace(0, ts.nseg - 1, masked_segments).round()] if masked_segments else []
     with ctx.Pool(max(1, min(workers, len(mq)))) as pool:
         _BASE["next"] = list(pool.imap_unordered(_oracle_next, mq)) if mq else []
+    step_s = {k: float(sum(r[4][k] for r in res)) for k in ("decode", "project", "n_corr", "bin")}
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": nsamp / wall, "unit": "TOD samples/s", "cores": workers, "kind": "oracle",
         "sample": "%d of %d segments (%d samples): decode+project+n_corr+bin, FP64 numpy/C, "
                   "one segment per process" % (nseg, ts.nseg, nsamp),
-    }, res
+        "cpu_model": model, "host_cpus": os.cpu_count(),
+        "single_core_value": single,
+        "per_step_core_seconds": {k: round(v, 3) for k, v in step_s.items()},
+        "per_step_samples_per_core_second": {k: nsamp / v if v > 0 else None for k, v in step_s.items()},
+        "wall_seconds": round(wall, 2),
+    }, [r[:4] for r in res]
 
 
 def oracle_binned(res):

@@ -21,6 +21,7 @@
 #include "common.h"
 #include "rowc.h"
 #include "tune.h"
+#include "validate.h"
 
 namespace {
 
@@ -189,43 +190,15 @@ tod_status fail(tod_ctx c, tod_status s, const std::string &msg) {
     } while (0)
 
 tod_status check_layout(tod_ctx ctx, const tod_layout *L) {
-    if (!L) return fail(ctx, TOD_EINVAL, "layout is NULL");
-    if (L->nseg < 0 || L->nband < 1 || L->nband > C3_MAXBAND || L->ndet < 1)
-        return fail(ctx, TOD_EINVAL, "nseg/nband/ndet out of range");
-    if (!L->seg_off || !L->seg_band || !L->seg_det || !L->h_seg_off || !L->h_seg_band || !L->bands)
-        return fail(ctx, TOD_EINVAL, "layout has a NULL array");
-    if (L->h_seg_off[0] != 0) return fail(ctx, TOD_EINVAL, "seg_off[0] != 0");
-    for (int s = 0; s < L->nseg; ++s) {
-        const int64_t n = L->h_seg_off[s + 1] - L->h_seg_off[s];
-        if (n < 0) return fail(ctx, TOD_EINVAL, "seg_off is not non-decreasing");
-        // the strided kernels step t + 4 S with t, S <= n in 32-bit arithmetic
-        if (n > (1 << 28)) return fail(ctx, TOD_ENOTSUP, "segment longer than 2^28 samples");
-        if (L->h_seg_band[s] < 0 || L->h_seg_band[s] >= L->nband)
-            return fail(ctx, TOD_EINVAL, "seg_band out of range");
-    }
-    if (L->h_seg_off[L->nseg] != L->nsamp) return fail(ctx, TOD_EINVAL, "nsamp != seg_off[nseg]");
-    int64_t off = 0;
-    for (int b = 0; b < L->nband; ++b) {
-        const tod_band &B = L->bands[b];
-        if (B.npsi != 4096) return fail(ctx, TOD_EINVAL, "npsi must be 4096");
-        if (B.nside < 1 || B.npix != 12ll * B.nside * B.nside)
-            return fail(ctx, TOD_EINVAL, "npix != 12 nside^2");
-        if (B.pix_off != off) return fail(ctx, TOD_EINVAL, "band pix_off not contiguous");
-        if (!(B.fsamp > 0)) return fail(ctx, TOD_EINVAL, "fsamp must be > 0");
-        off += B.npix;
-    }
-    if (off != L->npix_total) return fail(ctx, TOD_EINVAL, "npix_total != sum of band npix");
-    return TOD_OK;
+    std::string m;
+    const tod_status r = c3val::check_layout(L, m);
+    return r == TOD_OK ? r : fail(ctx, r, m);
 }
 
 tod_status check_huff(tod_ctx ctx, const tod_huff *h, const char *what) {
-    if (!h || !h->words || !h->seg_word_off || !h->seg_table || !h->tables || !h->table_off ||
-        !h->chunk_bit || !h->chunk_prev || !h->seg_chunk_off)
-        return fail(ctx, TOD_EINVAL, std::string(what) + " stream has a NULL array");
-    if (h->chunk_len < 32 || h->chunk_len > 4096 || (h->chunk_len % 32))
-        return fail(ctx, TOD_EINVAL, std::string(what) + " chunk_len must be a multiple of 32 in [32, 4096]");
-    if (h->ntable < 1) return fail(ctx, TOD_EINVAL, std::string(what) + " has no tables");
-    return TOD_OK;
+    std::string m;
+    const tod_status r = c3val::check_huff(h, what, m);
+    return r == TOD_OK ? r : fail(ctx, r, m);
 }
 
 LayoutDev make_layout_dev(const tod_layout *L) {
