@@ -93,7 +93,7 @@ struct BandDev {
     int32_t nside;
 };
 
-#define C3_MAXBAND 16        // bands of a layout (validate.h: C3_MAXBAND_HOST)
+#define C3_MAXBAND 16
 #define C3_XI_NBIN 231       // periodogram bins of modes k = 1 .. 2^31 - 1 (noise-parameter draw)
 
 struct LayoutDev {
