@@ -338,10 +338,11 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     // Row tasks are grouped by how many row blocks fit on a CU (their LDS is
     // two rows of M2), each launch sized to its own longest row.
     const int esz = mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
-    std::vector<int2> col, row;
-    std::map<int, std::vector<int2>> bcol;               // m1reg -> column tasks of the open batch
-    std::map<int, std::pair<int, std::vector<int2>>> brow;  // -blocks per CU -> (lds, row tasks)
-    std::map<int, std::vector<int2>> browc;              // compiled row length -> two-row tasks
+    std::vector<ColTask> col;
+    std::vector<RowTask> row;
+    std::map<int, std::vector<ColTask>> bcol;            // m1reg -> column tasks of the open batch
+    std::map<int, std::pair<int, std::vector<RowTask>>> brow;  // -blocks per CU -> (lds, row tasks)
+    std::map<int, std::vector<RowTask>> browc;           // compiled row length -> two-row tasks
     Plan::Batch cur{0, 0, 0, 0, {}, {}};
     auto close_batch = [&]() {
         cur.col0 = (int)col.size();
@@ -377,18 +378,35 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         g.scr_off = scr;
         scr += fp.M;
         P->work_elems = std::max(P->work_elems, scr);
-        std::vector<int2> &cv = bcol[fp.colreg ? fp.M1 : 0];
-        for (int c0 = 0; c0 < fp.M2; c0 += fp.B) cv.push_back(make_int2(s, c0));
+        std::vector<ColTask> &cv = bcol[fp.colreg ? fp.M1 : 0];
+        for (int c0 = 0; c0 < fp.M2; c0 += fp.B) {
+            ColTask ct;
+            memset(&ct, 0, sizeof(ct));
+            ct.samp_off = g.samp_off;
+            ct.scr_off = g.scr_off;
+            ct.ext_off = g.ext_off;
+            ct.seg = s;
+            ct.c0 = c0;
+            ct.n = g.n;
+            ct.M2 = fp.M2;
+            cv.push_back(ct);
+        }
         const int rl = 2 * fp.M2 * esz;
         const int per_cu = std::max(1, (C3_LDS_MAX - 1024) / std::max(rl, 1));
         auto &rg = brow[-per_cu];
         for (int k1 = 0; k1 <= fp.M1 / 2; ++k1) {
+            RowTask rt;
+            memset(&rt, 0, sizeof(rt));
+            rt.off_a = g.scr_off + (int64_t)k1 * fp.M2;
+            rt.off_b = g.scr_off + (int64_t)((fp.M1 - k1) % fp.M1) * fp.M2;
+            rt.seg = s;
+            rt.k1 = k1;
             // rows k1 and M1 - k1 distinct: the compiled kernel of the row length
             if (fp.twr >= 0 && k1 > 0 && 2 * k1 != fp.M1) {
-                browc[fp.M2].push_back(make_int2(s, k1));
+                browc[fp.M2].push_back(rt);
             } else {
                 rg.first = std::max(rg.first, rl);
-                rg.second.push_back(make_int2(s, k1));
+                rg.second.push_back(rt);
             }
         }
     }
@@ -698,9 +716,9 @@ c3::FftArgs fft_args(tod_ctx ctx, Plan *P, const tod_layout *L) {
     a.plans = (const FftPlan *)P->plans.p;
     a.twpool = P->twpool.p;
     a.work = ctx->work.p;
-    a.col_tasks = (const int2 *)P->col_tasks.p;
+    a.col_tasks = (const ColTask *)P->col_tasks.p;
     a.ncol_tasks = P->ncol;
-    a.row_tasks = (const int2 *)P->row_tasks.p;
+    a.row_tasks = (const RowTask *)P->row_tasks.p;
     a.nrow_tasks = P->nrow;
     a.fsamp_band = (const double *)P->fsamp.p;
     a.seed_iter = ctx->d_seed_iter;
@@ -756,16 +774,16 @@ tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::Ff
                    int first = 0) {
     for (const Plan::Batch &b : P->batches) {
         c3::FftArgs a = a0;
-        a.col_tasks = (const int2 *)P->col_tasks.p + b.col0;
+        a.col_tasks = (const ColTask *)P->col_tasks.p + b.col0;
         a.ncol_tasks = b.ncol;
-        a.row_tasks = (const int2 *)P->row_tasks.p + b.row0;
+        a.row_tasks = (const RowTask *)P->row_tasks.p + b.row0;
         a.nrow_tasks = b.nrow;
         for (int pass = first; pass < npass; ++pass) {
             if (pass == 1) {
                 for (const Plan::RowGroup &g : b.rgroups) {
                     if (g.nt <= 0) continue;
                     c3::FftArgs ag = a;
-                    ag.row_tasks = (const int2 *)P->row_tasks.p + g.t0;
+                    ag.row_tasks = (const RowTask *)P->row_tasks.p + g.t0;
                     ag.nrow_tasks = g.nt;
                     ag.row_lds = g.lds;
                     KTimer kt(ctx, K_ROW, st);
@@ -778,7 +796,7 @@ tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::Ff
             }
             for (const Plan::ColGroup &g : b.groups) {
                 c3::FftArgs ag = a;
-                ag.col_tasks = (const int2 *)P->col_tasks.p + g.t0;
+                ag.col_tasks = (const ColTask *)P->col_tasks.p + g.t0;
                 ag.ncol_tasks = g.nt;
                 KTimer kt(ctx, K_COLF + pass, st);
                 HIPCHK(c3::launch_fft_pass(st, mixed, ag, pass, g.m1reg));

@@ -84,6 +84,29 @@ struct FftPlan {
     int64_t twh;                 //   and w_(2 M2)^j, j < M2 (the mode loop's twiddle), -1 if none
 };
 
+// Column-pass work item: columns [c0, c0 + tile) of one segment's transform,
+// with the segment's offsets and sizes, so that a block can issue its column
+// loads as soon as it has read its task.
+struct ColTask {
+    int64_t samp_off;    // first sample
+    int64_t scr_off;     // first complex element of the FFT workspace
+    int64_t ext_off;     // first complex element of the whole extended vector
+    int32_t seg, c0;
+    int32_t n;           // samples
+    int32_t M2;          // row length of the split
+    int32_t pad[2];
+};
+
+// Row-pass work item: rows k1 and M1 - k1 of one segment's transform, with
+// the workspace offsets (complex elements) of both rows, so that a block can
+// issue its row loads as soon as it has read its task.
+struct RowTask {
+    int64_t off_a;       // row k1
+    int64_t off_b;       // row (M1 - k1) mod M1
+    int32_t seg, k1;
+    int32_t pad[2];
+};
+
 // Context-side view of the layout kept on the device.
 struct BandDev {
     int64_t npix;
@@ -196,9 +219,9 @@ struct FftArgs {
     const FftPlan *plans;
     const void *twpool;         // cx<T> pool
     void *work;                 // cx<T> workspace
-    const int2 *col_tasks;      // (seg, first column)
+    const ColTask *col_tasks;
     int ncol_tasks;
-    const int2 *row_tasks;      // (seg, k1)
+    const RowTask *row_tasks;
     int nrow_tasks;
     const void *in_a;           // pass-1 input: r = in_a - in_b (in_b may be NULL)
     int in_a_f64;

@@ -231,13 +231,13 @@ extern __shared__ __attribute__((aligned(16))) unsigned char c3_dyn_lds[];
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
     cx<T> *buf = (cx<T> *)c3_dyn_lds;  // M1 * B elements (sized per launch)
-    const int2 task = a.col_tasks[blockIdx.x];
-    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
-    const SegInfo sg = a.segs[task.x];
+    const ColTask task = a.col_tasks[blockIdx.x];
+    if (a.active && !a.active[task.seg]) return;  // converged segment (whole block)
+    const SegInfo sg = a.segs[task.seg];
     const FftPlan &p = a.plans[sg.plan];
     const int M1 = p.M1, M2 = p.M2, B = p.B;
     const int lb = __ffs(B) - 1;
-    const int col0 = task.y;
+    const int col0 = task.c0;
     const cx<T> *pool = (const cx<T> *)a.twpool;
     cx<T> *Y = (cx<T> *)a.work + sg.scr_off;
     const int tot = M1 * B;
@@ -293,13 +293,13 @@ __global__ __launch_bounds__(C3_NT) void k_col_fwd(FftArgs a) {
 template <typename T>
 __global__ __launch_bounds__(C3_NT) void k_col_inv(FftArgs a) {
     cx<T> *buf = (cx<T> *)c3_dyn_lds;
-    const int2 task = a.col_tasks[blockIdx.x];
-    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
-    const SegInfo sg = a.segs[task.x];
+    const ColTask task = a.col_tasks[blockIdx.x];
+    if (a.active && !a.active[task.seg]) return;  // converged segment (whole block)
+    const SegInfo sg = a.segs[task.seg];
     const FftPlan &p = a.plans[sg.plan];
     const int M1 = p.M1, M2 = p.M2, B = p.B;
     const int lb = __ffs(B) - 1;
-    const int col0 = task.y;
+    const int col0 = task.c0;
     const cx<T> *pool = (const cx<T> *)a.twpool;
     const cx<T> *Y = (const cx<T> *)a.work + sg.scr_off;
     const int tot = M1 * B;
@@ -340,13 +340,13 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     constexpr int NT = row_nt<T>();
     cx<T> *buf = (cx<T> *)c3_dyn_lds;  // 2 * M2 elements (sized per launch)
     __shared__ double red[3][NT / 64];
-    const int2 task = a.row_tasks[blockIdx.x];
-    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
-    const int seg = task.x;
+    const RowTask task = a.row_tasks[blockIdx.x];
+    if (a.active && !a.active[task.seg]) return;  // converged segment (whole block)
+    const int seg = task.seg;
     const SegInfo sg = a.segs[seg];
     const FftPlan &p = a.plans[sg.plan];
     const int M1 = p.M1, M2 = p.M2, M = p.M;
-    const int ka = task.y, kb = (M1 - ka) % M1;
+    const int ka = task.k1, kb = (M1 - ka) % M1;
     const int two = (kb != ka) ? 1 : 0;      // second row present
     const int lb = two;                      // rows interleaved: element (k2, row) at 2*k2 + row
     const int si = two ? 2 : 1;

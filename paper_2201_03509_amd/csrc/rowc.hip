@@ -116,20 +116,22 @@ template <int L, int MODE>
 __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     static_assert(plan(L).r[0] > 0, "row length without a three-stage plan");
     cx<float> *buf = (cx<float> *)c3_rowc_lds;  // 2 L elements
-    const int2 task = a.row_tasks[blockIdx.x];
-    if (a.active && !a.active[task.x]) return;  // converged segment (whole block)
-    const int seg = task.x;
+    const RowTask task = a.row_tasks[blockIdx.x];
+    // the rows' loads need only the task: they are issued first, and the
+    // segment's record, its plan and (masked draw) its active flag load
+    // while they are in flight
+    cx<float> *ya = (cx<float> *)a.work + task.off_a, *yb = (cx<float> *)a.work + task.off_b;
+    rstage<L, 0, -1, 1>(buf, ya, yb, nullptr, nullptr, nullptr);
+    if (a.active && !a.active[task.seg]) return;  // converged segment (whole block)
+    const int seg = task.seg;
     const SegInfo sg = a.segs[seg];
     const FftPlan &p = a.plans[sg.plan];
     const int M1 = p.M1, M = p.M;
-    const int ka = task.y, kb = M1 - ka;  // 0 < ka < M1 / 2: two distinct rows
+    const int ka = task.k1;  // 0 < ka < M1 / 2: rows ka and M1 - ka are distinct
     const cx<float> *pool = (const cx<float> *)a.twpool;
     const cx<float> *tws = pool + p.twr;
     const cx<float> *twh = pool + p.twh;
-    cx<float> *Y = (cx<float> *)a.work + sg.scr_off;
-    cx<float> *ya = Y + (int64_t)ka * L, *yb = Y + (int64_t)kb * L;
 
-    rstage<L, 0, -1, 1>(buf, ya, yb, nullptr, nullptr, tws);
     rstage<L, 1, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
     rstage<L, 2, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
 

@@ -106,3 +106,39 @@ def test_sigma0_of_a_scaled_residual():
     sig, _, _ = on.sample_noise_segment(r + nc, t, 1.0, nc, 10.0, 0.1, 0, 0, 0, mean_only=True)
     # median of chi^2_n by Wilson-Hilferty: n (1 - 2/(9n))^3
     assert abs(sig - 2.5 / (1 - 2 / (9 * n)) ** 1.5) <= 1e-12
+
+
+def test_approximate_conditionals_at_workload_sizes():
+    """How far the sampler's closed forms are from the exact conditionals
+    they stand for (Eq. 5 step; readings of the noise draw): the
+    Wilson-Hilferty chi^2 variate against scipy's exact quantiles, and the
+    Laplace (Gaussian) form of alpha | f_knee, sigma0 against the exact
+    conditional of the binned Whittle likelihood, inverted numerically on a
+    fine grid, for a 30,000-sample stationary 1/f segment."""
+    from scipy import stats
+    from oracle import tod as ot
+    z = np.array([-3.0, -1.0, 0.0, 1.0, 3.0])
+    for n, tol in ((1e4, 1e-6), (2.6e5, 1e-8)):
+        wh = on.wilson_hilferty_chi2(n, z)
+        ex = stats.chi2.ppf(stats.norm.cdf(z), n)
+        assert np.abs(wh / ex - 1).max() < tol
+    rng = np.random.default_rng(1)
+    n, fs, s0, fk, al = 30000, 78.8, 1.0, 0.1, -1.5
+    N = ot.fft_length(n)
+    k = np.arange(N // 2 + 1)
+    f = k * fs / N
+    P = np.zeros_like(f)
+    P[1:] = s0 ** 2 * (f[1:] / fk) ** al
+    X = (rng.normal(size=len(k)) + 1j * rng.normal(size=len(k))) * np.sqrt(P / 2)
+    X[0] = 0
+    nc = (np.fft.irfft(X, n=N) * np.sqrt(N))[:n]
+    J, c, fb = on.periodogram_bins(nc, fs)
+    ah, H = on.alpha_mode(J, c, fb, s0, fk)
+    x, a = np.log(fb / fk), J / s0 ** 2
+    grid = ah + np.linspace(-12, 12, 20001) / np.sqrt(H)
+    lnL = np.array([-np.sum(a * np.exp(-g * x) + c * (2 * np.log(s0) + g * x)) for g in grid])
+    p = np.exp(lnL - lnL.max())
+    cdf = np.concatenate([[0.0], np.cumsum((p[1:] + p[:-1]) / 2 * np.diff(grid))])
+    cdf /= cdf[-1]
+    dev = [(np.interp(stats.norm.cdf(zz), cdf, grid) - (ah + zz / np.sqrt(H))) * np.sqrt(H) for zz in z]
+    assert np.abs(dev).max() < 0.02   # in units of the conditional's width
