@@ -258,6 +258,41 @@ struct Pool {
     }
 };
 
+// Task order of one register column launch.  The chip dispatches a launch's
+// blocks to its XCDs round-robin (block b to XCD b mod kXcd), each XCD with
+// its own L2.  Position kXcd j + x takes the j-th task of XCD x's list, so
+// every column of a segment runs on one XCD, where the two reads of each
+// residual sample (at its place and at its mirror image 2n - 1 - t) meet in
+// that L2.  Segments (tasks of one segment are consecutive in v) go to the
+// XCD with the fewest tasks so far, in the LPT order of v; shorter lists are
+// padded with empty tasks (M2 = 0: the block returns at once).  Only speed
+// depends on the dispatch order, never results.
+constexpr int kXcd = 8;
+std::vector<ColTask> xcd_order(const std::vector<ColTask> &v) {
+    if (v.empty()) return v;
+    std::vector<std::vector<ColTask>> lists(kXcd);
+    for (size_t i = 0; i < v.size();) {
+        size_t j = i;
+        while (j < v.size() && v[j].seg == v[i].seg) ++j;
+        size_t x = 0;
+        for (size_t y = 1; y < lists.size(); ++y)
+            if (lists[y].size() < lists[x].size()) x = y;
+        lists[x].insert(lists[x].end(), v.begin() + (std::ptrdiff_t)i, v.begin() + (std::ptrdiff_t)j);
+        i = j;
+    }
+    size_t len = 0;
+    for (const auto &l : lists) len = std::max(len, l.size());
+    ColTask empty = v[0];
+    empty.c0 = 0;
+    empty.n = 0;
+    empty.M2 = 0;
+    std::vector<ColTask> out;
+    out.reserve(len * kXcd);
+    for (size_t j = 0; j < len; ++j)
+        for (int x = 0; x < kXcd; ++x) out.push_back(j < lists[x].size() ? lists[x][j] : empty);
+    return out;
+}
+
 tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key, Plan **out) {
     auto P = std::make_unique<Plan>();
     P->key = key;
@@ -347,6 +382,8 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     auto close_batch = [&]() {
         cur.col0 = (int)col.size();
         for (auto &kv : bcol) {
+            // register column kernels (kv.first = M1 > 0) return on an empty task
+            if (kv.first > 0) kv.second = xcd_order(kv.second);
             cur.groups.push_back({kv.first, (int)col.size(), (int)kv.second.size()});
             col.insert(col.end(), kv.second.begin(), kv.second.end());
         }

@@ -8,6 +8,11 @@
 
 namespace c3rng {
 
+// a ^ b ^ c in one instruction (three-input bitwise op, truth table 0x96)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -16,7 +21,13 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        if (r < 2) {
+            // words that are uniform when only the first counter word varies
+            // across lanes: plain XORs leave them to the scalar unit
+            c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        } else {
+            c = make_uint4(xor3(hi1, c.y, k.x), lo1, xor3(hi0, c.w, k.y), lo0);
+        }
         k.x += 0x9E3779B9u;
         k.y += 0xBB67AE85u;
     }
