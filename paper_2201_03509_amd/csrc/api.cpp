@@ -258,22 +258,24 @@ struct Pool {
     }
 };
 
-// Task order of one register column launch.  The chip dispatches a launch's
-// blocks to its XCDs round-robin (block b to XCD b mod kXcd), each XCD with
-// its own L2.  Position kXcd j + x takes the j-th task of XCD x's list, so
-// every column of a segment runs on one XCD, where the two reads of each
-// residual sample (at its place and at its mirror image 2n - 1 - t) meet in
-// that L2.  Segments (tasks of one segment are consecutive in v) go to the
-// XCD with the fewest tasks so far, in the LPT order of v; shorter lists are
-// padded with empty tasks (M2 = 0: the block returns at once).  Only speed
-// depends on the dispatch order, never results.
+// Work order of one launch.  The chip dispatches a launch's blocks to its
+// XCDs round-robin (block b to XCD b mod kXcd), each XCD with its own L2.
+// Position kXcd j + x takes the j-th item of XCD x's list, so all the items
+// of one group (consecutive items of v with equal key: a segment's columns or
+// rows, a tile group's phases) run on one XCD.  In the column pass the two
+// reads of each residual sample (at its place and at its mirror image) then
+// meet in that L2, and in every pass an XCD streams through its own
+// segments.  Groups go to the XCD with the fewest items so far, in the order
+// of v (longest first); shorter lists are padded with `empty`, an item its
+// kernel returns on at once.  Only speed depends on the order, never results.
 constexpr int kXcd = 8;
-std::vector<ColTask> xcd_order(const std::vector<ColTask> &v) {
-    if (v.empty()) return v;
-    std::vector<std::vector<ColTask>> lists(kXcd);
+template <typename T, typename Key>
+std::vector<T> xcd_order(const std::vector<T> &v, Key key, const T &empty) {
+    if (v.size() <= (size_t)kXcd) return v;
+    std::vector<std::vector<T>> lists(kXcd);
     for (size_t i = 0; i < v.size();) {
         size_t j = i;
-        while (j < v.size() && v[j].seg == v[i].seg) ++j;
+        while (j < v.size() && key(v[j]) == key(v[i])) ++j;
         size_t x = 0;
         for (size_t y = 1; y < lists.size(); ++y)
             if (lists[y].size() < lists[x].size()) x = y;
@@ -282,15 +284,31 @@ std::vector<ColTask> xcd_order(const std::vector<ColTask> &v) {
     }
     size_t len = 0;
     for (const auto &l : lists) len = std::max(len, l.size());
-    ColTask empty = v[0];
-    empty.c0 = 0;
-    empty.n = 0;
-    empty.M2 = 0;
-    std::vector<ColTask> out;
+    std::vector<T> out;
     out.reserve(len * kXcd);
     for (size_t j = 0; j < len; ++j)
         for (int x = 0; x < kXcd; ++x) out.push_back(j < lists[x].size() ? lists[x][j] : empty);
     return out;
+}
+
+// empty items: a column task of no columns, a row task of no segment, a
+// strided tile of no phases and no segments
+ColTask empty_col(const ColTask &like) {
+    ColTask e = like;
+    e.c0 = 0;
+    e.n = 0;
+    e.M2 = 0;
+    return e;
+}
+RowTask empty_row() {
+    RowTask e;
+    memset(&e, 0, sizeof(e));
+    e.seg = -1;
+    return e;
+}
+std::vector<int4> xcd_order_tiles(const std::vector<int4> &v) {
+    if (v.empty()) return v;
+    return xcd_order(v, [](const int4 &t) { return t.x; }, make_int4(v[0].x, 0, 1, 0));
 }
 
 tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key, Plan **out) {
@@ -383,16 +401,20 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         cur.col0 = (int)col.size();
         for (auto &kv : bcol) {
             // register column kernels (kv.first = M1 > 0) return on an empty task
-            if (kv.first > 0) kv.second = xcd_order(kv.second);
+            if (kv.first > 0 && !kv.second.empty())
+                kv.second = xcd_order(kv.second, [](const ColTask &t) { return t.seg; }, empty_col(kv.second[0]));
             cur.groups.push_back({kv.first, (int)col.size(), (int)kv.second.size()});
             col.insert(col.end(), kv.second.begin(), kv.second.end());
         }
         cur.row0 = (int)row.size();
+        auto row_seg = [](const RowTask &t) { return t.seg; };
         for (auto &kv : browc) {
+            kv.second = xcd_order(kv.second, row_seg, empty_row());
             cur.rgroups.push_back({2 * kv.first * esz, (int)row.size(), (int)kv.second.size(), kv.first});
             row.insert(row.end(), kv.second.begin(), kv.second.end());
         }
         for (auto &kv : brow) {
+            kv.second.second = xcd_order(kv.second.second, row_seg, empty_row());
             cur.rgroups.push_back({kv.second.first, (int)row.size(), (int)kv.second.second.size(), 0});
             row.insert(row.end(), kv.second.second.begin(), kv.second.second.end());
         }
@@ -625,6 +647,7 @@ tod_status get_bin_tiles(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_
             for (int p0 = 0; p0 < nph; p0 += C3_NT)
                 v.push_back(make_int4(first, p0, S, std::min(C3_NT, nph - p0) | (grp << 16)));
         }
+        v = xcd_order_tiles(v);
         HIPCHK(P->bin_tiles.upload(v, ctx->stream));
         P->nbin = (int)v.size();
         P->bin_stride = st;
@@ -733,6 +756,7 @@ tod_status get_bin_runs(tod_ctx ctx, const tod_layout *L, Plan *P, const int32_t
             for (int p0 = 0; p0 < nph; p0 += C3_NT)
                 tl.push_back(make_int4(first, p0, S, std::min(C3_NT, nph - p0) | (nsg << 16)));
         }
+        tl = xcd_order_tiles(tl);
         HIPCHK(P->run_tiles.upload(tl, ctx->stream));
         HIPCHK(P->run_segs.upload(segs, ctx->stream));
         P->nrun_tiles = (int)tl.size();

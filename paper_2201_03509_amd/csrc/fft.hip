@@ -341,6 +341,7 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     cx<T> *buf = (cx<T> *)c3_dyn_lds;  // 2 * M2 elements (sized per launch)
     __shared__ double red[3][NT / 64];
     const RowTask task = a.row_tasks[blockIdx.x];
+    if (task.seg < 0) return;                      // an empty task (launch padding)
     if (a.active && !a.active[task.seg]) return;  // converged segment (whole block)
     const int seg = task.seg;
     const SegInfo sg = a.segs[seg];

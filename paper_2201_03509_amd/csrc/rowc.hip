@@ -117,6 +117,7 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     static_assert(plan(L).r[0] > 0, "row length without a three-stage plan");
     cx<float> *buf = (cx<float> *)c3_rowc_lds;  // 2 L elements
     const RowTask task = a.row_tasks[blockIdx.x];
+    if (task.seg < 0) return;  // an empty task (launch padding)
     // the rows' loads need only the task: they are issued first, and the
     // segment's record, its plan and (masked draw) its active flag load
     // while they are in flight
