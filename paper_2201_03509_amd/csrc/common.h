@@ -153,7 +153,8 @@ struct alignas(16) DecTab {
     int32_t nsym;                // symbols with a code (sum of the counts)
     int32_t ok;                  // 0: the table blob is not a valid prefix code
     uint8_t lut[1 << C3_KLUT];   // code length shared by every code with this 12-bit
-                                 // prefix; 0 if the prefix holds several lengths or none
+                                 // prefix; 64 | the shortest if it holds several
+                                 // lengths; 0 if no code starts it
     int32_t pad[2];
 };
 

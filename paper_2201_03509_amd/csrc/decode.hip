@@ -27,11 +27,21 @@ constexpr int G = 16;          // symbols per thread per round
 constexpr int GP = G + 1;      // padded LDS row (no bank conflicts on the column writes)
 constexpr int SPLIT = 32 - C3_KLUT;
 
-// smallest L in [minlen, maxlen] with w < lim[L]; 0 if there is none
-__device__ __forceinline__ int code_len(const DecTab &T, unsigned long long w) {
-    for (int L = T.minlen; L <= T.maxlen; ++L)
+// smallest L in [from, maxlen] with w < lim[L]; 0 if there is none
+__device__ __forceinline__ int code_len(const DecTab &T, unsigned long long w, int from) {
+    for (int L = from; L <= T.maxlen; ++L)
         if (w < T.lim[L]) return L;
     return 0;
+}
+__device__ __forceinline__ int code_len(const DecTab &T, unsigned long long w) { return code_len(T, w, T.minlen); }
+
+// length of the code at the top of win from its prefix-table entry e: e itself
+// when the prefix resolves it (0 < e < 64); otherwise a search of the limits
+// from the shortest length under the prefix (e = 64 | that length) or from
+// minlen (e = 0: no code starts the prefix).  0: invalid code.
+__device__ __forceinline__ int resolve_len(const DecTab &T, uint32_t win, int e) {
+    if (e > 0 && e < 64) return e;
+    return code_len(T, win, e ? (e & 63) : T.minlen);
 }
 
 __global__ __launch_bounds__(C3_NT) void k_tables(HuffDev hp, HuffDev hs, DecTab *tabs) {
@@ -76,10 +86,13 @@ __global__ __launch_bounds__(C3_NT) void k_tables(HuffDev hp, HuffDev hs, DecTab
     for (int e = threadIdx.x; e < (1 << C3_KLUT); e += C3_NT) {
         uint8_t v = 0;
         if (T.ok) {
+            // code lengths only grow with the code value, so the prefix's
+            // codes have lengths from L0 (its first) to L1 (its last)
             const unsigned long long w0 = (unsigned long long)e << SPLIT;
             const unsigned long long w1 = w0 | ((1ull << SPLIT) - 1);
             const int L0 = code_len(T, w0);
-            v = (L0 != 0 && L0 == code_len(T, w1)) ? (uint8_t)L0 : 0;
+            const int L1 = code_len(T, w1);
+            v = L0 == 0 ? 0 : (uint8_t)(L0 == L1 ? L0 : 64 | L0);
         }
         T.lut[e] = v;
     }
@@ -153,16 +166,23 @@ struct BitReader {
             wp += 2u;
         }
     }
-    // symbol index of the next code; L = its length (0: invalid code)
-    __device__ __forceinline__ int32_t next(const DecTab &T, int &L) {
+    // the next 32 bits, the next code at the top (refilled first)
+    __device__ __forceinline__ uint32_t window() {
         refill();
-        const uint32_t win = (uint32_t)(buf >> 32);
-        L = T.lut[win >> SPLIT];
-        if (L == 0) L = code_len(T, win);  // split or invalid prefix (rare)
-        const int Lc = L ? L : 1;
-        const int32_t idx = (int32_t)(win >> (32 - Lc)) + T.delta[Lc];
+        return (uint32_t)(buf >> 32);
+    }
+    // drop the Lc bits of the code just read
+    __device__ __forceinline__ void consume(int Lc) {
         buf <<= Lc;
         nbits -= Lc;
+    }
+    // symbol index of the next code; L = its length (0: invalid code)
+    __device__ __forceinline__ int32_t next(const DecTab &T, int &L) {
+        const uint32_t win = window();
+        L = resolve_len(T, win, T.lut[win >> SPLIT]);
+        const int Lc = L ? L : 1;
+        const int32_t idx = (int32_t)(win >> (32 - Lc)) + T.delta[Lc];
+        consume(Lc);
         return L ? idx : -1;
     }
 };
@@ -249,14 +269,22 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
             // chunk end are parsed but never used
 #pragma unroll 4  // full unrolling runs out of scalar registers
             for (int k = 0; k < G; ++k) {
-                int Lp, Lq;
-                const int32_t ip = rp.next(cp, Lp);
-                const int32_t iq = rq.next(cq, Lq);
+                // the two streams' table reads are issued together: both
+                // prefix-table entries, then (after the rare searches) both
+                // index offsets
+                const uint32_t wp = rp.window(), wq = rq.window();
+                const int ep = cp.lut[wp >> SPLIT], eq = cq.lut[wq >> SPLIT];
+                const int Lp = resolve_len(cp, wp, ep), Lq = resolve_len(cq, wq, eq);
+                const int Lcp = Lp ? Lp : 1, Lcq = Lq ? Lq : 1;
+                const int32_t ip = (int32_t)(wp >> (32 - Lcp)) + cp.delta[Lcp];
+                const int32_t iq = (int32_t)(wq >> (32 - Lcq)) + cq.delta[Lcq];
+                rp.consume(Lcp);
+                rq.consume(Lcq);
                 const bool v = k0 + k < ns;
                 bad |= (v && (Lp == 0 || Lq == 0)) ? C3_ERR_CODE : 0u;
                 bitp += v ? Lp : 0;
                 bitq += v ? Lq : 0;
-                tp[l * GP + k] = ip;
+                tp[l * GP + k] = Lp ? ip : -1;
                 tq[l * GP + k] = (uint16_t)(Lq ? iq : 0xFFFF);
             }
             // symbol values (gathers issued in groups), running sums, range checks
