@@ -261,56 +261,62 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
     }
     const int nround = (C + G - 1) / G;
 
-    for (int rd = 0; rd < nround; ++rd) {
-        const int k0 = rd * G;
-        if (active && k0 < ns) {
-            // parse: symbol indices into this thread's tile row (psi tables hold
-            // at most 65535 symbols, checked with the table); codes past the
-            // chunk end are parsed but never used
+    // one round: parse G codes of both streams per chunk (symbol indices into
+    // this thread's tile row; psi tables hold at most 65535 symbols, checked
+    // with the table), then their symbol values (gathers issued in groups),
+    // running sums and range checks.  Values go to the thread's tile row, or
+    // to registers (v0p, v0q) when the caller asks for them there.
+    auto round = [&](int k0, bool to_regs, int32_t *v0p, uint16_t *v0q) {
+        if (!(active && k0 < ns)) return;
 #pragma unroll 4  // full unrolling runs out of scalar registers
-            for (int k = 0; k < G; ++k) {
-                // the two streams' table reads are issued together: both
-                // prefix-table entries, then (after the rare searches) both
-                // index offsets
-                const uint32_t wp = rp.window(), wq = rq.window();
-                const int ep = cp.lut[wp >> SPLIT], eq = cq.lut[wq >> SPLIT];
-                const int Lp = resolve_len(cp, wp, ep), Lq = resolve_len(cq, wq, eq);
-                const int Lcp = Lp ? Lp : 1, Lcq = Lq ? Lq : 1;
-                const int32_t ip = (int32_t)(wp >> (32 - Lcp)) + cp.delta[Lcp];
-                const int32_t iq = (int32_t)(wq >> (32 - Lcq)) + cq.delta[Lcq];
-                rp.consume(Lcp);
-                rq.consume(Lcq);
-                const bool v = k0 + k < ns;
-                bad |= (v && (Lp == 0 || Lq == 0)) ? C3_ERR_CODE : 0u;
-                bitp += v ? Lp : 0;
-                bitq += v ? Lq : 0;
-                tp[l * GP + k] = Lp ? ip : -1;
-                tq[l * GP + k] = (uint16_t)(Lq ? iq : 0xFFFF);
+        for (int k = 0; k < G; ++k) {
+            // the two streams' table reads are issued together: both
+            // prefix-table entries, then (after the rare searches) both
+            // index offsets
+            const uint32_t wp = rp.window(), wq = rq.window();
+            const int ep = cp.lut[wp >> SPLIT], eq = cq.lut[wq >> SPLIT];
+            const int Lp = resolve_len(cp, wp, ep), Lq = resolve_len(cq, wq, eq);
+            const int Lcp = Lp ? Lp : 1, Lcq = Lq ? Lq : 1;
+            const int32_t ip = (int32_t)(wp >> (32 - Lcp)) + cp.delta[Lcp];
+            const int32_t iq = (int32_t)(wq >> (32 - Lcq)) + cq.delta[Lcq];
+            rp.consume(Lcp);
+            rq.consume(Lcq);
+            const bool v = k0 + k < ns;
+            bad |= (v && (Lp == 0 || Lq == 0)) ? C3_ERR_CODE : 0u;
+            bitp += v ? Lp : 0;
+            bitq += v ? Lq : 0;
+            tp[l * GP + k] = Lp ? ip : -1;
+            tq[l * GP + k] = (uint16_t)(Lq ? iq : 0xFFFF);
+        }
+#pragma unroll
+        for (int h = 0; h < G; h += G / 2) {
+            int32_t gp_[G / 2], gq_[G / 2];
+#pragma unroll
+            for (int k = 0; k < G / 2; ++k) {
+                gp_[k] = (int32_t)buf_word(symp, (uint32_t)tp[l * GP + h + k]);
+                gq_[k] = (int32_t)buf_word(symq, (uint32_t)tq[l * GP + h + k]);
             }
-            // symbol values (gathers issued in groups), running sums, range checks
 #pragma unroll
-            for (int h = 0; h < G; h += G / 2) {
-                int32_t gp_[G / 2], gq_[G / 2];
-#pragma unroll
-                for (int k = 0; k < G / 2; ++k) {
-                    gp_[k] = (int32_t)buf_word(symp, (uint32_t)tp[l * GP + h + k]);
-                    gq_[k] = (int32_t)buf_word(symq, (uint32_t)tq[l * GP + h + k]);
-                }
-#pragma unroll
-                for (int k = 0; k < G / 2; ++k) {
-                    const bool v = k0 + h + k < ns;
-                    xp += v ? gp_[k] : 0;
-                    xq += v ? gq_[k] : 0;
-                    const bool okp = (uint32_t)xp < npix, okq = (uint32_t)xq < npsi;
-                    bad |= (v && !okp) ? C3_ERR_PIX : 0u;
-                    bad |= (v && !okq) ? C3_ERR_PSI : 0u;
+            for (int k = 0; k < G / 2; ++k) {
+                const bool v = k0 + h + k < ns;
+                xp += v ? gp_[k] : 0;
+                xq += v ? gq_[k] : 0;
+                const bool okp = (uint32_t)xp < npix, okq = (uint32_t)xq < npsi;
+                bad |= (v && !okp) ? C3_ERR_PIX : 0u;
+                bad |= (v && !okq) ? C3_ERR_PSI : 0u;
+                if (to_regs) {
+                    v0p[h + k] = okp ? xp : 0;
+                    v0q[h + k] = (uint16_t)(okq ? xq : 0);
+                } else {
                     tp[l * GP + h + k] = okp ? xp : 0;
                     tq[l * GP + h + k] = (uint16_t)(okq ? xq : 0);
                 }
             }
         }
-        __syncthreads();
-        // write the tile: 16-lane rows of consecutive samples of one chunk
+    };
+    // write the tile of the round at k0: 16-lane rows of consecutive samples
+    // of one chunk
+    auto write_tile = [&](int k0) {
 #pragma unroll 4
         for (int m = 0; m < G; ++m) {
             const int q = m * C3_NT + tid;
@@ -322,7 +328,36 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
                 psi_out[s0 + t] = tq[ll * GP + kk];
             }
         }
+    };
+    if (nround == 2) {
+        // a chunk of two rounds: every store after every load.  Stores and
+        // loads share one in-order completion counter, so a store followed by
+        // a load that is waited on costs the store's whole latency; the first
+        // round's values wait in registers until the second round's loads
+        // are done.
+        int32_t v0p[G];
+        uint16_t v0q[G];
+        round(0, true, v0p, v0q);
+        round(G, false, nullptr, nullptr);
         __syncthreads();
+        write_tile(G);
+        __syncthreads();
+        if (active && ns > 0) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                tp[l * GP + k] = v0p[k];
+                tq[l * GP + k] = v0q[k];
+            }
+        }
+        __syncthreads();
+        write_tile(0);
+    } else {
+        for (int rd = 0; rd < nround; ++rd) {
+            round(rd * G, false, nullptr, nullptr);
+            __syncthreads();
+            write_tile(rd * G);
+            __syncthreads();
+        }
     }
     // chunk boundary consistency with the side index: the codes of chunk c end
     // where chunk c + 1 starts, and the running value meets its stored one
