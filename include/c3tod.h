@@ -19,8 +19,8 @@
  *   pixel p is global pixel pix_off[b] + p; npix_total = sum of npix.
  * Maps: [3][npix_total] (T block, Q block, U block), FP32 for TOD_MIXED,
  *   FP64 for TOD_PLAIN_FP64.
- * Binned accumulators: [10][npix_total] FP64, component-major (ten blocks
- *   of npix_total, in the same pixel order as the maps):
+ * Binned accumulators: [npix_total][10] FP64, pixel-major (one record of ten
+ *   per pixel, in the same pixel order as the maps):
  *   { b_T, b_Q, b_U, A_TT, A_TQ, A_TU, A_QQ, A_QU, A_UU, hits }.
  * Pointers: "device" = HIP device memory on the context's device; "host" =
  *   ordinary host memory.  The caller owns every buffer it passes; the
@@ -311,7 +311,7 @@ tod_status sample_ncorr_masked(tod_ctx ctx, const tod_layout *lay, tod_prec prec
  * the fly during the TOD loop; binning row of the resource table): with
  * w = g/sigma0^2, v = d - n_corr, (c, s) = (cos 2psi, sin 2psi):
  *   b_p += w v (1, c, s),  A_p += g w (1, c, s)^T (1, c, s),  hits_p += 1.
- * acc: device [10][npix_total] FP64.  accumulate = 0 zeroes acc first.
+ * acc: device [npix_total][10] FP64 (pixel-major).  accumulate = 0 zeroes acc first.
  * ncorr may be NULL (v = d).  Segments with accept = 0 are skipped. */
 tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
                    const int32_t *pix, const uint16_t *psi,
@@ -321,7 +321,7 @@ tod_status bin_tod(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
 
 /* Per-pixel map solve m_p = A_p^-1 b_p in FP64 with the condition number
  * rcond_p = lambda_min / lambda_max of A_p; pixels with hits < 3 or
- * rcond < rcond_min get NaN.  acc: device [10][npix]; map_out: device
+ * rcond < rcond_min get NaN.  acc: device [npix][10]; map_out: device
  * [3][npix] of map_dtype; rcond_out: device [npix] FP64 (may be NULL). */
 tod_status solve_maps(tod_ctx ctx, int64_t npix, const double *acc, double rcond_min,
                       void *map_out, tod_dtype map_dtype, double *rcond_out);
@@ -368,7 +368,7 @@ tod_status tod_chisq_backward(tod_ctx ctx, const tod_layout *lay, tod_prec prec,
 /* One fused TOD sweep: decode -> project -> n_corr draw -> binning (the
  * decompress / project / correlated-noise / bin rows of the TOD loop).
  * Writes ncorr_out [nsamp] (FP32 mixed / FP64 plain), zeroes and fills acc
- * [10][npix_total].  pix_work/psi_work: device [nsamp] scratch that receives
+ * [npix_total][10].  pix_work/psi_work: device [nsamp] scratch that receives
  * the decoded pointing.  use_graph != 0 captures the sweep's kernels into a
  * hipGraph on the first call with a given set of arguments and replays it
  * afterwards (seed and iter are read from device memory, so they may change

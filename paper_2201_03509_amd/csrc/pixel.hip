@@ -16,11 +16,12 @@
 namespace {
 
 // ---------------------------------------------------------------- binning
-// acc is component-major, [10][npt]: a wave's flushes of one component land
-// on nearby pixels of one block instead of ten words of each pixel's record.
+// acc is pixel-major, [npt][10]: a flush adds to the ten words of one
+// pixel's record (one or two cache lines), not to ten lines npt apart.
 __device__ __forceinline__ void flush_acc(double *acc, int64_t npt, int64_t gp, const double *a) {
+    (void)npt;
 #pragma unroll
-    for (int j = 0; j < 10; ++j) atomicAdd(acc + j * npt + gp, a[j]);
+    for (int j = 0; j < 10; ++j) atomicAdd(acc + gp * 10 + j, a[j]);
 }
 
 // Bin tile (x = first entry of the run list, y = first phase, z = stride S,
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(C3_NT) void k_solve(int64_t npix, const double *__r
     if (p >= npix) return;
     double a[10];
 #pragma unroll
-    for (int j = 0; j < 10; ++j) a[j] = acc[j * npix + p];
+    for (int j = 0; j < 10; ++j) a[j] = acc[p * 10 + j];
     const double b0 = a[0], b1 = a[1], b2 = a[2];
     double A[3][3] = {{a[3], a[4], a[5]}, {a[4], a[6], a[7]}, {a[5], a[7], a[8]}};
     const double hits = a[9];

@@ -32,6 +32,23 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _acc(acc):
+    """Pointer of binned accumulators: a (10, npix) FP64 view of a pixel-major
+    [npix][10] device buffer, as new_acc returns."""
+    if (acc.dtype != torch.float64 or acc.dim() != 2 or acc.shape[0] != 10
+            or acc.stride() != (1, 10)):
+        raise ValueError("acc must be the (10, npix) view of a pixel-major [npix][10] FP64 buffer "
+                         "(ops.new_acc)")
+    return ctypes.c_void_p(acc.data_ptr())
+
+
+def new_acc(npix_total, device):
+    """Binned accumulators for npix_total pixels: stored pixel-major, [npix][10]
+    (one record of ten per pixel), returned as a (10, npix) view so that
+    acc[j] is component j of every pixel."""
+    return torch.empty((npix_total, 10), dtype=torch.float64, device=device).t()
+
+
 def _prec(prec):
     if prec in ("mixed", L.TOD_MIXED):
         return L.TOD_MIXED
@@ -243,13 +260,12 @@ class Context:
         self._chk(self.lib.bin_tod(
             self.h, ctypes.byref(tod.layout), _prec(prec), _ptr(pix), _ptr(psi), _ptr(d), _dt(d),
             _ptr(ncorr), _ptr(tod.gain if gain is None else gain),
-            _ptr(tod.sigma0 if sigma0 is None else sigma0), _ptr(acc), int(bool(accumulate))))
+            _ptr(tod.sigma0 if sigma0 is None else sigma0), _acc(acc), int(bool(accumulate))))
 
     def solve_maps(self, acc, rcond_min, map_out, rcond_out=None):
-        if acc.dim() != 2 or acc.shape[0] != 10:
-            raise ValueError("acc must be [10][npix] (component-major)")
+        a = _acc(acc)
         npix = acc.shape[1]
-        self._chk(self.lib.solve_maps(self.h, int(npix), _ptr(acc), float(rcond_min), _ptr(map_out),
+        self._chk(self.lib.solve_maps(self.h, int(npix), a, float(rcond_min), _ptr(map_out),
                                       _dt(map_out), _ptr(rcond_out)))
 
     def tod_chisq(self, tod, prec, pix, psi, d, ncorr, maps, chisq_seg, gain=None, sigma0=None,
@@ -283,7 +299,7 @@ class Context:
             self.h, ctypes.byref(tod.layout), _prec(prec), ctypes.byref(pix_huff or tod.pix_huff),
             ctypes.byref(psi_huff or tod.psi_huff), _ptr(tod.d), _dt(tod.d), _ptr(maps), _ptr(tod.gain),
             _ptr(tod.sigma0), _ptr(tod.fknee), _ptr(tod.alpha), ctypes.c_uint64(int(seed)),
-            ctypes.c_uint64(int(it)), _ptr(ncorr_out), _ptr(acc), _ptr(pix_work), _ptr(psi_work),
+            ctypes.c_uint64(int(it)), _ptr(ncorr_out), _acc(acc), _ptr(pix_work), _ptr(psi_work),
             int(bool(use_graph))))
 
     def tod_sweep_stream(self, tod, prec, maps, seed, it, ncorr_out, acc, pix_work, psi_work, d_work,
@@ -293,7 +309,7 @@ class Context:
             self.h, ctypes.byref(tod.layout), _prec(prec), ctypes.byref(tod.pix_huff),
             ctypes.byref(tod.psi_huff), ctypes.byref(tod.tod_huff), float(tod.tod_quantum), _ptr(d_work),
             _ptr(maps), _ptr(tod.gain), _ptr(tod.sigma0), _ptr(tod.fknee), _ptr(tod.alpha),
-            ctypes.c_uint64(int(seed)), ctypes.c_uint64(int(it)), _ptr(ncorr_out), _ptr(acc), _ptr(pix_work),
+            ctypes.c_uint64(int(seed)), ctypes.c_uint64(int(it)), _ptr(ncorr_out), _acc(acc), _ptr(pix_work),
             _ptr(psi_work), int(bool(use_graph))))
 
     def autotune(self, tod, prec, pix=None, cache_path=None):
@@ -338,5 +354,5 @@ def new_outputs(tod, prec):
         "pix": torch.empty(tod.nsamp, dtype=torch.int32, device=dev),
         "psi": torch.empty(tod.nsamp, dtype=torch.uint16, device=dev),
         "ncorr": torch.empty(tod.nsamp, dtype=ft, device=dev),
-        "acc": torch.empty((10, tod.npix_total), dtype=torch.float64, device=dev),
+        "acc": new_acc(tod.npix_total, dev),
     }

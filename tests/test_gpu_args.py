@@ -74,7 +74,7 @@ def test_noise_parameter_domain_sets_sticky_bit(env, which, value, bit):
     out = torch.empty(ts.nsamp, dtype=torch.float64, device="cuda")
     calls = [lambda: c.sample_ncorr(tod, "fp64", tod.d, s, 1, 0, out)]
     if which == "sigma0":
-        acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+        acc = ops.new_acc(ts.npix_total, "cuda")
         calls.append(lambda: c.bin_tod(tod, "fp64", torch.from_numpy(ts.pix.astype(np.int32)).cuda(),
                                        torch.from_numpy(ts.psi.astype(np.uint16)).cuda(), tod.d, None, acc))
     maps = torch.from_numpy(ts.maps).cuda()
@@ -113,7 +113,7 @@ def test_non_finite_data_sets_sticky_bit(env):
         c.sync()
     assert c.device_error_bits() == 128
     c.clear_error()
-    acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+    acc = ops.new_acc(ts.npix_total, "cuda")
     c.bin_tod(tod, "fp64", o["pix"], o["psi"], d, None, acc)
     with pytest.raises(ops.CorruptStream):
         c.sync()

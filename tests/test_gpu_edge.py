@@ -126,7 +126,7 @@ def test_edge_project_bin_chisq(prec, stride):
         tod = ops.DeviceTod(ts, "cuda:0")
         s = torch.empty(ts.nsamp, dtype=tf, device="cuda")
         c.project_sky(tod, prec, pix, psi, _dev(m), s)
-        acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+        acc = ops.new_acc(ts.npix_total, "cuda")
         c.bin_tod(tod, prec, pix, psi, tod.d, _dev(nc), acc)
         J = torch.empty(ts.nseg, dtype=torch.float64, device="cuda")
         c.tod_chisq(tod, prec, pix, psi, tod.d, _dev(nc), _dev(m), J)

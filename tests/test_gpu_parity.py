@@ -158,12 +158,13 @@ def test_ncorr(ctx, name, prec, mean_only):
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 @pytest.mark.parametrize("name", ["tiny", "lfi30_small", "mixed_small"])
 def test_bin_and_solve(ctx, name, prec):
+    from paper_2201_03509_amd import ops
     ts, pix, psi = dataset(name)
     tod = dev_tod(ts)
     rng = np.random.default_rng(5)
     nc = (rng.normal(size=ts.nsamp) * 0.3).astype(np.float32 if prec == "mixed" else np.float64)
     b, A, hits = ot.bin_tod(ts, pix, psi, ts.d, nc.astype(np.float64))
-    acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+    acc = ops.new_acc(ts.npix_total, "cuda")
     ctx.bin_tod(tod, prec, torch.from_numpy(pix.astype(np.int32)).cuda(),
                 torch.from_numpy(psi.astype(np.uint16)).cuda(), tod.d,
                 torch.from_numpy(nc).cuda(), acc)
@@ -196,10 +197,11 @@ def test_bin_and_solve(ctx, name, prec):
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_noiseless_round_trip(ctx, prec):
     """FP64 d = g P m exactly: the GPU bin + solve returns the input map."""
+    from paper_2201_03509_amd import ops
     ts, pix, psi = dataset("tiny")
     tod = dev_tod(ts)
     d = ot.project_all(ts, ts.maps, pix, psi)
-    acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+    acc = ops.new_acc(ts.npix_total, "cuda")
     ctx.bin_tod(tod, prec, torch.from_numpy(pix.astype(np.int32)).cuda(),
                 torch.from_numpy(psi.astype(np.uint16)).cuda(), torch.from_numpy(d).cuda(), None,
                 acc)
@@ -278,7 +280,7 @@ def test_bin_runs_across_scans(name, stride, runs):
             for band in range(ts.nband):
                 c.set_bin_stride(band, stride)
         tod = dev_tod(ts)
-        acc = torch.empty((10, ts.npix_total), dtype=torch.float64, device="cuda")
+        acc = ops.new_acc(ts.npix_total, "cuda")
         c.bin_tod(tod, "mixed", torch.from_numpy(pix.astype(np.int32)).cuda(),
                   torch.from_numpy(psi.astype(np.uint16)).cuda(), tod.d, torch.from_numpy(nc).cuda(), acc)
         c.sync()
