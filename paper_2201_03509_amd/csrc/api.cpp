@@ -135,6 +135,7 @@ struct tod_ctx_s {
     uint32_t *d_err = nullptr;
     uint64_t *d_seed_iter = nullptr;
     DevBuf trig32, trig64, work, seg_sums, seg_whittle, probe_counts, resid;
+    DevBuf gmap4;                         // map-gradient records (T, Q, U, unused) per pixel
     DevBuf dec_tabs;                      // decoding tables, rebuilt by every decode
     DevBuf dec_tabs2;                     // the TOD stream's decoding tables (tod_sweep_stream)
     DevBuf maps4;                         // the sweep's maps as (T, Q, U, 0) records
@@ -1489,7 +1490,10 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     hipStream_t st = ctx->stream;
     HIPCHK(c3::launch_zero(st, ctx->seg_sums.p, ssz));
     HIPCHK(c3::launch_zero(st, ctx->seg_whittle.p, ssz));
-    if (grad_maps) HIPCHK(c3::launch_zero(st, grad_maps, sizeof(double) * 3 * lay->npix_total));
+    if (grad_maps) {
+        HIPCHK(ctx->gmap4.ensure(sizeof(double) * 4 * (size_t)std::max<int64_t>(1, lay->npix_total)));
+        HIPCHK(c3::launch_zero(st, ctx->gmap4.p, sizeof(double) * 4 * lay->npix_total));
+    }
     if (gsig) HIPCHK(c3::launch_zero(st, gsig, sizeof(double) * lay->ndet));
     if (gfk) HIPCHK(c3::launch_zero(st, gfk, sizeof(double) * lay->ndet));
     if (galpha) HIPCHK(c3::launch_zero(st, galpha, sizeof(double) * lay->ndet));
@@ -1498,9 +1502,11 @@ static tod_status chisq_common(tod_ctx ctx, const tod_layout *lay, tod_prec prec
     HIPCHK(c3::launch_check_params(st, Ld, sigma0, fknee, alpha, ctx->d_err));
     {
         KTimer kt(ctx, K_CHISQ, st);
+        double *g4 = grad_maps ? (double *)ctx->gmap4.p : nullptr;
         HIPCHK(c3::launch_chisq_time_tiles(st, Ld, mixed, tiles, nt, pix, psi, d, d_dtype == TOD_F64,
                                            ncorr, maps, ctx->maps4.p, gain, sigma0, ctx->trig64.p,
-                                           (double *)ctx->seg_sums.p, grad_maps, gscale, gscale_dev));
+                                           (double *)ctx->seg_sums.p, g4, gscale, gscale_dev));
+        if (grad_maps) HIPCHK(c3::launch_gmap_out(st, lay->npix_total, g4, grad_maps));
     }
     c3::FftArgs a = fft_args(ctx, P, lay);
     a.in_a = ncorr;

@@ -277,14 +277,17 @@ hipError_t launch_repeat_probe(hipStream_t st, const int32_t *pix, int64_t off, 
                                unsigned long long *counts);
 
 // chi^2 time-domain part on strided tiles: per segment sum r^2/sigma0^2 (-> seg_sums[4s]),
-// sum (Pm) r (-> [4s+1]), sum r^2 (-> [4s+2]); with grad_maps != NULL also the map adjoint.
+// sum (Pm) r (-> [4s+1]), sum r^2 (-> [4s+2]); with grad_maps4 != NULL also the map adjoint,
+// added to grad_maps4: npix_total records (T, Q, U, unused) of FP64, zeroed by the caller.
 // maps4: workspace of npix_total records (T, Q, U, 0), filled from the [3][npix] maps first.
 hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed, const int4 *tiles,
                                    int ntile, const int32_t *pix, const uint16_t *psi,
                                    const void *d, int d_f64, const void *ncorr, const void *maps,
                                    void *maps4, const double *gain, const double *sigma0,
-                                   const void *trig64, double *seg_sums, double *grad_maps,
+                                   const void *trig64, double *seg_sums, double *grad_maps4,
                                    double grad_scale, const double *gscale_dev);
+// grad_maps [3][npt] from the records of grad_maps4
+hipError_t launch_gmap_out(hipStream_t st, int64_t npt, const double *grad_maps4, double *grad_maps);
 hipError_t launch_chisq_finish(hipStream_t st, const LayoutDev &L, const double *seg_time,
                                const double *seg_whittle, const double *gain, const double *sigma0,
                                const double *fknee, const double *alpha, double grad_scale,

@@ -275,6 +275,18 @@ __global__ __launch_bounds__(C3_NT) void k_resid(LayoutDev Ld, const int4 *__res
     if (SUB && bad && err) atomicOr(err, C3_ERR_NONFINITE);
 }
 
+// the map gradient from its pixel-major accumulation records (T, Q, U,
+// unused) into the [3][npt] layout of the maps
+__global__ __launch_bounds__(C3_NT) void k_gmap_out(int64_t npt, const double4 *__restrict__ g4,
+                                                    double *__restrict__ gm) {
+    for (int64_t p = (int64_t)blockIdx.x * C3_NT + threadIdx.x; p < npt; p += (int64_t)gridDim.x * C3_NT) {
+        const double4 r = g4[p];
+        gm[p] = r.x;
+        gm[npt + p] = r.y;
+        gm[2 * npt + p] = r.z;
+    }
+}
+
 // per non-empty segment: the noise parameters the draws and weights divide by
 __global__ __launch_bounds__(C3_NT) void k_check_params(LayoutDev Ld, const double *__restrict__ sigma0,
                                                         const double *__restrict__ fknee,
@@ -404,16 +416,18 @@ __global__ __launch_bounds__(C3_NT) void k_probe(const int32_t *__restrict__ pix
 // segment sum r^2/sigma0^2, sum (P m) r and sum r^2 (block sums, one atomic
 // each); with GRAD the map adjoint -2 g r / sigma0^2 (1, c, s) summed per
 // pixel in registers and added with FP64 atomics when the lane's pixel
-// changes.  The thread keeps its pixel's T, Q, U (interleaved records) in
-// registers across revisits, and keeps four revisits' loads in flight (d of
-// type TD; both types compile-time, so the loads issue with no branch between).
+// changes, into gmap4: one 32-byte record (T, Q, U, unused) per pixel, so a
+// flush's three atomics fall on one cache line.  The thread keeps its
+// pixel's T, Q, U (interleaved records) in registers across revisits, and
+// keeps eight revisits' loads in flight (d of type TD; both types
+// compile-time, so the loads issue with no branch between).
 template <typename T, typename TD, bool GRAD>
 __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     LayoutDev Ld, const int4 *__restrict__ tiles, const int32_t *__restrict__ pix,
     const uint16_t *__restrict__ psi, const TD *__restrict__ d, const T *__restrict__ ncorr,
     const Stokes4<T> *__restrict__ maps, const double *__restrict__ gain,
     const double *__restrict__ sigma0, const cx<double> *__restrict__ trig,
-    double *__restrict__ seg_sums, double *__restrict__ gmap, double gscale0,
+    double *__restrict__ seg_sums, double *__restrict__ gmap4, double gscale0,
     const double *__restrict__ gscale_dev) {
     // dL/dJ: a host factor times an optional device scalar (read here, so the
     // caller's autograd never waits for it)
@@ -430,7 +444,6 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     const int band = Ld.seg_band[tl.x];
     const int64_t poff = Ld.band[band].pix_off;
     const uint32_t npix = (uint32_t)Ld.band[band].npix;
-    const int64_t npt = Ld.npix_total;
     // map-adjoint sums of the current pixel and the two before it (most
     // recent first), flushed when a fourth pixel arrives or the tile ends (as
     // in the binning: a flush inside the loop also delays the next loads)
@@ -439,9 +452,10 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
     double a[3] = {0, 0, 0}, o[3] = {0, 0, 0}, q[3] = {0, 0, 0};
     double g = 0, cfac = 0, sr2 = 0, spr = 0;
     auto flush = [&](int pp, const double *x) {
-        atomicAdd(gmap + poff + pp, x[0]);
-        atomicAdd(gmap + npt + poff + pp, x[1]);
-        atomicAdd(gmap + 2 * npt + poff + pp, x[2]);
+        double *rec = gmap4 + (poff + pp) * 4;
+        atomicAdd(rec, x[0]);
+        atomicAdd(rec + 1, x[1]);
+        atomicAdd(rec + 2, x[2]);
     };
     auto step = [&](int p, int b, double dv, double nc) {
         if ((uint32_t)p >= npix) return;  // out-of-range pixels are not in the likelihood
@@ -506,12 +520,12 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
         cfac = -2.0 * g * is2 * gscale;
         sr2 = spr = 0;
         int t = act ? phi : n;
-        for (; t + 3 * S < n; t += 4 * S) {
-            int p[4], b[4];
-            TD v[4];
-            T c[4];
+        for (; t + 7 * S < n; t += 8 * S) {  // eight revisits' loads in flight
+            int p[8], b[8];
+            TD v[8];
+            T c[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const int64_t i = s0 + t + u * S;
                 p[u] = pix[i];
                 b[u] = psi[i];
@@ -519,7 +533,7 @@ __global__ __launch_bounds__(C3_NT) void k_chisq_time(
                 c[u] = ncorr[i];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) step(p[u], b[u], (double)v[u], (double)c[u]);
+            for (int u = 0; u < 8; ++u) step(p[u], b[u], (double)v[u], (double)c[u]);
         }
         for (; t < n; t += S) {
             const int64_t i = s0 + t;
@@ -625,7 +639,7 @@ template <typename T>
 void launch_chisq_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, int ntile, const int32_t *pix,
                         const uint16_t *psi, const void *d, int d_f64, const void *ncorr, const void *maps,
                         void *maps4, const double *gain, const double *sigma0, const void *trig64,
-                        double *seg_sums, double *grad_maps, double grad_scale, const double *gscale_dev) {
+                        double *seg_sums, double *grad_maps4, double grad_scale, const double *gscale_dev) {
     const int64_t npt = L.npix_total;
     const int gi = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
     hipLaunchKernelGGL(k_interleave<T>, dim3(gi), dim3(C3_NT), 0, st, (const T *)maps, npt, (Stokes4<T> *)maps4);
@@ -635,14 +649,14 @@ void launch_chisq_typed(hipStream_t st, const LayoutDev &L, const int4 *tiles, i
     const dim3 g(ntile), b(C3_NT);
 #define C3_CHISQ(TD, GRAD)                                                                              \
     hipLaunchKernelGGL((k_chisq_time<T, TD, GRAD>), g, b, 0, st, L, tiles, pix, psi, (const TD *)d, nc, m4, \
-                       gain, sigma0, tr, seg_sums, grad_maps, grad_scale, gscale_dev)
+                       gain, sigma0, tr, seg_sums, grad_maps4, grad_scale, gscale_dev)
     if (d_f64) {
-        if (grad_maps)
+        if (grad_maps4)
             C3_CHISQ(double, true);
         else
             C3_CHISQ(double, false);
     } else {
-        if (grad_maps)
+        if (grad_maps4)
             C3_CHISQ(float, true);
         else
             C3_CHISQ(float, false);
@@ -731,15 +745,22 @@ hipError_t launch_chisq_time_tiles(hipStream_t st, const LayoutDev &L, int mixed
                                    int ntile, const int32_t *pix, const uint16_t *psi,
                                    const void *d, int d_f64, const void *ncorr, const void *maps,
                                    void *maps4, const double *gain, const double *sigma0,
-                                   const void *trig64, double *seg_sums, double *grad_maps,
+                                   const void *trig64, double *seg_sums, double *grad_maps4,
                                    double grad_scale, const double *gscale_dev) {
     if (ntile <= 0) return hipSuccess;
     if (mixed)
         launch_chisq_typed<float>(st, L, tiles, ntile, pix, psi, d, d_f64, ncorr, maps, maps4, gain, sigma0,
-                                  trig64, seg_sums, grad_maps, grad_scale, gscale_dev);
+                                  trig64, seg_sums, grad_maps4, grad_scale, gscale_dev);
     else
         launch_chisq_typed<double>(st, L, tiles, ntile, pix, psi, d, d_f64, ncorr, maps, maps4, gain, sigma0,
-                                   trig64, seg_sums, grad_maps, grad_scale, gscale_dev);
+                                   trig64, seg_sums, grad_maps4, grad_scale, gscale_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmap_out(hipStream_t st, int64_t npt, const double *grad_maps4, double *grad_maps) {
+    if (npt <= 0) return hipSuccess;
+    const int g = (int)std::min<int64_t>((npt + C3_NT - 1) / C3_NT, 65536);
+    hipLaunchKernelGGL(k_gmap_out, dim3(g), dim3(C3_NT), 0, st, npt, (const double4 *)grad_maps4, grad_maps);
     return hipGetLastError();
 }
 
