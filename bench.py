@@ -108,6 +108,27 @@ def measured_counters(kernel, workload):
     return e
 
 
+def sweep_counters(workload, ms_step):
+    """HBM bytes of one whole sweep by counters (the committed per-family
+    FETCH_SIZE + WRITE_SIZE summary summed over every family of the sweep),
+    and the rate they make at the timed step; None unless every family's
+    counters were taken on its current sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p)).get(workload, {})
+    except ValueError:
+        return None
+    fams = [k for k in t if k in FAMILY_SOURCES]
+    if not fams or any(t[k].get("source_sha") != source_sha(k) for k in fams):
+        return None
+    gb = sum(t[k]["bytes_per_step"] for k in fams) / 1e9
+    return {"gb_per_step": round(gb, 2), "families": sorted(fams),
+            "gbs_at_step": round(gb / (ms_step / 1e3), 1),
+            "frac_of_peak": round(gb / (ms_step / 1e3) / HBM_PEAK_GBS, 4)}
+
+
 def row_pass_flops(ts, tuned):
     """Algorithmic FP32 flops of the row passes of one sweep.  A segment of
     M = M1 x M2 complex points has M1 rows: each is transformed forward and
@@ -851,6 +872,7 @@ def main():
         "plain_fp64": plain,
         "sweep_algorithmic_gb": round(sweep_alg / 1e9, 3),
         "sweep_algorithmic_frac": round(sweep_alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "sweep_counter_traffic": sweep_counters(workload, ms_step),
         "kernels": per,
         "fft_splits": plans,
         "bin_stride": tuned.get("bin_stride"),
