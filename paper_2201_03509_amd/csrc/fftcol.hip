@@ -53,13 +53,14 @@ __device__ __forceinline__ void col_twiddles(const cx<float> *pool, const FftPla
 // ------------------------------------------------------------- pass 1
 template <int M1>
 __global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
-    // the column's loads need only the task: they are issued first, the
-    // segment's plan (twiddles) and (masked draw) its active flag load while
-    // they are in flight
+    // the column's loads need only the task: they are issued first, and the
+    // segment's plan (twiddles) loads while they are in flight.  In the
+    // masked draw a converged segment's block returns before any load.
     const ColTask sg = a.col_tasks[blockIdx.x];
     const int M2 = sg.M2;
     const int j2 = sg.c0 + (int)threadIdx.x;
     if (j2 >= M2) return;
+    if (a.active && !a.active[sg.seg]) return;  // converged segment (whole block)
     const uint32_t n = (uint32_t)sg.n, n2 = 2u * (uint32_t)sg.n;
     cx<float> x[M1];
     if (a.full_io) {
@@ -115,7 +116,6 @@ __global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
             x[j1] = cx<float>{v[0], v[1]};
         }
     }
-    if (a.active && !a.active[sg.seg]) return;  // converged segment (whole block)
     const FftPlan &p = a.plans[a.segs[sg.seg].plan];
     reg_fft<M1, -1>(x);
     // the twiddle-table loads below must not be hoisted into the FFT, where
@@ -135,12 +135,12 @@ __global__ __launch_bounds__(C3_COL_NT) void k_colr_inv(FftArgs a) {
     const int M2 = sg.M2;
     const int j2 = sg.c0 + (int)threadIdx.x;
     if (j2 >= M2) return;
+    if (a.active && !a.active[sg.seg]) return;  // converged segment (whole block)
     const cx<float> *Y = (const cx<float> *)a.work + sg.scr_off;
     const uint32_t lo = 8u * (uint32_t)j2;
     cx<float> x[M1];
 #pragma unroll
     for (int k1 = 0; k1 < M1; ++k1) x[k1] = ld_off<cx<float>>(Y + (int64_t)k1 * M2, lo);
-    if (a.active && !a.active[sg.seg]) return;  // converged segment (whole block)
     const FftPlan &p = a.plans[a.segs[sg.seg].plan];
     col_twiddles<M1, tw_split(M1)>((const cx<float> *)a.twpool, p, j2, [&](int k1, cx<float> w) {
         x[k1] = cmulc(x[k1], w);  // times w_M^(-j2 k1)

@@ -117,13 +117,12 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     static_assert(plan(L).r[0] > 0, "row length without a three-stage plan");
     cx<float> *buf = (cx<float> *)c3_rowc_lds;  // 2 L elements
     const RowTask task = a.row_tasks[blockIdx.x];
-    if (task.seg < 0) return;  // an empty task (launch padding)
+    if (task.seg < 0) return;                      // an empty task (launch padding)
+    if (a.active && !a.active[task.seg]) return;  // converged segment (masked draw): no load
     // the rows' loads need only the task: they are issued first, and the
-    // segment's record, its plan and (masked draw) its active flag load
-    // while they are in flight
+    // segment's record and plan load while they are in flight
     cx<float> *ya = (cx<float> *)a.work + task.off_a, *yb = (cx<float> *)a.work + task.off_b;
     rstage<L, 0, -1, 1>(buf, ya, yb, nullptr, nullptr, nullptr);
-    if (a.active && !a.active[task.seg]) return;  // converged segment (whole block)
     const int seg = task.seg;
     const SegInfo sg = a.segs[seg];
     const FftPlan &p = a.plans[sg.plan];
