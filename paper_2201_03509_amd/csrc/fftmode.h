@@ -80,7 +80,16 @@ template <typename T>
 __device__ __forceinline__ cx<T> filt_mode(const ModeCtx &mc, int64_t k, cx<T> E, int which) {
     const T q = q_of<T>(mc, k);
     const T s2 = (T)(mc.sigma0 * mc.sigma0);
-    const T h = which == 0 ? q / s2 : (which == 1 ? s2 / ((T)1 + q) : q / (s2 * ((T)1 + q)));
+    T h;
+    if constexpr (sizeof(T) == 4) {
+        // the hardware reciprocal (about 1 ulp) in place of IEEE divisions,
+        // whose scale and fix-up sequences would dominate the filter
+        const float is2 = (float)(1.0 / (mc.sigma0 * mc.sigma0));
+        const float i1q = __builtin_amdgcn_rcpf(1.0f + q);
+        h = which == 0 ? q * is2 : (which == 1 ? s2 * i1q : q * is2 * i1q);
+    } else {
+        h = which == 0 ? q / s2 : (which == 1 ? s2 / ((T)1 + q) : q / (s2 * ((T)1 + q)));
+    }
     return cscale(E, (T)mc.invsqrtN * h);
 }
 
