@@ -90,14 +90,15 @@ __device__ __forceinline__ void rstage(cx<float> *buf, const cx<float> *g0, cons
 // k > 0 and k < M here, so both draws are complex.
 struct FastCtx {
     float c;        // -sigma0^2 ln 2
-    float isq;      // 1 / sqrt(N)
+    float isq;      // 1 / sqrt(N), times the 1/2 of the real-spectrum split
+    float oscale;   // the output scale sqrt(N)/M, times the 1/2 of the re-pack
     float malpha, lbase2;
 };
 
 __device__ __forceinline__ cx<float> cr_fast(const ModeCtx &mc, const FastCtx &fc, uint32_t k, cx<float> E) {
     const float x = fc.malpha * (__builtin_amdgcn_logf((float)k) + fc.lbase2);
     const float q = __builtin_amdgcn_exp2f(x);  // (f_k / f_knee)^-alpha = sigma0^2 / P_k
-    const float inv = __builtin_amdgcn_rcpf(1.0f + q);
+    const float inv = __builtin_amdgcn_rcpf(1.0f + q) * fc.oscale;
     cx<float> out = {E.x * fc.isq, E.y * fc.isq};
     if (!mc.mean_only) {
         const uint4 w = philox4x32_10(make_uint4(k, mc.it_lo, mc.it_hi, mc.seed_hi), mc.key);
@@ -138,20 +139,24 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     const ModeCtx mc = mode_ctx<MODE>(a, seg, sg.band, M);
     FastCtx fc;
     fc.c = (float)(-mc.sigma0 * mc.sigma0 * 0.69314718055994530942);
-    fc.isq = (float)mc.invsqrtN;
+    fc.isq = (float)(0.5 * mc.invsqrtN);
+    fc.oscale = (float)(0.5 * mc.outscale);
     fc.malpha = (float)mc.malpha;
     fc.lbase2 = (float)mc.lbase2;
     const cx<float> wa = twN(pool, p, ka);  // w_N^k1; w_N^(k1 + M1 k2) = w_N^k1 w_2L^k2
-    const float half = 0.5f;
-    const float osc = (float)mc.outscale;
+    const float osc2 = (float)(0.5 * mc.outscale), osc4 = (float)(0.25 * mc.outscale);
+    // The two factors 1/2 of the split and of the re-pack and the output
+    // scale are applied once per mode: E below is twice the spectrum value
+    // (halved in fc.isq or the mode scales) and nk, np come out already
+    // times sqrt(N)/(2M).
     for (int k2 = threadIdx.x; k2 < L; k2 += NT) {
         const int pk2 = L - 1 - k2;  // the partner mode M - k sits in row kb
         const cx<float> Za = buf[2 * k2], Zb = buf[2 * pk2 + 1];
         const cx<float> w = cmul(wa, twh[k2]);
         const int64_t k = ka + (int64_t)M1 * k2, kp = (int64_t)M - k;
-        // A = (Zk + conj Zp)/2, B = -i (Zk - conj Zp)/2, E_k = A + w_N^k B
-        const cx<float> Ak = {half * (Za.x + Zb.x), half * (Za.y - Zb.y)};
-        const cx<float> Dk = {half * (Za.x - Zb.x), half * (Za.y + Zb.y)};
+        // 2A = Zk + conj Zp, 2B = -i (Zk - conj Zp), 2 E_k = 2A + w_N^k 2B
+        const cx<float> Ak = {Za.x + Zb.x, Za.y - Zb.y};
+        const cx<float> Dk = {Za.x - Zb.x, Za.y + Zb.y};
         const cx<float> Bk = {Dk.y, -Dk.x};
         const cx<float> Ek = cadd(Ak, cmul(w, Bk));
         const cx<float> wp = {-w.x, w.y};  // w_N^(M-k) = -conj(w_N^k)
@@ -161,21 +166,21 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
             nk = cr_fast(mc, fc, (uint32_t)k, Ek);
             np = cr_fast(mc, fc, (uint32_t)kp, Ep);
         } else {
-            if (a.which == 3) {
-                nk = x0_mode(mc, k, Ek);
-                np = x0_mode(mc, kp, Ep);
+            if (a.which == 3) {  // not linear in E (its drawn term): E itself
+                nk = cscale(x0_mode(mc, k, cscale(Ek, 0.5f)), osc2);
+                np = cscale(x0_mode(mc, kp, cscale(Ep, 0.5f)), osc2);
             } else {
-                nk = filt_mode(mc, k, Ek, a.which);
-                np = filt_mode(mc, kp, Ep, a.which);
+                nk = cscale(filt_mode(mc, k, Ek, a.which), osc4);
+                np = cscale(filt_mode(mc, kp, Ep, a.which), osc4);
             }
         }
         // Z'_k = (nk + conj np)/2 + i (nk - conj np) conj(w_N^k)/2, scaled
-        const cx<float> Ap = {half * (nk.x + np.x), half * (nk.y - np.y)};
-        const cx<float> Dp = {half * (nk.x - np.x), half * (nk.y + np.y)};
+        const cx<float> Ap = {nk.x + np.x, nk.y - np.y};
+        const cx<float> Dp = {nk.x - np.x, nk.y + np.y};
         const cx<float> Bp = cmulc(Dp, w);
-        buf[2 * k2] = cx<float>{osc * (Ap.x - Bp.y), osc * (Ap.y + Bp.x)};
+        buf[2 * k2] = cx<float>{Ap.x - Bp.y, Ap.y + Bp.x};
         const cx<float> Bq = cmul(cconj(Dp), w);
-        buf[2 * pk2 + 1] = cx<float>{osc * (Ap.x - Bq.y), osc * (-Ap.y + Bq.x)};
+        buf[2 * pk2 + 1] = cx<float>{Ap.x - Bq.y, -Ap.y + Bq.x};
     }
     __syncthreads();
 
