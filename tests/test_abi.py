@@ -46,3 +46,23 @@ def test_struct_layouts():
     assert ctypes.sizeof(_lib.tod_band) == 32
     assert ctypes.sizeof(_lib.tod_layout) == 4 * 4 + 8 * 2 + 8 * 8
     assert ctypes.sizeof(_lib.tod_huff) == 8 * 8 + 4 * 2 + 8 * 2
+
+
+def test_accumulator_layout_is_pixel_major():
+    """The binned accumulators are [npix][10] in memory (one record of ten per
+    pixel); the binding hands them out as a (10, npix) view and refuses any
+    other layout before a call."""
+    import torch
+    from paper_2201_03509_amd import ops
+    acc = ops.new_acc(7, "cpu")
+    assert acc.shape == (10, 7) and acc.stride() == (1, 10)
+    acc.zero_()
+    acc[3, 5] = 1.0  # component 3 of pixel 5 is word 5 * 10 + 3 of the buffer
+    flat = torch.as_strided(acc, (70,), (1,))
+    assert flat[53].item() == 1.0 and flat.sum().item() == 1.0
+    assert ops._acc(acc).value == acc.data_ptr()
+    for bad in (torch.zeros((10, 7), dtype=torch.float64),      # component-major
+                torch.zeros((7, 10), dtype=torch.float64),      # pixel-major but not the view
+                ops.new_acc(7, "cpu").float()):                 # wrong type
+        with pytest.raises(ValueError):
+            ops._acc(bad)
