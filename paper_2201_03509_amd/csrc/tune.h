@@ -217,8 +217,13 @@ inline bool default_choice(int64_t M, int mixed, FftChoice &c) {
 
 inline std::vector<FftChoice> candidates(int64_t M, int mixed) {
     std::vector<FftChoice> out;
-    for (int64_t m1 : reg_cols(M, mixed))
+    // longest register columns first (the tuner keeps an earlier candidate
+    // unless a later one is clearly faster; long columns and short rows are
+    // the usual winners)
+    const std::vector<int64_t> cols = reg_cols(M, mixed);
+    for (auto it = cols.rbegin(); it != cols.rend(); ++it)
         for (int order : {0, 1}) {
+            const int64_t m1 = *it;
             FftChoice c;
             if (make_choice(M, M / m1, mixed, 64, order, 1, c)) out.push_back(c);
         }
