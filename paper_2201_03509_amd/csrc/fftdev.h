@@ -232,12 +232,66 @@ constexpr int tw_split(int M1) {
     return q;
 }
 
+// coprime split R = A B of a composite radix for the prime-factor (Good-Thomas)
+// algorithm, A the factor transformed first; 0 where R has no such split
+constexpr int pfa_first(int R) {
+    switch (R) {
+    case 6: return 2;
+    case 10: return 2;
+    case 12: return 4;
+    case 15: return 3;
+    case 18: return 2;
+    case 20: return 4;
+    case 24: return 8;
+    case 30: return 2;
+    default: return 0;
+    }
+}
+constexpr int inv_mod(int a, int m) {  // a^-1 mod m for coprime a, m > 1
+    for (int x = 1; x < m; ++x)
+        if ((a * x) % m == 1) return x;
+    return 0;
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_any(cx<T> *v);
+
+// DFT of length R = A B, gcd(A, B) = 1, without twiddle factors: input n =
+// (B n1 + A n2) mod R, output k = (B (B^-1 mod A) k1 + A (A^-1 mod B) k2) mod R,
+// so that w_R^(n k) = w_A^(n1 k1) w_B^(n2 k2) (Chinese remainder theorem).  The
+// index maps are compile-time constants: a permutation of registers.
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft_pfa(cx<T> *v) {
+    constexpr int A = pfa_first(R), B = R / A;
+    static_assert(A > 1 && B > 1 && A * B == R, "no coprime split");
+    constexpr int EA = B * inv_mod(B % A, A), EB = A * inv_mod(A % B, B);
+    cx<T> y[A][B];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+        cx<T> c[A];
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) c[n1] = v[(B * n1 + A * n2) % R];
+        dft_any<A, DIR>(c);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) y[k1][n2] = c[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        dft_any<B, DIR>(y[k1]);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[(EA * k1 + EB * k2) % R] = y[k1][k2];
+    }
+}
+
 // radix-R butterfly of any 5-smooth R: the hand-written DFTs for 2, 3, 4, 5
-// and 8, the compile-time register FFT for the composite radices
+// and 8, the prime-factor split for radices with coprime factors, the
+// compile-time register FFT for prime powers (9, 16, 25, 27, 32)
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft_any(cx<T> *v) {
     if constexpr (R == 2 || R == 3 || R == 4 || R == 5 || R == 8) {
         dft<R, DIR>(v);
+    } else if constexpr (pfa_first(R) > 0) {
+        dft_pfa<R, DIR>(v);
     } else {
         cx<T> x[R];
 #pragma unroll
