@@ -33,6 +33,21 @@ __device__ __forceinline__ void st_off(void *base, uint32_t byte_off, V v) {
     *(V *)((char *)base + byte_off) = v;
 }
 
+// reals t and t + 1 (t even) of the mirrored, padded extension of the n
+// samples in the raw buffer rb (4 n bytes) as one complex value, from one
+// 8-byte load: adjacent samples below n, the mirror image of an adjacent pair
+// (in reverse order) from n to 2n, the last sample twice at t = n - 1 (odd
+// n), and the first sample twice in the pad beyond 2n (the pad repeats r_0).
+// Needs n > 1: every load stays inside the n samples.
+__device__ __forceinline__ cx<float> ext_pair(__amdgpu_buffer_rsrc_t rb, uint32_t n, uint32_t t) {
+    const uint32_t n2 = 2u * n;
+    const bool lo = t + 1u < n, mir = t >= n, pad = t >= n2;
+    const uint32_t b = lo ? t : (pad ? 0u : (mir ? n2 - 2u - t : n - 2u));
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rb, (int)(4u * b), 0, 0);
+    const float v0 = __uint_as_float(v[0]), v1 = __uint_as_float(v[1]);
+    return cx<float>{lo || pad ? v0 : v1, mir ? v0 : v1};
+}
+
 // f(k1, w_M^(j2 k1)) for k1 < M1, with w_M^(j2 (a Q + b)) = w_M^(j2 Q a) w_M^(j2 b)
 // from the two-level w_N table (N = 2M); each factor is used as soon as it is
 // formed, so no table of M1 twiddles is held in registers
@@ -73,30 +88,28 @@ __global__ __launch_bounds__(C3_COL_NT) void k_colr_fwd(FftArgs a) {
             if ((j1 & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
     } else if (!a.in_b && !a.in_a_f64) {
-        // r = in_a (FP32): the sweep's residual
-        const float *r = (const float *)a.in_a + sg.samp_off;
+        // r = in_a (FP32): the sweep's residual (n > 12 here: M >= M1 >= 16
+        // is the next 5-smooth length >= n)
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc((float *)a.in_a + sg.samp_off, 0, 4 * sg.n, C3_BUF_WORD3);
 #pragma unroll
         for (int j1 = 0; j1 < M1; ++j1) {
-            const uint32_t t = 2u * (uint32_t)(M2 * j1 + j2);
-            const uint32_t u0 = t < n ? t : (t < n2 ? n2 - 1u - t : 0u);
-            const uint32_t u1 = t + 1u < n ? t + 1u : (t + 1u < n2 ? n2 - 2u - t : 0u);
-            x[j1] = cx<float>{ld_off<float>(r, 4u * u0), ld_off<float>(r, 4u * u1)};
+            x[j1] = ext_pair(r, n, 2u * (uint32_t)(M2 * j1 + j2));
             // keep the scheduler from computing every offset before the first
-            // load: 16 rows (32 loads per lane) in flight is plenty
+            // load: 16 rows in flight is plenty
             if ((j1 & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
     } else if (a.in_b && !a.in_a_f64 && !a.in_b_f64) {
         // r = in_a - in_b, both FP32 (d and s of a standalone draw): every
         // load of the column is issued before the first subtraction
-        const float *ra = (const float *)a.in_a + sg.samp_off;
-        const float *rb = (const float *)a.in_b + sg.samp_off;
+        const __amdgpu_buffer_rsrc_t ra =
+            __builtin_amdgcn_make_buffer_rsrc((float *)a.in_a + sg.samp_off, 0, 4 * sg.n, C3_BUF_WORD3);
+        const __amdgpu_buffer_rsrc_t rb =
+            __builtin_amdgcn_make_buffer_rsrc((float *)a.in_b + sg.samp_off, 0, 4 * sg.n, C3_BUF_WORD3);
 #pragma unroll
         for (int j1 = 0; j1 < M1; ++j1) {
             const uint32_t t = 2u * (uint32_t)(M2 * j1 + j2);
-            const uint32_t u0 = t < n ? t : (t < n2 ? n2 - 1u - t : 0u);
-            const uint32_t u1 = t + 1u < n ? t + 1u : (t + 1u < n2 ? n2 - 2u - t : 0u);
-            x[j1] = cx<float>{ld_off<float>(ra, 4u * u0) - ld_off<float>(rb, 4u * u0),
-                              ld_off<float>(ra, 4u * u1) - ld_off<float>(rb, 4u * u1)};
+            x[j1] = csub(ext_pair(ra, n, t), ext_pair(rb, n, t));
             if ((j1 & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
     } else {
