@@ -141,3 +141,63 @@ def test_compiled_row_lengths(tmp_path, L):
             assert np.linalg.norm(got[a:b] - ref[a:b]) / np.linalg.norm(ref[a:b]) < TOL["mixed"], (L, mo, q)
     g_ref, _ = og.sample_gain_all(ts, ts.d, t.astype(np.float32).astype(np.float64), seed, it)
     assert np.all(np.abs(g.cpu().numpy() - g_ref) <= TOL["mixed"] * np.abs(g_ref))
+
+
+def _next_5smooth(n):
+    while not _smooth(n):
+        n += 1
+    return n
+
+
+# register column splits with segments of ragged lengths: every length has
+# M = M1 M2 as its next 5-smooth number, so one forced split serves them all;
+# odd and even n, n = M and n < M (the pad repeats r_0), and, with several
+# detectors per scan, odd and even sample offsets
+RAGGED = [
+    (27, 16, [8, 2], [431, 407, 432, 420]),
+    (81, 25, [25], [2025, 2023, 2001, 2012]),
+    (16, 135, [27, 5], [2160, 2159, 2053, 2100]),
+]
+
+
+@pytest.mark.parametrize("case", RAGGED, ids=lambda c: "%dx%d" % (c[0], c[1]))
+def test_register_columns_ragged_lengths(tmp_path, case):
+    """The forward column pass reads each pair of reals of the mirrored,
+    padded extension with one load: adjacent samples, mirrored pairs, the last
+    sample twice (odd n) and the pad's r_0.  Both of its inputs (d - s of a
+    standalone draw, the sweep's residual) against the oracle per segment."""
+    from paper_2201_03509_amd import ops
+    M1, M2, r2, lengths = case
+    M = M1 * M2
+    assert all(_next_5smooth(n) == M for n in lengths)
+    ts = synth.make(1, nscan=len(lengths), length=("list", *lengths), keep_truth=True)
+    offs = np.asarray(ts.seg_off[:-1])
+    assert (offs % 2 == 1).any() and (np.diff(ts.seg_off) % 2 == 1).any()
+    choice = {"mixed": 1, "M": M, "M1": M1, "M2": M2, "B": 64, "colreg": 1, "r1": [], "r2": r2}
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"fft": [choice], "bin_stride": {}}))
+    m32 = ts.maps.astype(np.float32)
+    s_ref = ot.project_all(ts, m32.astype(np.float64), ts.pix, ts.psi)
+    s_in = s_ref.astype(np.float32)
+    seed, it = synth.seed32(ts.config), 3
+    c = ops.Context(0)
+    try:
+        c.load_tuning(str(path))
+        tod = ops.DeviceTod(ts, "cuda:0")
+        draw = torch.empty(ts.nsamp, dtype=torch.float32, device="cuda")
+        c.sample_ncorr(tod, "mixed", tod.d, torch.from_numpy(s_in).cuda(), seed, it, draw)
+        out = ops.new_outputs(tod, "mixed")
+        c.tod_sweep(tod, "mixed", torch.from_numpy(np.ascontiguousarray(m32)).cuda(), seed, it,
+                    out["ncorr"], out["acc"], out["pix"], out["psi"])
+        c.sync()
+    finally:
+        c.close()
+    refs = {"draw": ot.sample_ncorr_all(ts, ts.d, s_in.astype(np.float64), seed, it),
+            "sweep": ot.sample_ncorr_all(ts, ts.d, s_ref, seed, it)}
+    gots = {"draw": draw.cpu().numpy().astype(np.float64),
+            "sweep": out["ncorr"].cpu().numpy().astype(np.float64)}
+    for key in refs:
+        for q in range(ts.nseg):
+            a, b = ts.seg_off[q], ts.seg_off[q + 1]
+            ref, got = refs[key][a:b], gots[key][a:b]
+            assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < TOL["mixed"], (key, q, b - a)
