@@ -5,8 +5,9 @@
 // z[M2 j1 + j2] (consecutive lanes read consecutive addresses), runs the whole
 // FFT_M1 in registers as unrolled Stockham stages whose twiddles are folded to
 // constants at compile time, applies the four-step twiddle w_M^(j2 k1) and
-// writes Y[k1][j2].  No LDS and no barriers: every lane keeps 2 M1 loads in
-// flight, which is what hides HBM latency in this pass.  The inverse kernel
+// writes Y[k1][j2].  No LDS and no barriers: every lane keeps its column's
+// loads (one 8-byte load per element) in flight, which is what hides HBM
+// latency in this pass.  The inverse kernel
 // takes Y[k1][j2] times w_M^(-j2 k1), inverts the column and writes the first
 // n real samples.  The LDS-tiled column kernels in fft.hip cover every other
 // M1 and the FP64 path.
