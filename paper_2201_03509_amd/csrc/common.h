@@ -16,9 +16,10 @@
 #define C3_ROW_RADICES_F32(X) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10) X(12) X(20) X(24) X(25) X(27)
 #define C3_ROW_RADICES_F64(X) X(2) X(3) X(4) X(5) X(6) X(8) X(9) X(10)
 
-// column lengths M1 with register column kernels (5-smooth, 16..81; FP32 only)
+// column lengths M1 with register column kernels (5-smooth, 16..100; FP32 only)
 #define C3_COLREG_LIST(X) \
-    X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(50) X(54) X(60) X(64) X(72) X(75) X(80) X(81)
+    X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) X(48) X(50) X(54) X(60) X(64) X(72) X(75) X(80) X(81) \
+        X(90) X(96) X(100)
 
 // sticky device error bits
 #define C3_ERR_CODE 1u       // bit pattern matches no code

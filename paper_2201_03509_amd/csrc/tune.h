@@ -165,7 +165,7 @@ inline std::vector<int64_t> lds_rows(int64_t M, int mixed) {
 // column lengths of the register splits, ascending
 inline std::vector<int64_t> reg_cols(int64_t M, int mixed) {
     std::vector<int64_t> m1s;
-    for (int64_t m1 = 2; m1 <= 81 && m1 <= M; ++m1)
+    for (int64_t m1 = 2; m1 <= 100 && m1 <= M; ++m1)
         if (M % m1 == 0 && M / m1 <= row_cap(mixed) && colreg_ok(mixed, m1)) m1s.push_back(m1);
     return m1s;
 }

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"mixed": 1e-5, "fp64": 1e-12}
 
-# (prec, M1, M2, colreg, r1, r2): the register column lengths 16..81 paired with
+# (prec, M1, M2, colreg, r1, r2): the register column lengths 16..100 paired with
 # row lengths that use every FP32 row radix; LDS column tiles; the FP64 radices
 CASES = [
     ("mixed", 16, 27, 1, [], [27]), ("mixed", 18, 25, 1, [], [25]), ("mixed", 20, 24, 1, [], [24]),
@@ -30,6 +30,7 @@ CASES = [
     ("mixed", 64, 36, 1, [], [9, 4]), ("mixed", 72, 40, 1, [], [8, 5]), ("mixed", 75, 48, 1, [], [12, 4]),
     ("mixed", 80, 50, 1, [], [25, 2]), ("mixed", 81, 54, 1, [], [27, 2]),
     ("mixed", 60, 600, 1, [], [24, 25]), ("mixed", 81, 729, 1, [], [27, 27]),
+    ("mixed", 90, 32, 1, [], [8, 4]), ("mixed", 96, 45, 1, [], [9, 5]), ("mixed", 100, 27, 1, [], [27]),
     ("mixed", 96, 45, 0, [8, 4, 3], [9, 5]), ("mixed", 128, 30, 0, [8, 8, 2], [5, 6]),
     ("fp64", 96, 90, 0, [8, 4, 3], [10, 9]), ("fp64", 40, 36, 0, [8, 5], [6, 6]),
     ("fp64", 30, 64, 0, [5, 3, 2], [8, 8]),
@@ -157,6 +158,7 @@ RAGGED = [
     (27, 16, [8, 2], [431, 407, 432, 420]),
     (81, 25, [25], [2025, 2023, 2001, 2012]),
     (16, 135, [27, 5], [2160, 2159, 2053, 2100]),
+    (100, 30, [6, 5], [3000, 2999, 2917, 2950]),
 ]
 
 

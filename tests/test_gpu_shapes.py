@@ -2,7 +2,7 @@
 
 * 70 GHz-like shape: nside 1024, 12 detectors, two scans of 230k-290k
   samples at 78.8 Hz (24 segments).  The FFT splits are autotuned, as in the
-  benchmark, so the column lengths M1 in 50..81 and row lengths M2 of
+  benchmark, so the column lengths M1 in 50..100 and row lengths M2 of
   3125..5000 the full set uses run here: decode bit-exact, n_corr of the
   fused sweep (eager and graph-replayed) and of sample_ncorr within 1e-5 per
   segment, b and A of the sweep's binning within 1e-12 of the oracle's.
@@ -70,7 +70,7 @@ def test_lfi70_shape_autotuned(lfi70, tmp_path):
         c.autotune(tod, "mixed", out["pix"], cache_path=str(path))
         plans = [e for e in json.loads(path.read_text())["fft"] if e["mixed"] == 1]
         print("autotuned splits:", sorted({(e["M1"], e["M2"]) for e in plans}))
-        assert all(e["colreg"] == 1 and 50 <= e["M1"] <= 81 for e in plans)
+        assert all(e["colreg"] == 1 and 50 <= e["M1"] <= 100 for e in plans)
         maps = torch.from_numpy(m32).cuda()
         c.set_bin_runs(2)  # binning walks both scans of a detector pair per run
         c.tod_sweep(tod, "mixed", maps, seed, 4, out["ncorr"], out["acc"], out["pix"], out["psi"])
