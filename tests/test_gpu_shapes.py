@@ -2,8 +2,8 @@
 
 * 70 GHz-like shape: nside 1024, 12 detectors, two scans of 230k-290k
   samples at 78.8 Hz (24 segments).  The FFT splits are autotuned, as in the
-  benchmark, so the column lengths M1 in 50..100 and row lengths M2 of
-  3125..5000 the full set uses run here: decode bit-exact, n_corr of the
+  benchmark, so the column lengths M1 in 50..100 and the compiled row
+  lengths (2430..4096 on the full set) run here: decode bit-exact, n_corr of the
   fused sweep (eager and graph-replayed) and of sample_ncorr within 1e-5 per
   segment, b and A of the sweep's binning within 1e-12 of the oracle's.
 * 30 GHz-like shape at full length (the differentiation workload): nside
