@@ -96,6 +96,7 @@ struct Plan {
         int lds;                          // dynamic LDS bytes of the launch
         int t0, nt;                       // range of the row task list
         int rowc;                         // row length of a compiled row kernel, 0: generic
+        bool not_mode0 = false;           // rows the compiled kernel's pair tasks cover in mode 0
     };
     struct Batch {
         int col0, ncol, row0, nrow;
@@ -397,6 +398,7 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
     std::map<int, std::vector<ColTask>> bcol;            // m1reg -> column tasks of the open batch
     std::map<int, std::pair<int, std::vector<RowTask>>> brow;  // -blocks per CU -> (lds, row tasks)
     std::map<int, std::vector<RowTask>> browc;           // compiled row length -> two-row tasks
+    std::map<int, std::vector<RowTask>> bself;           // compiled row length -> rows k1 = 0, M1/2
     Plan::Batch cur{0, 0, 0, 0, {}, {}};
     auto close_batch = [&]() {
         cur.col0 = (int)col.size();
@@ -409,6 +411,31 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         }
         cur.row0 = (int)row.size();
         auto row_seg = [](const RowTask &t) { return t.seg; };
+        // rows that hold their own mirror modes (k1 = 0, M1/2) of a compiled
+        // row length: in mode 0 two of them share a task of the compiled
+        // kernel (pad[0] = 1 + the second row's segment, pad[1] = its k1);
+        // other modes take them one per task on the generic kernel (the
+        // compiled and generic kernels skip the pair tasks there).  An odd
+        // one out takes the generic kernel in every mode.
+        std::vector<RowTask> singles;
+        for (auto &kv : bself) {
+            std::vector<RowTask> &v = kv.second;
+            if (v.size() % 2) {
+                const int rl = 2 * kv.first * esz;
+                auto &rg = brow[-std::max(1, (C3_LDS_MAX - 1024) / rl)];
+                rg.first = std::max(rg.first, rl);
+                rg.second.push_back(v.back());
+                v.pop_back();
+            }
+            for (size_t i = 0; i + 1 < v.size(); i += 2) {
+                RowTask t = v[i];
+                t.pad[0] = 1 + v[i + 1].seg;
+                t.pad[1] = v[i + 1].k1;
+                t.off_b = v[i + 1].off_a;
+                browc[kv.first].push_back(t);
+            }
+            singles.insert(singles.end(), v.begin(), v.end());
+        }
         for (auto &kv : browc) {
             kv.second = xcd_order(kv.second, row_seg, empty_row());
             cur.rgroups.push_back({2 * kv.first * esz, (int)row.size(), (int)kv.second.size(), kv.first});
@@ -419,12 +446,20 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
             cur.rgroups.push_back({kv.second.first, (int)row.size(), (int)kv.second.second.size(), 0});
             row.insert(row.end(), kv.second.second.begin(), kv.second.second.end());
         }
+        if (!singles.empty()) {
+            int lds = 0;
+            for (const auto &kv : bself) lds = std::max(lds, 2 * kv.first * esz);
+            singles = xcd_order(singles, row_seg, empty_row());
+            cur.rgroups.push_back({lds, (int)row.size(), (int)singles.size(), 0, true});
+            row.insert(row.end(), singles.begin(), singles.end());
+        }
         cur.ncol = (int)col.size() - cur.col0;
         cur.nrow = (int)row.size() - cur.row0;
         if (cur.ncol > 0 || cur.nrow > 0) P->batches.push_back(cur);
         bcol.clear();
         brow.clear();
         browc.clear();
+        bself.clear();
         cur = Plan::Batch{(int)col.size(), 0, (int)row.size(), 0, {}, {}};
     };
     for (int s : P->seg_order) {
@@ -464,6 +499,8 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
             // rows k1 and M1 - k1 distinct: the compiled kernel of the row length
             if (fp.twr >= 0 && k1 > 0 && 2 * k1 != fp.M1) {
                 browc[fp.M2].push_back(rt);
+            } else if (fp.twr >= 0) {
+                bself[fp.M2].push_back(rt);
             } else {
                 rg.first = std::max(rg.first, rl);
                 rg.second.push_back(rt);
@@ -843,7 +880,7 @@ tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::Ff
         for (int pass = first; pass < npass; ++pass) {
             if (pass == 1) {
                 for (const Plan::RowGroup &g : b.rgroups) {
-                    if (g.nt <= 0) continue;
+                    if (g.nt <= 0 || (g.not_mode0 && a.mode == 0)) continue;
                     c3::FftArgs ag = a;
                     ag.row_tasks = (const RowTask *)P->row_tasks.p + g.t0;
                     ag.nrow_tasks = g.nt;

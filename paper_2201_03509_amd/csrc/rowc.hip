@@ -10,8 +10,10 @@
 // takes w_N^k = w_N^k1 w_2L^k2 from a block constant and a table of L values.
 // The first forward stage reads the two rows from memory and the last inverse
 // stage writes them back.  Modes: 0 (n_corr constrained realisation) and 2
-// (Fourier-diagonal filters); the other modes, and the rows k1 = 0 and
-// k1 = M1/2, run on the generic kernel.
+// (Fourier-diagonal filters); the other modes run on the generic kernel.  The
+// rows k1 = 0 and k1 = M1/2, each holding its own mirror modes, come two to a
+// task in mode 0 (of one segment or two) and run on the generic kernel in
+// mode 2.
 #include "fftmode.h"
 #include "rowc.h"
 
@@ -113,36 +115,93 @@ __device__ __forceinline__ cx<float> cr_fast(const ModeCtx &mc, const FastCtx &f
     return {out.x * inv, out.y * inv};
 }
 
-template <int L, int MODE>
-__global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
-    static_assert(plan(L).r[0] > 0, "row length without a three-stage plan");
-    cx<float> *buf = (cx<float> *)c3_rowc_lds;  // 2 L elements
-    const RowTask task = a.row_tasks[blockIdx.x];
-    if (task.seg < 0) return;                      // an empty task (launch padding)
-    if (a.active && !a.active[task.seg]) return;  // converged segment (masked draw): no load
-    // the rows' loads need only the task: they are issued first, and the
-    // segment's record and plan load while they are in flight
-    cx<float> *ya = (cx<float> *)a.work + task.off_a, *yb = (cx<float> *)a.work + task.off_b;
-    rstage<L, 0, -1, 1>(buf, ya, yb, nullptr, nullptr, nullptr);
-    const int seg = task.seg;
-    const SegInfo sg = a.segs[seg];
-    const FftPlan &p = a.plans[sg.plan];
-    const int M1 = p.M1, M = p.M;
-    const int ka = task.k1;  // 0 < ka < M1 / 2: rows ka and M1 - ka are distinct
-    const cx<float> *pool = (const cx<float> *)a.twpool;
-    const cx<float> *tws = pool + p.twr;
-    const cx<float> *twh = pool + p.twh;
-
-    rstage<L, 1, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
-    rstage<L, 2, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
-
-    const ModeCtx mc = mode_ctx<MODE>(a, seg, sg.band, M);
+__device__ __forceinline__ FastCtx fast_ctx(const ModeCtx &mc) {
     FastCtx fc;
     fc.c = (float)(-mc.sigma0 * mc.sigma0 * 0.69314718055994530942);
     fc.isq = (float)(0.5 * mc.invsqrtN);
     fc.oscale = (float)(0.5 * mc.outscale);
     fc.malpha = (float)mc.malpha;
     fc.lbase2 = (float)mc.lbase2;
+    return fc;
+}
+
+// The real-spectrum split of a mirror pair: from Z_k (za) and Z_{M-k} (zb) of
+// the packed transform and w = w_N^k, twice E_k and twice E_{M-k}:
+// 2A = Zk + conj Zp, 2B = -i (Zk - conj Zp), 2 E_k = 2A + w_N^k 2B, and the
+// partner from conj A, conj B and w_N^(M-k) = -conj(w_N^k).
+__device__ __forceinline__ void split_pair(cx<float> za, cx<float> zb, cx<float> w, cx<float> &ek,
+                                           cx<float> &ep) {
+    const cx<float> A = {za.x + zb.x, za.y - zb.y};
+    const cx<float> D = {za.x - zb.x, za.y + zb.y};
+    const cx<float> B = {D.y, -D.x};
+    ek = cadd(A, cmul(w, B));
+    const cx<float> wp = {-w.x, w.y};
+    ep = cadd(cconj(A), cmul(wp, cconj(B)));
+}
+
+// The re-pack of a mirror pair: Z'_k = (nk + conj np)/2 + i (nk - conj np)
+// conj(w_N^k)/2 and its partner (the factors 1/2 are in the modes' scales).
+__device__ __forceinline__ void repack_pair(cx<float> nk, cx<float> np, cx<float> w, cx<float> &zk,
+                                            cx<float> &zq) {
+    const cx<float> A = {nk.x + np.x, nk.y - np.y};
+    const cx<float> D = {nk.x - np.x, nk.y + np.y};
+    const cx<float> B = cmulc(D, w);
+    zk = cx<float>{A.x - B.y, A.y + B.x};
+    const cx<float> Bq = cmul(cconj(D), w);
+    zq = cx<float>{A.x - Bq.y, -A.y + Bq.x};
+}
+
+// The modes of a row that holds its own mirror modes (n_corr draw), in LDS
+// row b: k1 = 0 pairs k = M1 k2 with M - k at k2' = (L - k2) mod L and holds
+// k = 0 and k = M (both real, from Z_0); k1 = M1/2 pairs k2 with
+// L - 1 - k2.  A pair with k2' = k2 is the single mode k = M/2.
+template <int L>
+__device__ __forceinline__ void self_row_modes(const FftArgs &a, cx<float> *buf, int seg, int k1, int b,
+                                               const cx<float> *twh) {
+    const SegInfo sg = a.segs[seg];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M1 = p.M1, M = p.M;
+    const ModeCtx mc = mode_ctx<0>(a, seg, sg.band, M);
+    const FastCtx fc = fast_ctx(mc);
+    const cx<float> wa = twN((const cx<float> *)a.twpool, p, k1);
+    const bool zero = k1 == 0;
+    const int npair = zero ? L / 2 + 1 : (L + 1) / 2;
+    for (int k2 = threadIdx.x; k2 < npair; k2 += NT) {
+        const int e = 2 * k2 + b;
+        if (zero && k2 == 0) {
+            // E_0 = Re Z_0 + Im Z_0 and E_M = Re Z_0 - Im Z_0, drawn as real modes
+            const cx<float> z = buf[e];
+            const cx<float> n0 = cr_mode<float>(mc, 0, cx<float>{z.x + z.y, 0.f});
+            const cx<float> nM = cr_mode<float>(mc, M, cx<float>{z.x - z.y, 0.f});
+            const float h = 0.5f * (float)mc.outscale;
+            buf[e] = cx<float>{h * (n0.x + nM.x), h * (n0.x - nM.x)};
+            continue;
+        }
+        const int pk2 = zero ? L - k2 : L - 1 - k2;
+        const int ep = 2 * pk2 + b;
+        const cx<float> w = cmul(wa, twh[k2]);
+        const uint32_t k = (uint32_t)(k1 + M1 * k2), kp = (uint32_t)M - k;
+        cx<float> Ek, Ep;
+        split_pair(buf[e], buf[ep], w, Ek, Ep);
+        const cx<float> nk = cr_fast(mc, fc, k, Ek);
+        const cx<float> np = pk2 == k2 ? nk : cr_fast(mc, fc, kp, Ep);
+        cx<float> zk, zq;
+        repack_pair(nk, np, w, zk, zq);
+        buf[e] = zk;
+        if (pk2 != k2) buf[ep] = zq;
+    }
+}
+
+// The modes of rows k1 and M1 - k1 (LDS rows 0 and 1), which hold each
+// other's mirror modes: mode k = k1 + M1 k2 of row 0 pairs with M - k at
+// k2' = L - 1 - k2 of row 1.
+template <int L, int MODE>
+__device__ __forceinline__ void pair_row_modes(const FftArgs &a, cx<float> *buf, int seg, const SegInfo &sg,
+                                               const FftPlan &p, int ka, const cx<float> *twh) {
+    const int M1 = p.M1, M = p.M;
+    const cx<float> *pool = (const cx<float> *)a.twpool;
+    const ModeCtx mc = mode_ctx<MODE>(a, seg, sg.band, M);
+    const FastCtx fc = fast_ctx(mc);
     const cx<float> wa = twN(pool, p, ka);  // w_N^k1; w_N^(k1 + M1 k2) = w_N^k1 w_2L^k2
     const float osc2 = (float)(0.5 * mc.outscale), osc4 = (float)(0.25 * mc.outscale);
     // The two factors 1/2 of the split and of the re-pack and the output
@@ -150,17 +209,12 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     // (halved in fc.isq or the mode scales) and nk, np come out already
     // times sqrt(N)/(2M).
     for (int k2 = threadIdx.x; k2 < L; k2 += NT) {
-        const int pk2 = L - 1 - k2;  // the partner mode M - k sits in row kb
+        const int pk2 = L - 1 - k2;  // the partner mode M - k sits in row 1
         const cx<float> Za = buf[2 * k2], Zb = buf[2 * pk2 + 1];
         const cx<float> w = cmul(wa, twh[k2]);
         const int64_t k = ka + (int64_t)M1 * k2, kp = (int64_t)M - k;
-        // 2A = Zk + conj Zp, 2B = -i (Zk - conj Zp), 2 E_k = 2A + w_N^k 2B
-        const cx<float> Ak = {Za.x + Zb.x, Za.y - Zb.y};
-        const cx<float> Dk = {Za.x - Zb.x, Za.y + Zb.y};
-        const cx<float> Bk = {Dk.y, -Dk.x};
-        const cx<float> Ek = cadd(Ak, cmul(w, Bk));
-        const cx<float> wp = {-w.x, w.y};  // w_N^(M-k) = -conj(w_N^k)
-        const cx<float> Ep = cadd(cconj(Ak), cmul(wp, cconj(Bk)));
+        cx<float> Ek, Ep;
+        split_pair(Za, Zb, w, Ek, Ep);
         cx<float> nk, np;
         if constexpr (MODE == 0) {
             nk = cr_fast(mc, fc, (uint32_t)k, Ek);
@@ -174,13 +228,46 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
                 np = cscale(filt_mode(mc, kp, Ep, a.which), osc4);
             }
         }
-        // Z'_k = (nk + conj np)/2 + i (nk - conj np) conj(w_N^k)/2, scaled
-        const cx<float> Ap = {nk.x + np.x, nk.y - np.y};
-        const cx<float> Dp = {nk.x - np.x, nk.y + np.y};
-        const cx<float> Bp = cmulc(Dp, w);
-        buf[2 * k2] = cx<float>{Ap.x - Bp.y, Ap.y + Bp.x};
-        const cx<float> Bq = cmul(cconj(Dp), w);
-        buf[2 * pk2 + 1] = cx<float>{Ap.x - Bq.y, -Ap.y + Bq.x};
+        cx<float> zk, zq;
+        repack_pair(nk, np, w, zk, zq);
+        buf[2 * k2] = zk;
+        buf[2 * pk2 + 1] = zq;
+    }
+}
+
+template <int L, int MODE>
+__global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
+    static_assert(plan(L).r[0] > 0, "row length without a three-stage plan");
+    cx<float> *buf = (cx<float> *)c3_rowc_lds;  // 2 L elements
+    const RowTask task = a.row_tasks[blockIdx.x];
+    if (task.seg < 0) return;                      // an empty task (launch padding)
+    // a task of two rows that each hold their own mirror modes (k1 = 0 or
+    // M1/2): pad[0] = 1 + the second row's segment, pad[1] = its k1.  Mode 0
+    // takes them here; other modes take those rows on the generic kernel.
+    const bool self = task.pad[0] > 0;
+    if (MODE != 0 && self) return;
+    if (a.active && !a.active[task.seg]) return;  // converged segment (masked draw): no load
+    // the rows' loads need only the task: they are issued first, and the
+    // segment's record and plan load while they are in flight
+    cx<float> *ya = (cx<float> *)a.work + task.off_a, *yb = (cx<float> *)a.work + task.off_b;
+    rstage<L, 0, -1, 1>(buf, ya, yb, nullptr, nullptr, nullptr);
+    const int seg = task.seg;
+    const SegInfo sg = a.segs[seg];
+    const FftPlan &p = a.plans[sg.plan];
+    const int ka = task.k1;  // 0 < ka < M1 / 2 (rows ka and M1 - ka), or a row of a self task
+    const cx<float> *pool = (const cx<float> *)a.twpool;
+    const cx<float> *tws = pool + p.twr;
+    const cx<float> *twh = pool + p.twh;
+
+    rstage<L, 1, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+    rstage<L, 2, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+
+    if (self) {
+        // the stage and w_2L tables depend on L alone: the first row's serve both
+        self_row_modes<L>(a, buf, seg, ka, 0, twh);
+        self_row_modes<L>(a, buf, task.pad[0] - 1, task.pad[1], 1, twh);
+    } else {
+        pair_row_modes<L, MODE>(a, buf, seg, sg, p, ka, twh);
     }
     __syncthreads();
 
