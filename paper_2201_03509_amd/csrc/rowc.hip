@@ -9,11 +9,12 @@
 // butterfly) instead of being built by chained products, and the mode loop
 // takes w_N^k = w_N^k1 w_2L^k2 from a block constant and a table of L values.
 // The first forward stage reads the two rows from memory and the last inverse
-// stage writes them back.  Modes: 0 (n_corr constrained realisation) and 2
+// stage writes them back.  Modes: 0 (n_corr constrained realisation), 1 (the
+// chi^2's Whittle sums: forward stages only, nothing written back) and 2
 // (Fourier-diagonal filters); the other modes run on the generic kernel.  The
 // rows k1 = 0 and k1 = M1/2, each holding its own mirror modes, come two to a
-// task in mode 0 (of one segment or two) and run on the generic kernel in
-// mode 2.
+// task in modes 0 and 1 (of one segment or two) and run on the generic kernel
+// in mode 2.
 #include "fftmode.h"
 #include "rowc.h"
 
@@ -235,6 +236,78 @@ __device__ __forceinline__ void pair_row_modes(const FftArgs &a, cx<float> *buf,
     }
 }
 
+// Whittle sums (the chi^2's noise term, mode 1) of rows k1 and M1 - k1: every
+// mode k and its partner M - k, E_k from the split (halved: the split gives
+// twice E)
+template <int L>
+__device__ __forceinline__ Wsum pair_row_whittle(const FftArgs &a, const cx<float> *buf, int seg,
+                                                 const SegInfo &sg, const FftPlan &p, int ka,
+                                                 const cx<float> *twh) {
+    const ModeCtx mc = mode_ctx<1>(a, seg, sg.band, p.M);
+    const cx<float> wa = twN((const cx<float> *)a.twpool, p, ka);
+    Wsum ws = {0, 0, 0};
+    for (int k2 = threadIdx.x; k2 < L; k2 += NT) {
+        const int pk2 = L - 1 - k2;
+        const cx<float> w = cmul(wa, twh[k2]);
+        const int64_t k = ka + (int64_t)p.M1 * k2;
+        cx<float> Ek, Ep;
+        split_pair(buf[2 * k2], buf[2 * pk2 + 1], w, Ek, Ep);
+        whittle_mode(mc, k, cscale(Ek, 0.5f), ws);
+        whittle_mode(mc, (int64_t)p.M - k, cscale(Ep, 0.5f), ws);
+    }
+    return ws;
+}
+
+// the same for a row that holds its own mirror modes (pairs as in
+// self_row_modes; row 0 adds the real mode k = M, E_M = Re Z_0 - Im Z_0, and
+// leaves out the mean)
+template <int L>
+__device__ __forceinline__ Wsum self_row_whittle(const FftArgs &a, const cx<float> *buf, int seg, int k1, int b,
+                                                 const cx<float> *twh) {
+    const SegInfo sg = a.segs[seg];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M1 = p.M1, M = p.M;
+    const ModeCtx mc = mode_ctx<1>(a, seg, sg.band, M);
+    const cx<float> wa = twN((const cx<float> *)a.twpool, p, k1);
+    const bool zero = k1 == 0;
+    const int npair = zero ? L / 2 + 1 : (L + 1) / 2;
+    Wsum ws = {0, 0, 0};
+    for (int k2 = threadIdx.x; k2 < npair; k2 += NT) {
+        if (zero && k2 == 0) {
+            const cx<float> z = buf[b];
+            whittle_mode(mc, (int64_t)M, cx<float>{z.x - z.y, 0.f}, ws);
+            continue;
+        }
+        const int pk2 = zero ? L - k2 : L - 1 - k2;
+        const cx<float> w = cmul(wa, twh[k2]);
+        const int64_t k = k1 + (int64_t)M1 * k2;
+        cx<float> Ek, Ep;
+        split_pair(buf[2 * k2 + b], buf[2 * pk2 + b], w, Ek, Ep);
+        whittle_mode(mc, k, cscale(Ek, 0.5f), ws);
+        if (pk2 != k2) whittle_mode(mc, (int64_t)M - k, cscale(Ep, 0.5f), ws);
+    }
+    return ws;
+}
+
+// block sum of a thread's Whittle sums, added to the segment's; red: 3 NT/64
+// doubles of LDS that no thread reads or writes otherwise
+__device__ __forceinline__ void whittle_flush(const FftArgs &a, double *red, Wsum ws, int seg) {
+    double v[3] = {ws.a, ws.b, ws.c};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        double x = v[j];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+        if ((threadIdx.x & 63) == 0) red[j * (NT / 64) + (threadIdx.x >> 6)] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double x = 0;
+        for (int w = 0; w < NT / 64; ++w) x += red[threadIdx.x * (NT / 64) + w];
+        atomicAdd(&a.whittle[(int64_t)seg * 4 + threadIdx.x], x);
+    }
+    __syncthreads();
+}
+
 template <int L, int MODE>
 __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     static_assert(plan(L).r[0] > 0, "row length without a three-stage plan");
@@ -242,10 +315,10 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     const RowTask task = a.row_tasks[blockIdx.x];
     if (task.seg < 0) return;                      // an empty task (launch padding)
     // a task of two rows that each hold their own mirror modes (k1 = 0 or
-    // M1/2): pad[0] = 1 + the second row's segment, pad[1] = its k1.  Mode 0
-    // takes them here; other modes take those rows on the generic kernel.
+    // M1/2): pad[0] = 1 + the second row's segment, pad[1] = its k1.  Modes 0
+    // and 1 take them here; mode 2 takes those rows on the generic kernel.
     const bool self = task.pad[0] > 0;
-    if (MODE != 0 && self) return;
+    if (MODE == 2 && self) return;
     if (a.active && !a.active[task.seg]) return;  // converged segment (masked draw): no load
     // the rows' loads need only the task: they are issued first, and the
     // segment's record and plan load while they are in flight
@@ -262,18 +335,36 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     rstage<L, 1, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
     rstage<L, 2, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
 
-    if (self) {
-        // the stage and w_2L tables depend on L alone: the first row's serve both
-        self_row_modes<L>(a, buf, seg, ka, 0, twh);
-        self_row_modes<L>(a, buf, task.pad[0] - 1, task.pad[1], 1, twh);
+    if constexpr (MODE == 1) {
+        // the rows' buffer is not written back: after the sums, it holds the
+        // block's partial sums
+        double *red = (double *)buf;
+        if (self) {
+            const int seg1 = task.pad[0] - 1;
+            const Wsum w0 = self_row_whittle<L>(a, buf, seg, ka, 0, twh);
+            const Wsum w1 = self_row_whittle<L>(a, buf, seg1, task.pad[1], 1, twh);
+            __syncthreads();
+            whittle_flush(a, red, w0, seg);
+            whittle_flush(a, red, w1, seg1);
+        } else {
+            const Wsum w = pair_row_whittle<L>(a, buf, seg, sg, p, ka, twh);
+            __syncthreads();
+            whittle_flush(a, red, w, seg);
+        }
     } else {
-        pair_row_modes<L, MODE>(a, buf, seg, sg, p, ka, twh);
-    }
-    __syncthreads();
+        if (self) {
+            // the stage and w_2L tables depend on L alone: the first row's serve both
+            self_row_modes<L>(a, buf, seg, ka, 0, twh);
+            self_row_modes<L>(a, buf, task.pad[0] - 1, task.pad[1], 1, twh);
+        } else {
+            pair_row_modes<L, MODE>(a, buf, seg, sg, p, ka, twh);
+        }
+        __syncthreads();
 
-    rstage<L, 0, 1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
-    rstage<L, 1, 1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
-    rstage<L, 2, 1, 2>(buf, nullptr, nullptr, ya, yb, tws);
+        rstage<L, 0, 1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+        rstage<L, 1, 1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
+        rstage<L, 2, 1, 2>(buf, nullptr, nullptr, ya, yb, tws);
+    }
 }
 
 }  // namespace
@@ -281,7 +372,7 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
 namespace c3 {
 
 bool rowc_supported(int mixed, int L, int mode) {
-    return mixed && (mode == 0 || mode == 2) && c3rowc::compiled(L);
+    return mixed && (mode == 0 || mode == 1 || mode == 2) && c3rowc::compiled(L);
 }
 
 hipError_t rowc_init_attributes() {
@@ -292,6 +383,7 @@ hipError_t rowc_init_attributes() {
     };
 #define C3_ROWC_ATTR(LL)                       \
     set((const void *)k_rowc<LL, 0>);          \
+    set((const void *)k_rowc<LL, 1>);          \
     set((const void *)k_rowc<LL, 2>);
     C3_ROWC_LIST(C3_ROWC_ATTR)
 #undef C3_ROWC_ATTR
@@ -307,6 +399,8 @@ hipError_t launch_rowc(hipStream_t st, const FftArgs &a, int L) {
     case LL:                                                                  \
         if (a.mode == 0)                                                      \
             hipLaunchKernelGGL((k_rowc<LL, 0>), g, b, lds, st, a);            \
+        else if (a.mode == 1)                                                 \
+            hipLaunchKernelGGL((k_rowc<LL, 1>), g, b, lds, st, a);            \
         else if (a.mode == 2)                                                 \
             hipLaunchKernelGGL((k_rowc<LL, 2>), g, b, lds, st, a);            \
         else                                                                  \
