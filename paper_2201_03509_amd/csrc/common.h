@@ -258,7 +258,7 @@ hipError_t launch_fft_pass(hipStream_t st, int prec_mixed, const FftArgs &a, int
 // column length without a compiled kernel
 hipError_t launch_fft_col_reg(hipStream_t st, int prec_mixed, const FftArgs &a, int pass, int m1);
 bool fft_col_reg_supported(int prec_mixed, int m1);
-// row kernels compiled per row length (rowc.hip): FP32, modes 0, 1 and 2, the
+// row kernels compiled per row length (rowc.hip): FP32, modes 0, 1, 2 and 4, the
 // two-row tasks (0 < k1 < M1/2) of plans whose M2 is compiled
 bool rowc_supported(int prec_mixed, int L, int mode);
 hipError_t launch_rowc(hipStream_t st, const FftArgs &a, int L);

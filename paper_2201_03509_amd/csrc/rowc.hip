@@ -10,11 +10,12 @@
 // takes w_N^k = w_N^k1 w_2L^k2 from a block constant and a table of L values.
 // The first forward stage reads the two rows from memory and the last inverse
 // stage writes them back.  Modes: 0 (n_corr constrained realisation), 1 (the
-// chi^2's Whittle sums: forward stages only, nothing written back) and 2
-// (Fourier-diagonal filters); the other modes run on the generic kernel.  The
+// chi^2's Whittle sums) and 4 (the periodogram of the noise-parameter draw):
+// forward stages only, nothing written back; 2 (Fourier-diagonal filters).
+// Mode 3 runs on the generic kernel.  The
 // rows k1 = 0 and k1 = M1/2, each holding its own mirror modes, come two to a
-// task in modes 0 and 1 (of one segment or two) and run on the generic kernel
-// in mode 2.
+// task in modes 0, 1 and 4 (of one segment or two) and run on the generic
+// kernel in mode 2.
 #include "fftmode.h"
 #include "rowc.h"
 
@@ -289,6 +290,90 @@ __device__ __forceinline__ Wsum self_row_whittle(const FftArgs &a, const cx<floa
     return ws;
 }
 
+// Periodogram of a row pair's modes into the block's LDS bins (mode 4, the
+// noise-parameter draw): |E_k|^2 / N for every mode k and its partner M - k
+// of rows k1 and M1 - k1 (E from the split, halved).  Every lane of a wave
+// walks the same number of steps (hist_add is a wave operation).
+template <int L>
+__device__ __forceinline__ void pair_row_periodogram(const FftArgs &a, const cx<float> *buf, int seg,
+                                                     const SegInfo &sg, const FftPlan &p, int ka,
+                                                     const cx<float> *twh, double *hist) {
+    const ModeCtx mc = mode_ctx<4>(a, seg, sg.band, p.M);
+    const double s2 = 0.25 * mc.invsqrtN * mc.invsqrtN;  // the split gives twice E
+    const cx<float> wa = twN((const cx<float> *)a.twpool, p, ka);
+    for (int base = 0; base < L; base += NT) {
+        const int k2 = base + (int)threadIdx.x;
+        int bk = -1, bp = -1;
+        double vk = 0.0, vp = 0.0;
+        if (k2 < L) {
+            const int pk2 = L - 1 - k2;
+            const cx<float> w = cmul(wa, twh[k2]);
+            const int64_t k = ka + (int64_t)p.M1 * k2;
+            cx<float> Ek, Ep;
+            split_pair(buf[2 * k2], buf[2 * pk2 + 1], w, Ek, Ep);
+            vk = ((double)Ek.x * Ek.x + (double)Ek.y * Ek.y) * s2;
+            vp = ((double)Ep.x * Ep.x + (double)Ep.y * Ep.y) * s2;
+            bk = xi_bin(k);
+            bp = xi_bin((int64_t)p.M - k);
+        }
+        hist_add(hist, bk, vk);
+        hist_add(hist, bp, vp);
+    }
+}
+
+// the same for a row that holds its own mirror modes (pairs as in
+// self_row_modes; row 0 adds the real mode k = M and leaves out the mean)
+template <int L>
+__device__ __forceinline__ void self_row_periodogram(const FftArgs &a, const cx<float> *buf, int seg, int k1,
+                                                     int b, const cx<float> *twh, double *hist) {
+    const SegInfo sg = a.segs[seg];
+    const FftPlan &p = a.plans[sg.plan];
+    const int M1 = p.M1, M = p.M;
+    const ModeCtx mc = mode_ctx<4>(a, seg, sg.band, M);
+    const double s1 = mc.invsqrtN * mc.invsqrtN, s2 = 0.25 * s1;
+    const cx<float> wa = twN((const cx<float> *)a.twpool, p, k1);
+    const bool zero = k1 == 0;
+    const int npair = zero ? L / 2 + 1 : (L + 1) / 2;
+    for (int base = 0; base < npair; base += NT) {
+        const int k2 = base + (int)threadIdx.x;
+        int bk = -1, bp = -1;
+        double vk = 0.0, vp = 0.0;
+        if (k2 < npair) {
+            if (zero && k2 == 0) {
+                const cx<float> z = buf[b];
+                const double em = (double)(z.x - z.y);  // E_M, real
+                vk = em * em * s1;
+                bk = xi_bin(M);
+            } else {
+                const int pk2 = zero ? L - k2 : L - 1 - k2;
+                const cx<float> w = cmul(wa, twh[k2]);
+                const int64_t k = k1 + (int64_t)M1 * k2;
+                cx<float> Ek, Ep;
+                split_pair(buf[2 * k2 + b], buf[2 * pk2 + b], w, Ek, Ep);
+                vk = ((double)Ek.x * Ek.x + (double)Ek.y * Ek.y) * s2;
+                bk = xi_bin(k);
+                if (pk2 != k2) {
+                    vp = ((double)Ep.x * Ep.x + (double)Ep.y * Ep.y) * s2;
+                    bp = xi_bin((int64_t)M - k);
+                }
+            }
+        }
+        hist_add(hist, bk, vk);
+        hist_add(hist, bp, vp);
+    }
+}
+
+// the block's bins added to the segment's (FP64 atomics), then cleared
+__device__ __forceinline__ void hist_flush(const FftArgs &a, double *hist, int seg) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < C3_XI_NBIN; i += NT)
+        if (hist[i] != 0.0) {
+            atomicAdd(&a.bins[(int64_t)seg * C3_XI_NBIN + i], hist[i]);
+            hist[i] = 0.0;
+        }
+    __syncthreads();
+}
+
 // block sum of a thread's Whittle sums, added to the segment's; red: 3 NT/64
 // doubles of LDS that no thread reads or writes otherwise
 __device__ __forceinline__ void whittle_flush(const FftArgs &a, double *red, Wsum ws, int seg) {
@@ -315,8 +400,8 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     const RowTask task = a.row_tasks[blockIdx.x];
     if (task.seg < 0) return;                      // an empty task (launch padding)
     // a task of two rows that each hold their own mirror modes (k1 = 0 or
-    // M1/2): pad[0] = 1 + the second row's segment, pad[1] = its k1.  Modes 0
-    // and 1 take them here; mode 2 takes those rows on the generic kernel.
+    // M1/2): pad[0] = 1 + the second row's segment, pad[1] = its k1.  Modes 0,
+    // 1 and 4 take them here; mode 2 takes those rows on the generic kernel.
     const bool self = task.pad[0] > 0;
     if (MODE == 2 && self) return;
     if (a.active && !a.active[task.seg]) return;  // converged segment (masked draw): no load
@@ -335,7 +420,21 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     rstage<L, 1, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
     rstage<L, 2, -1, 0>(buf, nullptr, nullptr, nullptr, nullptr, tws);
 
-    if constexpr (MODE == 1) {
+    if constexpr (MODE == 4) {
+        __shared__ double hist[C3_XI_NBIN];
+        for (int i = threadIdx.x; i < C3_XI_NBIN; i += NT) hist[i] = 0.0;
+        __syncthreads();
+        if (self) {
+            const int seg1 = task.pad[0] - 1;
+            self_row_periodogram<L>(a, buf, seg, ka, 0, twh, hist);
+            hist_flush(a, hist, seg);
+            self_row_periodogram<L>(a, buf, seg1, task.pad[1], 1, twh, hist);
+            hist_flush(a, hist, seg1);
+        } else {
+            pair_row_periodogram<L>(a, buf, seg, sg, p, ka, twh, hist);
+            hist_flush(a, hist, seg);
+        }
+    } else if constexpr (MODE == 1) {
         // the rows' buffer is not written back: after the sums, it holds the
         // block's partial sums
         double *red = (double *)buf;
@@ -372,7 +471,7 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
 namespace c3 {
 
 bool rowc_supported(int mixed, int L, int mode) {
-    return mixed && (mode == 0 || mode == 1 || mode == 2) && c3rowc::compiled(L);
+    return mixed && (mode == 0 || mode == 1 || mode == 2 || mode == 4) && c3rowc::compiled(L);
 }
 
 hipError_t rowc_init_attributes() {
@@ -384,7 +483,8 @@ hipError_t rowc_init_attributes() {
 #define C3_ROWC_ATTR(LL)                       \
     set((const void *)k_rowc<LL, 0>);          \
     set((const void *)k_rowc<LL, 1>);          \
-    set((const void *)k_rowc<LL, 2>);
+    set((const void *)k_rowc<LL, 2>);          \
+    set((const void *)k_rowc<LL, 4>);
     C3_ROWC_LIST(C3_ROWC_ATTR)
 #undef C3_ROWC_ATTR
     return e;
@@ -403,6 +503,8 @@ hipError_t launch_rowc(hipStream_t st, const FftArgs &a, int L) {
             hipLaunchKernelGGL((k_rowc<LL, 1>), g, b, lds, st, a);            \
         else if (a.mode == 2)                                                 \
             hipLaunchKernelGGL((k_rowc<LL, 2>), g, b, lds, st, a);            \
+        else if (a.mode == 4)                                                 \
+            hipLaunchKernelGGL((k_rowc<LL, 4>), g, b, lds, st, a);            \
         else                                                                  \
             return hipErrorInvalidValue;                                      \
         break;

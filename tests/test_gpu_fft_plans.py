@@ -203,3 +203,94 @@ def test_register_columns_ragged_lengths(tmp_path, case):
             a, b = ts.seg_off[q], ts.seg_off[q + 1]
             ref, got = refs[key][a:b], gots[key][a:b]
             assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < TOL["mixed"], (key, q, b - a)
+
+
+def _chisq_noise_case(tmp_path, ts, choice, seed, it):
+    """tod_chisq (the row pass's Whittle sums, mode 1) and sample_noise (its
+    periodogram, mode 4) under a forced split, against the oracle."""
+    from paper_2201_03509_amd import ops
+    from oracle import noise as on
+    from chisq_bounds import magnitudes
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"fft": [choice], "bin_stride": {}}))
+    m32 = ts.maps.astype(np.float32)
+    t = ot.project(m32.astype(np.float64), ot.global_pix(ts, ts.pix), ts.psi, 1.0)
+    s = t * np.repeat(ts.gain, np.diff(ts.seg_off))
+    nc32 = ot.sample_ncorr_all(ts, ts.d, s, seed, it).astype(np.float32)
+    c = ops.Context(0)
+    try:
+        c.load_tuning(str(path))
+        tod = ops.DeviceTod(ts, "cuda:0")
+        ncd = torch.from_numpy(nc32).cuda()
+        J = torch.empty(ts.nseg, dtype=torch.float64, device="cuda")
+        c.tod_chisq(tod, "mixed", torch.from_numpy(ts.pix.astype(np.int32)).cuda(),
+                    torch.from_numpy(ts.psi.astype(np.uint16)).cuda(), tod.d, ncd,
+                    torch.from_numpy(m32).cuda(), J)
+        outs = [torch.empty(ts.nseg, dtype=torch.float64, device="cuda") for _ in range(3)]
+        fk_in = torch.from_numpy(np.asarray(ts.fknee, dtype=np.float64)).cuda()
+        c.sample_noise(tod, "mixed", tod.d, torch.from_numpy(t.astype(np.float32)).cuda(), ncd, seed, it,
+                       *outs, fknee=fk_in)
+        c.sync()
+    finally:
+        c.close()
+    nc_r = nc32.astype(np.float64)
+    J_ref = ot.chisq_all(ts, m32.astype(np.float64), ts.pix, ts.psi, ts.d, nc_r)
+    mag, fft, _ = magnitudes(ts, m32.astype(np.float64), nc_r, float(np.finfo(np.float32).eps))
+    assert np.all(np.abs(J.cpu().numpy() - J_ref) <= TOL["mixed"] * mag[0] + fft[0])
+    nz_ref = on.sample_noise_all(ts, ts.d, t.astype(np.float32).astype(np.float64), ts.gain, nc_r, ts.fknee,
+                                 seed, it)
+    got = np.stack([o.cpu().numpy() for o in outs])
+    assert np.isfinite(got).all()
+    assert (np.abs(got - nz_ref) / np.abs(nz_ref)).max() < TOL["mixed"]
+
+
+@pytest.mark.parametrize("L", ROWC)
+def test_compiled_row_lengths_chisq_noise(tmp_path, L):
+    """Every compiled row length, as M = 16 x L (rows 0 and 8 of the split
+    share one task): the chi^2's Whittle sums and the noise draw's periodogram
+    against the oracle."""
+    M = 16 * L
+    choice = {"mixed": 1, "M": M, "M1": 16, "M2": L, "B": 64, "colreg": 1, "r1": [],
+              "r2": _generic_radices(L)}
+    ts = synth.make(1, nscan=1, length=("uniform", M, M), keep_truth=True)
+    _chisq_noise_case(tmp_path, ts, choice, 41, 3)
+
+
+def test_self_rows_of_two_segments(tmp_path):
+    """An odd column length (27): each segment has one row that holds its own
+    mirror modes (k1 = 0), and the compiled kernel pairs such rows of two
+    segments in one task (eight segments: four pair tasks).  n_corr, the
+    chi^2 and the noise draw against the oracle; the gain draw (mode 2) takes
+    those rows on the generic kernel."""
+    from paper_2201_03509_amd import ops
+    from oracle import gain as og
+    M1, L = 27, 2000
+    M = M1 * L
+    choice = {"mixed": 1, "M": M, "M1": M1, "M2": L, "B": 64, "colreg": 1, "r1": [],
+              "r2": _generic_radices(L)}
+    ts = synth.make(1, nscan=2, length=("uniform", M, M), keep_truth=True)
+    assert ts.nseg == 8
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"fft": [choice], "bin_stride": {}}))
+    t = ot.project(ts.maps.astype(np.float32).astype(np.float64), ot.global_pix(ts, ts.pix), ts.psi, 1.0)
+    s_in = (t * np.repeat(ts.gain, np.diff(ts.seg_off))).astype(np.float32)
+    seed, it = 17, 5
+    c = ops.Context(0)
+    try:
+        c.load_tuning(str(path))
+        tod = ops.DeviceTod(ts, "cuda:0")
+        out = torch.empty(ts.nsamp, dtype=torch.float32, device="cuda")
+        c.sample_ncorr(tod, "mixed", tod.d, torch.from_numpy(s_in).cuda(), seed, it, out)
+        g = torch.empty(ts.nseg, dtype=torch.float64, device="cuda")
+        c.sample_gain(tod, "mixed", tod.d, torch.from_numpy(t.astype(np.float32)).cuda(), seed, it, g)
+        c.sync()
+    finally:
+        c.close()
+    ref = ot.sample_ncorr_all(ts, ts.d, s_in.astype(np.float64), seed, it)
+    got = out.cpu().numpy().astype(np.float64)
+    for q in range(ts.nseg):
+        a, b = ts.seg_off[q], ts.seg_off[q + 1]
+        assert np.linalg.norm(got[a:b] - ref[a:b]) / np.linalg.norm(ref[a:b]) < TOL["mixed"], q
+    g_ref, _ = og.sample_gain_all(ts, ts.d, t.astype(np.float32).astype(np.float64), seed, it)
+    assert np.all(np.abs(g.cpu().numpy() - g_ref) <= TOL["mixed"] * np.abs(g_ref))
+    _chisq_noise_case(tmp_path, ts, choice, seed, it)
