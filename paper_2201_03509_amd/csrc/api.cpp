@@ -96,7 +96,7 @@ struct Plan {
         int lds;                          // dynamic LDS bytes of the launch
         int t0, nt;                       // range of the row task list
         int rowc;                         // row length of a compiled row kernel, 0: generic
-        bool pair_rows = false;           // rows the compiled kernel's pair tasks cover in modes 0, 1, 4
+        bool pair_rows = false;           // rows the compiled kernel's pair tasks cover (not mode 3)
     };
     struct Batch {
         int col0, ncol, row0, nrow;
@@ -412,11 +412,11 @@ tod_status build_plan(tod_ctx ctx, const tod_layout *L, int mixed, uint64_t key,
         cur.row0 = (int)row.size();
         auto row_seg = [](const RowTask &t) { return t.seg; };
         // rows that hold their own mirror modes (k1 = 0, M1/2) of a compiled
-        // row length: in modes 0, 1 and 4 two of them share a task of the
-        // compiled kernel (pad[0] = 1 + the second row's segment, pad[1] =
-        // its k1); other modes take them one per task on the generic kernel
-        // (the compiled and generic kernels skip the pair tasks there).  An
-        // odd one out takes the generic kernel in every mode.
+        // row length: two of them share a task of the compiled kernel
+        // (pad[0] = 1 + the second row's segment, pad[1] = its k1); mode 3,
+        // which has no compiled kernel, takes them one per task on the
+        // generic kernel (which skips the pair tasks).  An odd one out takes
+        // the generic kernel in every mode.
         std::vector<RowTask> singles;
         for (auto &kv : bself) {
             std::vector<RowTask> &v = kv.second;
@@ -880,7 +880,7 @@ tod_status run_fft(tod_ctx ctx, hipStream_t st, Plan *P, int mixed, const c3::Ff
         for (int pass = first; pass < npass; ++pass) {
             if (pass == 1) {
                 for (const Plan::RowGroup &g : b.rgroups) {
-                    if (g.nt <= 0 || (g.pair_rows && (a.mode == 0 || a.mode == 1 || a.mode == 4))) continue;
+                    if (g.nt <= 0 || (g.pair_rows && a.mode != 3)) continue;
                     c3::FftArgs ag = a;
                     ag.row_tasks = (const RowTask *)P->row_tasks.p + g.t0;
                     ag.nrow_tasks = g.nt;

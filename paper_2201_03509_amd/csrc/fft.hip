@@ -342,7 +342,7 @@ __global__ __launch_bounds__(row_nt<T>()) void k_row(FftArgs a) {
     __shared__ double red[3][NT / 64];
     const RowTask task = a.row_tasks[blockIdx.x];
     if (task.seg < 0) return;                      // an empty task (launch padding)
-    if (task.pad[0] > 0) return;  // a pair of rows k1 = 0, M1/2 for the compiled mode-0 kernel
+    if (task.pad[0] > 0) return;  // a pair of rows k1 = 0, M1/2 for the compiled kernel
     if (a.active && !a.active[task.seg]) return;  // converged segment (whole block)
     const int seg = task.seg;
     const SegInfo sg = a.segs[seg];

@@ -14,8 +14,7 @@
 // forward stages only, nothing written back; 2 (Fourier-diagonal filters).
 // Mode 3 runs on the generic kernel.  The
 // rows k1 = 0 and k1 = M1/2, each holding its own mirror modes, come two to a
-// task in modes 0, 1 and 4 (of one segment or two) and run on the generic
-// kernel in mode 2.
+// task (of one segment or two).
 #include "fftmode.h"
 #include "rowc.h"
 
@@ -153,28 +152,36 @@ __device__ __forceinline__ void repack_pair(cx<float> nk, cx<float> np, cx<float
     zq = cx<float>{A.x - Bq.y, -A.y + Bq.x};
 }
 
-// The modes of a row that holds its own mirror modes (n_corr draw), in LDS
+// The modes of a row that holds its own mirror modes (modes 0 and 2), in LDS
 // row b: k1 = 0 pairs k = M1 k2 with M - k at k2' = (L - k2) mod L and holds
 // k = 0 and k = M (both real, from Z_0); k1 = M1/2 pairs k2 with
 // L - 1 - k2.  A pair with k2' = k2 is the single mode k = M/2.
-template <int L>
+template <int L, int MODE>
 __device__ __forceinline__ void self_row_modes(const FftArgs &a, cx<float> *buf, int seg, int k1, int b,
                                                const cx<float> *twh) {
     const SegInfo sg = a.segs[seg];
     const FftPlan &p = a.plans[sg.plan];
     const int M1 = p.M1, M = p.M;
-    const ModeCtx mc = mode_ctx<0>(a, seg, sg.band, M);
+    const ModeCtx mc = mode_ctx<MODE>(a, seg, sg.band, M);
     const FastCtx fc = fast_ctx(mc);
+    const float osc2 = (float)(0.5 * mc.outscale), osc4 = (float)(0.25 * mc.outscale);
     const cx<float> wa = twN((const cx<float> *)a.twpool, p, k1);
     const bool zero = k1 == 0;
     const int npair = zero ? L / 2 + 1 : (L + 1) / 2;
     for (int k2 = threadIdx.x; k2 < npair; k2 += NT) {
         const int e = 2 * k2 + b;
         if (zero && k2 == 0) {
-            // E_0 = Re Z_0 + Im Z_0 and E_M = Re Z_0 - Im Z_0, drawn as real modes
+            // E_0 = Re Z_0 + Im Z_0 and E_M = Re Z_0 - Im Z_0, real modes
             const cx<float> z = buf[e];
-            const cx<float> n0 = cr_mode<float>(mc, 0, cx<float>{z.x + z.y, 0.f});
-            const cx<float> nM = cr_mode<float>(mc, M, cx<float>{z.x - z.y, 0.f});
+            const cx<float> E0 = {z.x + z.y, 0.f}, EM = {z.x - z.y, 0.f};
+            cx<float> n0, nM;
+            if constexpr (MODE == 0) {
+                n0 = cr_mode<float>(mc, 0, E0);
+                nM = cr_mode<float>(mc, M, EM);
+            } else {
+                n0 = a.which == 3 ? x0_mode(mc, 0, E0) : filt_mode(mc, 0, E0, a.which);
+                nM = a.which == 3 ? x0_mode(mc, M, EM) : filt_mode(mc, M, EM, a.which);
+            }
             const float h = 0.5f * (float)mc.outscale;
             buf[e] = cx<float>{h * (n0.x + nM.x), h * (n0.x - nM.x)};
             continue;
@@ -182,11 +189,20 @@ __device__ __forceinline__ void self_row_modes(const FftArgs &a, cx<float> *buf,
         const int pk2 = zero ? L - k2 : L - 1 - k2;
         const int ep = 2 * pk2 + b;
         const cx<float> w = cmul(wa, twh[k2]);
-        const uint32_t k = (uint32_t)(k1 + M1 * k2), kp = (uint32_t)M - k;
+        const int64_t k = k1 + (int64_t)M1 * k2, kp = (int64_t)M - k;
         cx<float> Ek, Ep;
         split_pair(buf[e], buf[ep], w, Ek, Ep);
-        const cx<float> nk = cr_fast(mc, fc, k, Ek);
-        const cx<float> np = pk2 == k2 ? nk : cr_fast(mc, fc, kp, Ep);
+        cx<float> nk, np;
+        if constexpr (MODE == 0) {
+            nk = cr_fast(mc, fc, (uint32_t)k, Ek);
+            np = pk2 == k2 ? nk : cr_fast(mc, fc, (uint32_t)kp, Ep);
+        } else if (a.which == 3) {  // not linear in E (its drawn term): E itself
+            nk = cscale(x0_mode(mc, k, cscale(Ek, 0.5f)), osc2);
+            np = pk2 == k2 ? nk : cscale(x0_mode(mc, kp, cscale(Ep, 0.5f)), osc2);
+        } else {
+            nk = cscale(filt_mode(mc, k, Ek, a.which), osc4);
+            np = pk2 == k2 ? nk : cscale(filt_mode(mc, kp, Ep, a.which), osc4);
+        }
         cx<float> zk, zq;
         repack_pair(nk, np, w, zk, zq);
         buf[e] = zk;
@@ -400,11 +416,12 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     const RowTask task = a.row_tasks[blockIdx.x];
     if (task.seg < 0) return;                      // an empty task (launch padding)
     // a task of two rows that each hold their own mirror modes (k1 = 0 or
-    // M1/2): pad[0] = 1 + the second row's segment, pad[1] = its k1.  Modes 0,
-    // 1 and 4 take them here; mode 2 takes those rows on the generic kernel.
+    // M1/2): pad[0] = 1 + the second row's segment, pad[1] = its k1
     const bool self = task.pad[0] > 0;
-    if (MODE == 2 && self) return;
-    if (a.active && !a.active[task.seg]) return;  // converged segment (masked draw): no load
+    // converged segments (masked draw): no load.  A task of two segments runs
+    // while either is active; the workspace rows of a converged one are not
+    // read again (its column passes return before any load or store).
+    if (a.active && !a.active[task.seg] && !(self && a.active[task.pad[0] - 1])) return;
     // the rows' loads need only the task: they are issued first, and the
     // segment's record and plan load while they are in flight
     cx<float> *ya = (cx<float> *)a.work + task.off_a, *yb = (cx<float> *)a.work + task.off_b;
@@ -453,8 +470,8 @@ __global__ __launch_bounds__(NT) void k_rowc(FftArgs a) {
     } else {
         if (self) {
             // the stage and w_2L tables depend on L alone: the first row's serve both
-            self_row_modes<L>(a, buf, seg, ka, 0, twh);
-            self_row_modes<L>(a, buf, task.pad[0] - 1, task.pad[1], 1, twh);
+            self_row_modes<L, MODE>(a, buf, seg, ka, 0, twh);
+            self_row_modes<L, MODE>(a, buf, task.pad[0] - 1, task.pad[1], 1, twh);
         } else {
             pair_row_modes<L, MODE>(a, buf, seg, sg, p, ka, twh);
         }
