@@ -591,11 +591,11 @@ tod_status get_decode_tasks(tod_ctx ctx, Plan *P, int C, const DecodeTask **task
         for (int s : P->seg_order) {
             const int n = P->h_segs[s].n;
             const int nch = (n + C - 1) / C;
-            for (int c0 = 0; c0 < nch; c0 += C3_NT) {
+            for (int c0 = 0; c0 < nch; c0 += C3_DEC_NT) {
                 DecodeTask t;
                 t.seg = s;
                 t.chunk0 = c0;
-                t.nchunk = std::min(C3_NT, nch - c0);
+                t.nchunk = std::min(C3_DEC_NT, nch - c0);
                 t.pad = 0;
                 v.push_back(t);
             }
@@ -1045,7 +1045,7 @@ tod_status decode_pointing_noalloc(tod_ctx ctx, const tod_layout *lay, const tod
     for (int s = 0; s < lay->nseg; ++s) {
         const int64_t n = lay->h_seg_off[s + 1] - lay->h_seg_off[s];
         const int64_t nch = n > 0 ? (n + C - 1) / C : 0;
-        ntask += (nch + C3_NT - 1) / C3_NT;
+        ntask += (nch + C3_DEC_NT - 1) / C3_DEC_NT;
     }
     const int64_t need = c3::noalloc_task_offset((int64_t)pix->ntable + psi->ntable) +
                          ntask * (int64_t)sizeof(DecodeTask);

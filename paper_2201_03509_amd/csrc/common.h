@@ -6,6 +6,7 @@
 #include "../../include/c3tod.h"
 
 #define C3_NT 256            // threads per block of every kernel but the two below
+#define C3_DEC_NT 512        // threads per block of the decoders: one side-index chunk each
 #define C3_ROW_NT_F32 512    // threads per block of the FFT row pass (two blocks per CU)
 #define C3_ROW_NT_F64 1024
 #define C3_COL_NT 64         // threads (= columns) per block of the register column passes
@@ -163,7 +164,7 @@ struct alignas(16) DecTab {
 struct DecodeTask {
     int32_t seg;
     int32_t chunk0;   // first chunk (segment-local)
-    int32_t nchunk;   // chunks in this task (<= C3_NT)
+    int32_t nchunk;   // chunks in this task (<= C3_DEC_NT)
     int32_t pad;
 };
 

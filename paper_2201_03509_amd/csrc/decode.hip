@@ -12,7 +12,7 @@
 // than 12 bits); only codes behind one of the <= 20 split prefixes search the
 // limits.
 //
-// k_decode: a block owns up to C3_NT consecutive chunks of one segment; each
+// k_decode: a block owns up to C3_DEC_NT consecutive chunks of one segment; each
 // thread parses one chunk of both streams from the side index, G codes per
 // round, adds the symbol values to its running value (x_i = x_{i-1} + d_i),
 // range-checks, and leaves the samples in an LDS tile; the block then writes
@@ -187,14 +187,14 @@ struct BitReader {
     }
 };
 
-__global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, HuffDev hs,
+__global__ __launch_bounds__(C3_DEC_NT) void k_decode(LayoutDev Ld, HuffDev hp, HuffDev hs,
                                                   const DecTab *__restrict__ tabs,
                                                   const DecodeTask *__restrict__ tasks,
                                                   int32_t *__restrict__ pix_out,
                                                   uint16_t *__restrict__ psi_out, uint32_t *err) {
     __shared__ DecTab cp, cq;
-    __shared__ int32_t tp[C3_NT * GP];
-    __shared__ uint16_t tq[C3_NT * GP];  // psi symbol indices, then psi values
+    __shared__ int32_t tp[C3_DEC_NT * GP];
+    __shared__ uint16_t tq[C3_DEC_NT * GP];  // psi symbol indices, then psi values
     __shared__ uint32_t blk_err;
 
     const DecodeTask task = tasks[blockIdx.x];
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
         const uint4 *sp = (const uint4 *)(tabs + (tabs_ok ? tpi : 0));
         const uint4 *sq = (const uint4 *)(tabs + hp.ntable + (tabs_ok ? tqi : 0));
         uint4 *dp = (uint4 *)&cp, *dq = (uint4 *)&cq;
-        for (int i = tid; i < (int)(sizeof(DecTab) / 16); i += C3_NT) {
+        for (int i = tid; i < (int)(sizeof(DecTab) / 16); i += C3_DEC_NT) {
             dp[i] = sp[i];
             dq[i] = sq[i];
         }
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
     auto write_tile = [&](int k0) {
 #pragma unroll 4
         for (int m = 0; m < G; ++m) {
-            const int q = m * C3_NT + tid;
+            const int q = m * C3_DEC_NT + tid;
             const int ll = q >> 4, kk = q & 15;
             const int cc = task.chunk0 + ll;
             const int t = cc * C + k0 + kk;
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode(LayoutDev Ld, HuffDev hp, Huff
 static __device__ __align__(256) unsigned char scratch[C3_NOALLOC_BYTES];
 
 // The work list of k_decode in segment order: segment s takes
-// ceil(ceil(n_s / C) / C3_NT) tasks, starting at the sum of the counts before
+// ceil(ceil(n_s / C) / C3_DEC_NT) tasks, starting at the sum of the counts before
 // it.  One block scans the counts 1024 segments at a time.  Exactly ntask
 // entries are written: the host counts them from its mirror of the offsets;
 // entries the device offsets do not fill are empty tasks (no chunk), and
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(1024) void k_decode_tasks(const int64_t *__restrict
         if (s < nseg) {
             const int64_t n = seg_off[s + 1] - seg_off[s];
             nch = n > 0 ? (int)((n + C - 1) / C) : 0;
-            cnt = (nch + C3_NT - 1) / C3_NT;
+            cnt = (nch + C3_DEC_NT - 1) / C3_DEC_NT;
         }
         pre[tid] = cnt;
         __syncthreads();
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(1024) void k_decode_tasks(const int64_t *__restrict
         }
         const int64_t start = carry + pre[tid] - cnt;
         for (int j = 0; j < cnt && start + j < ntask; ++j)
-            tasks[start + j] = DecodeTask{s, j * C3_NT, min(C3_NT, nch - j * C3_NT), 0};
+            tasks[start + j] = DecodeTask{s, j * C3_DEC_NT, min(C3_DEC_NT, nch - j * C3_DEC_NT), 0};
         __syncthreads();
         if (tid == 1023) carry += pre[1023];
         __syncthreads();
@@ -426,12 +426,12 @@ __global__ __launch_bounds__(1024) void k_decode_tasks(const int64_t *__restrict
 // written as KIND 0: FP32 quantum * x, 1: FP64 quantum * x, 2: flag words
 // (and, if mask_out, the mask byte (x & flag_mask) == 0).
 template <int KIND>
-__global__ __launch_bounds__(C3_NT) void k_decode1(LayoutDev Ld, HuffDev h, const DecTab *__restrict__ tabs,
+__global__ __launch_bounds__(C3_DEC_NT) void k_decode1(LayoutDev Ld, HuffDev h, const DecTab *__restrict__ tabs,
                                                    const DecodeTask *__restrict__ tasks, double quantum,
                                                    uint32_t flag_mask, void *__restrict__ out,
                                                    uint8_t *__restrict__ mask_out, uint32_t *err) {
     __shared__ DecTab cp;
-    __shared__ int32_t tp[C3_NT * GP];
+    __shared__ int32_t tp[C3_DEC_NT * GP];
     __shared__ uint32_t blk_err;
 
     const DecodeTask task = tasks[blockIdx.x];
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode1(LayoutDev Ld, HuffDev h, cons
     {
         const uint4 *sp = (const uint4 *)(tabs + (tabs_ok ? ti : 0));
         uint4 *dp = (uint4 *)&cp;
-        for (int i = tid; i < (int)(sizeof(DecTab) / 16); i += C3_NT) dp[i] = sp[i];
+        for (int i = tid; i < (int)(sizeof(DecTab) / 16); i += C3_DEC_NT) dp[i] = sp[i];
         if (tid == 0) blk_err = 0;
     }
     __syncthreads();
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(C3_NT) void k_decode1(LayoutDev Ld, HuffDev h, cons
         __syncthreads();
 #pragma unroll 4
         for (int m = 0; m < G; ++m) {
-            const int q = m * C3_NT + tid;
+            const int q = m * C3_DEC_NT + tid;
             const int ll = q >> 4, kk = q & 15;
             const int cc = task.chunk0 + ll;
             const int t = cc * C + k0 + kk;
@@ -543,13 +543,13 @@ hipError_t launch_decode_stream(hipStream_t st, const LayoutDev &L, const HuffDe
     none.ntable = 0;
     hipLaunchKernelGGL(k_tables, dim3(h.ntable), dim3(C3_NT), 0, st, h, none, tabs);
     if (kind == 0)
-        hipLaunchKernelGGL(k_decode1<0>, dim3(ntask), dim3(C3_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
+        hipLaunchKernelGGL(k_decode1<0>, dim3(ntask), dim3(C3_DEC_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
                            out, mask_out, err);
     else if (kind == 1)
-        hipLaunchKernelGGL(k_decode1<1>, dim3(ntask), dim3(C3_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
+        hipLaunchKernelGGL(k_decode1<1>, dim3(ntask), dim3(C3_DEC_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
                            out, mask_out, err);
     else
-        hipLaunchKernelGGL(k_decode1<2>, dim3(ntask), dim3(C3_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
+        hipLaunchKernelGGL(k_decode1<2>, dim3(ntask), dim3(C3_DEC_NT), 0, st, L, h, tabs, tasks, quantum, flag_mask,
                            out, mask_out, err);
     return hipGetLastError();
 }
@@ -588,7 +588,7 @@ hipError_t launch_decode(hipStream_t st, const LayoutDev &L, const HuffDev &hp, 
                          uint16_t *psi_out, uint32_t *err) {
     if (ntask <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_tables, dim3(hp.ntable + hs.ntable), dim3(C3_NT), 0, st, hp, hs, tabs);
-    hipLaunchKernelGGL(k_decode, dim3(ntask), dim3(C3_NT), 0, st, L, hp, hs, tabs, tasks, pix_out,
+    hipLaunchKernelGGL(k_decode, dim3(ntask), dim3(C3_DEC_NT), 0, st, L, hp, hs, tabs, tasks, pix_out,
                        psi_out, err);
     return hipGetLastError();
 }
