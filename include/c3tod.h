@@ -166,12 +166,12 @@ tod_status decode_pointing(tod_ctx ctx, const tod_layout *lay,
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * decode_pointing with its device scratch -- the canonical decoding tables of
  * both streams (4528 bytes per table blob) and the decode work list (16 bytes
- * per block of up to 256 chunks, built on the device) -- in one static array
+ * per block of up to 512 chunks, built on the device) -- in one static array
  * of 16 MiB per device instead of context-owned buffers.  It calls no
  * hipMalloc/hipFree and builds no plan.  Same arguments, outputs and error
  * reporting as decode_pointing; TOD_ENOTSUP (before any launch) when the
  * tables and work list exceed the 16 MiB (the 70 GHz-like set of 600 table
- * blobs and 9.35e8 samples needs 4.4 MiB).  Every call on a device shares
+ * blobs and 9.35e8 samples needs 3.5 MiB).  Every call on a device shares
  * that device's array and rewrites what it uses: calls on one stream are
  * ordered, calls that overlap on one device (other streams or contexts) race. */
 tod_status decode_pointing_noalloc(tod_ctx ctx, const tod_layout *lay,
