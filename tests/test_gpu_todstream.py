@@ -153,3 +153,35 @@ def test_sweep_from_compressed_tod(prec):
     for q in range(ts.nseg):
         lo, hi = ts.seg_off[q], ts.seg_off[q + 1]
         assert np.linalg.norm(got[lo:hi] - ref[lo:hi]) / np.linalg.norm(ref[lo:hi]) < tol
+
+
+def test_decoder_block_boundaries(ctx):
+    """Segments whose chunk counts straddle the decoders' 512-chunk blocks
+    (511, 512 and 513 chunks of 32 symbols, the last of one symbol; 1025
+    chunks), at odd and even sample offsets: the pointing (with and without
+    allocation), TOD and flag streams bit-exact."""
+    ts = synth.make(1, nscan=4, length=("list", 16352, 16384, 16385, 32800), keep_truth=True,
+                    tod_streams=True)
+    tod = _tod(ts)
+    pix = torch.empty(ts.nsamp, dtype=torch.int32, device="cuda")
+    psi = torch.empty(ts.nsamp, dtype=torch.uint16, device="cuda")
+    ctx.decode_pointing(tod, pix, psi)
+    ctx.sync()
+    assert np.array_equal(pix.cpu().numpy(), ts.pix)
+    assert np.array_equal(psi.cpu().numpy().astype(np.int64), ts.psi)
+    pix.fill_(-1)
+    psi.fill_(0)
+    ctx.decode_pointing_noalloc(tod, pix, psi)
+    ctx.sync()
+    assert np.array_equal(pix.cpu().numpy(), ts.pix)
+    assert np.array_equal(psi.cpu().numpy().astype(np.int64), ts.psi)
+    d = torch.empty(ts.nsamp, dtype=torch.float32, device="cuda")
+    ctx.decode_tod(tod, "mixed", d)
+    f = torch.empty(ts.nsamp, dtype=torch.int32, device="cuda")
+    m = torch.empty(ts.nsamp, dtype=torch.uint8, device="cuda")
+    ctx.decode_flags(tod, synth.FLAG_PLANE | synth.FLAG_GLITCH, f, m)
+    ctx.sync()
+    assert np.array_equal(d.cpu().numpy(), ts.d.astype(np.float32))
+    ref = oh.decode_stream(ts, ts.flag_huff)
+    assert np.array_equal(f.cpu().numpy().astype(np.int64), ref)
+    assert np.array_equal(m.cpu().numpy(), (ref == 0).astype(np.uint8))
